@@ -1,0 +1,197 @@
+/*
+ * Plain FP64 CPU oracle for the TSBTS hot path (Kaplan & Saygin, arXiv 1205.2288).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code with the HIP path.
+ *
+ * Every routine is the plain definition written out as a double loop over particles in
+ * ascending index order, IEEE double rounding, compiled with -O2 -ffp-contract=off (no
+ * fused multiply-add), optionally with OpenMP over the outer index.  Arrays are float64
+ * structure-of-arrays: x[n], y[n], z[n] (and likewise for velocities).
+ *
+ * Units (Section 3): G = 1.  Plummer softening (Section 3): a pair at separation d
+ * interacts through (|d|^2 + eps^2)^(-1/2).
+ */
+#include <math.h>
+#include <stdint.h>
+
+/* Acceleration and potential on the listed target particles (Section 2; Algorithm 2,
+ * "calculate forces on the active particles"):
+ *   a_i   =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2)
+ *   phi_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps^2)^(1/2)
+ * The self pair is excluded by index.  Outputs are indexed by position in idx. */
+void oracle_force(int64_t n, const double *x, const double *y, const double *z,
+                  const double *m, double eps, const int32_t *idx, int64_t nact,
+                  double *ax, double *ay, double *az, double *pot)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nact; ++k) {
+        const int64_t i = idx[k];
+        double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[j] - x[i];
+            const double dy = y[j] - y[i];
+            const double dz = z[j] - z[i];
+            const double s = dx * dx + dy * dy + dz * dz + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double rinv3 = rinv * rinv * rinv;
+            sx += m[j] * dx * rinv3;
+            sy += m[j] * dy * rinv3;
+            sz += m[j] * dz * rinv3;
+            sp -= m[j] * rinv;
+        }
+        ax[k] = sx;
+        ay[k] = sy;
+        az[k] = sz;
+        if (pot) pot[k] = sp;
+    }
+}
+
+/* Total energy E = K + W (Section 3 energy-error diagnostic), with the same softening
+ * as the force:
+ *   K =  1/2 sum_i m_i |v_i|^2
+ *   W = -sum_{i<j} m_i m_j / (|r_i - r_j|^2 + eps^2)^(1/2)
+ * Each row i sums j > i in ascending order; rows are added in ascending i. */
+void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz,
+                   const double *m, double eps, double *kin, double *pot)
+{
+    const double eps2 = eps * eps;
+    double k = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        k += 0.5 * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    double w = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : w)
+    for (int64_t i = 0; i < n; ++i) {
+        double row = 0.0;
+        for (int64_t j = i + 1; j < n; ++j) {
+            const double dx = x[j] - x[i];
+            const double dy = y[j] - y[i];
+            const double dz = z[j] - z[i];
+            row += m[i] * m[j] / sqrt(dx * dx + dy * dy + dz * dz + eps2);
+        }
+        w -= row;
+    }
+    *kin = k;
+    *pot = w;
+}
+
+/* Time-step criterion, Eq. (nbdt) of Section 2:
+ *   dt_i = eta * min_{j != i} min( |r_ij| / |v_ij| , sqrt(|r_ij| / |a_ij|) )
+ * with the pairwise acceleration taken as the softened pull of j on i,
+ *   |a_ij| = m_j |r_ij| / (|r_ij|^2 + eps^2)^(3/2),
+ * so that |r_ij| / |a_ij| = (|r_ij|^2 + eps^2)^(3/2) / m_j (this form also defines the
+ * limit |r_ij| -> 0).  A zero relative speed makes the collision term infinite. */
+void oracle_timestep(int64_t n, const double *x, const double *y, const double *z,
+                     const double *vx, const double *vy, const double *vz,
+                     const double *m, double eps, double eta,
+                     const int32_t *idx, int64_t nact, double *dt)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nact; ++k) {
+        const int64_t i = idx[k];
+        double best = INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[j] - x[i];
+            const double dy = y[j] - y[i];
+            const double dz = z[j] - z[i];
+            const double dvx = vx[j] - vx[i];
+            const double dvy = vy[j] - vy[i];
+            const double dvz = vz[j] - vz[i];
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double v = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
+            const double s = r * r + eps2;
+            const double tcol = (v > 0.0) ? r / v : INFINITY;
+            const double tff = (m[j] > 0.0) ? sqrt(s * sqrt(s) / m[j]) : INFINITY;
+            if (tcol < best) best = tcol;
+            if (tff < best) best = tff;
+        }
+        dt[k] = eta * best;
+    }
+}
+
+/* Vector-Jacobian product of oracle_force (not in the paper; the adjoint of the force
+ * step).  Given g_c = dL/da_c and gp_c = dL/dphi_c for every listed target c, add to
+ * grad_r[k] = dL/dr_k and grad_m[k] = dL/dm_k for every particle k:
+ *
+ *   with d = r_k - r_c, s = |d|^2 + eps^2 and T(d) = s^(-3/2) I - 3 s^(-5/2) d d^T,
+ *   source term (k is the source of the pull on target c, k != c):
+ *     dL/dr_k += m_k [ T(d) g_c + gp_c s^(-3/2) d ]
+ *     dL/dm_k += g_c . d s^(-3/2) - gp_c s^(-1/2)
+ *   target term (k = c is a target, summed over all sources j != k, d = r_k - r_j):
+ *     dL/dr_k += -sum_j m_j T(d) g_k + gp_k sum_j m_j s^(-3/2) d
+ *
+ * The loops below evaluate these sums literally, one pair at a time. */
+void oracle_force_backward(int64_t n, const double *x, const double *y, const double *z,
+                           const double *m, double eps, const int32_t *idx, int64_t nact,
+                           const double *gax, const double *gay, const double *gaz,
+                           const double *gp, double *grx, double *gry, double *grz,
+                           double *gm)
+{
+    const double eps2 = eps * eps;
+    /* source terms: every particle k against every target c */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n; ++k) {
+        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+        for (int64_t q = 0; q < nact; ++q) {
+            const int64_t c = idx[q];
+            if (c == k) continue;
+            const double dx = x[k] - x[c];
+            const double dy = y[k] - y[c];
+            const double dz = z[k] - z[c];
+            const double s = dx * dx + dy * dy + dz * dz + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double r3 = rinv * rinv * rinv;
+            const double r5 = r3 * rinv * rinv;
+            const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
+            const double g2 = gp ? gp[q] : 0.0;
+            sx += r3 * gax[q] - 3.0 * r5 * dg * dx + g2 * r3 * dx;
+            sy += r3 * gay[q] - 3.0 * r5 * dg * dy + g2 * r3 * dy;
+            sz += r3 * gaz[q] - 3.0 * r5 * dg * dz + g2 * r3 * dz;
+            sm += dg * r3 - g2 * rinv;
+        }
+        grx[k] += m[k] * sx;
+        gry[k] += m[k] * sy;
+        grz[k] += m[k] * sz;
+        gm[k] += sm;
+    }
+    /* target terms: every listed target k against every source j */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < nact; ++q) {
+        const int64_t k = idx[q];
+        const double g2 = gp ? gp[q] : 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            const double dx = x[k] - x[j];
+            const double dy = y[k] - y[j];
+            const double dz = z[k] - z[j];
+            const double s = dx * dx + dy * dy + dz * dz + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double r3 = rinv * rinv * rinv;
+            const double r5 = r3 * rinv * rinv;
+            const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
+            sx += -m[j] * (r3 * gax[q] - 3.0 * r5 * dg * dx) + g2 * m[j] * r3 * dx;
+            sy += -m[j] * (r3 * gay[q] - 3.0 * r5 * dg * dy) + g2 * m[j] * r3 * dy;
+            sz += -m[j] * (r3 * gaz[q] - 3.0 * r5 * dg * dz) + g2 * m[j] * r3 * dz;
+        }
+        grx[k] += sx;
+        gry[k] += sy;
+        grz[k] += sz;
+    }
+}
+
+/* Number of threads the OpenMP runtime will use (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

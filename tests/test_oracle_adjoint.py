@@ -1,0 +1,82 @@
+"""Pins of the oracle's force adjoint and of its gradient through a leapfrog run.
+
+The force adjoint is checked against central finite differences of the oracle force
+(a different code path: only the forward loops), and against two exact identities:
+translation invariance (the gradient summed over particles vanishes) and Euler's theorem
+(acceleration and potential are homogeneous of degree one in the masses)."""
+import numpy as np
+import pytest
+
+from workloads import plummer, active_subset, gaussian
+from oracle import adjoint
+
+
+def _loss(oracle, r, m, eps, idx, ga, gp):
+    a, p = oracle.force(r, m, eps, idx)
+    return float((a * ga).sum() + (p * gp).sum())
+
+
+@pytest.mark.parametrize("n_act", [1, 5, 12])
+def test_force_backward_vs_finite_differences(oracle, n_act):
+    n, eps = 12, 0.05
+    r, _, m = plummer(n, 21, masses="loguniform")
+    idx = active_subset(n, n_act, 3 + n_act)
+    ga = gaussian((3, n_act), 31)
+    gp = gaussian(n_act, 32)
+    gr, gm = oracle.force_backward(r, m, eps, idx, ga, gp)
+    h = 1e-5
+    for trial in range(6):
+        dr = gaussian((3, n), 100 + trial)
+        dm = gaussian(n, 200 + trial) * m
+        fd_r = (_loss(oracle, r + h * dr, m, eps, idx, ga, gp)
+                - _loss(oracle, r - h * dr, m, eps, idx, ga, gp)) / (2 * h)
+        fd_m = (_loss(oracle, r, m + h * dm, eps, idx, ga, gp)
+                - _loss(oracle, r, m - h * dm, eps, idx, ga, gp)) / (2 * h)
+        assert (gr * dr).sum() == pytest.approx(fd_r, rel=1e-6, abs=1e-9)
+        assert (gm * dm).sum() == pytest.approx(fd_m, rel=1e-6, abs=1e-9)
+
+
+def test_force_backward_identities(oracle):
+    n, eps = 200, 0.02
+    r, _, m = plummer(n, 22, masses="loguniform")
+    idx = active_subset(n, 50, 9)
+    ga = gaussian((3, 50), 41)
+    gp = gaussian(50, 42)
+    gr, gm = oracle.force_backward(r, m, eps, idx, ga, gp)
+    a, p = oracle.force(r, m, eps, idx)
+    scale = np.abs(gr).sum()
+    assert np.abs(gr.sum(axis=1)).max() <= 1e-12 * scale
+    euler = (a * ga).sum() + (p * gp).sum()
+    assert (m * gm).sum() == pytest.approx(euler, rel=1e-11)
+
+
+def test_force_backward_accumulates(oracle):
+    n = 20
+    r, _, m = plummer(n, 23)
+    idx = np.arange(n, dtype=np.int32)
+    ga = gaussian((3, n), 5)
+    gr, gm = oracle.force_backward(r, m, 0.1, idx, ga)
+    gr2, gm2 = oracle.force_backward(r, m, 0.1, idx, 2.0 * ga)
+    assert np.allclose(gr2, 2 * gr, rtol=1e-14, atol=0)
+    assert np.allclose(gm2, 2 * gm, rtol=1e-14, atol=0)
+
+
+def test_leapfrog_gradient_vs_finite_differences(oracle):
+    n, eps, h, steps = 16, 1.0 / 16, 1.0 / 64, 8
+    r0, v0, m = plummer(n, 24, masses="loguniform")
+    target = adjoint.forward(r0, v0, m, eps, h, steps)[0] + 0.01 * gaussian((3, n), 6)
+    L, gr, gv, gm = adjoint.gradient(r0, v0, m, eps, h, steps, target)
+    assert L == pytest.approx(adjoint.loss(r0, v0, m, eps, h, steps, target), rel=1e-15)
+    step = 1e-6
+    for trial in range(4):
+        dr = gaussian((3, n), 300 + trial)
+        dv = gaussian((3, n), 400 + trial)
+        dm = gaussian(n, 500 + trial) * m
+        for (g, d, which) in ((gr, dr, "r"), (gv, dv, "v"), (gm, dm, "m")):
+            def f(sgn):
+                rr = r0 + sgn * step * d if which == "r" else r0
+                vv = v0 + sgn * step * d if which == "v" else v0
+                mm = m + sgn * step * d if which == "m" else m
+                return adjoint.loss(rr, vv, mm, eps, h, steps, target)
+            fd = (f(1) - f(-1)) / (2 * step)
+            assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which

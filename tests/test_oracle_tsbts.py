@@ -1,0 +1,182 @@
+"""Pins of the oracle's TSBTS driver (Algorithms 1-3, Eq. blockcondition).
+
+* Eq. (blockcondition) and every branch of Algorithm 1 / the first-pass rule are checked
+  on hand-built cases in integer ticks.
+* Algorithm 3's clamps and the era alignment are checked on hand-built block times.
+* When every particle sits on one shared level the scheme must reduce, bit for bit, to
+  the shared-step leapfrog of Section 2, whatever the number of passes.
+* Structural invariants of a real run (alignment, synchronisation at dt_max multiples),
+  checkpoint / resume, and the paper's qualitative claim that symmetrization passes
+  reduce the energy error (Section 6, Fig. 9 discussion).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.tsbts import OracleTSBTS, History, level_from_criterion, ticks, TICK
+from workloads import plummer
+
+DTMAX = ticks(1.0 / 64)  # 2^14 ticks
+
+
+@pytest.mark.parametrize("begin,end,expect", [
+    (1.0 / 64, 1.0 / 64, DTMAX),                  # tie accepted (<=)
+    (1.0 / 64 * (1 - 1e-12), 1.0 / 64, DTMAX // 2),
+    (10.0, 10.0, DTMAX),                          # capped at dt_max
+    (0.75 * 2 ** -10, 0.75 * 2 ** -10, 1 << 9),   # 2^-11
+    (2 ** -10, 2 ** -12, 1 << 9),                 # mean 0.625 * 2^-10 -> 2^-11
+    (1e-9, 1e-9, 1),                              # floored at dt_min
+    (0.3, 0.3, DTMAX),
+])
+def test_block_condition(begin, end, expect):
+    assert level_from_criterion(begin, end, 1, DTMAX) == expect
+
+
+def test_block_condition_uncapped_reaches_one():
+    # with no dt_max cap the admissible level never exceeds 2^0 (k >= 1)
+    assert level_from_criterion(5.0, 5.0, 1, 1 << 30) == 1 << 20
+
+
+def _sched(dt_ticks, n=1):
+    """A bare integrator object with one particle of step dt (ticks) for rule tests."""
+    s = OracleTSBTS.__new__(OracleTSBTS)
+    s.n = n
+    s.dt_max = DTMAX
+    s.dt_min = 1
+    s.dt = np.full(n, dt_ticks, dtype=np.int64)
+    return s
+
+
+def _prev(times, values):
+    h = History()
+    for t, c in zip(times, values):
+        h.append([0], t, np.zeros((3, 1)), np.zeros((3, 1)), np.zeros((3, 1)), [c])
+    return h.freeze(1)
+
+
+DT = 1 << 10  # current step: 2^-10
+
+
+def test_first_pass_rules():
+    s = _sched(DT)
+    dt = DT * TICK
+    assert s._new_step(0, 6 * DT, 0.2 * dt, None) == DT // 8   # several halvings
+    assert s._new_step(0, 6 * DT, 3.0 * dt, None) == 2 * DT    # even time: double
+    assert s._new_step(0, 5 * DT, 3.0 * dt, None) == DT        # odd time: keep
+    assert s._new_step(0, 6 * DT, 1.0 * dt, None) == DT        # exactly admissible: keep
+    assert _sched(DTMAX)._new_step(0, 2 * DTMAX, 9.0, None) == DTMAX  # never above dt_max
+
+
+def test_algorithm1_even_time_branches():
+    s = _sched(DT)
+    dt = DT * TICK
+    tb = 6 * DT  # 6 = even multiple of the step
+    flat = lambda c: _prev([0, 10 * DT], [c, c])
+    assert s._new_step(0, tb, 4.0 * dt, flat(4.0 * dt)) == 2 * DT   # doubling admissible
+    assert s._new_step(0, tb, 1.5 * dt, flat(1.5 * dt)) == DT       # keep
+    assert s._new_step(0, tb, 0.6 * dt, flat(0.6 * dt)) == DT // 2  # halve once only
+    assert s._new_step(0, tb, 0.1 * dt, flat(0.1 * dt)) == DT // 2
+    # end values from the previous pass, linear in time: at tb+2dt -> 0.9dt, at tb+dt -> 1.5dt
+    prev = _prev([tb, tb + DT, tb + 2 * DT], [3.0 * dt, 1.5 * dt, 0.9 * dt])
+    # 2dt: mean(3, 0.9) = 1.95dt -> level dt < 2dt ; dt: mean(3, 1.5) = 2.25dt -> ok
+    assert s._new_step(0, tb, 3.0 * dt, prev) == DT
+    # linear interpolation between stored points: end at tb+2dt from (tb, 4dt) -> (tb+4dt, 0)
+    prev2 = _prev([tb, tb + 4 * DT], [4.0 * dt, 0.0])
+    # end(2dt) = 2dt, mean(4, 2) = 3dt -> level 2dt -> double
+    assert s._new_step(0, tb, 4.0 * dt, prev2) == 2 * DT
+    # beyond the stored history the end value falls back to the begin value
+    short = _prev([tb - 2 * DT, tb], [0.1 * dt, 0.1 * dt])
+    assert s._new_step(0, tb, 4.0 * dt, short) == 2 * DT
+
+
+def test_algorithm1_odd_time_branches():
+    s = _sched(DT)
+    dt = DT * TICK
+    tb = 5 * DT
+    flat = lambda c: _prev([0, 10 * DT], [c, c])
+    assert s._new_step(0, tb, 4.0 * dt, flat(4.0 * dt)) == DT       # no doubling at odd time
+    assert s._new_step(0, tb, 1.0 * dt, flat(1.0 * dt)) == DT
+    assert s._new_step(0, tb, 0.9 * dt, flat(0.9 * dt)) == DT // 2
+
+
+def test_dynamic_era_size():
+    s = OracleTSBTS.__new__(OracleTSBTS)
+    s.era = None
+    s.dt_max = DTMAX
+    s.t = np.array([0, 0, 0], dtype=np.int64)
+    s.dt = np.array([DTMAX, DTMAX, DTMAX], dtype=np.int64)
+    assert s._era_end(0) == DTMAX // 8            # all equal: lower clamp dt_max/8
+    s.dt = np.array([1, 1 << 12, DTMAX], dtype=np.int64)
+    assert s._era_end(0) == DTMAX // 2            # spread dt_max - 1 rounds down
+    s.t = np.array([0, 0, 2 * DTMAX], dtype=np.int64)
+    assert s._era_end(0) == DTMAX                 # spread above dt_max: upper clamp
+    s.t = np.array([0, 0, 0], dtype=np.int64)
+    s.dt = np.array([1 << 10, 1 << 12, 1 << 12], dtype=np.int64)
+    assert s._era_end(0) == 1 << 11               # 3*2^10 rounds down to 2^11
+    # era end aligned to a multiple of the size
+    s.t = np.array([3 << 11, 3 << 11, 3 << 11], dtype=np.int64)
+    s.dt = np.array([1 << 10, 1 << 13, 1 << 13], dtype=np.int64)
+    assert s._era_end(3 << 11) == 1 << 13         # size 2^12 ... next multiple of 2^12
+
+
+def _big_criterion(r, v, idx):
+    return np.full(len(idx), 10.0)
+
+
+@pytest.mark.parametrize("passes", [1, 3])
+def test_shared_level_reduces_to_leapfrog(passes):
+    r, v, m = plummer(32, 17)
+    eps = 1.0 / 64
+    sim = OracleTSBTS(r, v, m, eps, passes=passes, era=1.0 / 8, criterion=_big_criterion)
+    assert np.all(sim.dt == DTMAX)
+    sim.run(0.25)
+    r_ref, v_ref, a_ref = oracle.leapfrog_shared(r, v, m, eps, 1.0 / 64, 16)
+    assert np.array_equal(sim.r, r_ref)
+    assert np.array_equal(sim.v, v_ref)
+    assert np.array_equal(sim.a, a_ref)
+
+
+def test_run_invariants_and_resume():
+    r, v, m = plummer(48, 18)
+    kw = dict(eta=0.3, passes=3, era=1.0 / 16)
+    a = OracleTSBTS(r, v, m, 1.0 / 64, **kw)
+    out = a.run(0.25)
+    assert len(out) == 1 + 4  # energy at every era end (all are dt_max multiples)
+    assert np.all(a.t == ticks(0.25))
+    assert np.all((a.dt & (a.dt - 1)) == 0) and a.dt.min() >= 1 and a.dt.max() <= DTMAX
+    assert a.stats["block_steps"] > 3 * 16  # 3 passes x 16 dt_max steps: finer levels used
+    # resume: 0 -> 1/8, save, 1/8 -> 1/4 in a fresh object equals the straight run
+    b = OracleTSBTS(r, v, m, 1.0 / 64, **kw)
+    b.run(0.125)
+    saved = b.state()
+    c = OracleTSBTS(r, v, m, 1.0 / 64, **kw)
+    c.load_state(saved)
+    c.run(0.25)
+    assert np.array_equal(c.r, a.r) and np.array_equal(c.v, a.v)
+    assert np.array_equal(c.dt, a.dt)
+
+
+def test_history_records_follow_schedule():
+    r, v, m = plummer(24, 19)
+    sim = OracleTSBTS(r, v, m, 1.0 / 64, eta=0.3, passes=2, era=1.0 / 64)
+    sim.era_step()
+    h = sim.last_history
+    # each particle: first record at the era start, last at its final time, times increase
+    for j in range(24):
+        ts = h.T[h.off[j]:h.off[j + 1]]
+        assert ts[0] == 0 and ts[-1] == sim.t[j]
+        assert np.all(np.diff(ts) > 0)
+
+
+@pytest.mark.slow
+def test_symmetrization_reduces_energy_error():
+    # the paper reports much smaller long-term energy errors with 3 iterations than with
+    # one at the same eta (Section 6); checked qualitatively on a small seeded sphere
+    r, v, m = plummer(64, 20)
+    errs = {}
+    for passes in (1, 3):
+        sim = OracleTSBTS(r, v, m, 1.0 / 64, eta=0.1, passes=passes, era=1.0 / 64)
+        out = sim.run(2.0)
+        e = np.array([x[1] for x in out])
+        errs[passes] = np.abs((e - e[0]) / e[0]).max()
+    assert errs[3] < errs[1]
