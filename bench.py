@@ -1,0 +1,304 @@
+"""Benchmark of the TSBTS hot path on one MI355X.
+
+Workload: seeded Plummer sphere, N = 131072, eps = 1/4096, log-uniform masses (1 decade,
+total mass 1), Henon units.  Particles sit on two block levels (half at step h, half at
+h/2, h = 2^-10), and one benchmark step is one era [0, h] of the method with two passes:
+
+  for each pass: restore the era-start state, start recording history,
+      block step at h/2: predict all (pass 2: Hermite interpolation of the non-active
+          half from pass 1's records), force on the active half, corrector, criterion;
+      block step at h:   predict all, force on all, corrector, criterion;
+      finish the history (group records by particle);
+  then the float64 energy of the synchronised state and the force adjoint for all
+  particles at time h (dL/dacc drawn from a seeded normal distribution).
+
+So each step issues 3 N^2 force interactions (mixed precision) and N^2 adjoint
+interactions; `value` is (force + adjoint interactions) per second over the timed steps
+(inputs resident in HBM).  The same step is timed with the float64 force as the
+comparison, plus a sweep of single force calls at active fractions 2^-k.
+
+Prints one JSON line.  `--gpus` above 1 is not supported (one-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+from workloads import config, active_subset, gaussian  # noqa: E402
+
+METRIC = "force interactions/s (mixed vs FP64, same accuracy) + adjoint interactions/s"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+# algorithmic flops per interaction (FMA = 2 flops)
+FLOPS_FORCE = 20.0
+FLOPS_ADJOINT = 73.0
+FLOPS_ENERGY_PAIR = 12.0
+
+
+class Timer:
+    """HIP-event timing of calls on torch's current stream (the stream the library
+    launches on)."""
+
+    def __init__(self):
+        self.events = {}
+
+    def __call__(self, name, fn, *a, **k):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        out = fn(*a, **k)
+        e.record()
+        self.events.setdefault(name, []).append((s, e))
+        return out
+
+    def ms(self):
+        torch.cuda.synchronize()
+        return {k: [s.elapsed_time(e) for s, e in v] for k, v in self.events.items()}
+
+
+class EraBench:
+    def __init__(self, cfg, r, v, m, precision, h=2.0 ** -10, seed=0):
+        from paper_1205_2288_amd import Context
+        n = cfg.n
+        self.n, self.h = n, h
+        self.ctx = c = Context(n, cfg.eps, precision=precision)
+        fine = active_subset(n, n // 2, cfg.seed + 11)
+        dt = np.full(n, h)
+        dt[fine] = h / 2
+        c.bind(r, v, m, t_last=np.zeros(n), dt=dt)
+        self.idx_all = c.idx(np.arange(n, dtype=np.int32))
+        self.idx_fine = c.idx(fine)
+        c.predict(0.0)
+        acc, _ = c.force(self.idx_all, 0.0, with_pot=False)
+        c.a.copy_(acc)
+        self.s0 = [x.clone() for x in (c.r, c.v, c.a, c.t_last, c.dt)]
+        dev = c.device
+        self.acc_all = torch.empty((3, n), dtype=torch.float64, device=dev)
+        self.acc_fine = torch.empty((3, fine.size), dtype=torch.float64, device=dev)
+        self.dtc_all = torch.empty(n, dtype=torch.float64, device=dev)
+        self.dtc_fine = torch.empty(fine.size, dtype=torch.float64, device=dev)
+        self.kw = torch.empty(2, dtype=torch.float64, device=dev)
+        self.g = torch.tensor(gaussian((3, n), cfg.seed + 7), device=dev)
+        self.gr = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.gm = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.eta = cfg.eta
+        self.interactions = 3 * n * n + n * n  # force (2 passes x 1.5 N^2) + adjoint
+        torch.cuda.synchronize()
+
+    def step(self, T: Timer | None = None):
+        c, h = self.ctx, self.h
+        t = T if T is not None else (lambda name, fn, *a, **k: fn(*a, **k))
+        for p in range(2):
+            for dst, src in zip((c.r, c.v, c.a, c.t_last, c.dt), self.s0):
+                dst.copy_(src)
+            c.history_begin()
+            for tb, idx, acc, dtc in ((h / 2, self.idx_fine, self.acc_fine, self.dtc_fine),
+                                      (h, self.idx_all, self.acc_all, self.dtc_all)):
+                t("predict", c.predict, tb, use_history=p > 0)
+                t("force_full" if idx is self.idx_all else "force_half", c.force, idx, tb,
+                  with_pot=False, acc=acc)
+                t("correct", c.correct, idx, tb, acc)
+                t("timestep", c.timestep, idx, self.eta, dtc=dtc)
+            t("history_end", c.history_end)
+        t("energy", c.energy, out=self.kw)
+        self.gr.zero_()
+        self.gm.zero_()
+        t("backward", c.force_backward, self.idx_all, h, self.g, None, self.gr, self.gm)
+
+    def close(self):
+        self.ctx.close()
+
+
+def time_steps(b: EraBench, steps: int, warmup: int):
+    for _ in range(warmup):
+        b.step()
+    torch.cuda.synchronize()
+    T = Timer()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.step(T)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, T.ms()
+
+
+def sweep(cfg, r, v, m, precision, reps=5):
+    """Single force calls at active fractions 2^-k (k = 0..17), median of reps."""
+    from paper_1205_2288_amd import Context
+    n = cfg.n
+    out = []
+    with Context(n, cfg.eps, precision=precision) as c:
+        c.bind(r, v, m)
+        c.predict(0.0)
+        for k in range(18):
+            n_act = max(1, n >> k)
+            idx = c.idx(active_subset(n, n_act, cfg.seed + 1000 * k))
+            acc = torch.empty((3, n_act), dtype=torch.float64, device=c.device)
+            pot = torch.empty(n_act, dtype=torch.float64, device=c.device)
+            for _ in range(2):
+                c.force(idx, 0.0, acc=acc, pot=pot)
+            T = Timer()
+            for _ in range(reps):
+                T("force", c.force, idx, 0.0, acc=acc, pot=pot)
+            ms = float(np.median(T.ms()["force"]))
+            out.append({"n_active": n_act, "us": round(ms * 1e3, 2),
+                        "interactions_per_s": n_act * n / (ms * 1e-3)})
+    return out
+
+
+def cpu_baseline(cfg, r, v, m, gpu_force_rows, target_s=12.0):
+    """The oracle (plain FP64 C loops, OpenMP) on a bounded sample of the same step's
+    work: force plus adjoint for a sample of targets against all N particles."""
+    import oracle
+    n = cfg.n
+    g = gaussian((3, n), cfg.seed + 7)
+    probe = np.arange(0, n, n // 64, dtype=np.int32)[:64]
+    t0 = time.perf_counter()
+    oracle.force(r, m, cfg.eps, probe)
+    oracle.force_backward(r, m, cfg.eps, probe, g[:, probe])
+    dt_probe = time.perf_counter() - t0
+    per_target = dt_probe / probe.size
+    s = int(np.clip(target_s / max(per_target, 1e-9), 64, n))
+    sample = np.sort(np.random.default_rng(cfg.seed).choice(n, size=s, replace=False)
+                     ).astype(np.int32)
+    t0 = time.perf_counter()
+    a_ref, _ = oracle.force(r, m, cfg.eps, sample)
+    t_force = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.force_backward(r, m, cfg.eps, sample, g[:, sample])
+    t_bwd = time.perf_counter() - t0
+    rate = 2.0 * s * n / (t_force + t_bwd)
+    # accuracy of the GPU force on the same sample (same arrays, time 0)
+    acc = {}
+    for prec, rows in gpu_force_rows.items():
+        got = rows[:, sample]
+        err = np.sqrt(((got - a_ref) ** 2).sum(0) / (a_ref ** 2).sum(0))
+        acc[prec] = {"median_rel_err": float(np.median(err)),
+                     "p99_rel_err": float(np.quantile(err, 0.99)),
+                     "max_rel_err": float(err.max())}
+    return {"value": rate, "unit": "interactions/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"force + adjoint of {s} random targets against all {n} particles "
+                      f"(plain FP64 C, {oracle.threads()} OpenMP threads); "
+                      f"force {t_force:.2f} s, adjoint {t_bwd:.2f} s",
+            "force_accuracy_vs_oracle": acc}
+
+
+def gpu_force_rows(cfg, r, v, m):
+    from paper_1205_2288_amd import Context
+    out = {}
+    for prec in ("mixed", "fp64"):
+        with Context(cfg.n, cfg.eps, precision=prec) as c:
+            c.bind(r, v, m)
+            c.predict(0.0)
+            acc, _ = c.force(np.arange(cfg.n, dtype=np.int32), 0.0, with_pot=False)
+            out[prec] = acc.cpu().numpy()
+    return out
+
+
+def roofline_for(name, ms_list, b: EraBench, n):
+    ms = float(np.mean(ms_list))
+    if name in ("force_full", "force_half"):
+        k = n if name == "force_full" else n // 2
+        achieved = FLOPS_FORCE * k * n / (ms * 1e-3) / 1e12
+        return {"kernel": "k_force (mixed, " + name + ")", "bound": "alu",
+                "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "avg_launch_us": ms * 1e3}
+    if name == "backward":
+        achieved = FLOPS_ADJOINT * n * n / (ms * 1e-3) / 1e12
+        return {"kernel": "k_bwd_src + k_bwd_tgt (mixed)", "bound": "alu",
+                "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "avg_launch_us": ms * 1e3}
+    if name == "energy":
+        achieved = FLOPS_ENERGY_PAIR * n * (n - 1) / 2 / (ms * 1e-3) / 1e12
+        return {"kernel": "k_energy_pairs", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "avg_launch_us": ms * 1e3}
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    cfg = config("plummer131k")
+    n = cfg.n
+    r, v, m = cfg.ic()
+
+    b = EraBench(cfg, r, v, m, "mixed")
+    wall, ms = time_steps(b, args.steps, args.warmup)
+    per_call = {k: {"calls_per_step": len(x) / args.steps, "mean_us": float(np.mean(x)) * 1e3}
+                for k, x in ms.items()}
+    totals = {k: float(np.sum(x)) for k, x in ms.items()}
+    dominant = max(totals, key=totals.get)
+    value = b.interactions * args.steps / wall
+    roof = roofline_for(dominant, ms[dominant], b, n)
+    roof_force = roofline_for("force_full", ms["force_full"], b, n)
+    b.close()
+
+    fp64 = None
+    if not args.no_fp64:
+        b64 = EraBench(cfg, r, v, m, "fp64")
+        steps64 = max(2, args.steps // 2)
+        wall64, ms64 = time_steps(b64, steps64, 1)
+        fp64 = {"ms_per_step": wall64 / steps64 * 1e3,
+                "value": b64.interactions * steps64 / wall64,
+                "force_full_us": float(np.mean(ms64["force_full"])) * 1e3,
+                "force_interactions_per_s": n * n / (np.mean(ms64["force_full"]) * 1e-3),
+                "backward_us": float(np.mean(ms64["backward"])) * 1e3}
+        b64.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 sums", "data": "synthetic",
+        "config": {"workload": "plummer131k: Plummer N=131072, eps=1/4096, log-uniform "
+                               "masses; one two-level two-pass era per step",
+                   "n": n, "eps": cfg.eps, "seed": cfg.seed, "precision": "mixed",
+                   "interactions_per_step": b.interactions},
+        "roofline": roof,
+        "roofline_force": roof_force,
+        "force_interactions_per_s": n * n / (np.mean(ms["force_full"]) * 1e-3),
+        "adjoint_interactions_per_s": n * n / (np.mean(ms["backward"]) * 1e-3),
+        "energy_pairs_per_s": n * (n - 1) / 2 / (np.mean(ms["energy"]) * 1e-3),
+        "breakdown_us": per_call,
+        "fp64_mode": fp64,
+    }
+    if not args.no_sweep:
+        out["sweep_mixed"] = sweep(cfg, r, v, m, "mixed")
+        out["sweep_fp64"] = sweep(cfg, r, v, m, "fp64")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, r, v, m, gpu_force_rows(cfg, r, v, m))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * tsbts.h - C ABI of the MI355X (gfx950) hot path of the dynamic-era time-symmetric block
+ * time-step (TSBTS) N-body method of Kaplan & Saygin, arXiv 1205.2288.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Pointers are DEVICE pointers (HIP global memory on the current device) unless the
+ *   comment says "host".  Vectors of particles are float64 structure-of-arrays: an array
+ *   documented as [3][n] holds all x, then all y, then all z.
+ * - Every call that takes a stream enqueues its work asynchronously on that stream (0 is
+ *   the legacy default stream) and returns without synchronising, except where stated.
+ *   Results are valid once the stream has been synchronised.
+ * - The return value is a status: TSBTS_OK (0) or a negative code below.  Argument checks
+ *   are done on the host before anything is enqueued; on error nothing is enqueued and
+ *   tsbts_last_error() describes the problem.  No C++ exception crosses this interface.
+ * - One context serves one stream at a time; calls on one context must not overlap.
+ * - Caller-owned arrays stay owned by the caller.  The context owns only its scratch
+ *   (predicted particle arrays, partial sums, stored era history) and frees it in
+ *   tsbts_destroy().
+ * - Units: G = 1 (Section 3 of the paper).  Softening is of Plummer type with length eps:
+ *   a pair at separation d interacts through (|d|^2 + eps^2)^(-1/2).
+ */
+#ifndef TSBTS_H
+#define TSBTS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TSBTS_OK 0
+#define TSBTS_EINVAL (-1) /* invalid argument (null pointer, size or index out of range) */
+#define TSBTS_ENOMEM (-2) /* device allocation failed */
+#define TSBTS_EHIP (-3)   /* a HIP runtime call failed; tsbts_last_error() has its text */
+#define TSBTS_ESTATE (-4) /* call out of order (e.g. force at a time that was not predicted) */
+
+/* force precision, chosen at creation */
+#define TSBTS_FP64 0  /* all pair arithmetic in float64 */
+#define TSBTS_MIXED 1 /* float64 positions, float32 pair arithmetic, float64 tile sums */
+
+/* creation flags */
+#define TSBTS_FLAG_F64_SEPARATION 1 /* MIXED: form separations in float64, then round to
+                                       float32 (default: hi/lo float32 pairs) */
+#define TSBTS_FLAG_NO_NEWTON 2      /* MIXED: use the hardware float32 1/sqrt without the
+                                       Newton refinement step */
+
+typedef struct tsbts_ctx tsbts_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int tsbts_version(void);
+
+/* Human-readable text of a status code (static string). */
+const char *tsbts_strerror(int status);
+
+/* Text of the last error reported on ctx (host string owned by ctx; "" if none). */
+const char *tsbts_last_error(const tsbts_ctx *ctx);
+
+/* Create a context for n particles (n >= 1) with softening length eps >= 0 on the current
+ * HIP device.  precision is TSBTS_FP64 or TSBTS_MIXED; flags is a bitwise OR of
+ * TSBTS_FLAG_* values.  Allocates the context's scratch (synchronous).  *out receives the
+ * context, or NULL on error. */
+int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flags);
+
+/* Free the context and everything it owns (synchronises the device first).  NULL is a
+ * no-op. */
+int tsbts_destroy(tsbts_ctx *ctx);
+
+/* Attach the caller's particle state, used by predict / correct / timestep / snapshot /
+ * history calls (Algorithm 2's per-particle data: positions, velocities, accelerations,
+ * time of the last step and current block step).
+ *   r, v, a   [3][n] float64   positions, velocities, accelerations (read and written)
+ *   m         [n]    float64   masses (read)
+ *   t_last    [n]    float64   time of each particle's last step (read and written)
+ *   dt        [n]    float64   current block step of each particle (read)
+ * Times and steps must be dyadic (multiples of a power of two), so that the activity test
+ * t_last + dt == t_block is exact.  The pointers must stay valid while bound. */
+int tsbts_bind_state(tsbts_ctx *ctx, double *r, double *v, double *a, const double *m,
+                     double *t_last, double *dt);
+
+/* Predict every particle to t_block (Section 2 predictor; Algorithm 2, step 4) into the
+ * context's particle arrays used by tsbts_force / tsbts_timestep / tsbts_force_backward:
+ *   - a particle with t_last + dt == t_block (active) is Taylor-predicted from its own
+ *     state: r + v h + a h^2/2, v + a h with h = t_block - t_last;
+ *   - otherwise, when use_history != 0 and the stored records of the previous pass (see
+ *     tsbts_history_end) bracket t_block, it is interpolated between the two bracketing
+ *     records by cubic Hermite interpolation (positions from (r, v), velocities from
+ *     (v, a) at both ends) - the time-symmetric interpolation of the second and later
+ *     passes;
+ *   - otherwise it is Taylor-predicted.
+ * Requires bound state.  use_history requires a completed history (else TSBTS_ESTATE).
+ * Within one pass successive t_block values must not decrease. */
+int tsbts_predict(tsbts_ctx *ctx, double t_block, int use_history, hipStream_t stream);
+
+/* Load explicit positions r [3][n] and masses m [n] (float64) into the context's particle
+ * arrays, labelled with time t_label, in place of a prediction (used to evaluate forces
+ * of arbitrary configurations, e.g. inside a differentiated leapfrog).  Velocities used by
+ * tsbts_timestep are set to zero. */
+int tsbts_load_positions(tsbts_ctx *ctx, const double *r, const double *m, double t_label,
+                         hipStream_t stream);
+
+/* Softened acceleration and potential of the active particles against all n particles
+ * (Algorithm 2, step 5; Plummer softening of Section 3), from the arrays of the last
+ * tsbts_predict / tsbts_load_positions, whose time must equal t_block (else
+ * TSBTS_ESTATE):
+ *   acc_i =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2)
+ *   pot_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps^2)^(1/2)
+ *   active_idx [n_active] int32   particle indices in [0, n) (any order, no duplicates
+ *                                 required by the physics, not checked)
+ *   acc        [3][n_active]      float64 output, row k for particle active_idx[k]
+ *   pot        [n_active]         float64 output, or NULL to skip
+ * 1 <= n_active <= n.  The sum over j is split over workgroups when the active set is small
+ * (the paper's work partitioning, Section 5) and combined in a fixed order, so results are
+ * bit-reproducible. */
+int tsbts_force(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active, double t_block,
+                double *acc, double *pot, hipStream_t stream);
+
+/* Vector-Jacobian product of tsbts_force at the same arrays and time (the adjoint used for
+ * gradients; not in the paper).  Given grad_acc = dL/dacc [3][n_active] and optionally
+ * grad_pot = dL/dpot [n_active] (NULL = zero), ADDS dL/dr into grad_r [3][n] and dL/dm into
+ * grad_m [n] (both float64, caller-initialised):
+ *   d = r_k - r_c, s = |d|^2 + eps^2, T(d) = s^(-3/2) I - 3 s^(-5/2) d d^T;
+ *   for every particle k and active target c != k:
+ *     dL/dr_k += m_k (T(d) g_c + gp_c s^(-3/2) d),  dL/dm_k += g_c.d s^(-3/2) - gp_c s^(-1/2)
+ *   for every active k (over all j != k, d = r_k - r_j):
+ *     dL/dr_k += -sum_j m_j T(d) g_k + gp_k sum_j m_j s^(-3/2) d
+ * 1 <= n_active <= n. */
+int tsbts_force_backward(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                         double t_block, const double *grad_acc, const double *grad_pot,
+                         double *grad_r, double *grad_m, hipStream_t stream);
+
+/* Leapfrog corrector of the active particles (Section 2, Eq. leapfrog) at t_block, after
+ * tsbts_predict(t_block) and tsbts_force:
+ *   r <- r + v h + a h^2/2 (= the predicted position),  v <- v + (a + acc_new) h / 2,
+ *   a <- acc_new,  t_last <- t_block,  with h = t_block - t_last.
+ * acc_new [3][n_active] float64.  The corrected velocities also replace the predicted ones
+ * used by tsbts_timestep.  While a history is being recorded (tsbts_history_begin) the new
+ * states are appended to it (Section 2: every step of the era is stored); the stored log
+ * grows geometrically, and a growth synchronises the stream. */
+int tsbts_correct(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                  double t_block, const double *acc_new, hipStream_t stream);
+
+/* Time-step criterion Eq. (nbdt) for the active particles, against all others at the last
+ * predicted time (corrected velocities for the active ones):
+ *   dtc_i = eta * min_{j != i} min(|r_ij| / |v_ij|, (|r_ij|^2 + eps^2)^(3/4) / sqrt(m_j))
+ * i.e. the collision time and the free-fall time sqrt(|r_ij| / |a_ij|) with
+ * |a_ij| = m_j |r_ij| / (|r_ij|^2 + eps^2)^(3/2).  dtc [n_active] float64 output. */
+int tsbts_timestep(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active, double eta,
+                   double *dtc, hipStream_t stream);
+
+/* Scatter new block steps: dt[active_idx[k]] = dt_new[k] (dt_new device [n_active]). */
+int tsbts_set_dt(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                 const double *dt_new, hipStream_t stream);
+
+/* Start recording a pass of an era (Section 2: positions, velocities and accelerations of
+ * every step are stored during each era).  The first record of every particle is its
+ * current bound state at its own t_last. */
+int tsbts_history_begin(tsbts_ctx *ctx, hipStream_t stream);
+
+/* Finish the recording: group the records by particle (in time order) so that they become
+ * the interpolation source of tsbts_predict(..., use_history=1) and tsbts_snapshot, and
+ * reset the per-particle interpolation cursors.  The previous source is replaced. */
+int tsbts_history_end(tsbts_ctx *ctx, hipStream_t stream);
+
+/* Forget the interpolation source (e.g. at the start of a new era's first pass). */
+int tsbts_history_clear(tsbts_ctx *ctx);
+
+/* Positions and velocities of all particles at time T (era-end synchronisation, Section 2):
+ * a particle whose t_last equals T gives its state; otherwise, if the finished history
+ * brackets T, cubic Hermite interpolation of its records; otherwise its Taylor prediction.
+ * r_out, v_out [3][n] float64.  Does not modify the bound state. */
+int tsbts_snapshot(tsbts_ctx *ctx, double T, double *r_out, double *v_out, hipStream_t stream);
+
+/* Total energy terms (Section 3 energy-error diagnostic), all in float64:
+ *   out_KW[0] = K =  1/2 sum_i m_i |v_i|^2
+ *   out_KW[1] = W = -sum_{i<j} m_i m_j / (|r_i - r_j|^2 + eps^2)^(1/2)
+ * r, v [3][n], m [n] float64; out_KW device [2].  Fixed-order reduction (bit-reproducible). */
+int tsbts_energy(tsbts_ctx *ctx, const double *r, const double *v, const double *m,
+                 double *out_KW, hipStream_t stream);
+
+/* Reverse sweep of one shared-step leapfrog step (adjoint of the corrector of Section 2),
+ * element-wise over [3][n] float64 arrays, for step h:
+ *   phase 0:  g_out = abar + (h/2) vbar                      (the adjoint of a_{k+1})
+ *   phase 1:  abar  = (h/2) vbar + (h^2/2) rbar ;  vbar += h rbar   (adjoints of step k)
+ * rbar is read in phase 1; g_out is written in phase 0 only. */
+int tsbts_leapfrog_adjoint(tsbts_ctx *ctx, int phase, double h, const double *rbar,
+                           double *vbar, double *abar, double *g_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSBTS_H */

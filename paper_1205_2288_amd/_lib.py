@@ -1,0 +1,223 @@
+"""ctypes binding of libtsbts.so: one Python function per C entry point, same names.
+
+Argument marshalling only.  Device arrays are torch tensors on the HIP device (float64 or
+int32, contiguous); the stream is torch's current stream unless one is given.  Every
+status other than TSBTS_OK raises TsbtsError with the library's message.  There is no
+fallback: if the shared library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsbts.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "tsbts.h")
+
+TSBTS_OK = 0
+TSBTS_EINVAL = -1
+TSBTS_ENOMEM = -2
+TSBTS_EHIP = -3
+TSBTS_ESTATE = -4
+TSBTS_FP64 = 0
+TSBTS_MIXED = 1
+TSBTS_FLAG_F64_SEPARATION = 1
+TSBTS_FLAG_NO_NEWTON = 2
+
+
+class TsbtsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "or python paper_1205_2288_amd/build.py")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_int = ctypes.c_int
+
+_SIGS = {
+    "tsbts_version": ([], _int),
+    "tsbts_strerror": ([_int], ctypes.c_char_p),
+    "tsbts_last_error": ([_p], ctypes.c_char_p),
+    "tsbts_create": ([ctypes.POINTER(_p), _i64, _d, _int, _int], _int),
+    "tsbts_destroy": ([_p], _int),
+    "tsbts_bind_state": ([_p, _p, _p, _p, _p, _p, _p], _int),
+    "tsbts_predict": ([_p, _d, _int, _p], _int),
+    "tsbts_load_positions": ([_p, _p, _p, _d, _p], _int),
+    "tsbts_force": ([_p, _p, _i32, _d, _p, _p, _p], _int),
+    "tsbts_force_backward": ([_p, _p, _i32, _d, _p, _p, _p, _p, _p], _int),
+    "tsbts_correct": ([_p, _p, _i32, _d, _p, _p], _int),
+    "tsbts_timestep": ([_p, _p, _i32, _d, _p, _p], _int),
+    "tsbts_set_dt": ([_p, _p, _i32, _p, _p], _int),
+    "tsbts_history_begin": ([_p, _p], _int),
+    "tsbts_history_end": ([_p, _p], _int),
+    "tsbts_history_clear": ([_p], _int),
+    "tsbts_snapshot": ([_p, _d, _p, _p, _p], _int),
+    "tsbts_energy": ([_p, _p, _p, _p, _p, _p], _int),
+    "tsbts_leapfrog_adjoint": ([_p, _int, _d, _p, _p, _p, _p, _p], _int),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/tsbts.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"\b(tsbts_[a-z_]+)\s*\(", text)))
+
+
+def _check(ctx, status: int):
+    if status != TSBTS_OK:
+        msg = lib.tsbts_last_error(ctx).decode() if ctx else ""
+        if not msg:
+            msg = lib.tsbts_strerror(status).decode()
+        raise TsbtsError(status, msg)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    """Device pointer of a contiguous tensor (None -> NULL), with light validation."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t, shape=None, name="array"):
+    return _ptr(t, torch.float64, shape, name)
+
+
+def _i32p(t, name="active_idx"):
+    return _ptr(t, torch.int32, None, name)
+
+
+# ------------------------------------------------------------------ entry points
+
+def tsbts_version() -> int:
+    return lib.tsbts_version()
+
+
+def tsbts_strerror(status: int) -> str:
+    return lib.tsbts_strerror(status).decode()
+
+
+def tsbts_last_error(ctx) -> str:
+    return lib.tsbts_last_error(ctx).decode()
+
+
+def tsbts_create(n: int, eps: float, precision: int, flags: int = 0):
+    out = ctypes.c_void_p()
+    st = lib.tsbts_create(ctypes.byref(out), int(n), float(eps), int(precision), int(flags))
+    if st != TSBTS_OK:
+        raise TsbtsError(st, f"tsbts_create: {tsbts_strerror(st)}")
+    return out
+
+
+def tsbts_destroy(ctx):
+    _check(None, lib.tsbts_destroy(ctx))
+
+
+def tsbts_bind_state(ctx, n, r, v, a, m, t_last, dt):
+    _check(ctx, lib.tsbts_bind_state(ctx, _f64(r, (3, n), "r"), _f64(v, (3, n), "v"),
+                                     _f64(a, (3, n), "a"), _f64(m, (n,), "m"),
+                                     _f64(t_last, (n,), "t_last"), _f64(dt, (n,), "dt")))
+
+
+def tsbts_predict(ctx, t_block, use_history=False, stream=None):
+    _check(ctx, lib.tsbts_predict(ctx, float(t_block), int(bool(use_history)), _stream(stream)))
+
+
+def tsbts_load_positions(ctx, n, r, m, t_label=0.0, stream=None):
+    _check(ctx, lib.tsbts_load_positions(ctx, _f64(r, (3, n), "r"), _f64(m, (n,), "m"),
+                                         float(t_label), _stream(stream)))
+
+
+def tsbts_force(ctx, active_idx, t_block, acc, pot=None, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_force(ctx, _i32p(active_idx), k, float(t_block),
+                                _f64(acc, (3, k), "acc"), _f64(pot, (k,), "pot"),
+                                _stream(stream)))
+
+
+def tsbts_force_backward(ctx, n, active_idx, t_block, grad_acc, grad_pot, grad_r, grad_m,
+                         stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_force_backward(
+        ctx, _i32p(active_idx), k, float(t_block), _f64(grad_acc, (3, k), "grad_acc"),
+        _f64(grad_pot, (k,), "grad_pot"), _f64(grad_r, (3, n), "grad_r"),
+        _f64(grad_m, (n,), "grad_m"), _stream(stream)))
+
+
+def tsbts_correct(ctx, active_idx, t_block, acc_new, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_correct(ctx, _i32p(active_idx), k, float(t_block),
+                                  _f64(acc_new, (3, k), "acc_new"), _stream(stream)))
+
+
+def tsbts_timestep(ctx, active_idx, eta, dtc, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_timestep(ctx, _i32p(active_idx), k, float(eta),
+                                   _f64(dtc, (k,), "dtc"), _stream(stream)))
+
+
+def tsbts_set_dt(ctx, active_idx, dt_new, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_set_dt(ctx, _i32p(active_idx), k, _f64(dt_new, (k,), "dt_new"),
+                                 _stream(stream)))
+
+
+def tsbts_history_begin(ctx, stream=None):
+    _check(ctx, lib.tsbts_history_begin(ctx, _stream(stream)))
+
+
+def tsbts_history_end(ctx, stream=None):
+    _check(ctx, lib.tsbts_history_end(ctx, _stream(stream)))
+
+
+def tsbts_history_clear(ctx):
+    _check(ctx, lib.tsbts_history_clear(ctx))
+
+
+def tsbts_snapshot(ctx, n, T, r_out, v_out, stream=None):
+    _check(ctx, lib.tsbts_snapshot(ctx, float(T), _f64(r_out, (3, n), "r_out"),
+                                   _f64(v_out, (3, n), "v_out"), _stream(stream)))
+
+
+def tsbts_energy(ctx, n, r, v, m, out_kw, stream=None):
+    _check(ctx, lib.tsbts_energy(ctx, _f64(r, (3, n), "r"), _f64(v, (3, n), "v"),
+                                 _f64(m, (n,), "m"), _f64(out_kw, (2,), "out_KW"),
+                                 _stream(stream)))
+
+
+def tsbts_leapfrog_adjoint(ctx, n, phase, h, rbar, vbar, abar, g_out, stream=None):
+    _check(ctx, lib.tsbts_leapfrog_adjoint(
+        ctx, int(phase), float(h), _f64(rbar, (3, n), "rbar"), _f64(vbar, (3, n), "vbar"),
+        _f64(abar, (3, n), "abar"), _f64(g_out, (3, n), "g_out"), _stream(stream)))

@@ -1,0 +1,173 @@
+"""Context: a libtsbts context plus the device tensors of one particle state.
+
+Thin convenience layer over the C ABI (paper_1205_2288_amd._lib): it allocates the
+caller-owned state tensors (float64 structure of arrays on the HIP device), binds them,
+and wraps the entry points so that callers pass index tensors and get result tensors.
+All arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.TSBTS_FP64, "mixed": L.TSBTS_MIXED}
+
+
+def _dev(x, dtype=torch.float64, device="cuda"):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+class Context:
+    """Device-resident particle state and a libtsbts context.
+
+    precision: "mixed" (float32 pair arithmetic, float64 sums) or "fp64".
+    separation: "hilo" (float32 hi/lo pairs) or "f64" (float64 separation rounded to float32);
+    newton: refine the float32 1/sqrt by one Newton step (mixed precision only).
+    """
+
+    def __init__(self, n: int, eps: float, precision: str = "mixed", separation: str = "hilo",
+                 newton: bool = True, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtsbts needs a HIP device")
+        self.n = int(n)
+        self.eps = float(eps)
+        self.precision = precision
+        self.device = torch.device(device)
+        flags = 0
+        if separation == "f64":
+            flags |= L.TSBTS_FLAG_F64_SEPARATION
+        elif separation != "hilo":
+            raise ValueError("separation must be 'hilo' or 'f64'")
+        if not newton:
+            flags |= L.TSBTS_FLAG_NO_NEWTON
+        self.flags = flags
+        self.ctx = L.tsbts_create(self.n, self.eps, PRECISIONS[precision], flags)
+        self.r = self.v = self.a = self.m = self.t_last = self.dt = None
+
+    # ---------------------------------------------------------------- state
+    def bind(self, r, v, m, a=None, t_last=None, dt=None):
+        n = self.n
+        self.r = _dev(r, device=self.device).reshape(3, n).contiguous()
+        self.v = _dev(v, device=self.device).reshape(3, n).contiguous()
+        self.m = _dev(m, device=self.device).reshape(n).contiguous()
+        self.a = (torch.zeros((3, n), dtype=torch.float64, device=self.device) if a is None
+                  else _dev(a, device=self.device).reshape(3, n).contiguous())
+        self.t_last = (torch.zeros(n, dtype=torch.float64, device=self.device) if t_last is None
+                       else _dev(t_last, device=self.device).reshape(n).contiguous())
+        self.dt = (torch.zeros(n, dtype=torch.float64, device=self.device) if dt is None
+                   else _dev(dt, device=self.device).reshape(n).contiguous())
+        L.tsbts_bind_state(self.ctx, n, self.r, self.v, self.a, self.m, self.t_last, self.dt)
+        return self
+
+    def idx(self, active):
+        """Active-set index tensor; host arrays are range-checked here (the kernels index
+        particle arrays with these values directly)."""
+        if not isinstance(active, torch.Tensor):
+            a = np.asarray(active)
+            if a.size and (a.min() < 0 or a.max() >= self.n):
+                raise IndexError("active index outside [0, n)")
+        elif active.device.type == "cpu" and active.numel():
+            if int(active.min()) < 0 or int(active.max()) >= self.n:
+                raise IndexError("active index outside [0, n)")
+        return _dev(active, dtype=torch.int32, device=self.device).reshape(-1).contiguous()
+
+    # ---------------------------------------------------------------- entry points
+    def predict(self, t_block, use_history=False, stream=None):
+        L.tsbts_predict(self.ctx, t_block, use_history, stream)
+
+    def load_positions(self, r, m=None, t_label=0.0, stream=None):
+        r = _dev(r, device=self.device).reshape(3, self.n).contiguous()
+        m = self.m if m is None else _dev(m, device=self.device).reshape(self.n).contiguous()
+        self._loaded = (r, m)  # keep the buffers alive until the kernels have run
+        L.tsbts_load_positions(self.ctx, self.n, r, m, t_label, stream)
+
+    def force(self, active, t_block, with_pot=True, acc=None, pot=None, stream=None):
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        k = idx.numel()
+        if acc is None:
+            acc = torch.empty((3, k), dtype=torch.float64, device=self.device)
+        if with_pot and pot is None:
+            pot = torch.empty(k, dtype=torch.float64, device=self.device)
+        L.tsbts_force(self.ctx, idx, t_block, acc, pot if with_pot else None, stream)
+        return acc, pot
+
+    def force_backward(self, active, t_block, grad_acc, grad_pot=None, grad_r=None,
+                       grad_m=None, stream=None):
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        if grad_r is None:
+            grad_r = torch.zeros((3, self.n), dtype=torch.float64, device=self.device)
+        if grad_m is None:
+            grad_m = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        ga = _dev(grad_acc, device=self.device).contiguous()
+        gp = None if grad_pot is None else _dev(grad_pot, device=self.device).contiguous()
+        L.tsbts_force_backward(self.ctx, self.n, idx, t_block, ga, gp, grad_r, grad_m, stream)
+        return grad_r, grad_m
+
+    def correct(self, active, t_block, acc_new, stream=None):
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        L.tsbts_correct(self.ctx, idx, t_block, acc_new, stream)
+
+    def timestep(self, active, eta, dtc=None, stream=None):
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        if dtc is None:
+            dtc = torch.empty(idx.numel(), dtype=torch.float64, device=self.device)
+        L.tsbts_timestep(self.ctx, idx, eta, dtc, stream)
+        return dtc
+
+    def set_dt(self, active, dt_new, stream=None):
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        L.tsbts_set_dt(self.ctx, idx, _dev(dt_new, device=self.device), stream)
+
+    def history_begin(self, stream=None):
+        L.tsbts_history_begin(self.ctx, stream)
+
+    def history_end(self, stream=None):
+        L.tsbts_history_end(self.ctx, stream)
+
+    def history_clear(self):
+        L.tsbts_history_clear(self.ctx)
+
+    def snapshot(self, T, stream=None):
+        r = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        v = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        L.tsbts_snapshot(self.ctx, self.n, T, r, v, stream)
+        return r, v
+
+    def energy(self, r=None, v=None, m=None, out=None, stream=None):
+        r = self.r if r is None else _dev(r, device=self.device)
+        v = self.v if v is None else _dev(v, device=self.device)
+        m = self.m if m is None else _dev(m, device=self.device)
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=self.device)
+        L.tsbts_energy(self.ctx, self.n, r, v, m, out, stream)
+        return out
+
+    def leapfrog_adjoint(self, phase, h, rbar, vbar, abar, g_out=None, stream=None):
+        L.tsbts_leapfrog_adjoint(self.ctx, self.n, phase, h, rbar, vbar, abar, g_out, stream)
+
+    # ---------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            L.tsbts_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,429 @@
+// C-ABI entry points of libtsbts (declared and documented in include/tsbts.h): context
+// lifecycle, host-side argument validation, scratch management and error reporting.  All
+// arithmetic happens in the kernels of the other files.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace tsbts {
+int64_t backward_partials_needed(const tsbts_ctx *c, int n_act);
+}
+
+using namespace tsbts;
+
+namespace {
+
+int fail(tsbts_ctx *c, int status, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return status;
+}
+
+int hip_fail(tsbts_ctx *c, hipError_t e, const char *what) {
+  return fail(c, TSBTS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define TSBTS_CHECK_HIP(ctx, expr)                              \
+  do {                                                          \
+    hipError_t _e = (expr);                                     \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #expr);    \
+  } while (0)
+
+template <class T>
+int dev_alloc(tsbts_ctx *c, T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return TSBTS_OK;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * static_cast<size_t>(count));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TSBTS_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                static_cast<long long>(sizeof(T) * count), hipGetErrorString(e));
+  }
+  return TSBTS_OK;
+}
+
+template <class T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int check_ctx(const tsbts_ctx *c) { return c ? TSBTS_OK : TSBTS_EINVAL; }
+
+int check_active(tsbts_ctx *c, const int32_t *idx, int32_t n_act) {
+  if (!idx) return fail(c, TSBTS_EINVAL, "active_idx is NULL");
+  if (n_act < 1 || n_act > c->n)
+    return fail(c, TSBTS_EINVAL, "n_active=%d outside [1, %lld]", n_act,
+                static_cast<long long>(c->n));
+  return TSBTS_OK;
+}
+
+int check_bound(tsbts_ctx *c) {
+  if (!c->r || !c->v || !c->a || !c->m || !c->t_last || !c->dt)
+    return fail(c, TSBTS_ESTATE, "no particle state bound (call tsbts_bind_state)");
+  return TSBTS_OK;
+}
+
+int check_pred(tsbts_ctx *c, double t_block) {
+  if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
+  if (c->pred_t != t_block)
+    return fail(c, TSBTS_ESTATE, "t_block=%.17g differs from the predicted time %.17g",
+                t_block, c->pred_t);
+  return TSBTS_OK;
+}
+
+// Grow the split-j partial buffer to at least `need` float64 elements (synchronous).
+int ensure_part(tsbts_ctx *c, int64_t need) {
+  if (need <= c->part_cap) return TSBTS_OK;
+  TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
+  const int64_t cap = std::max<int64_t>(need, c->part_cap * 2);
+  dev_free(c->part);
+  c->part_cap = 0;
+  int st = dev_alloc(c, &c->part, cap);
+  if (st) return st;
+  c->part_cap = cap;
+  return TSBTS_OK;
+}
+
+// Grow a [planes][cap] float64 buffer, preserving the first `used` entries of each plane.
+int grow_planes(tsbts_ctx *c, double *&buf, int64_t &cap, int planes, int64_t used,
+                int64_t need, hipStream_t st, double **t_buf = nullptr) {
+  if (need <= cap) return TSBTS_OK;
+  const int64_t ncap = std::max<int64_t>(need, cap + cap / 2 + 1024);
+  double *nb = nullptr;
+  int s = dev_alloc(c, &nb, ncap * planes);
+  if (s) return s;
+  double *nt = nullptr;
+  if (t_buf) {
+    s = dev_alloc(c, &nt, ncap);
+    if (s) {
+      dev_free(nb);
+      return s;
+    }
+  }
+  if (used > 0) {
+    for (int p = 0; p < planes; ++p)
+      TSBTS_CHECK_HIP(c, hipMemcpyAsync(nb + p * ncap, buf + p * cap, used * sizeof(double),
+                                        hipMemcpyDeviceToDevice, st));
+    if (t_buf)
+      TSBTS_CHECK_HIP(c, hipMemcpyAsync(nt, *t_buf, used * sizeof(double),
+                                        hipMemcpyDeviceToDevice, st));
+  }
+  // earlier kernels may still read the old buffer: wait before freeing it
+  TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
+  dev_free(buf);
+  buf = nb;
+  if (t_buf) {
+    dev_free(*t_buf);
+    *t_buf = nt;
+  }
+  cap = ncap;
+  return TSBTS_OK;
+}
+
+int grow_log(tsbts_ctx *c, int64_t need, hipStream_t st) {
+  History &h = c->h;
+  if (need <= h.cap) return TSBTS_OK;
+  const int64_t old_cap = h.cap;
+  int64_t cap = h.cap;
+  int s = grow_planes(c, h.s, cap, kHistPlanes, h.count, need, st, &h.t);
+  if (s) return s;
+  // index arrays
+  int32_t *np = nullptr, *nr = nullptr;
+  if ((s = dev_alloc(c, &np, cap))) return s;
+  if ((s = dev_alloc(c, &nr, cap))) {
+    dev_free(np);
+    return s;
+  }
+  if (h.count > 0) {
+    TSBTS_CHECK_HIP(c, hipMemcpyAsync(np, h.pid, h.count * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, st));
+    TSBTS_CHECK_HIP(c, hipMemcpyAsync(nr, h.rank, h.count * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, st));
+  }
+  TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
+  (void)old_cap;
+  dev_free(h.pid);
+  dev_free(h.rank);
+  h.pid = np;
+  h.rank = nr;
+  h.cap = cap;
+  return TSBTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsbts_version(void) { return 10000; }
+
+const char *tsbts_strerror(int status) {
+  switch (status) {
+    case TSBTS_OK: return "ok";
+    case TSBTS_EINVAL: return "invalid argument";
+    case TSBTS_ENOMEM: return "device memory allocation failed";
+    case TSBTS_EHIP: return "HIP runtime error";
+    case TSBTS_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char *tsbts_last_error(const tsbts_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flags) {
+  if (!out) return TSBTS_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > (int64_t(1) << 30)) return TSBTS_EINVAL;
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return TSBTS_EINVAL;
+  if (precision != TSBTS_FP64 && precision != TSBTS_MIXED) return TSBTS_EINVAL;
+  if (flags & ~(TSBTS_FLAG_F64_SEPARATION | TSBTS_FLAG_NO_NEWTON)) return TSBTS_EINVAL;
+  tsbts_ctx *c = new (std::nothrow) tsbts_ctx();
+  if (!c) return TSBTS_ENOMEM;
+  c->n = n;
+  c->npad = round_up(n, kPad);
+  c->eps = eps;
+  c->precision = precision;
+  c->flags = flags;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return TSBTS_EHIP;
+  }
+  int st = TSBTS_OK;
+  if (!st) st = dev_alloc(c, &c->p64, P64_PLANES * c->npad);
+  if (!st) st = dev_alloc(c, &c->v64, 3 * c->npad);
+  if (!st && precision == TSBTS_MIXED) st = dev_alloc(c, &c->p32, P32_PLANES * c->npad);
+  if (!st) st = dev_alloc(c, &c->h.cnt, n);
+  if (!st) st = dev_alloc(c, &c->h.off, n + 1);
+  if (!st) st = dev_alloc(c, &c->h.cur, n);
+  if (!st) {
+    c->epart_cap = energy_partials_needed(c);
+    st = dev_alloc(c, &c->epart, c->epart_cap);
+  }
+  if (!st) {
+    const int64_t need = std::max(partial_elems_needed(c, static_cast<int>(n)),
+                                  backward_partials_needed(c, static_cast<int>(n)));
+    st = ensure_part(c, need);
+  }
+  if (st) {
+    tsbts_destroy(c);
+    return st;
+  }
+  *out = c;
+  return TSBTS_OK;
+}
+
+int tsbts_destroy(tsbts_ctx *c) {
+  if (!c) return TSBTS_OK;
+  (void)hipDeviceSynchronize();
+  dev_free(c->p64);
+  dev_free(c->v64);
+  dev_free(c->p32);
+  dev_free(c->part);
+  dev_free(c->epart);
+  dev_free(c->h.pid);
+  dev_free(c->h.rank);
+  dev_free(c->h.t);
+  dev_free(c->h.s);
+  dev_free(c->h.ht);
+  dev_free(c->h.hs);
+  dev_free(c->h.off);
+  dev_free(c->h.cur);
+  dev_free(c->h.cnt);
+  delete c;
+  return TSBTS_OK;
+}
+
+int tsbts_bind_state(tsbts_ctx *c, double *r, double *v, double *a, const double *m,
+                     double *t_last, double *dt) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!r || !v || !a || !m || !t_last || !dt)
+    return fail(c, TSBTS_EINVAL, "tsbts_bind_state: NULL array");
+  c->r = r;
+  c->v = v;
+  c->a = a;
+  c->m = m;
+  c->t_last = t_last;
+  c->dt = dt;
+  c->have_pred = false;
+  return TSBTS_OK;
+}
+
+int tsbts_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
+  if (use_history && !c->h.valid)
+    return fail(c, TSBTS_ESTATE, "use_history requested without a finished history");
+  hipError_t e = launch_predict(c, t_block, use_history ? 1 : 0, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_predict launch");
+  c->pred_t = t_block;
+  c->have_pred = true;
+  return TSBTS_OK;
+}
+
+int tsbts_load_positions(tsbts_ctx *c, const double *r, const double *m, double t_label,
+                         hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!r || !m) return fail(c, TSBTS_EINVAL, "tsbts_load_positions: NULL array");
+  // velocities are zeroed so that tsbts_timestep sees a defined state
+  TSBTS_CHECK_HIP(c, hipMemsetAsync(c->v64, 0, 3 * c->npad * sizeof(double), stream));
+  hipError_t e = launch_load_positions(c, r, m, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_load_positions launch");
+  c->pred_t = t_label;
+  c->have_pred = true;
+  return TSBTS_OK;
+}
+
+int tsbts_force(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block, double *acc,
+                double *pot, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
+  if (int s = check_pred(c, t_block)) return s;
+  if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  hipError_t e = launch_force(c, idx, n_act, acc, pot, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_force launch");
+  return TSBTS_OK;
+}
+
+int tsbts_force_backward(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                         const double *ga, const double *gp, double *gr, double *gm,
+                         hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!ga || !gr || !gm) return fail(c, TSBTS_EINVAL, "tsbts_force_backward: NULL array");
+  if (int s = check_pred(c, t_block)) return s;
+  if (int s = ensure_part(c, backward_partials_needed(c, n_act))) return s;
+  hipError_t e = launch_backward(c, idx, n_act, ga, gp, gr, gm, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_force_backward launch");
+  return TSBTS_OK;
+}
+
+int tsbts_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                  const double *acc_new, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc_new) return fail(c, TSBTS_EINVAL, "acc_new is NULL");
+  if (int s = check_pred(c, t_block)) return s;
+  if (c->h.recording) {
+    const int64_t need = c->h.count + n_act;
+    if (need >= (int64_t(1) << 31))
+      return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
+    if (int s = grow_log(c, need, stream)) return s;
+  }
+  hipError_t e = launch_correct(c, idx, n_act, t_block, acc_new, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_correct launch");
+  if (c->h.recording) c->h.count += n_act;
+  return TSBTS_OK;
+}
+
+int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, double *dtc,
+                   hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!dtc) return fail(c, TSBTS_EINVAL, "dtc is NULL");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
+  if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
+  if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  hipError_t e = launch_timestep(c, idx, n_act, eta, dtc, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_timestep launch");
+  return TSBTS_OK;
+}
+
+int tsbts_set_dt(tsbts_ctx *c, const int32_t *idx, int32_t n_act, const double *dt_new,
+                 hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!dt_new) return fail(c, TSBTS_EINVAL, "dt_new is NULL");
+  hipError_t e = launch_set_dt(c, idx, n_act, dt_new, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_set_dt launch");
+  return TSBTS_OK;
+}
+
+int tsbts_history_begin(tsbts_ctx *c, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  c->h.count = 0;
+  if (int s = grow_log(c, c->n, stream)) return s;
+  c->h.recording = true;
+  hipError_t e = launch_history_begin(c, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_history_begin launch");
+  c->h.count = c->n;
+  return TSBTS_OK;
+}
+
+int tsbts_history_end(tsbts_ctx *c, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!c->h.recording) return fail(c, TSBTS_ESTATE, "no history is being recorded");
+  History &h = c->h;
+  if (h.count > h.hcap) {
+    // the finished buffers are replaced wholesale, nothing to preserve
+    TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
+    dev_free(h.ht);
+    dev_free(h.hs);
+    h.hcap = 0;
+    const int64_t cap = std::max<int64_t>(h.count, h.cap);
+    if (int s = dev_alloc(c, &h.hs, cap * kHistPlanes)) return s;
+    if (int s = dev_alloc(c, &h.ht, cap)) return s;
+    h.hcap = cap;
+  }
+  hipError_t e = launch_history_end(c, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_history_end launch");
+  h.hcount = h.count;
+  h.recording = false;
+  h.valid = true;
+  return TSBTS_OK;
+}
+
+int tsbts_history_clear(tsbts_ctx *c) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  c->h.valid = false;
+  c->h.recording = false;
+  c->h.count = 0;
+  return TSBTS_OK;
+}
+
+int tsbts_snapshot(tsbts_ctx *c, double T, double *r_out, double *v_out, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (!r_out || !v_out) return fail(c, TSBTS_EINVAL, "tsbts_snapshot: NULL output");
+  if (!std::isfinite(T)) return fail(c, TSBTS_EINVAL, "T is not finite");
+  hipError_t e = launch_snapshot(c, T, r_out, v_out, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_snapshot launch");
+  return TSBTS_OK;
+}
+
+int tsbts_energy(tsbts_ctx *c, const double *r, const double *v, const double *m,
+                 double *out_KW, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!r || !v || !m || !out_KW) return fail(c, TSBTS_EINVAL, "tsbts_energy: NULL array");
+  hipError_t e = launch_energy(c, r, v, m, out_KW, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_energy launch");
+  return TSBTS_OK;
+}
+
+int tsbts_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
+                           double *vbar, double *abar, double *g_out, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (phase != 0 && phase != 1) return fail(c, TSBTS_EINVAL, "phase must be 0 or 1");
+  if (!vbar || !abar) return fail(c, TSBTS_EINVAL, "tsbts_leapfrog_adjoint: NULL array");
+  if (phase == 0 && !g_out) return fail(c, TSBTS_EINVAL, "g_out is NULL");
+  if (phase == 1 && !rbar) return fail(c, TSBTS_EINVAL, "rbar is NULL");
+  hipError_t e = launch_leapfrog_adjoint(c, phase, h, rbar, vbar, abar, g_out, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_leapfrog_adjoint launch");
+  return TSBTS_OK;
+}
+
+}  // extern "C"

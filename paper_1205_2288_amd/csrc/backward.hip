@@ -1,0 +1,294 @@
+// Adjoint of the force (vector-Jacobian product; not in the paper): from g_c = dL/dacc_c
+// and gp_c = dL/dpot_c of the active targets c, accumulate dL/dr and dL/dm of all
+// particles.  With e = r_source - r_target, s = |e|^2 + eps^2, y = s^(-1/2) and
+// u = e . g, the two parts are
+//
+//   source part, every particle k (rows) against every active target c (columns), k != c:
+//     dL/dr_k += m_k sum_c [ y^3 g_c - (3 y^5 u + gp_c y^3) e ],   e = r_c - r_k
+//     dL/dm_k +=     sum_c [ -y^3 u - gp_c y ]
+//   target part, every active k (rows) against every particle j (columns), j != k:
+//     dL/dr_k += sum_j m_j [ -y^3 g_k + (3 y^5 u - gp_k y^3) e ],  e = r_j - r_k
+//
+// Both are gathers (each row owns its sums), with the same register/LDS tiling and
+// split-column scheme as the force kernel: no scatter, no atomics, fixed-order float64
+// combination.  The self pair is masked by index.
+#include "pair.hpp"
+
+namespace tsbts {
+namespace {
+
+template <class V> struct GradT { using T = float4; };
+template <> struct GradT<Fp64> { struct __align__(16) T { double x, y, z, w; }; };
+
+// Column record of the source part: an active target's position, (g, gp) and index.
+template <class V>
+struct __align__(16) Col {
+  typename V::J p;
+  typename GradT<V>::T g;
+  int idx;
+  int pad[3];
+};
+
+struct BwdArgs {
+  const float *p32;
+  const double *p64;
+  int64_t n, npad;
+  const int32_t *idx;
+  int n_act;
+  const double *ga, *gp;
+  double *gr, *gm;
+  SplitPlan plan;
+  int n_ctiles;
+  double eps2;
+  double *part;
+};
+
+template <class V, int NEWTON>
+__device__ __forceinline__ typename V::F inv_r(typename V::F s) {
+  if constexpr (sizeof(typename V::F) == 4) {
+    return NEWTON ? 0.5f * rsq_refined<1>(s) : rsq_refined<0>(s);
+  } else {
+    return rsqrt_f64<2>(s);
+  }
+}
+
+template <class V, int NEWTON>
+__device__ __forceinline__ void pair_src(const typename V::I &row, const Col<V> &c,
+                                         typename V::F eps2, bool self,
+                                         typename V::F acc[4]) {
+  using F = typename V::F;
+  F ex, ey, ez;
+  V::sep(row, c.p, ex, ey, ez);
+  const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
+  F y = inv_r<V, NEWTON>(s);
+  if (self) y = F(0);
+  const F y2 = y * y;
+  const F y3 = y2 * y;
+  const F y5 = y3 * y2;
+  const F u = fma(ex, F(c.g.x), fma(ey, F(c.g.y), ez * F(c.g.z)));
+  const F gpc = F(c.g.w);
+  const F coef = -fma(F(3) * y5, u, gpc * y3);
+  acc[0] = fma(y3, F(c.g.x), fma(coef, ex, acc[0]));
+  acc[1] = fma(y3, F(c.g.y), fma(coef, ey, acc[1]));
+  acc[2] = fma(y3, F(c.g.z), fma(coef, ez, acc[2]));
+  acc[3] -= fma(y3, u, gpc * y);
+}
+
+template <class V, int NEWTON>
+__device__ __forceinline__ void pair_tgt(const typename V::I &row, const typename V::J &j,
+                                         const typename V::F g[4], typename V::F eps2,
+                                         bool self, typename V::F acc[3]) {
+  using F = typename V::F;
+  F ex, ey, ez;
+  V::sep(row, j, ex, ey, ez);
+  const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
+  F y = inv_r<V, NEWTON>(s);
+  if (self) y = F(0);
+  const F m = V::mass(j);
+  const F y2 = y * y;
+  const F my3 = m * (y2 * y);
+  const F my5 = my3 * y2;
+  const F u = fma(ex, g[0], fma(ey, g[1], ez * g[2]));
+  const F coef = fma(F(3) * my5, u, -g[3] * my3);
+  acc[0] = fma(-my3, g[0], fma(coef, ex, acc[0]));
+  acc[1] = fma(-my3, g[1], fma(coef, ey, acc[1]));
+  acc[2] = fma(-my3, g[2], fma(coef, ez, acc[2]));
+}
+
+// ---------------------------------------------------------------- source part
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
+  using F = typename V::F;
+  __shared__ Col<V> sc[kTJ];
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int rtile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int ct0 = slice * A.plan.tiles_per_slice;
+  const int ct1 = min(ct0 + A.plan.tiles_per_slice, A.n_ctiles);
+  const int64_t P = A.npad;
+  const int64_t k = static_cast<int64_t>(rtile) * kWG + tid;  // row particle (< npad)
+  const typename V::I row = V::load_i(A.p32, A.p64, P, k);
+  const F eps2 = static_cast<F>(A.eps2);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ct = ct0; ct < ct1; ++ct) {
+    const int q = ct * kTJ + tid;
+    Col<V> rec;
+    if (q < A.n_act) {
+      const int64_t c = A.idx[q];
+      rec.p = V::load_j(A.p32, A.p64, P, c, 1.0f);
+      rec.g.x = A.ga[q];
+      rec.g.y = A.ga[A.n_act + q];
+      rec.g.z = A.ga[2 * A.n_act + q];
+      rec.g.w = A.gp ? A.gp[q] : 0.0;
+      rec.idx = static_cast<int>(c);
+    } else {
+      rec.p = V::load_j(A.p32, A.p64, P, P - 1, 1.0f);  // a padding particle
+      rec.g.x = rec.g.y = rec.g.z = rec.g.w = 0.0f;
+      rec.idx = -1;
+    }
+    const int cnt = min(kTJ, A.n_act - ct * kTJ);
+    __syncthreads();
+    sc[tid] = rec;
+    __syncthreads();
+    F acc[4] = {F(0), F(0), F(0), F(0)};
+    for (int cc = 0; cc < cnt; ++cc) {
+      const Col<V> c = sc[cc];
+      pair_src<V, NEWTON>(row, c, eps2, c.idx == k, acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tot[e] += static_cast<double>(acc[e]);
+  }
+  if (k >= A.n) return;
+  if (A.plan.n_slices == 1) {
+    const double mk = A.p64[P64_M * P + k];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += mk * tot[e];
+    A.gm[k] += tot[3];
+  } else {
+    double *out = A.part + static_cast<int64_t>(slice) * 4 * A.n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e * A.n + k] = tot[e];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_src_reduce(BwdArgs A) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (k >= A.n) return;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < A.plan.n_slices; ++s) {
+    const double *in = A.part + static_cast<int64_t>(s) * 4 * A.n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tot[e] += in[e * A.n + k];
+  }
+  const double mk = A.p64[P64_M * A.npad + k];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += mk * tot[e];
+  A.gm[k] += tot[3];
+}
+
+// ---------------------------------------------------------------- target part
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_bwd_tgt(BwdArgs A) {
+  using F = typename V::F;
+  __shared__ typename V::J sj[kTJ];
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int itile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);
+  const int64_t P = A.npad;
+  const int q = itile * kWG + tid;
+  const int qq = min(q, A.n_act - 1);
+  const int64_t g = A.idx[qq];
+  const typename V::I row = V::load_i(A.p32, A.p64, P, g);
+  const F gk[4] = {static_cast<F>(A.ga[qq]), static_cast<F>(A.ga[A.n_act + qq]),
+                   static_cast<F>(A.ga[2 * A.n_act + qq]),
+                   static_cast<F>(A.gp ? A.gp[qq] : 0.0)};
+  const F eps2 = static_cast<F>(A.eps2);
+  double tot[3] = {0.0, 0.0, 0.0};
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const typename V::J rec = V::load_j(A.p32, A.p64, P, jbase + tid, 1.0f);
+    __syncthreads();
+    sj[tid] = rec;
+    __syncthreads();
+    F acc[3] = {F(0), F(0), F(0)};
+#pragma unroll 2
+    for (int jj = 0; jj < kTJ; ++jj)
+      pair_tgt<V, NEWTON>(row, sj[jj], gk, eps2, jbase + jj == g, acc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) tot[e] += static_cast<double>(acc[e]);
+  }
+  if (q >= A.n_act) return;
+  if (A.plan.n_slices == 1) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) A.gr[e * A.n + g] += tot[e];
+  } else {
+    double *out = A.part + static_cast<int64_t>(slice) * 3 * A.n_act;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) out[e * A.n_act + q] = tot[e];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_tgt_reduce(BwdArgs A) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= A.n_act) return;
+  double tot[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < A.plan.n_slices; ++s) {
+    const double *in = A.part + static_cast<int64_t>(s) * 3 * A.n_act;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) tot[e] += in[e * A.n_act + q];
+  }
+  const int64_t g = A.idx[q];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) A.gr[e * A.n + g] += tot[e];
+}
+
+SplitPlan plan_src(const BwdArgs &A) {
+  return plan_split(A.npad, 1, (A.n_act + kTJ - 1) / kTJ, 2048);
+}
+SplitPlan plan_tgt(const BwdArgs &A) { return plan_split(A.n_act, 1, A.npad / kTJ, 2048); }
+
+template <class V, int NEWTON>
+hipError_t run(BwdArgs &A, hipStream_t st) {
+  // source part over all particles
+  A.plan = plan_src(A);
+  A.n_ctiles = (A.n_act + kTJ - 1) / kTJ;
+  hipLaunchKernelGGL((k_bwd_src<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.plan.n_slices > 1) {
+    const int nb = static_cast<int>((A.n + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_bwd_src_reduce, dim3(nb), dim3(kWG), 0, st, A);
+  }
+  // target part over the active set
+  A.plan = plan_tgt(A);
+  A.n_ctiles = static_cast<int>(A.npad / kTJ);
+  hipLaunchKernelGGL((k_bwd_tgt<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.plan.n_slices > 1) {
+    const int nb = (A.n_act + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_bwd_tgt_reduce, dim3(nb), dim3(kWG), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t backward_partials_needed(const tsbts_ctx *c, int n_act) {
+  BwdArgs A;
+  A.n = c->n;
+  A.npad = c->npad;
+  A.n_act = n_act;
+  const SplitPlan s = plan_src(A);
+  const SplitPlan t = plan_tgt(A);
+  int64_t need = 0;
+  if (s.n_slices > 1) need = static_cast<int64_t>(s.n_slices) * 4 * c->n;
+  if (t.n_slices > 1) need = std::max<int64_t>(need, static_cast<int64_t>(t.n_slices) * 3 * n_act);
+  return need;
+}
+
+hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const double *ga,
+                           const double *gp, double *gr, double *gm, hipStream_t st) {
+  BwdArgs A;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.n = c->n;
+  A.npad = c->npad;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.ga = ga;
+  A.gp = gp;
+  A.gr = gr;
+  A.gm = gm;
+  A.eps2 = c->eps * c->eps;
+  A.part = c->part;
+  if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st);
+  const bool newton = (c->flags & TSBTS_FLAG_NO_NEWTON) == 0;
+  if (c->flags & TSBTS_FLAG_F64_SEPARATION)
+    return newton ? run<MixSep64, 1>(A, st) : run<MixSep64, 0>(A, st);
+  return newton ? run<MixHiLo, 1>(A, st) : run<MixHiLo, 0>(A, st);
+}
+
+}  // namespace tsbts

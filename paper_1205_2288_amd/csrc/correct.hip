@@ -1,0 +1,227 @@
+// Leapfrog corrector of the active block (Section 2, Eq. leapfrog; Algorithm 2, step 6),
+// storage of every step of the era (Section 2), and small element-wise kernels.
+//
+// Era history: during a pass each corrected state is appended as a record
+// (particle, time, r, v, a) in block-step order, together with its rank among that
+// particle's records (a per-particle counter; each particle appears at most once per block
+// step, so no atomics are needed).  At the end of the pass an exclusive scan of the
+// per-particle counts gives each particle's first slot, and every record is scattered to
+// slot offset[particle] + rank: the records end up grouped by particle and in time order
+// (a stable counting sort).  Predictions of later passes walk these groups with a
+// per-particle cursor that only moves forward.
+#include "internal.hpp"
+
+namespace tsbts {
+namespace {
+
+struct CorrectArgs {
+  int64_t n, npad;
+  const int32_t *idx;
+  int n_act;
+  double tb;
+  const double *acc_new;
+  const double *p64;
+  double *v64;
+  double *r, *v, *a, *t_last;
+  int record;
+  int64_t base;    // first free record slot
+  int64_t cap;
+  int32_t *pid, *rank, *cnt;
+  double *rt, *rs;
+};
+
+__global__ __launch_bounds__(kWG) void k_correct(CorrectArgs p) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= p.n_act) return;
+  const int64_t g = p.idx[q];
+  const int64_t n = p.n, P = p.npad;
+  const double h = p.tb - p.t_last[g];
+  double st[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double an = p.acc_new[c * p.n_act + q];
+    const double rn = p.p64[c * P + g];  // predicted position = r + v h + a h^2/2
+    const double vn = p.v[c * n + g] + 0.5 * (p.a[c * n + g] + an) * h;
+    p.r[c * n + g] = rn;
+    p.v[c * n + g] = vn;
+    p.a[c * n + g] = an;
+    p.v64[c * P + g] = vn;
+    st[c] = rn;
+    st[c + 3] = vn;
+    st[c + 6] = an;
+  }
+  p.t_last[g] = p.tb;
+  if (p.record) {
+    const int64_t slot = p.base + q;
+    p.pid[slot] = static_cast<int32_t>(g);
+    const int32_t k = p.cnt[g];
+    p.rank[slot] = k;
+    p.cnt[g] = k + 1;
+    p.rt[slot] = p.tb;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) p.rs[c * p.cap + slot] = st[c];
+  }
+}
+
+// First record of every particle: its state at its own last time.
+__global__ __launch_bounds__(kWG) void k_history_begin(CorrectArgs p) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (j >= p.n) return;
+  const int64_t n = p.n;
+  p.pid[j] = static_cast<int32_t>(j);
+  p.rank[j] = 0;
+  p.cnt[j] = 1;
+  p.rt[j] = p.t_last[j];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    p.rs[c * p.cap + j] = p.r[c * n + j];
+    p.rs[(c + 3) * p.cap + j] = p.v[c * n + j];
+    p.rs[(c + 6) * p.cap + j] = p.a[c * n + j];
+  }
+}
+
+// Exclusive scan of cnt[0..n) into off[0..n], one workgroup of 1024 threads, each thread
+// owning a contiguous chunk.  Also resets the interpolation cursors to the group starts.
+constexpr int kScanWG = 1024;
+__global__ __launch_bounds__(kScanWG) void k_scan(const int32_t *cnt, int32_t *off,
+                                                  int32_t *cur, int64_t n) {
+  __shared__ int64_t part[kScanWG];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + kScanWG - 1) / kScanWG;
+  const int64_t b = t * chunk, e = min(n, b + chunk);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the per-thread sums
+  for (int d = 1; d < kScanWG; d <<= 1) {
+    const int64_t add = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;  // exclusive prefix of this chunk
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = static_cast<int32_t>(run);
+    cur[i] = static_cast<int32_t>(run);
+    run += cnt[i];
+  }
+  if (t == kScanWG - 1) off[n] = static_cast<int32_t>(part[t]);
+}
+
+struct ScatterArgs {
+  int64_t count, cap, hcap;
+  const int32_t *pid, *rank, *off;
+  const double *rt, *rs;
+  double *ht, *hs;
+};
+
+__global__ __launch_bounds__(kWG) void k_scatter(ScatterArgs p) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (r >= p.count) return;
+  const int64_t dst = static_cast<int64_t>(p.off[p.pid[r]]) + p.rank[r];
+  p.ht[dst] = p.rt[r];
+#pragma unroll
+  for (int c = 0; c < kHistPlanes; ++c) p.hs[c * p.hcap + dst] = p.rs[c * p.cap + r];
+}
+
+__global__ __launch_bounds__(kWG) void k_set_dt(const int32_t *idx, int n_act, const double *dt_new,
+                                                double *dt) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q < n_act) dt[idx[q]] = dt_new[q];
+}
+
+__global__ __launch_bounds__(kWG) void k_lf_adjoint(int64_t len, int phase, double h,
+                                                    const double *rbar, double *vbar,
+                                                    double *abar, double *g_out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (e >= len) return;
+  const double vb = vbar[e];
+  if (phase == 0) {
+    g_out[e] = abar[e] + 0.5 * h * vb;
+  } else {
+    const double rb = rbar[e];
+    abar[e] = 0.5 * h * vb + 0.5 * h * h * rb;
+    vbar[e] = vb + h * rb;
+  }
+}
+
+CorrectArgs base_args(tsbts_ctx *c) {
+  CorrectArgs p;
+  p.n = c->n;
+  p.npad = c->npad;
+  p.p64 = c->p64;
+  p.v64 = c->v64;
+  p.r = c->r;
+  p.v = c->v;
+  p.a = c->a;
+  p.t_last = c->t_last;
+  p.record = c->h.recording ? 1 : 0;
+  p.base = c->h.count;
+  p.cap = c->h.cap;
+  p.pid = c->h.pid;
+  p.rank = c->h.rank;
+  p.cnt = c->h.cnt;
+  p.rt = c->h.t;
+  p.rs = c->h.s;
+  return p;
+}
+
+}  // namespace
+
+hipError_t launch_correct(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                          const double *acc_new, hipStream_t st) {
+  CorrectArgs p = base_args(c);
+  p.idx = idx;
+  p.n_act = n_act;
+  p.tb = t_block;
+  p.acc_new = acc_new;
+  const int nb = (n_act + kWG - 1) / kWG;
+  hipLaunchKernelGGL(k_correct, dim3(nb), dim3(kWG), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_history_begin(tsbts_ctx *c, hipStream_t st) {
+  CorrectArgs p = base_args(c);
+  const int nb = static_cast<int>((c->n + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_history_begin, dim3(nb), dim3(kWG), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanWG), 0, st, c->h.cnt, c->h.off, c->h.cur,
+                     c->n);
+  ScatterArgs p;
+  p.count = c->h.count;
+  p.cap = c->h.cap;
+  p.hcap = c->h.hcap;
+  p.pid = c->h.pid;
+  p.rank = c->h.rank;
+  p.off = c->h.off;
+  p.rt = c->h.t;
+  p.rs = c->h.s;
+  p.ht = c->h.ht;
+  p.hs = c->h.hs;
+  const int nb = static_cast<int>((c->h.count + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kWG), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_dt(tsbts_ctx *c, const int32_t *idx, int n_act, const double *dt_new,
+                         hipStream_t st) {
+  const int nb = (n_act + kWG - 1) / kWG;
+  hipLaunchKernelGGL(k_set_dt, dim3(nb), dim3(kWG), 0, st, idx, n_act, dt_new, c->dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
+                                   double *vbar, double *abar, double *g_out,
+                                   hipStream_t st) {
+  const int64_t len = 3 * c->n;
+  const int nb = static_cast<int>((len + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_lf_adjoint, dim3(nb), dim3(kWG), 0, st, len, phase, h, rbar, vbar,
+                     abar, g_out);
+  return hipGetLastError();
+}
+
+}  // namespace tsbts

@@ -1,0 +1,166 @@
+// Total energy E = K + W for the energy-error diagnostic (Section 3), in float64:
+//   K =  1/2 sum_i m_i |v_i|^2,   W = -sum_{i<j} m_i m_j (|r_i - r_j|^2 + eps^2)^(-1/2).
+// The upper triangle of 256x256 particle tiles (I <= J) is enumerated one tile pair per
+// workgroup: target i = 256 I + lane in registers, the 256 sources of tile J in LDS, and on
+// diagonal tiles only j > i counts.  Each workgroup reduces its sums in a fixed order into
+// one partial; a single workgroup then adds the partials in a fixed order, so the result
+// is bit-reproducible.  1/sqrt uses the hardware estimate with two Newton steps.
+#include "internal.hpp"
+
+namespace tsbts {
+namespace {
+
+constexpr int kTE = 256;
+
+struct EnergyArgs {
+  int64_t n;
+  const double *r, *v, *m;
+  double eps2;
+  int64_t T;       // tile rows
+  int64_t ntp;     // tile pairs T (T + 1) / 2
+  double *part;    // [ntp][2]
+  double *out;
+};
+
+struct __align__(16) SRec { double x, y, z, m; };
+
+// Tile pair b -> (I, J), I <= J, rows enumerated I = 0, 1, ... with T - I pairs each.
+__device__ __forceinline__ void tile_pair(int64_t b, int64_t T, int64_t &I, int64_t &J) {
+  const double a = 2.0 * static_cast<double>(T) + 1.0;
+  int64_t i = static_cast<int64_t>((a - sqrt(a * a - 8.0 * static_cast<double>(b))) * 0.5);
+  auto first = [T](int64_t r) { return r * T - r * (r - 1) / 2; };
+  while (i > 0 && first(i) > b) --i;
+  while (first(i + 1) <= b) ++i;
+  I = i;
+  J = i + (b - first(i));
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
+  __shared__ SRec sj[kTE];
+  __shared__ double red[2][kWG / 64];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  int64_t I, J;
+  tile_pair(b, A.T, I, J);
+  const int64_t n = A.n;
+  const int64_t i = I * kTE + tid;
+  const int64_t j = J * kTE + tid;
+  SRec rec;
+  if (j < n) {
+    rec.x = A.r[j];
+    rec.y = A.r[n + j];
+    rec.z = A.r[2 * n + j];
+    rec.m = A.m[j];
+  } else {
+    rec.x = rec.y = rec.z = kFar;
+    rec.m = 0.0;
+  }
+  sj[tid] = rec;
+  double xi = kFar, yi = kFar, zi = kFar, mi = 0.0, ki = 0.0;
+  if (i < n) {
+    xi = A.r[i];
+    yi = A.r[n + i];
+    zi = A.r[2 * n + i];
+    mi = A.m[i];
+    if (I == J) {
+      const double vx = A.v[i], vy = A.v[n + i], vz = A.v[2 * n + i];
+      ki = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+    }
+  }
+  __syncthreads();
+  double w = 0.0;
+  if (i >= n) {
+    // padding target: contributes nothing (and must not meet padding sources at d = 0)
+  } else if (I != J) {
+#pragma unroll 4
+    for (int jj = 0; jj < kTE; ++jj) {
+      const SRec s = sj[jj];
+      const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+      const double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
+      w = fma(s.m, rsqrt_f64<2>(q), w);
+    }
+  } else {
+    for (int jj = 0; jj < kTE; ++jj) {
+      const SRec s = sj[jj];
+      const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+      double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
+      const bool upper = jj > tid;
+      q = upper ? q : 1.0;
+      const double mj = upper ? s.m : 0.0;
+      w = fma(mj, rsqrt_f64<2>(q), w);
+    }
+  }
+  double pw = wave_sum(mi * w);
+  double pk = wave_sum(ki);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = pw;
+    red[1][tid >> 6] = pk;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sw = 0.0, sk = 0.0;
+    for (int k = 0; k < kWG / 64; ++k) {
+      sw += red[0][k];
+      sk += red[1][k];
+    }
+    A.part[2 * b] = sw;
+    A.part[2 * b + 1] = sk;
+  }
+}
+
+constexpr int kRedWG = 1024;
+__global__ __launch_bounds__(kRedWG) void k_energy_reduce(EnergyArgs A) {
+  __shared__ double sw[kRedWG], sk[kRedWG];
+  const int t = threadIdx.x;
+  double w = 0.0, k = 0.0;
+  for (int64_t b = t; b < A.ntp; b += kRedWG) {
+    w += A.part[2 * b];
+    k += A.part[2 * b + 1];
+  }
+  sw[t] = w;
+  sk[t] = k;
+  __syncthreads();
+  for (int s = kRedWG / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sw[t] += sw[t + s];
+      sk[t] += sk[t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    A.out[0] = sk[0];
+    A.out[1] = -sw[0];
+  }
+}
+
+}  // namespace
+
+int64_t energy_partials_needed(const tsbts_ctx *c) {
+  const int64_t T = (c->n + kTE - 1) / kTE;
+  return T * (T + 1);  // two doubles per tile pair
+}
+
+hipError_t launch_energy(tsbts_ctx *c, const double *r, const double *v, const double *m,
+                         double *out, hipStream_t st) {
+  EnergyArgs A;
+  A.n = c->n;
+  A.r = r;
+  A.v = v;
+  A.m = m;
+  A.eps2 = c->eps * c->eps;
+  A.T = (c->n + kTE - 1) / kTE;
+  A.ntp = A.T * (A.T + 1) / 2;
+  A.part = c->epart;
+  A.out = out;
+  hipLaunchKernelGGL(k_energy_pairs, dim3(static_cast<unsigned>(A.ntp)), dim3(kWG), 0, st, A);
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(kRedWG), 0, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace tsbts

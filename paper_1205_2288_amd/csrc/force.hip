@@ -1,0 +1,262 @@
+// Softened direct-summation acceleration and potential of the active set against all
+// particles (Algorithm 2, step 5; Plummer softening of Section 3).
+//
+// Layout and schedule (gfx950):
+//   - a workgroup of 256 threads holds IPL*256 target particles, IPL per lane, in
+//     registers (gathered through active_idx from the predicted arrays);
+//   - the j-particles are streamed through LDS in tiles of 256 records, staged with
+//     coalesced structure-of-arrays loads (one record per thread) and read back as
+//     wave-uniform broadcasts;
+//   - mixed precision accumulates each tile in float32 and folds the tile sums into
+//     float64 accumulators; float64 mode accumulates in float64;
+//   - when the active set is small the j-sum is split over workgroups (the paper's work
+//     partitioning, Section 5), each writing float64 partials that a second kernel adds
+//     in slice order (no atomics, bit-reproducible);
+//   - logical block ids are renumbered so that the workgroups on one XCD share j-slices
+//     and hit in that XCD's L2.
+// The self pair (j == i) is masked by index, but only in the tiles that contain some
+// lane's own particle: a wave-uniform vote picks a masked copy of the inner loop for
+// those tiles and the unmasked one elsewhere, so the mask costs nothing on almost every
+// tile and no large self term ever enters a float32 accumulator.
+#include "pair.hpp"
+
+namespace tsbts {
+namespace {
+
+struct ForceArgs {
+  const float *p32;
+  const double *p64;
+  int64_t npad;
+  const int32_t *idx;
+  int n_act;
+  SplitPlan plan;
+  int n_jtiles;
+  float eps2f;
+  double eps2;
+  double *part;  // [S][4][n_act] raw sums when S > 1
+  double *acc;   // [3][n_act]
+  double *pot;   // [n_act] or null
+};
+
+// ----- pair contributions -------------------------------------------------------------
+// acc += m r^-3 d (times a constant scale), pot += m r^-1.
+
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void pair_acc(const typename V::I &i, const typename V::J &j,
+                                         float eps2, bool self, float &ax, float &ay,
+                                         float &az, float &pp) {
+  float dx, dy, dz;
+  V::sep(i, j, dx, dy, dz);
+  float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  float m = V::mass(j);
+  if (MASK && self) {
+    s = 1.0f;
+    m = 0.0f;
+  }
+  const float y = rsq_refined<NEWTON>(s);
+  const float mr1 = m * y;
+  const float mr3 = mr1 * (y * y);
+  ax = fmaf(mr3, dx, ax);
+  ay = fmaf(mr3, dy, ay);
+  az = fmaf(mr3, dz, az);
+  pp += mr1;
+}
+
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void pair_acc(const typename V::I &i, const typename V::J &j,
+                                         double eps2, bool self, double &ax, double &ay,
+                                         double &az, double &pp) {
+  double dx, dy, dz;
+  V::sep(i, j, dx, dy, dz);
+  double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  double m = V::mass(j);
+  if (MASK && self) {
+    s = 1.0;
+    m = 0.0;
+  }
+  const double y = rsqrt_f64<2>(s);
+  const double mr1 = m * y;
+  const double mr3 = mr1 * (y * y);
+  ax = fma(mr3, dx, ax);
+  ay = fma(mr3, dy, ay);
+  az = fma(mr3, dz, az);
+  pp += mr1;
+}
+
+// Mass scale held in LDS and the final acceleration scale (see rsq_refined).
+template <class V, int NEWTON>
+struct Scale {
+  static constexpr float kMass = (NEWTON && sizeof(typename V::F) == 4) ? 0.5f : 1.0f;
+  static constexpr double kAcc = (NEWTON && sizeof(typename V::F) == 4) ? 0.25 : 1.0;
+};
+
+template <class V, int NEWTON>
+__device__ __forceinline__ void finish(const ForceArgs &A, int q, int64_t g, double sx,
+                                       double sy, double sz, double sp) {
+  const double k = Scale<V, NEWTON>::kAcc;
+  A.acc[q] = k * sx;
+  A.acc[A.n_act + q] = k * sy;
+  A.acc[2 * A.n_act + q] = k * sz;
+  if (A.pot) A.pot[q] = -sp;
+}
+
+template <class V, int NEWTON, int MASK, int IPL, class F>
+__device__ __forceinline__ void tile_loop(const typename V::J *sj, const typename V::I *I,
+                                          const int *g, int64_t jbase, F eps2, F *fx, F *fy,
+                                          F *fz, F *fp) {
+#pragma unroll 4
+  for (int jj = 0; jj < kTJ; ++jj) {
+    const typename V::J J = sj[jj];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+      pair_acc<V, NEWTON, MASK>(I[k], J, eps2, MASK && (jbase + jj == g[k]), fx[k], fy[k],
+                                fz[k], fp[k]);
+  }
+}
+
+template <class V, int NEWTON, int IPL>
+__global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
+  static_assert(kTJ == kWG, "one staged record per thread");
+  using F = typename V::F;
+  __shared__ typename V::J sj[kTJ];
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int itile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
+  const int64_t P = A.npad;
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
+
+  typename V::I I[IPL];
+  int q[IPL];
+  int g[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    q[k] = (itile * IPL + k) * kWG + tid;
+    g[k] = A.idx[min(q[k], A.n_act - 1)];
+    I[k] = V::load_i(A.p32, A.p64, P, g[k]);
+  }
+  double sx[IPL], sy[IPL], sz[IPL], sp[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) sx[k] = sy[k] = sz[k] = sp[k] = 0.0;
+
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const typename V::J rec = V::load_j(A.p32, A.p64, P, jbase + tid, Scale<V, NEWTON>::kMass);
+    __syncthreads();
+    sj[tid] = rec;
+    __syncthreads();
+    F fx[IPL], fy[IPL], fz[IPL], fp[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) fx[k] = fy[k] = fz[k] = fp[k] = F(0);
+    bool mine = false;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
+    if (__ballot(mine) != 0)
+      tile_loop<V, NEWTON, 1, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
+    else
+      tile_loop<V, NEWTON, 0, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      sx[k] += static_cast<double>(fx[k]);
+      sy[k] += static_cast<double>(fy[k]);
+      sz[k] += static_cast<double>(fz[k]);
+      sp[k] += static_cast<double>(fp[k]);
+    }
+  }
+
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    if (q[k] >= A.n_act) continue;
+    if (A.plan.n_slices == 1) {
+      finish<V, NEWTON>(A, q[k], g[k], sx[k], sy[k], sz[k], sp[k]);
+    } else {
+      double *out = A.part + static_cast<int64_t>(slice) * 4 * A.n_act;
+      out[q[k]] = sx[k];
+      out[A.n_act + q[k]] = sy[k];
+      out[2 * A.n_act + q[k]] = sz[k];
+      out[3 * A.n_act + q[k]] = sp[k];
+    }
+  }
+}
+
+// Add the slices' partials in slice order and finish (scale, sign).
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_force_reduce(ForceArgs A) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= A.n_act) return;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+  const int64_t stride = 4 * static_cast<int64_t>(A.n_act);
+  for (int s = 0; s < A.plan.n_slices; ++s) {
+    const double *in = A.part + s * stride;
+    sx += in[q];
+    sy += in[A.n_act + q];
+    sz += in[2 * A.n_act + q];
+    sp += in[3 * A.n_act + q];
+  }
+  finish<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp);
+}
+
+template <class V, int NEWTON, int IPL>
+hipError_t run(ForceArgs &A, hipStream_t st) {
+  A.plan = plan_split(A.n_act, IPL, A.n_jtiles, 2048);
+  hipLaunchKernelGGL((k_force<V, NEWTON, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.plan.n_slices > 1) {
+    const int nb = (A.n_act + kWG - 1) / kWG;
+    hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+template <class V, int NEWTON>
+hipError_t pick_ipl(ForceArgs &A, hipStream_t st) {
+  if (A.n_act >= 8192) return run<V, NEWTON, 2>(A, st);
+  return run<V, NEWTON, 1>(A, st);
+}
+
+}  // namespace
+
+SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_blocks) {
+  SplitPlan p;
+  p.n_itiles = static_cast<int>((n_targets + ipl * kWG - 1) / (ipl * kWG));
+  int64_t s = (target_blocks + p.n_itiles - 1) / p.n_itiles;
+  if (s < 1) s = 1;
+  if (s > n_jtiles) s = n_jtiles;
+  p.tiles_per_slice = static_cast<int>((n_jtiles + s - 1) / s);
+  p.n_slices = static_cast<int>((n_jtiles + p.tiles_per_slice - 1) / p.tiles_per_slice);
+  p.nblk = static_cast<int>(round_up(static_cast<int64_t>(p.n_itiles) * p.n_slices, 8));
+  return p;
+}
+
+int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
+  const int64_t n_jtiles = c->npad / kTJ;
+  const int ipl = n_act >= 8192 ? 2 : 1;
+  const SplitPlan p = plan_split(n_act, ipl, n_jtiles, 2048);
+  int64_t need = p.n_slices > 1 ? static_cast<int64_t>(p.n_slices) * 4 * n_act : 0;
+  return need;
+}
+
+hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                        double *pot, hipStream_t st) {
+  ForceArgs A;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.npad = c->npad;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.n_jtiles = static_cast<int>(c->npad / kTJ);
+  A.eps2f = static_cast<float>(c->eps * c->eps);
+  A.eps2 = c->eps * c->eps;
+  A.part = c->part;
+  A.acc = acc;
+  A.pot = pot;
+  if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
+  const bool sep64 = (c->flags & TSBTS_FLAG_F64_SEPARATION) != 0;
+  const bool newton = (c->flags & TSBTS_FLAG_NO_NEWTON) == 0;
+  if (sep64) return newton ? pick_ipl<MixSep64, 1>(A, st) : pick_ipl<MixSep64, 0>(A, st);
+  return newton ? pick_ipl<MixHiLo, 1>(A, st) : pick_ipl<MixHiLo, 0>(A, st);
+}
+
+}  // namespace tsbts

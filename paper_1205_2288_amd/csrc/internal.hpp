@@ -1,0 +1,151 @@
+// Internal declarations of the TSBTS HIP library: the context, device helpers shared by
+// the kernels, and the host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tsbts.h"
+
+namespace tsbts {
+
+constexpr int kWG = 256;    // threads per workgroup (4 wave64)
+constexpr int kTJ = 256;    // j-particles per LDS tile
+constexpr int kPad = 512;   // particle arrays are padded to a multiple of this
+constexpr float kFarF = 1.0e18f;  // position of padding particles (zero mass)
+constexpr double kFar = 1.0e18;
+
+// Plane indices of the context's particle arrays.
+//   p64: [5][npad] float64: x, y, z, m, w = m^(-2/3)
+//   v64: [3][npad] float64: velocities at the predicted time
+//   p32: [8][npad] float32: x_hi, y_hi, z_hi, m, x_lo, y_lo, z_lo, w = m^(-2/3)
+enum { P64_X = 0, P64_M = 3, P64_W = 4, P64_PLANES = 5 };
+enum { P32_XH = 0, P32_M = 3, P32_XL = 4, P32_W = 7, P32_PLANES = 8 };
+// History record state planes: r(3), v(3), a(3)
+constexpr int kHistPlanes = 9;
+
+struct History {
+  // records being appended during a pass
+  int32_t *pid = nullptr, *rank = nullptr;
+  double *t = nullptr, *s = nullptr;  // s: [9][cap]
+  int64_t cap = 0, count = 0;
+  bool recording = false;
+  // finished pass, grouped by particle
+  double *ht = nullptr, *hs = nullptr;  // hs: [9][hcap]
+  int32_t *off = nullptr;               // [n + 1]
+  int32_t *cur = nullptr;               // [n] interpolation cursor
+  int64_t hcap = 0, hcount = 0;
+  bool valid = false;
+  int32_t *cnt = nullptr;               // [n] records per particle in the current pass
+};
+
+}  // namespace tsbts
+
+struct tsbts_ctx {
+  int64_t n = 0, npad = 0;
+  double eps = 0.0;
+  int precision = TSBTS_MIXED;
+  int flags = 0;
+  int device = 0;
+  // bound caller state
+  double *r = nullptr, *v = nullptr, *a = nullptr, *t_last = nullptr, *dt = nullptr;
+  const double *m = nullptr;
+  // predicted particle arrays
+  double *p64 = nullptr, *v64 = nullptr;
+  float *p32 = nullptr;
+  double pred_t = 0.0;
+  bool have_pred = false;
+  // partial sums of split-j reductions
+  double *part = nullptr;
+  int64_t part_cap = 0;  // elements
+  // energy partials
+  double *epart = nullptr;
+  int64_t epart_cap = 0;
+  tsbts::History h;
+  char err[512] = {0};
+};
+
+namespace tsbts {
+
+// ------------------------------------------------------------------ device helpers
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Renumber
+// so that each XCD receives a contiguous range of logical block ids; nblk is a multiple
+// of 8.
+__device__ __forceinline__ int xcd_linear(int bid, int nblk) {
+  return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_f64_approx(double x) { return __builtin_amdgcn_rsq(x); }
+
+// 1/sqrt(s) in float64: hardware estimate refined by Newton-Raphson iterations
+// y <- y (3 - s y^2) / 2, each of which roughly doubles the number of correct bits.
+template <int STEPS>
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  double y = rsq_f64_approx(s);
+  const double hs = 0.5 * s;
+#pragma unroll
+  for (int k = 0; k < STEPS; ++k) y = y * fma(-hs * y, y, 1.5);
+  return y;
+}
+
+// Split a float64 into a float32 pair whose sum carries ~48 significant bits.
+__device__ __forceinline__ void split_hilo(double x, float &hi, float &lo) {
+  hi = static_cast<float>(x);
+  lo = static_cast<float>(x - static_cast<double>(hi));
+}
+
+// m^(-2/3): the per-source weight of the free-fall criterion term (infinite for m = 0).
+__device__ __forceinline__ double ff_weight(double m) {
+  return m > 0.0 ? 1.0 / cbrt(m * m) : __builtin_inf();
+}
+
+__host__ __device__ constexpr int64_t round_up(int64_t x, int64_t q) {
+  return (x + q - 1) / q * q;
+}
+
+// ------------------------------------------------------------------ launch plans
+
+struct SplitPlan {
+  int n_itiles;        // i-tiles of ipl*kWG targets
+  int n_slices;        // j-slices
+  int tiles_per_slice; // j-tiles of kTJ per slice
+  int nblk;            // launched blocks (multiple of 8)
+};
+
+SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_blocks);
+
+// ------------------------------------------------------------------ launchers
+// Each returns a hipError_t from the launch (hipSuccess on success).
+
+hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st);
+hipError_t launch_load_positions(tsbts_ctx *c, const double *r, const double *m,
+                                 hipStream_t st);
+hipError_t launch_snapshot(tsbts_ctx *c, double T, double *r_out, double *v_out,
+                           hipStream_t st);
+
+hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                        double *pot, hipStream_t st);
+hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                           double *dtc, hipStream_t st);
+hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const double *ga,
+                           const double *gp, double *gr, double *gm, hipStream_t st);
+hipError_t launch_energy(tsbts_ctx *c, const double *r, const double *v, const double *m,
+                         double *out, hipStream_t st);
+
+hipError_t launch_correct(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                          const double *acc_new, hipStream_t st);
+hipError_t launch_set_dt(tsbts_ctx *c, const int32_t *idx, int n_act, const double *dt_new,
+                         hipStream_t st);
+hipError_t launch_history_begin(tsbts_ctx *c, hipStream_t st);
+hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st);
+hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
+                                   double *vbar, double *abar, double *g_out,
+                                   hipStream_t st);
+
+// Scratch needed by the split-j kernels for a given active-set size (float64 elements).
+int64_t partial_elems_needed(const tsbts_ctx *c, int n_act);
+int64_t energy_partials_needed(const tsbts_ctx *c);
+
+}  // namespace tsbts

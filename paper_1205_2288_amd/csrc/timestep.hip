@@ -1,0 +1,228 @@
+// Time-step criterion, Eq. (nbdt) of Section 2, for the active particles:
+//   dtc_i = eta * min_{j != i} min(|r_ij| / |v_ij|, sqrt(|r_ij| / |a_ij|)),
+//   |a_ij| = m_j |r_ij| / s^(3/2),  s = |r_ij|^2 + eps^2,
+// so the free-fall term is s^(3/4) m_j^(-1/2) = (s m_j^(-2/3))^(3/4).
+// Per pair the kernel keeps max(|v_ij|^2 / |r_ij|^2) and min(s * m_j^(-2/3)); the square
+// root and the 3/4 power are taken once per target.  No transcendental per pair in
+// float64 mode apart from the division; mixed mode uses the float32 reciprocal.
+// Same tiling and split-j scheme as the force kernel; the self pair is masked by index.
+#include "pair.hpp"
+
+namespace tsbts {
+namespace {
+
+struct StepArgs {
+  const float *p32;
+  const double *p64;
+  const double *v64;
+  int64_t npad;
+  const int32_t *idx;
+  int n_act;
+  SplitPlan plan;
+  int n_jtiles;
+  double eps2;
+  double eta;
+  double *part;  // [S][2][n_act]: max q, min s*w
+  double *dtc;
+};
+
+template <class V> struct StepRec;
+
+template <> struct StepRec<MixHiLo> {
+  struct __align__(16) J { MixHiLo::J p; float4 v; };
+  struct I { MixHiLo::I p; float vx, vy, vz; };
+};
+template <> struct StepRec<MixSep64> {
+  struct __align__(16) J { MixSep64::J p; float4 v; };
+  struct I { MixSep64::I p; float vx, vy, vz; };
+};
+template <> struct StepRec<Fp64> {
+  struct __align__(16) J { Fp64::J p; double vx, vy, vz, w; };
+  struct I { Fp64::I p; double vx, vy, vz; };
+};
+
+template <class V>
+__device__ __forceinline__ typename StepRec<V>::J load_jv(const StepArgs &A, int64_t j) {
+  typename StepRec<V>::J r;
+  const int64_t P = A.npad;
+  r.p = V::load_j(A.p32, A.p64, P, j, 1.0f);
+  if constexpr (sizeof(typename V::F) == 4) {
+    r.v = make_float4(static_cast<float>(A.v64[j]), static_cast<float>(A.v64[P + j]),
+                      static_cast<float>(A.v64[2 * P + j]), 0.0f);
+  } else {
+    r.vx = A.v64[j];
+    r.vy = A.v64[P + j];
+    r.vz = A.v64[2 * P + j];
+    r.w = A.p64[P64_W * P + j];
+  }
+  return r;
+}
+
+template <class V>
+__device__ __forceinline__ typename StepRec<V>::I load_iv(const StepArgs &A, int64_t g) {
+  typename StepRec<V>::I r;
+  const int64_t P = A.npad;
+  r.p = V::load_i(A.p32, A.p64, P, g);
+  r.vx = A.v64[g];
+  r.vy = A.v64[P + g];
+  r.vz = A.v64[2 * P + g];
+  return r;
+}
+
+__device__ __forceinline__ void pair_step(const StepRec<MixHiLo>::I &i,
+                                          const StepRec<MixHiLo>::J &j, float eps2, bool self,
+                                          float &qmax, float &swmin) {
+  float dx, dy, dz;
+  MixHiLo::sep(i.p, j.p, dx, dy, dz);
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const float ux = j.v.x - i.vx, uy = j.v.y - i.vy, uz = j.v.z - i.vz;
+  const float v2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+  float q = v2 * __builtin_amdgcn_rcpf(r2);
+  float sw = (r2 + eps2) * MixHiLo::weight(j.p);
+  if (self) {
+    q = 0.0f;
+    sw = __builtin_inff();
+  }
+  qmax = fmaxf(qmax, q);
+  swmin = fminf(swmin, sw);
+}
+
+__device__ __forceinline__ void pair_step(const StepRec<MixSep64>::I &i,
+                                          const StepRec<MixSep64>::J &j, float eps2, bool self,
+                                          float &qmax, float &swmin) {
+  float dx, dy, dz;
+  MixSep64::sep(i.p, j.p, dx, dy, dz);
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const float ux = j.v.x - i.vx, uy = j.v.y - i.vy, uz = j.v.z - i.vz;
+  const float v2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+  float q = v2 * __builtin_amdgcn_rcpf(r2);
+  float sw = (r2 + eps2) * MixSep64::weight(j.p);
+  if (self) {
+    q = 0.0f;
+    sw = __builtin_inff();
+  }
+  qmax = fmaxf(qmax, q);
+  swmin = fminf(swmin, sw);
+}
+
+__device__ __forceinline__ void pair_step(const StepRec<Fp64>::I &i, const StepRec<Fp64>::J &j,
+                                          double eps2, bool self, double &qmax,
+                                          double &swmin) {
+  double dx, dy, dz;
+  Fp64::sep(i.p, j.p, dx, dy, dz);
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ux = j.vx - i.vx, uy = j.vy - i.vy, uz = j.vz - i.vz;
+  const double v2 = ux * ux + uy * uy + uz * uz;
+  double q = v2 / r2;
+  double sw = (r2 + eps2) * j.w;
+  if (self) {
+    q = 0.0;
+    sw = __builtin_inf();
+  }
+  qmax = fmax(qmax, q);
+  swmin = fmin(swmin, sw);
+}
+
+__device__ __forceinline__ double finish_dt(double eta, double qmax, double swmin) {
+  const double tcol = qmax > 0.0 ? sqrt(1.0 / qmax) : __builtin_inf();
+  const double tff = pow(swmin, 0.75);
+  return eta * fmin(tcol, tff);
+}
+
+template <class V, int IPL>
+__global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
+  using F = typename V::F;
+  using J = typename StepRec<V>::J;
+  __shared__ J sj[kTJ];
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int itile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
+  const F eps2 = static_cast<F>(A.eps2);
+
+  typename StepRec<V>::I I[IPL];
+  int q[IPL], g[IPL];
+  F qmax[IPL], swmin[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    q[k] = (itile * IPL + k) * kWG + tid;
+    g[k] = A.idx[min(q[k], A.n_act - 1)];
+    I[k] = load_iv<V>(A, g[k]);
+    qmax[k] = F(0);
+    swmin[k] = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
+  }
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const J rec = load_jv<V>(A, jbase + tid);
+    __syncthreads();
+    sj[tid] = rec;
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < kTJ; ++jj) {
+      const J Jr = sj[jj];
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+        pair_step(I[k], Jr, eps2, jbase + jj == g[k], qmax[k], swmin[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    if (q[k] >= A.n_act) continue;
+    if (A.plan.n_slices == 1) {
+      A.dtc[q[k]] = finish_dt(A.eta, qmax[k], swmin[k]);
+    } else {
+      double *out = A.part + static_cast<int64_t>(slice) * 2 * A.n_act;
+      out[q[k]] = qmax[k];
+      out[A.n_act + q[k]] = swmin[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_timestep_reduce(StepArgs A) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= A.n_act) return;
+  double qm = 0.0, sm = __builtin_inf();
+  for (int s = 0; s < A.plan.n_slices; ++s) {
+    const double *in = A.part + static_cast<int64_t>(s) * 2 * A.n_act;
+    qm = fmax(qm, in[q]);
+    sm = fmin(sm, in[A.n_act + q]);
+  }
+  A.dtc[q] = finish_dt(A.eta, qm, sm);
+}
+
+template <class V>
+hipError_t run(StepArgs &A, hipStream_t st) {
+  A.plan = plan_split(A.n_act, 1, A.n_jtiles, 2048);
+  hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.plan.n_slices > 1) {
+    const int nb = (A.n_act + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_timestep_reduce, dim3(nb), dim3(kWG), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                           double *dtc, hipStream_t st) {
+  StepArgs A;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.v64 = c->v64;
+  A.npad = c->npad;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.n_jtiles = static_cast<int>(c->npad / kTJ);
+  A.eps2 = c->eps * c->eps;
+  A.eta = eta;
+  A.part = c->part;
+  A.dtc = dtc;
+  if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
+  if (c->flags & TSBTS_FLAG_F64_SEPARATION) return run<MixSep64>(A, st);
+  return run<MixHiLo>(A, st);
+}
+
+}  // namespace tsbts

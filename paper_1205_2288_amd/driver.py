@@ -1,0 +1,259 @@
+"""Host-side TSBTS scheduler driving the HIP kernels (eras, passes, block steps).
+
+The device holds the particle state and does all arithmetic (prediction / interpolation,
+force, corrector with history recording, criterion, energy).  The host keeps integer
+copies of each particle's last time and block step, picks the block time and active set,
+and applies the step-size rules, vectorised over the active set:
+
+* block times are integers in ticks of 2^-20; steps are powers of two of ticks;
+* Eq. (blockcondition): the admissible step for a candidate is the largest power of two
+  not above the mean of the criterion at the start of the step and at its end, within
+  [dt_min, dt_max];
+* first pass (Section 2, "standard block step"): drop to the admissible step (several
+  halvings allowed), or double at times that are multiples of twice the step;
+* later passes, Algorithm 1 as described in its prose: at even times double if admissible,
+  else keep if admissible, else halve once; at odd times keep if admissible, else halve
+  once.  The end-of-step criterion comes from the previous pass's values of the same
+  particle, linear in time between stored values (the start value beyond the last one);
+* Algorithm 2: every pass of an era restarts from the era-start state; passes after the
+  first interpolate the non-active particles from the previous pass's stored states;
+* Algorithm 3 (dynamic era): era size = last minus first next block time, clamped to
+  [dt_max / 8, dt_max], rounded down to a power of two; the era ends at the next multiple.
+  A particle whose next time is past the era end is not advanced in that era.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .context import Context
+
+TICK_BITS = 20
+TICK = 2.0 ** -TICK_BITS
+_KEY_SHIFT = 40
+
+
+def to_ticks(t: float) -> int:
+    k = t / TICK
+    if k != int(k):
+        raise ValueError(f"{t} is not a multiple of 2^-{TICK_BITS}")
+    return int(k)
+
+
+def admissible(begin, end, dt_min: int, dt_max: int):
+    """Largest power of two (ticks) not above (begin + end) / 2, clipped to [dt_min, dt_max]."""
+    avg = 0.5 * (np.asarray(begin, dtype=np.float64) + np.asarray(end, dtype=np.float64))
+    x = avg / TICK
+    big = ~np.isfinite(x) | (x >= dt_max)
+    mant, ex = np.frexp(np.where(big, 1.0, x))      # x = mant * 2^ex, mant in [0.5, 1)
+    p2 = np.where(x >= 1.0, np.ldexp(1.0, ex - 1), 0.0).astype(np.int64)
+    out = np.clip(p2, dt_min, dt_max)
+    return np.where(big, dt_max, out)
+
+
+class CriterionHistory:
+    """Criterion values of one pass (start values per particle plus one per step), grouped
+    by particle in time order for the end-of-step lookups of the next pass."""
+
+    def __init__(self):
+        self._pid, self._t, self._c = [], [], []
+
+    def add(self, pid, t, c):
+        self._pid.append(np.asarray(pid, dtype=np.int64))
+        self._t.append(np.broadcast_to(np.asarray(t, dtype=np.int64), np.shape(pid)))
+        self._c.append(np.asarray(c, dtype=np.float64))
+
+    def close(self, n: int):
+        pid = np.concatenate(self._pid)
+        order = np.argsort(pid, kind="stable")
+        self.pid = pid[order]
+        self.t = np.concatenate(self._t)[order]
+        self.c = np.concatenate(self._c)[order]
+        self.key = (self.pid << _KEY_SHIFT) + self.t
+        self.end = np.zeros(n, dtype=np.int64)  # one past each particle's last value
+        np.cumsum(np.bincount(self.pid, minlength=n), out=self.end)
+        self._pid = self._t = self._c = None
+        return self
+
+    def value_at(self, pid, t, fallback):
+        """Criterion of particles pid at times t (linear between stored values)."""
+        k = np.searchsorted(self.key, (pid << _KEY_SHIFT) + t, side="right") - 1
+        tk = self.t[k]
+        has_next = k + 1 < self.end[pid]
+        k1 = np.where(has_next, k + 1, k)
+        t1 = self.t[k1]
+        w = np.where(has_next, (t - tk) / np.where(has_next, t1 - tk, 1), 0.0)
+        lin = (1.0 - w) * self.c[k] + w * self.c[k1]
+        return np.where(tk == t, self.c[k], np.where(has_next, lin, fallback))
+
+
+class TSBTS:
+    """Dynamic- or fixed-era TSBTS integration on the GPU.
+
+    r, v: (3, N) float64; m: (N,).  era=None selects the dynamic era size.
+    precision / separation / newton select the force kernel (see Context)."""
+
+    def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
+                 era=None, precision="mixed", separation="hilo", newton=True):
+        self.n = n = int(np.asarray(m).size)
+        self.eta = float(eta)
+        self.passes = int(passes)
+        self.dt_max = to_ticks(dt_max)
+        self.dt_min = to_ticks(dt_min)
+        self.era = None if era is None else to_ticks(era)
+        self.ctx = Context(n, eps, precision=precision, separation=separation, newton=newton)
+        self.ctx.bind(r, v, m)
+        dev = self.ctx.device
+        # staging: pinned host buffers and device buffers sized for the full set
+        self._idx_h = torch.empty(n, dtype=torch.int32, pin_memory=True)
+        self._dtc_h = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        self._dtn_h = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        self._idx_d = torch.empty(n, dtype=torch.int32, device=dev)
+        self._acc_d = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        self._dtc_d = torch.empty(n, dtype=torch.float64, device=dev)
+        self._dtn_d = torch.empty(n, dtype=torch.float64, device=dev)
+        self._ek_d = torch.empty(2, dtype=torch.float64, device=dev)
+        # host mirrors (ticks) and last criterion values
+        self.t = np.zeros(n, dtype=np.int64)
+        self.dt = np.zeros(n, dtype=np.int64)
+        self.dtc = np.zeros(n)
+        self.time = 0
+        self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0,
+                      "wall_s": 0.0}
+        self._initialise()
+
+    # ------------------------------------------------------------------ device plumbing
+    def _upload_idx(self, idx: np.ndarray) -> torch.Tensor:
+        k = idx.size
+        self._idx_h[:k].numpy()[:] = idx
+        d = self._idx_d[:k]
+        d.copy_(self._idx_h[:k], non_blocking=True)
+        return d
+
+    def _initialise(self):
+        c = self.ctx
+        every = self._upload_idx(np.arange(self.n, dtype=np.int32))
+        c.predict(0.0)  # t_last = dt = 0: every particle is predicted to itself
+        acc = self._acc_d.view(3, self.n)
+        c.force(every, 0.0, with_pot=False, acc=acc)
+        c.a.copy_(acc)
+        dtc = c.timestep(every, self.eta, dtc=self._dtc_d)
+        self.dtc[:] = dtc.cpu().numpy()
+        self.dt[:] = admissible(self.dtc, self.dtc, self.dt_min, self.dt_max)
+        c.dt.copy_(torch.from_numpy(self.dt * TICK))
+        torch.cuda.synchronize()
+
+    # ------------------------------------------------------------------ step rules
+    def _new_steps(self, idx, tb, begin, prev: CriterionHistory | None):
+        dt = self.dt[idx]
+        if prev is None:
+            lvl = admissible(begin, begin, self.dt_min, self.dt_max)
+            new = np.minimum(dt, lvl)
+            grow = (lvl >= 2 * dt) & (tb % (2 * dt) == 0)
+            return np.where(grow, 2 * dt, new)
+        pid = idx.astype(np.int64)
+        even = (tb // dt) % 2 == 0
+        end2 = prev.value_at(pid, tb + 2 * dt, begin)
+        end1 = prev.value_at(pid, tb + dt, begin)
+        ok2 = even & (2 * dt <= self.dt_max) & \
+            (2 * dt <= admissible(begin, end2, self.dt_min, self.dt_max))
+        ok1 = dt <= admissible(begin, end1, self.dt_min, self.dt_max)
+        return np.where(ok2, 2 * dt, np.where(ok1, dt, np.maximum(dt // 2, self.dt_min)))
+
+    # ------------------------------------------------------------------ era / pass
+    def _era_end(self, t0: int) -> int:
+        if self.era is not None:
+            return t0 + self.era
+        nxt = self.t + self.dt
+        size = int(np.clip(nxt.max() - nxt.min(), self.dt_max // 8, self.dt_max))
+        size = 1 << (size.bit_length() - 1)
+        return (t0 // size + 1) * size
+
+    def _pass(self, p: int, T1: int, prev: CriterionHistory | None) -> CriterionHistory:
+        c = self.ctx
+        hist = CriterionHistory()
+        hist.add(np.arange(self.n), self.t, self.dtc)
+        c.history_begin()
+        stream = torch.cuda.current_stream()
+        while True:
+            nxt = self.t + self.dt
+            tb = int(nxt.min())
+            if tb > T1:
+                break
+            idx = np.flatnonzero(nxt == tb).astype(np.int32)
+            k = idx.size
+            tbs = tb * TICK
+            d_idx = self._upload_idx(idx)
+            c.predict(tbs, use_history=p > 0)
+            acc = self._acc_d[:3 * k].view(3, k)
+            c.force(d_idx, tbs, with_pot=False, acc=acc)
+            c.correct(d_idx, tbs, acc)
+            dtc = c.timestep(d_idx, self.eta, dtc=self._dtc_d[:k])
+            self._dtc_h[:k].copy_(dtc, non_blocking=True)
+            stream.synchronize()
+            begin = self._dtc_h[:k].numpy().copy()
+            self.dtc[idx] = begin
+            self.t[idx] = tb
+            hist.add(idx, tb, begin)
+            new = self._new_steps(idx, tb, begin, prev)
+            self.dt[idx] = new
+            self._dtn_h[:k].numpy()[:] = new * TICK
+            dtn = self._dtn_d[:k]
+            dtn.copy_(self._dtn_h[:k], non_blocking=True)
+            c.set_dt(d_idx, dtn)
+            self.stats["block_steps"] += 1
+            self.stats["force_calls"] += 1
+            self.stats["interactions"] += k * self.n
+        c.history_end()
+        return hist.close(self.n)
+
+    def era_step(self) -> int:
+        c = self.ctx
+        T0 = self.time
+        T1 = self._era_end(T0)
+        saved_dev = [x.clone() for x in (c.r, c.v, c.a, c.t_last, c.dt)]
+        saved_host = [x.copy() for x in (self.t, self.dt, self.dtc)]
+        prev = None
+        for p in range(self.passes):
+            if p > 0:
+                for dst, src in zip((c.r, c.v, c.a, c.t_last, c.dt), saved_dev):
+                    dst.copy_(src)
+                for dst, src in zip((self.t, self.dt, self.dtc), saved_host):
+                    dst[...] = src
+            prev = self._pass(p, T1, prev)
+        self.time = T1
+        self.stats["eras"] += 1
+        return T1
+
+    def energy(self) -> float:
+        kw = self.ctx.energy(out=self._ek_d).cpu().numpy()
+        return float(kw[0] + kw[1])
+
+    def run(self, t_end: float, energy_every: float | None = None):
+        """Integrate to t_end; return [(t, E)] at era ends that are multiples of
+        energy_every (default dt_max), where every particle is synchronised."""
+        stop = to_ticks(t_end)
+        every = self.dt_max if energy_every is None else to_ticks(energy_every)
+        out = [(0.0, self.energy())]
+        t0 = time.perf_counter()
+        while self.time < stop:
+            T1 = self.era_step()
+            if T1 % every == 0:
+                if not np.all(self.t == T1):
+                    raise RuntimeError("particles not synchronised at a dt_max multiple")
+                out.append((T1 * TICK, self.energy()))
+        torch.cuda.synchronize()
+        self.stats["wall_s"] += time.perf_counter() - t0
+        return out
+
+    def state(self):
+        c = self.ctx
+        torch.cuda.synchronize()
+        return {"r": c.r.cpu().numpy(), "v": c.v.cpu().numpy(), "a": c.a.cpu().numpy(),
+                "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
+                "time": self.time}
+
+    def close(self):
+        self.ctx.close()

@@ -1,0 +1,108 @@
+"""GPU TSBTS integrations (host scheduler + HIP kernels) against the oracle.
+
+* One shared level (huge eta): the scheme reduces to the shared-step leapfrog of
+  Section 2, for any number of passes.
+* The N=256 fixed-era workload in float64: same schedule and trajectory as the oracle
+  over t = 0..1 (differences only from rounding order).
+* Energy drift of the GPU runs (float64 and mixed force) within a factor 2 of the
+  oracle's drift over the same run (stored references written by
+  tests/golden/make_golden.py, which calls only the oracle).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.tsbts import OracleTSBTS
+from workloads import plummer, config
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"tsbts_{name}.json")) as f:
+        return json.load(f)
+
+
+def _drift(series):
+    e = np.array([x[1] for x in series])
+    return np.abs((e - e[0]) / e[0]).max()
+
+
+@pytest.mark.parametrize("passes", [1, 3])
+def test_shared_level_reduces_to_leapfrog(passes):
+    from paper_1205_2288_amd.driver import TSBTS
+    r, v, m = plummer(64, 17)
+    eps = 1 / 64
+    sim = TSBTS(r, v, m, eps, eta=1e9, passes=passes, era=1 / 8, precision="fp64")
+    assert np.all(sim.dt == 1 << 14)
+    sim.run(0.25)
+    st = sim.state()
+    r_ref, v_ref, _ = oracle.leapfrog_shared(r, v, m, eps, 1 / 64, 16)
+    assert np.abs(st["r"] - r_ref).max() <= 1e-12
+    assert np.abs(st["v"] - v_ref).max() <= 1e-12
+    sim.close()
+
+
+def test_plummer256_fp64_follows_oracle():
+    from paper_1205_2288_amd.driver import TSBTS
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=cfg.eta, passes=3, era=cfg.era, dt_max=cfg.dt_max, dt_min=cfg.dt_min)
+    gpu = TSBTS(r, v, m, cfg.eps, precision="fp64", **kw)
+    ref = OracleTSBTS(r, v, m, cfg.eps, **kw)
+    assert np.array_equal(gpu.dt, ref.dt)
+    for _ in range(4):  # four eras of 1/8: t = 0..1/2, compared era by era
+        gpu.era_step()
+        ref.era_step()
+        st = gpu.state()
+        assert np.array_equal(st["t"], ref.t)
+        assert np.array_equal(st["dt"], ref.dt), "schedules diverged"
+        assert np.abs(st["r"] - ref.r).max() <= 1e-9
+        assert np.abs(st["v"] - ref.v).max() <= 1e-8
+    gpu.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["plummer256", "plummer256_1pass", "plummer4096_t1"])
+def test_energy_drift_within_twice_oracle(prec, name):
+    from paper_1205_2288_amd.driver import TSBTS
+    g = _golden(name)
+    cfg = config(g["workload"])
+    r, v, m = cfg.ic()
+    sim = TSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=g["passes"], era=cfg.era,
+                dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=prec)
+    series = sim.run(g["t_end"])
+    d = _drift(series)
+    print(f"{name} {prec}: GPU drift {d:.3e}, oracle {g['max_rel_energy_error']:.3e}, "
+          f"steps {sim.stats['block_steps']} vs {g['stats']['block_steps']}, "
+          f"{sim.stats['wall_s']:.1f} s")
+    assert len(series) == len(g["times"])
+    assert d <= 2.0 * g["max_rel_energy_error"]
+    # the schedule work is comparable (chaotic divergence allowed)
+    assert 0.5 <= sim.stats["block_steps"] / g["stats"]["block_steps"] <= 2.0
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plummer4096_dynamic_era_t10_drift(prec):
+    path = os.path.join(GOLDEN, "tsbts_plummer4096.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference for the t=10 run not generated")
+    from paper_1205_2288_amd.driver import TSBTS
+    g = _golden("plummer4096")
+    cfg = config("plummer4096")
+    r, v, m = cfg.ic()
+    sim = TSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=None, dt_max=cfg.dt_max,
+                dt_min=cfg.dt_min, precision=prec)
+    series = sim.run(cfg.t_end)
+    d = _drift(series)
+    print(f"plummer4096 t=10 {prec}: GPU drift {d:.3e}, oracle "
+          f"{g['max_rel_energy_error']:.3e}, {sim.stats['block_steps']} block steps, "
+          f"{sim.stats['wall_s']:.1f} s")
+    assert d <= 2.0 * g["max_rel_energy_error"]
+    sim.close()

@@ -1,0 +1,115 @@
+"""GPU parity of the force / potential kernels against the FP64 oracle.
+
+Element by element on seeded Plummer spheres spanning several 256-particle tiles with a
+ragged tail, random active subsets (including a single particle and the full set),
+eps > 0 and eps = 0 (masked self pair), every precision variant; and, at the full
+N=32768 and N=131072 sizes in the launch configuration the benchmark uses, on sampled
+targets the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import plummer, active_subset, config
+from gpu_util import rel_err_vec, rel_err, summary, make_ctx, VARIANTS, TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ctx, r, v, m, idx, t=0.0):
+    ctx.bind(r, v, m)
+    ctx.predict(t)
+    acc, pot = ctx.force(idx, t)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), pot.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec,sep,newton", VARIANTS)
+@pytest.mark.parametrize("n,eps,n_act", [
+    (2, 0.0, 2), (3, 0.01, 1), (16, 1 / 64, 16), (257, 1 / 64, 100), (1000, 0.0, 999),
+    (4099, 1 / 256, 4099), (4099, 1 / 256, 1), (4099, 1 / 256, 37), (1536, 1 / 1024, 1536),
+])
+def test_force_matches_oracle(prec, sep, newton, n, eps, n_act):
+    r, v, m = plummer(n, 1000 + n, masses="loguniform")
+    idx = active_subset(n, n_act, 7 + n_act)
+    ctx = make_ctx(n, eps, prec, sep, newton)
+    acc, pot = _run(ctx, r, v, m, idx)
+    a_ref, p_ref = oracle.force(r, m, eps, idx)
+    ea = summary(rel_err_vec(acc, a_ref))
+    ep = summary(rel_err(pot, p_ref))
+    tol = TOL[prec]
+    assert ea["median"] <= tol["median"], ea
+    assert ea["max"] <= tol["max"], ea
+    assert ep["median"] <= tol["median"], ep
+    assert ep["max"] <= tol["max"], ep
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_force_bitwise_reproducible_and_third_law(prec):
+    n = 3000
+    r, v, m = plummer(n, 5, masses="loguniform")
+    ctx = make_ctx(n, 1 / 256, prec)
+    idx = np.arange(n, dtype=np.int32)
+    a1, p1 = _run(ctx, r, v, m, idx)
+    a2, p2 = _run(ctx, r, v, m, idx)
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    # Newton's third law: sum m a = 0 up to rounding of the pair sums
+    tot = np.abs((a1 * m).sum(axis=1)).max()
+    scale = (np.abs(a1) * m).sum()
+    assert tot <= (1e-13 if prec == "fp64" else 1e-6) * scale
+    ctx.close()
+
+
+def test_force_subset_rows_match_full():
+    n = 2048
+    r, v, m = plummer(n, 6)
+    ctx = make_ctx(n, 1 / 128, "fp64")
+    full, fp = _run(ctx, r, v, m, np.arange(n, dtype=np.int32))
+    idx = active_subset(n, 33, 2)
+    sub, sp = _run(ctx, r, v, m, idx)
+    assert np.allclose(sub, full[:, idx], rtol=1e-13, atol=0)
+    assert np.allclose(sp, fp[idx], rtol=1e-13, atol=0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["sweep32768", "plummer131k"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_force_full_size_sampled(name, prec):
+    cfg = config(name)
+    r, v, m = cfg.ic()
+    n = cfg.n
+    ctx = make_ctx(n, cfg.eps, prec)
+    sizes = [n, n // 8, 64, 1] if name == "plummer131k" else [1, 8, 64, 512, 4096, 32768]
+    for k, n_act in enumerate(sizes):
+        idx = active_subset(n, n_act, cfg.seed + 1000 * k)
+        acc, pot = _run(ctx, r, v, m, idx)
+        take = np.sort(np.random.default_rng(k).choice(n_act, size=min(n_act, 256),
+                                                       replace=False))
+        a_ref, p_ref = oracle.force(r, m, cfg.eps, idx[take])
+        ea = summary(rel_err_vec(acc[:, take], a_ref))
+        ep = summary(rel_err(pot[take], p_ref))
+        assert ea["median"] <= TOL[prec]["median"], (n_act, ea)
+        assert ea["max"] <= TOL[prec]["max"], (n_act, ea)
+        assert ep["max"] <= TOL[prec]["max"], (n_act, ep)
+    ctx.close()
+
+
+def test_force_out_of_order_and_bad_arguments():
+    from paper_1205_2288_amd._lib import TsbtsError, TSBTS_ESTATE, TSBTS_EINVAL
+    n = 100
+    r, v, m = plummer(n, 3)
+    ctx = make_ctx(n, 0.01, "mixed")
+    ctx.bind(r, v, m)
+    with pytest.raises(TsbtsError) as e:
+        ctx.force(np.arange(n, dtype=np.int32), 0.0)  # nothing predicted yet
+    assert e.value.status == TSBTS_ESTATE
+    ctx.predict(0.25)
+    with pytest.raises(TsbtsError) as e:
+        ctx.force(np.arange(n, dtype=np.int32), 0.5)  # not the predicted time
+    assert e.value.status == TSBTS_ESTATE
+    with pytest.raises(TsbtsError) as e:
+        ctx.force(np.arange(n + 1, dtype=np.int32) % n, 0.25)  # more targets than particles
+    assert e.value.status == TSBTS_EINVAL
+    ctx.close()
