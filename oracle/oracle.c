@@ -14,6 +14,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 /* Acceleration and potential on the listed target particles (Section 2; Algorithm 2,
  * "calculate forces on the active particles"):
@@ -62,18 +63,23 @@ void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
     double k = 0.0;
     for (int64_t i = 0; i < n; ++i)
         k += 0.5 * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
-    double w = 0.0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : w)
+    /* rows in parallel, each row's j-sum in ascending order; rows then added in
+     * ascending i, so the result does not depend on the thread count */
+    double *row = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
-        double row = 0.0;
+        double s = 0.0;
         for (int64_t j = i + 1; j < n; ++j) {
             const double dx = x[j] - x[i];
             const double dy = y[j] - y[i];
             const double dz = z[j] - z[i];
-            row += m[i] * m[j] / sqrt(dx * dx + dy * dy + dz * dz + eps2);
+            s += m[i] * m[j] / sqrt(dx * dx + dy * dy + dz * dz + eps2);
         }
-        w -= row;
+        row[i] = s;
     }
+    double w = 0.0;
+    for (int64_t i = 0; i < n; ++i) w -= row[i];
+    free(row);
     *kin = k;
     *pot = w;
 }

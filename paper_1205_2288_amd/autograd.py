@@ -1,0 +1,122 @@
+"""torch.autograd Functions over the HIP force adjoint.
+
+* ``TsbtsForce``: acceleration and potential of an active set for explicit positions and
+  masses; backward calls ``tsbts_force_backward`` (tidal-tensor products).
+* ``TsbtsLeapfrog``: a shared-step leapfrog run (Section 2's self-starting leapfrog with
+  one step h for all particles) from (r0, v0, m) to (r_S, v_S).  The forward pass keeps
+  only era-start checkpoints (r, v, a every `era` steps); the backward pass recomputes
+  each era from its checkpoint and sweeps it in reverse with the element-wise leapfrog
+  adjoint kernel and the force adjoint kernel.
+
+All arithmetic runs in libtsbts kernels; torch provides the tensors and the graph.
+"""
+from __future__ import annotations
+
+import torch
+
+from .context import Context
+
+
+class TsbtsForce(torch.autograd.Function):
+    """acc[3, k], pot[k] = force(r[3, N], m[N]) on the targets idx (int32 device tensor)."""
+
+    @staticmethod
+    def forward(fctx, r, m, idx, ctx: Context):
+        r = r.detach().contiguous()
+        m = m.detach().contiguous()
+        ctx.load_positions(r, m, 0.0)
+        acc, pot = ctx.force(idx, 0.0)
+        fctx.save_for_backward(r, m, idx)
+        fctx.tsbts = ctx
+        return acc, pot
+
+    @staticmethod
+    def backward(fctx, g_acc, g_pot):
+        r, m, idx = fctx.saved_tensors
+        ctx = fctx.tsbts
+        ctx.load_positions(r, m, 0.0)
+        if g_acc is None:
+            g_acc = torch.zeros((3, idx.numel()), dtype=torch.float64, device=r.device)
+        gr, gm = ctx.force_backward(idx, 0.0, g_acc.contiguous(),
+                                    None if g_pot is None else g_pot.contiguous())
+        return gr, gm, None, None
+
+
+def tsbts_force(r, m, idx, ctx: Context):
+    return TsbtsForce.apply(r, m, idx, ctx)
+
+
+class TsbtsLeapfrog(torch.autograd.Function):
+    """(r_S, v_S) after `steps` shared leapfrog steps of size h, with era checkpoints."""
+
+    @staticmethod
+    def forward(fctx, r0, v0, m, ctx: Context, h: float, steps: int, era: int):
+        n = ctx.n
+        dev = ctx.device
+        r0, v0, m = (x.detach().contiguous() for x in (r0, v0, m))
+        ctx.bind(r0.clone(), v0.clone(), m.clone(), t_last=torch.zeros(n, dtype=torch.float64,
+                                                                        device=dev),
+                 dt=torch.full((n,), h, dtype=torch.float64, device=dev))
+        every = ctx.idx(torch.arange(n, dtype=torch.int32))
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+        ctx.predict(0.0)
+        ctx.force(every, 0.0, with_pot=False, acc=acc)
+        ctx.a.copy_(acc)
+        checkpoints = []
+        for s in range(steps):
+            if s % era == 0:
+                checkpoints.append((s, ctx.r.clone(), ctx.v.clone(), ctx.a.clone()))
+            _step(ctx, every, acc, s, h)
+        fctx.tsbts = ctx
+        fctx.meta = (h, steps, era)
+        fctx.checkpoints = checkpoints
+        fctx.save_for_backward(m)
+        fctx.every = every
+        return ctx.r.clone(), ctx.v.clone()
+
+    @staticmethod
+    def backward(fctx, g_r, g_v):
+        ctx = fctx.tsbts
+        (m,) = fctx.saved_tensors
+        h, steps, era = fctx.meta
+        n = ctx.n
+        dev = ctx.device
+        every = fctx.every
+        z = lambda: torch.zeros((3, n), dtype=torch.float64, device=dev)  # noqa: E731
+        rbar = z() if g_r is None else g_r.contiguous().clone()
+        vbar = z() if g_v is None else g_v.contiguous().clone()
+        abar = z()
+        g = z()
+        mbar = torch.zeros(n, dtype=torch.float64, device=dev)
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+        ctx.bind(ctx.r, ctx.v, m, a=ctx.a, t_last=ctx.t_last, dt=ctx.dt)
+        for (s0, r_c, v_c, a_c) in reversed(fctx.checkpoints):
+            s1 = min(s0 + era, steps)
+            # recompute the era from its checkpoint, keeping the positions of every step
+            ctx.r.copy_(r_c)
+            ctx.v.copy_(v_c)
+            ctx.a.copy_(a_c)
+            ctx.t_last.fill_(s0 * h)
+            pos = []
+            for s in range(s0, s1):
+                _step(ctx, every, acc, s, h)
+                pos.append(ctx.r.clone())
+            for s in range(s1 - 1, s0 - 1, -1):
+                ctx.leapfrog_adjoint(0, h, rbar, vbar, abar, g)      # g = abar + h vbar / 2
+                ctx.load_positions(pos[s - s0], m, 0.0)
+                ctx.force_backward(every, 0.0, g, None, rbar, mbar)  # through a_{s+1}
+                ctx.leapfrog_adjoint(1, h, rbar, vbar, abar, g)      # adjoints of step s
+        ctx.load_positions(fctx.checkpoints[0][1], m, 0.0)
+        ctx.force_backward(every, 0.0, abar, None, rbar, mbar)      # through a_0
+        return rbar, vbar, mbar, None, None, None, None
+
+
+def _step(ctx: Context, every, acc, s: int, h: float):
+    tb = (s + 1) * h
+    ctx.predict(tb)
+    ctx.force(every, tb, with_pot=False, acc=acc)
+    ctx.correct(every, tb, acc)
+
+
+def tsbts_leapfrog(r0, v0, m, ctx: Context, h: float, steps: int, era: int = 16):
+    return TsbtsLeapfrog.apply(r0, v0, m, ctx, h, steps, era)

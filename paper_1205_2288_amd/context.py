@@ -63,6 +63,13 @@ class Context:
         L.tsbts_bind_state(self.ctx, n, self.r, self.v, self.a, self.m, self.t_last, self.dt)
         return self
 
+    def host_buffer(self, n, dtype):
+        """Page-locked host staging buffer (for asynchronous copies)."""
+        return torch.empty(n, dtype=dtype, pin_memory=True)
+
+    def synchronize(self, stream=None):
+        (stream or torch.cuda.current_stream()).synchronize()
+
     def idx(self, active):
         """Active-set index tensor; host arrays are range-checked here (the kernels index
         particle arrays with these values directly)."""

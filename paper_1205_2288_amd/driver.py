@@ -61,9 +61,10 @@ class CriterionHistory:
         self._pid, self._t, self._c = [], [], []
 
     def add(self, pid, t, c):
-        self._pid.append(np.asarray(pid, dtype=np.int64))
-        self._t.append(np.broadcast_to(np.asarray(t, dtype=np.int64), np.shape(pid)))
-        self._c.append(np.asarray(c, dtype=np.float64))
+        # copies: the caller keeps updating its own arrays in place
+        self._pid.append(np.array(pid, dtype=np.int64))
+        self._t.append(np.array(np.broadcast_to(np.asarray(t, dtype=np.int64), np.shape(pid))))
+        self._c.append(np.array(c, dtype=np.float64))
 
     def close(self, n: int):
         pid = np.concatenate(self._pid)
@@ -96,20 +97,22 @@ class TSBTS:
     precision / separation / newton select the force kernel (see Context)."""
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
-                 era=None, precision="mixed", separation="hilo", newton=True):
+                 era=None, precision="mixed", separation="hilo", newton=True, context=None):
         self.n = n = int(np.asarray(m).size)
         self.eta = float(eta)
         self.passes = int(passes)
         self.dt_max = to_ticks(dt_max)
         self.dt_min = to_ticks(dt_min)
         self.era = None if era is None else to_ticks(era)
-        self.ctx = Context(n, eps, precision=precision, separation=separation, newton=newton)
+        # `context` lets a caller supply an object with the Context interface
+        self.ctx = context if context is not None else Context(
+            n, eps, precision=precision, separation=separation, newton=newton)
         self.ctx.bind(r, v, m)
         dev = self.ctx.device
-        # staging: pinned host buffers and device buffers sized for the full set
-        self._idx_h = torch.empty(n, dtype=torch.int32, pin_memory=True)
-        self._dtc_h = torch.empty(n, dtype=torch.float64, pin_memory=True)
-        self._dtn_h = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        # staging: host buffers (pinned by the context) and device buffers
+        self._idx_h = self.ctx.host_buffer(n, torch.int32)
+        self._dtc_h = self.ctx.host_buffer(n, torch.float64)
+        self._dtn_h = self.ctx.host_buffer(n, torch.float64)
         self._idx_d = torch.empty(n, dtype=torch.int32, device=dev)
         self._acc_d = torch.empty(3 * n, dtype=torch.float64, device=dev)
         self._dtc_d = torch.empty(n, dtype=torch.float64, device=dev)
@@ -143,7 +146,7 @@ class TSBTS:
         self.dtc[:] = dtc.cpu().numpy()
         self.dt[:] = admissible(self.dtc, self.dtc, self.dt_min, self.dt_max)
         c.dt.copy_(torch.from_numpy(self.dt * TICK))
-        torch.cuda.synchronize()
+        c.synchronize()
 
     # ------------------------------------------------------------------ step rules
     def _new_steps(self, idx, tb, begin, prev: CriterionHistory | None):
@@ -176,7 +179,6 @@ class TSBTS:
         hist = CriterionHistory()
         hist.add(np.arange(self.n), self.t, self.dtc)
         c.history_begin()
-        stream = torch.cuda.current_stream()
         while True:
             nxt = self.t + self.dt
             tb = int(nxt.min())
@@ -192,7 +194,7 @@ class TSBTS:
             c.correct(d_idx, tbs, acc)
             dtc = c.timestep(d_idx, self.eta, dtc=self._dtc_d[:k])
             self._dtc_h[:k].copy_(dtc, non_blocking=True)
-            stream.synchronize()
+            c.synchronize()
             begin = self._dtc_h[:k].numpy().copy()
             self.dtc[idx] = begin
             self.t[idx] = tb
@@ -244,13 +246,13 @@ class TSBTS:
                 if not np.all(self.t == T1):
                     raise RuntimeError("particles not synchronised at a dt_max multiple")
                 out.append((T1 * TICK, self.energy()))
-        torch.cuda.synchronize()
+        self.ctx.synchronize()
         self.stats["wall_s"] += time.perf_counter() - t0
         return out
 
     def state(self):
         c = self.ctx
-        torch.cuda.synchronize()
+        c.synchronize()
         return {"r": c.r.cpu().numpy(), "v": c.v.cpu().numpy(), "a": c.a.cpu().numpy(),
                 "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
                 "time": self.time}
