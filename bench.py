@@ -206,28 +206,67 @@ def gpu_force_rows(cfg, r, v, m):
     return out
 
 
-def roofline_for(name, ms_list, b: EraBench, n):
-    ms = float(np.mean(ms_list))
-    if name in ("force_full", "force_half"):
-        k = n if name == "force_full" else n // 2
-        achieved = FLOPS_FORCE * k * n / (ms * 1e-3) / 1e12
-        return {"kernel": "k_force (mixed, " + name + ")", "bound": "alu",
-                "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "avg_launch_us": ms * 1e3}
-    if name == "backward":
-        achieved = FLOPS_ADJOINT * n * n / (ms * 1e-3) / 1e12
-        return {"kernel": "k_bwd_src + k_bwd_tgt (mixed)", "bound": "alu",
-                "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "avg_launch_us": ms * 1e3}
-    if name == "energy":
-        achieved = FLOPS_ENERGY_PAIR * n * (n - 1) / 2 / (ms * 1e-3) / 1e12
-        return {"kernel": "k_energy_pairs", "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "avg_launch_us": ms * 1e3}
-    return None
+def rooflines(ms, n, precision="mixed"):
+    """Roofline entries per kernel from HIP-event times of their calls in the timed steps.
+
+    Each entry: algorithmic TFLOP/s = (flops per unit x units per call) / mean call time.
+    Units per call: force n_act*N interactions; criterion n_act*N pairs; adjoint N^2
+    interactions (all active); energy N(N-1)/2 pairs."""
+    peak32 = PEAK_FP32_TFLOPS if precision == "mixed" else PEAK_FP64_TFLOPS
+    out = {}
+
+    def entry(kernel, flops, ms_list, peak):
+        t = float(np.sum(ms_list)) * 1e-3
+        achieved = flops / t / 1e12
+        return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "avg_launch_us": t / len(ms_list) * 1e6, "calls": len(ms_list),
+                "total_ms": t * 1e3}
+
+    nf, nh = len(ms["force_full"]), len(ms["force_half"])
+    out["k_force"] = entry("k_force", FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
+                           ms["force_full"] + ms["force_half"], peak32)
+    # the criterion kernel's calls alternate half / full active sets
+    nts = len(ms["timestep"])
+    out["k_timestep"] = entry("k_timestep", 20.0 * n * (nts // 2) * (n + n // 2),
+                              ms["timestep"], peak32)
+    out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * len(ms["backward"]),
+                             ms["backward"], peak32)
+    out["k_energy_pairs"] = entry("k_energy_pairs",
+                                  FLOPS_ENERGY_PAIR * n * (n - 1) / 2 * len(ms["energy"]),
+                                  ms["energy"], PEAK_FP64_TFLOPS)
+    return out
+
+
+def force_variants(cfg, r, v, m, reps=5):
+    """Full-active force time and accuracy (vs the float64 kernel) of each mixed variant."""
+    from paper_1205_2288_amd import Context
+    n = cfg.n
+    res = {}
+    ref = None
+    for prec, sep, newton in (("fp64", "f64", False), ("mixed", "f64", False),
+                              ("mixed", "f64", True), ("mixed", "hilo", False),
+                              ("mixed", "hilo", True)):
+        with Context(n, cfg.eps, precision=prec, separation=sep, newton=newton) as c:
+            c.bind(r, v, m)
+            c.predict(0.0)
+            idx = c.idx(np.arange(n, dtype=np.int32))
+            acc = torch.empty((3, n), dtype=torch.float64, device=c.device)
+            for _ in range(2):
+                c.force(idx, 0.0, with_pot=False, acc=acc)
+            T = Timer()
+            for _ in range(reps):
+                T("f", c.force, idx, 0.0, with_pot=False, acc=acc)
+            ms = float(np.median(T.ms()["f"]))
+            a = acc.cpu().numpy()
+        if ref is None:
+            ref = a
+        err = np.sqrt(((a - ref) ** 2).sum(0) / (ref ** 2).sum(0))
+        name = "fp64" if prec == "fp64" else f"mixed-{sep}-{'newton' if newton else 'rsq'}"
+        res[name] = {"ms": ms, "interactions_per_s": n * n / (ms * 1e-3),
+                     "median_rel_err_vs_fp64_kernel": float(np.median(err)),
+                     "max_rel_err_vs_fp64_kernel": float(err.max())}
+    return res
 
 
 def main():
@@ -238,6 +277,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB "
+                         "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -249,16 +291,23 @@ def main():
     cfg = config("plummer131k")
     n = cfg.n
     r, v, m = cfg.ic()
+    if args.calibration_copy_mb > 0:
+        nbytes = args.calibration_copy_mb << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     b = EraBench(cfg, r, v, m, "mixed")
     wall, ms = time_steps(b, args.steps, args.warmup)
     per_call = {k: {"calls_per_step": len(x) / args.steps, "mean_us": float(np.mean(x)) * 1e3}
                 for k, x in ms.items()}
-    totals = {k: float(np.sum(x)) for k, x in ms.items()}
-    dominant = max(totals, key=totals.get)
     value = b.interactions * args.steps / wall
-    roof = roofline_for(dominant, ms[dominant], b, n)
-    roof_force = roofline_for("force_full", ms["force_full"], b, n)
+    roofs = rooflines(ms, n)
+    dominant = max(roofs, key=lambda k: roofs[k]["total_ms"])
+    roof = roofs[dominant]
     b.close()
 
     fp64 = None
@@ -283,7 +332,7 @@ def main():
                    "n": n, "eps": cfg.eps, "seed": cfg.seed, "precision": "mixed",
                    "interactions_per_step": b.interactions},
         "roofline": roof,
-        "roofline_force": roof_force,
+        "rooflines": roofs,
         "force_interactions_per_s": n * n / (np.mean(ms["force_full"]) * 1e-3),
         "adjoint_interactions_per_s": n * n / (np.mean(ms["backward"]) * 1e-3),
         "energy_pairs_per_s": n * (n - 1) / 2 / (np.mean(ms["energy"]) * 1e-3),
@@ -291,6 +340,7 @@ def main():
         "fp64_mode": fp64,
     }
     if not args.no_sweep:
+        out["force_variants"] = force_variants(cfg, r, v, m)
         out["sweep_mixed"] = sweep(cfg, r, v, m, "mixed")
         out["sweep_fp64"] = sweep(cfg, r, v, m, "fp64")
     if not args.no_cpu_baseline:

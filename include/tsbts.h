@@ -41,11 +41,12 @@ extern "C" {
 #define TSBTS_FP64 0  /* all pair arithmetic in float64 */
 #define TSBTS_MIXED 1 /* float64 positions, float32 pair arithmetic, float64 tile sums */
 
-/* creation flags */
-#define TSBTS_FLAG_F64_SEPARATION 1 /* MIXED: form separations in float64, then round to
-                                       float32 (default: hi/lo float32 pairs) */
-#define TSBTS_FLAG_NO_NEWTON 2      /* MIXED: use the hardware float32 1/sqrt without the
-                                       Newton refinement step */
+/* creation flags (MIXED precision only; the default is the fastest variant on gfx950:
+ * separations formed in float64 and rounded once to float32, and the hardware float32
+ * reciprocal square root used as is) */
+#define TSBTS_FLAG_HILO_SEPARATION 1 /* form separations from float32 hi/lo position pairs:
+                                        (x_hi_j - x_hi_i) + (x_lo_j - x_lo_i) */
+#define TSBTS_FLAG_NEWTON 2          /* refine the float32 1/sqrt by one Newton step */
 
 typedef struct tsbts_ctx tsbts_ctx;
 

@@ -24,8 +24,8 @@ TSBTS_EHIP = -3
 TSBTS_ESTATE = -4
 TSBTS_FP64 = 0
 TSBTS_MIXED = 1
-TSBTS_FLAG_F64_SEPARATION = 1
-TSBTS_FLAG_NO_NEWTON = 2
+TSBTS_FLAG_HILO_SEPARATION = 1
+TSBTS_FLAG_NEWTON = 2
 
 
 class TsbtsError(RuntimeError):

@@ -25,12 +25,13 @@ class Context:
     """Device-resident particle state and a libtsbts context.
 
     precision: "mixed" (float32 pair arithmetic, float64 sums) or "fp64".
-    separation: "hilo" (float32 hi/lo pairs) or "f64" (float64 separation rounded to float32);
-    newton: refine the float32 1/sqrt by one Newton step (mixed precision only).
+    separation: "f64" (float64 separation rounded to float32, the default) or "hilo"
+    (float32 hi/lo position pairs); newton: refine the float32 1/sqrt by one Newton step
+    (mixed precision only; off by default).
     """
 
-    def __init__(self, n: int, eps: float, precision: str = "mixed", separation: str = "hilo",
-                 newton: bool = True, device: str = "cuda"):
+    def __init__(self, n: int, eps: float, precision: str = "mixed", separation: str = "f64",
+                 newton: bool = False, device: str = "cuda"):
         if not torch.cuda.is_available():
             raise RuntimeError("libtsbts needs a HIP device")
         self.n = int(n)
@@ -38,12 +39,12 @@ class Context:
         self.precision = precision
         self.device = torch.device(device)
         flags = 0
-        if separation == "f64":
-            flags |= L.TSBTS_FLAG_F64_SEPARATION
-        elif separation != "hilo":
+        if separation == "hilo":
+            flags |= L.TSBTS_FLAG_HILO_SEPARATION
+        elif separation != "f64":
             raise ValueError("separation must be 'hilo' or 'f64'")
-        if not newton:
-            flags |= L.TSBTS_FLAG_NO_NEWTON
+        if newton:
+            flags |= L.TSBTS_FLAG_NEWTON
         self.flags = flags
         self.ctx = L.tsbts_create(self.n, self.eps, PRECISIONS[precision], flags)
         self.r = self.v = self.a = self.m = self.t_last = self.dt = None

@@ -186,7 +186,7 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
   if (n < 1 || n > (int64_t(1) << 30)) return TSBTS_EINVAL;
   if (!(eps >= 0.0) || !std::isfinite(eps)) return TSBTS_EINVAL;
   if (precision != TSBTS_FP64 && precision != TSBTS_MIXED) return TSBTS_EINVAL;
-  if (flags & ~(TSBTS_FLAG_F64_SEPARATION | TSBTS_FLAG_NO_NEWTON)) return TSBTS_EINVAL;
+  if (flags & ~(TSBTS_FLAG_HILO_SEPARATION | TSBTS_FLAG_NEWTON)) return TSBTS_EINVAL;
   tsbts_ctx *c = new (std::nothrow) tsbts_ctx();
   if (!c) return TSBTS_ENOMEM;
   c->n = n;
@@ -202,6 +202,7 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
   if (!st) st = dev_alloc(c, &c->p64, P64_PLANES * c->npad);
   if (!st) st = dev_alloc(c, &c->v64, 3 * c->npad);
   if (!st && precision == TSBTS_MIXED) st = dev_alloc(c, &c->p32, P32_PLANES * c->npad);
+  if (!st) st = dev_alloc(c, &c->gord, 4 * c->npad);
   if (!st) st = dev_alloc(c, &c->h.cnt, n);
   if (!st) st = dev_alloc(c, &c->h.off, n + 1);
   if (!st) st = dev_alloc(c, &c->h.cur, n);
@@ -230,6 +231,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   dev_free(c->p32);
   dev_free(c->part);
   dev_free(c->epart);
+  dev_free(c->gord);
   dev_free(c->h.pid);
   dev_free(c->h.rank);
   dev_free(c->h.t);

@@ -11,7 +11,10 @@
 //
 // Both are gathers (each row owns its sums), with the same register/LDS tiling and
 // split-column scheme as the force kernel: no scatter, no atomics, fixed-order float64
-// combination.  The self pair is masked by index.
+// combination.  When every particle is active the two parts run over the same pairs and
+// are fused into one kernel that shares each pair's separation, 1/sqrt(s) and its powers
+// (the adjoint seeds are first put in particle order).  The self pair is masked by index,
+// only in tiles that can contain it (wave-uniform vote).
 #include "pair.hpp"
 
 namespace tsbts {
@@ -29,6 +32,13 @@ struct __align__(16) Col {
   int pad[3];
 };
 
+// Column record of the fused kernel: a particle's position and mass, and its (g, gp).
+template <class V>
+struct __align__(16) ColAll {
+  typename V::J p;
+  typename GradT<V>::T g;
+};
+
 struct BwdArgs {
   const float *p32;
   const double *p64;
@@ -41,6 +51,7 @@ struct BwdArgs {
   int n_ctiles;
   double eps2;
   double *part;
+  double *gord;  // [4][npad] seeds in particle order (fused kernel)
 };
 
 template <class V, int NEWTON>
@@ -52,7 +63,7 @@ __device__ __forceinline__ typename V::F inv_r(typename V::F s) {
   }
 }
 
-template <class V, int NEWTON>
+template <class V, int NEWTON, int MASK>
 __device__ __forceinline__ void pair_src(const typename V::I &row, const Col<V> &c,
                                          typename V::F eps2, bool self,
                                          typename V::F acc[4]) {
@@ -61,7 +72,7 @@ __device__ __forceinline__ void pair_src(const typename V::I &row, const Col<V> 
   V::sep(row, c.p, ex, ey, ez);
   const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
   F y = inv_r<V, NEWTON>(s);
-  if (self) y = F(0);
+  if (MASK && self) y = F(0);
   const F y2 = y * y;
   const F y3 = y2 * y;
   const F y5 = y3 * y2;
@@ -74,7 +85,7 @@ __device__ __forceinline__ void pair_src(const typename V::I &row, const Col<V> 
   acc[3] -= fma(y3, u, gpc * y);
 }
 
-template <class V, int NEWTON>
+template <class V, int NEWTON, int MASK>
 __device__ __forceinline__ void pair_tgt(const typename V::I &row, const typename V::J &j,
                                          const typename V::F g[4], typename V::F eps2,
                                          bool self, typename V::F acc[3]) {
@@ -83,7 +94,7 @@ __device__ __forceinline__ void pair_tgt(const typename V::I &row, const typenam
   V::sep(row, j, ex, ey, ez);
   const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
   F y = inv_r<V, NEWTON>(s);
-  if (self) y = F(0);
+  if (MASK && self) y = F(0);
   const F m = V::mass(j);
   const F y2 = y * y;
   const F my3 = m * (y2 * y);
@@ -95,11 +106,66 @@ __device__ __forceinline__ void pair_tgt(const typename V::I &row, const typenam
   acc[2] = fma(-my3, g[2], fma(coef, ez, acc[2]));
 }
 
+// Both parts for one pair (row k, column j): acc[0..2] source sum P, acc[3] mass sum Q,
+// acc[4..6] target sum R.
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void pair_all(const typename V::I &row, const typename V::F gk[4],
+                                         const ColAll<V> &c, typename V::F eps2, bool self,
+                                         typename V::F acc[7]) {
+  using F = typename V::F;
+  F ex, ey, ez;
+  V::sep(row, c.p, ex, ey, ez);
+  const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
+  F y = inv_r<V, NEWTON>(s);
+  if (MASK && self) y = F(0);
+  const F y2 = y * y;
+  const F y3 = y2 * y;
+  const F y5 = y3 * y2;
+  // source part: k pulls on target j
+  const F gx = F(c.g.x), gy = F(c.g.y), gz = F(c.g.z), gpj = F(c.g.w);
+  const F us = fma(ex, gx, fma(ey, gy, ez * gz));
+  const F cs = -fma(F(3) * y5, us, gpj * y3);
+  acc[0] = fma(y3, gx, fma(cs, ex, acc[0]));
+  acc[1] = fma(y3, gy, fma(cs, ey, acc[1]));
+  acc[2] = fma(y3, gz, fma(cs, ez, acc[2]));
+  acc[3] -= fma(y3, us, gpj * y);
+  // target part: j pulls on target k
+  const F m = V::mass(c.p);
+  const F my3 = m * y3;
+  const F my5 = m * y5;
+  const F ut = fma(ex, gk[0], fma(ey, gk[1], ez * gk[2]));
+  const F ct = fma(F(3) * my5, ut, -gk[3] * my3);
+  acc[4] = fma(-my3, gk[0], fma(ct, ex, acc[4]));
+  acc[5] = fma(-my3, gk[1], fma(ct, ey, acc[5]));
+  acc[6] = fma(-my3, gk[2], fma(ct, ez, acc[6]));
+}
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
 // ---------------------------------------------------------------- source part
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void src_tile(const typename V::I &row, const Col<V> *sc, int cnt,
+                                         int64_t k, typename V::F eps2, typename V::F acc[4]) {
+  for (int cc = 0; cc < cnt; ++cc) {
+    const Col<V> c = sc[cc];
+    pair_src<V, NEWTON, MASK>(row, c, eps2, MASK && c.idx == k, acc);
+  }
+}
+
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
   using F = typename V::F;
   __shared__ Col<V> sc[kTJ];
+  __shared__ int srange[2][kWG / 64];
   const int tid = threadIdx.x;
   const int L = xcd_linear(blockIdx.x, A.plan.nblk);
   const int rtile = L % A.plan.n_itiles;
@@ -115,6 +181,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
   for (int ct = ct0; ct < ct1; ++ct) {
     const int q = ct * kTJ + tid;
     Col<V> rec;
+    int lo, hi;
     if (q < A.n_act) {
       const int64_t c = A.idx[q];
       rec.p = V::load_j(A.p32, A.p64, P, c, 1.0f);
@@ -123,20 +190,36 @@ __global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
       rec.g.z = A.ga[2 * A.n_act + q];
       rec.g.w = A.gp ? A.gp[q] : 0.0;
       rec.idx = static_cast<int>(c);
+      lo = hi = rec.idx;
     } else {
-      rec.p = V::load_j(A.p32, A.p64, P, P - 1, 1.0f);  // a padding particle
+      rec.p = V::load_j(A.p32, A.p64, P, P - 1, 1.0f);  // never used (beyond cnt)
       rec.g.x = rec.g.y = rec.g.z = rec.g.w = 0.0f;
       rec.idx = -1;
+      lo = 0x7fffffff;
+      hi = -1;
     }
+    // index range of this tile's columns: rows outside it cannot meet themselves
+    lo = wave_min_i(lo);
+    hi = wave_max_i(hi);
     const int cnt = min(kTJ, A.n_act - ct * kTJ);
     __syncthreads();
     sc[tid] = rec;
-    __syncthreads();
-    F acc[4] = {F(0), F(0), F(0), F(0)};
-    for (int cc = 0; cc < cnt; ++cc) {
-      const Col<V> c = sc[cc];
-      pair_src<V, NEWTON>(row, c, eps2, c.idx == k, acc);
+    if ((tid & 63) == 0) {
+      srange[0][tid >> 6] = lo;
+      srange[1][tid >> 6] = hi;
     }
+    __syncthreads();
+    int tlo = srange[0][0], thi = srange[1][0];
+#pragma unroll
+    for (int w = 1; w < kWG / 64; ++w) {
+      tlo = min(tlo, srange[0][w]);
+      thi = max(thi, srange[1][w]);
+    }
+    F acc[4] = {F(0), F(0), F(0), F(0)};
+    if (__ballot(k >= tlo && k <= thi) != 0)
+      src_tile<V, NEWTON, 1>(row, sc, cnt, k, eps2, acc);
+    else
+      src_tile<V, NEWTON, 0>(row, sc, cnt, k, eps2, acc);
 #pragma unroll
     for (int e = 0; e < 4; ++e) tot[e] += static_cast<double>(acc[e]);
   }
@@ -153,7 +236,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_bwd_src_reduce(BwdArgs A) {
+// Combine the source part's slices; SCALE_R multiplies the position sums by m_k.
+template <int SCALE_R>
+__global__ __launch_bounds__(kWG) void k_bwd_rows_reduce(BwdArgs A) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (k >= A.n) return;
   double tot[4] = {0.0, 0.0, 0.0, 0.0};
@@ -162,13 +247,42 @@ __global__ __launch_bounds__(kWG) void k_bwd_src_reduce(BwdArgs A) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) tot[e] += in[e * A.n + k];
   }
-  const double mk = A.p64[P64_M * A.npad + k];
+  const double mk = SCALE_R ? A.p64[P64_M * A.npad + k] : 1.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += mk * tot[e];
+  A.gm[k] += tot[3];
+}
+
+template <int SCALE_R>
+__global__ __launch_bounds__(kWG) void k_bwd_rows_reduce_wave(BwdArgs A) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * (kWG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= A.n) return;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = lane; s < A.plan.n_slices; s += 64) {
+    const double *in = A.part + static_cast<int64_t>(s) * 4 * A.n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tot[e] += in[e * A.n + k];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) tot[e] = wave_sum(tot[e]);
+  if (lane != 0) return;
+  const double mk = SCALE_R ? A.p64[P64_M * A.npad + k] : 1.0;
 #pragma unroll
   for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += mk * tot[e];
   A.gm[k] += tot[3];
 }
 
 // ---------------------------------------------------------------- target part
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void tgt_tile(const typename V::I &row, const typename V::J *sj,
+                                         const typename V::F gk[4], int64_t jbase, int64_t g,
+                                         typename V::F eps2, typename V::F acc[3]) {
+#pragma unroll 2
+  for (int jj = 0; jj < kTJ; ++jj)
+    pair_tgt<V, NEWTON, MASK>(row, sj[jj], gk, eps2, MASK && (jbase + jj == g), acc);
+}
+
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_bwd_tgt(BwdArgs A) {
   using F = typename V::F;
@@ -197,9 +311,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_tgt(BwdArgs A) {
     sj[tid] = rec;
     __syncthreads();
     F acc[3] = {F(0), F(0), F(0)};
-#pragma unroll 2
-    for (int jj = 0; jj < kTJ; ++jj)
-      pair_tgt<V, NEWTON>(row, sj[jj], gk, eps2, jbase + jj == g, acc);
+    if (__ballot(g >= jbase && g < jbase + kTJ) != 0)
+      tgt_tile<V, NEWTON, 1>(row, sj, gk, jbase, g, eps2, acc);
+    else
+      tgt_tile<V, NEWTON, 0>(row, sj, gk, jbase, g, eps2, acc);
 #pragma unroll
     for (int e = 0; e < 3; ++e) tot[e] += static_cast<double>(acc[e]);
   }
@@ -228,26 +343,145 @@ __global__ __launch_bounds__(kWG) void k_bwd_tgt_reduce(BwdArgs A) {
   for (int e = 0; e < 3; ++e) A.gr[e * A.n + g] += tot[e];
 }
 
+__global__ __launch_bounds__(kWG) void k_bwd_tgt_reduce_wave(BwdArgs A) {
+  const int q = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= A.n_act) return;
+  double tot[3] = {0.0, 0.0, 0.0};
+  for (int s = lane; s < A.plan.n_slices; s += 64) {
+    const double *in = A.part + static_cast<int64_t>(s) * 3 * A.n_act;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) tot[e] += in[e * A.n_act + q];
+  }
+#pragma unroll
+  for (int e = 0; e < 3; ++e) tot[e] = wave_sum(tot[e]);
+  if (lane != 0) return;
+  const int64_t g = A.idx[q];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) A.gr[e * A.n + g] += tot[e];
+}
+
+// ---------------------------------------------------------------- fused, all active
+// Seeds in particle order: gord[c][idx[q]] = g[c][q]; padding particles get zero.
+__global__ __launch_bounds__(kWG) void k_bwd_order(BwdArgs A) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  const int64_t P = A.npad;
+  if (t < A.n_act) {
+    const int64_t j = A.idx[t];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.gord[c * P + j] = A.ga[c * A.n_act + t];
+    A.gord[3 * P + j] = A.gp ? A.gp[t] : 0.0;
+  } else if (t < A.n_act + (P - A.n)) {
+    const int64_t j = A.n + (t - A.n_act);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A.gord[c * P + j] = 0.0;
+  }
+}
+
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void all_tile(const typename V::I &row, const typename V::F gk[4],
+                                         const ColAll<V> *sc, int64_t jbase, int64_t k,
+                                         typename V::F eps2, typename V::F acc[7]) {
+#pragma unroll 2
+  for (int jj = 0; jj < kTJ; ++jj)
+    pair_all<V, NEWTON, MASK>(row, gk, sc[jj], eps2, MASK && (jbase + jj == k), acc);
+}
+
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_bwd_all(BwdArgs A) {
+  using F = typename V::F;
+  __shared__ ColAll<V> sc[kTJ];
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int rtile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);
+  const int64_t P = A.npad;
+  const int64_t k = static_cast<int64_t>(rtile) * kWG + tid;  // row particle (< npad)
+  const typename V::I row = V::load_i(A.p32, A.p64, P, k);
+  const F gk[4] = {static_cast<F>(A.gord[k]), static_cast<F>(A.gord[P + k]),
+                   static_cast<F>(A.gord[2 * P + k]), static_cast<F>(A.gord[3 * P + k])};
+  const F eps2 = static_cast<F>(A.eps2);
+  double tot[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const int64_t j = jbase + tid;
+    ColAll<V> rec;
+    rec.p = V::load_j(A.p32, A.p64, P, j, 1.0f);
+    rec.g.x = A.gord[j];
+    rec.g.y = A.gord[P + j];
+    rec.g.z = A.gord[2 * P + j];
+    rec.g.w = A.gord[3 * P + j];
+    __syncthreads();
+    sc[tid] = rec;
+    __syncthreads();
+    F acc[7] = {F(0), F(0), F(0), F(0), F(0), F(0), F(0)};
+    if (__ballot(k >= jbase && k < jbase + kTJ) != 0)
+      all_tile<V, NEWTON, 1>(row, gk, sc, jbase, k, eps2, acc);
+    else
+      all_tile<V, NEWTON, 0>(row, gk, sc, jbase, k, eps2, acc);
+#pragma unroll
+    for (int e = 0; e < 7; ++e) tot[e] += static_cast<double>(acc[e]);
+  }
+  if (k >= A.n) return;
+  const double mk = A.p64[P64_M * P + k];
+  double out4[4] = {mk * tot[0] + tot[4], mk * tot[1] + tot[5], mk * tot[2] + tot[6], tot[3]};
+  if (A.plan.n_slices == 1) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += out4[e];
+    A.gm[k] += out4[3];
+  } else {
+    double *out = A.part + static_cast<int64_t>(slice) * 4 * A.n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e * A.n + k] = out4[e];
+  }
+}
+
 SplitPlan plan_src(const BwdArgs &A) {
   return plan_split(A.npad, 1, (A.n_act + kTJ - 1) / kTJ, 2048);
 }
 SplitPlan plan_tgt(const BwdArgs &A) { return plan_split(A.n_act, 1, A.npad / kTJ, 2048); }
+SplitPlan plan_all(const BwdArgs &A) { return plan_split(A.npad, 1, A.npad / kTJ, 2048); }
+
+template <int SCALE_R>
+void reduce_rows(BwdArgs &A, hipStream_t st) {
+  if (A.plan.n_slices >= kWaveReduceSlices) {
+    const int nb = static_cast<int>((A.n + kWG / 64 - 1) / (kWG / 64));
+    hipLaunchKernelGGL(k_bwd_rows_reduce_wave<SCALE_R>, dim3(nb), dim3(kWG), 0, st, A);
+  } else if (A.plan.n_slices > 1) {
+    const int nb = static_cast<int>((A.n + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_bwd_rows_reduce<SCALE_R>, dim3(nb), dim3(kWG), 0, st, A);
+  }
+}
 
 template <class V, int NEWTON>
 hipError_t run(BwdArgs &A, hipStream_t st) {
+  if (A.n_act == A.n) {
+    // every particle is active (the active set is a permutation of all particles)
+    const int64_t cnt = A.n_act + (A.npad - A.n);
+    hipLaunchKernelGGL(k_bwd_order, dim3(static_cast<unsigned>((cnt + kWG - 1) / kWG)),
+                       dim3(kWG), 0, st, A);
+    A.plan = plan_all(A);
+    A.n_ctiles = static_cast<int>(A.npad / kTJ);
+    hipLaunchKernelGGL((k_bwd_all<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+    reduce_rows<0>(A, st);
+    return hipGetLastError();
+  }
   // source part over all particles
   A.plan = plan_src(A);
   A.n_ctiles = (A.n_act + kTJ - 1) / kTJ;
   hipLaunchKernelGGL((k_bwd_src<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices > 1) {
-    const int nb = static_cast<int>((A.n + kWG - 1) / kWG);
-    hipLaunchKernelGGL(k_bwd_src_reduce, dim3(nb), dim3(kWG), 0, st, A);
-  }
+  reduce_rows<1>(A, st);
   // target part over the active set
   A.plan = plan_tgt(A);
   A.n_ctiles = static_cast<int>(A.npad / kTJ);
   hipLaunchKernelGGL((k_bwd_tgt<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices > 1) {
+  if (A.plan.n_slices >= kWaveReduceSlices) {
+    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL(k_bwd_tgt_reduce_wave, dim3(nb), dim3(kWG), 0, st, A);
+  } else if (A.plan.n_slices > 1) {
     const int nb = (A.n_act + kWG - 1) / kWG;
     hipLaunchKernelGGL(k_bwd_tgt_reduce, dim3(nb), dim3(kWG), 0, st, A);
   }
@@ -261,9 +495,14 @@ int64_t backward_partials_needed(const tsbts_ctx *c, int n_act) {
   A.n = c->n;
   A.npad = c->npad;
   A.n_act = n_act;
+  int64_t need = 0;
+  if (n_act == c->n) {
+    const SplitPlan a = plan_all(A);
+    if (a.n_slices > 1) need = static_cast<int64_t>(a.n_slices) * 4 * c->n;
+    return need;
+  }
   const SplitPlan s = plan_src(A);
   const SplitPlan t = plan_tgt(A);
-  int64_t need = 0;
   if (s.n_slices > 1) need = static_cast<int64_t>(s.n_slices) * 4 * c->n;
   if (t.n_slices > 1) need = std::max<int64_t>(need, static_cast<int64_t>(t.n_slices) * 3 * n_act);
   return need;
@@ -284,11 +523,12 @@ hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const do
   A.gm = gm;
   A.eps2 = c->eps * c->eps;
   A.part = c->part;
+  A.gord = c->gord;
   if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st);
-  const bool newton = (c->flags & TSBTS_FLAG_NO_NEWTON) == 0;
-  if (c->flags & TSBTS_FLAG_F64_SEPARATION)
-    return newton ? run<MixSep64, 1>(A, st) : run<MixSep64, 0>(A, st);
-  return newton ? run<MixHiLo, 1>(A, st) : run<MixHiLo, 0>(A, st);
+  const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
+  if (c->flags & TSBTS_FLAG_HILO_SEPARATION)
+    return newton ? run<MixHiLo, 1>(A, st) : run<MixHiLo, 0>(A, st);
+  return newton ? run<MixSep64, 1>(A, st) : run<MixSep64, 0>(A, st);
 }
 
 }  // namespace tsbts

@@ -80,33 +80,53 @@ __global__ __launch_bounds__(kWG) void k_history_begin(CorrectArgs p) {
   }
 }
 
-// Exclusive scan of cnt[0..n) into off[0..n], one workgroup of 1024 threads, each thread
-// owning a contiguous chunk.  Also resets the interpolation cursors to the group starts.
+// Exclusive scan of cnt[0..n) into off[0..n] by one workgroup of 1024 threads walking
+// the array in tiles of 8192 counts: each thread owns 8 consecutive counts (coalesced
+// loads), waves scan their thread sums with shuffles, wave totals are combined through
+// LDS, and a running carry links the tiles.  Also resets the interpolation cursors.
 constexpr int kScanWG = 1024;
+constexpr int kScanPer = 8;
 __global__ __launch_bounds__(kScanWG) void k_scan(const int32_t *cnt, int32_t *off,
                                                   int32_t *cur, int64_t n) {
-  __shared__ int64_t part[kScanWG];
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + kScanWG - 1) / kScanWG;
-  const int64_t b = t * chunk, e = min(n, b + chunk);
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread sums
-  for (int d = 1; d < kScanWG; d <<= 1) {
-    const int64_t add = t >= d ? part[t - d] : 0;
+  __shared__ int wsum[kScanWG / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int carry = 0;
+  for (int64_t base = 0; base < n; base += kScanWG * kScanPer) {
+    const int64_t i0 = base + static_cast<int64_t>(t) * kScanPer;
+    int v[kScanPer];
+    int local = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      v[e] = i0 + e < n ? cnt[i0 + e] : 0;
+      local += v[e];
+    }
+    int x = local;  // inclusive scan over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    part[t] += add;
+    int before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kScanWG / 64; ++k) {
+      before += k < w ? wsum[k] : 0;
+      total += wsum[k];
+    }
+    int run = carry + before + x - local;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      if (i0 + e < n) {
+        off[i0 + e] = run;
+        cur[i0 + e] = run;
+      }
+      run += v[e];
+    }
+    carry += total;
     __syncthreads();
   }
-  int64_t run = part[t] - s;  // exclusive prefix of this chunk
-  for (int64_t i = b; i < e; ++i) {
-    off[i] = static_cast<int32_t>(run);
-    cur[i] = static_cast<int32_t>(run);
-    run += cnt[i];
-  }
-  if (t == kScanWG - 1) off[n] = static_cast<int32_t>(part[t]);
+  if (t == 0) off[n] = carry;
 }
 
 struct ScatterArgs {

@@ -4,13 +4,15 @@
 // workgroup: target i = 256 I + lane in registers, the 256 sources of tile J in LDS, and on
 // diagonal tiles only j > i counts.  Each workgroup reduces its sums in a fixed order into
 // one partial; a single workgroup then adds the partials in a fixed order, so the result
-// is bit-reproducible.  1/sqrt uses the hardware estimate with two Newton steps.
+// is bit-reproducible.  1/sqrt uses the hardware float64 estimate refined by kNewton
+// Newton steps.
 #include "internal.hpp"
 
 namespace tsbts {
 namespace {
 
 constexpr int kTE = 256;
+constexpr int kNewton = 1;
 
 struct EnergyArgs {
   int64_t n;
@@ -33,12 +35,6 @@ __device__ __forceinline__ void tile_pair(int64_t b, int64_t T, int64_t &I, int6
   while (first(i + 1) <= b) ++i;
   I = i;
   J = i + (b - first(i));
-}
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
 }
 
 __global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
@@ -83,7 +79,7 @@ __global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
       const SRec s = sj[jj];
       const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
       const double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
-      w = fma(s.m, rsqrt_f64<2>(q), w);
+      w = fma(s.m, rsqrt_f64<kNewton>(q), w);
     }
   } else {
     for (int jj = 0; jj < kTE; ++jj) {
@@ -93,7 +89,7 @@ __global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
       const bool upper = jj > tid;
       q = upper ? q : 1.0;
       const double mj = upper ? s.m : 0.0;
-      w = fma(mj, rsqrt_f64<2>(q), w);
+      w = fma(mj, rsqrt_f64<kNewton>(q), w);
     }
   }
   double pw = wave_sum(mi * w);

@@ -199,11 +199,36 @@ __global__ __launch_bounds__(kWG) void k_force_reduce(ForceArgs A) {
   finish<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp);
 }
 
+// Same, one wave per target, lanes striding over the slices (many slices).
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_force_reduce_wave(ForceArgs A) {
+  const int q = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= A.n_act) return;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+  const int64_t stride = 4 * static_cast<int64_t>(A.n_act);
+  for (int s = lane; s < A.plan.n_slices; s += 64) {
+    const double *in = A.part + s * stride;
+    sx += in[q];
+    sy += in[A.n_act + q];
+    sz += in[2 * A.n_act + q];
+    sp += in[3 * A.n_act + q];
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  sz = wave_sum(sz);
+  sp = wave_sum(sp);
+  if (lane == 0) finish<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp);
+}
+
 template <class V, int NEWTON, int IPL>
 hipError_t run(ForceArgs &A, hipStream_t st) {
   A.plan = plan_split(A.n_act, IPL, A.n_jtiles, 2048);
   hipLaunchKernelGGL((k_force<V, NEWTON, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices > 1) {
+  if (A.plan.n_slices >= kWaveReduceSlices) {
+    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  } else if (A.plan.n_slices > 1) {
     const int nb = (A.n_act + kWG - 1) / kWG;
     hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
   }
@@ -253,8 +278,8 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   A.acc = acc;
   A.pot = pot;
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
-  const bool sep64 = (c->flags & TSBTS_FLAG_F64_SEPARATION) != 0;
-  const bool newton = (c->flags & TSBTS_FLAG_NO_NEWTON) == 0;
+  const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
+  const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (sep64) return newton ? pick_ipl<MixSep64, 1>(A, st) : pick_ipl<MixSep64, 0>(A, st);
   return newton ? pick_ipl<MixHiLo, 1>(A, st) : pick_ipl<MixHiLo, 0>(A, st);
 }

@@ -58,6 +58,8 @@ struct tsbts_ctx {
   // partial sums of split-j reductions
   double *part = nullptr;
   int64_t part_cap = 0;  // elements
+  // adjoint seeds in particle order (all-active adjoint), [4][npad]
+  double *gord = nullptr;
   // energy partials
   double *epart = nullptr;
   int64_t epart_cap = 0;
@@ -100,6 +102,27 @@ __device__ __forceinline__ void split_hilo(double x, float &hi, float &lo) {
 __device__ __forceinline__ double ff_weight(double m) {
   return m > 0.0 ? 1.0 / cbrt(m * m) : __builtin_inf();
 }
+
+// Fixed-order butterfly reductions over one wave64 (every lane receives the result).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// Split-j partials are combined by one thread per target when there are few slices and
+// by one wave per target (lanes striding over the slices) when there are many.
+constexpr int kWaveReduceSlices = 16;
 
 __host__ __device__ constexpr int64_t round_up(int64_t x, int64_t q) {
   return (x + q - 1) / q * q;

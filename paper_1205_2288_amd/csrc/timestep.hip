@@ -5,7 +5,8 @@
 // Per pair the kernel keeps max(|v_ij|^2 / |r_ij|^2) and min(s * m_j^(-2/3)); the square
 // root and the 3/4 power are taken once per target.  No transcendental per pair in
 // float64 mode apart from the division; mixed mode uses the float32 reciprocal.
-// Same tiling and split-j scheme as the force kernel; the self pair is masked by index.
+// Same tiling and split-j scheme as the force kernel; the self pair is masked by index
+// in the tiles that hold some lane's own particle (wave-uniform vote), as in the force.
 #include "pair.hpp"
 
 namespace tsbts {
@@ -129,6 +130,18 @@ __device__ __forceinline__ double finish_dt(double eta, double qmax, double swmi
   return eta * fmin(tcol, tff);
 }
 
+template <class V, int MASK, int IPL, class J, class I, class F>
+__device__ __forceinline__ void step_tile(const J *sj, const I *Ir, const int *g, int64_t jbase,
+                                          F eps2, F *qmax, F *swmin) {
+#pragma unroll 2
+  for (int jj = 0; jj < kTJ; ++jj) {
+    const J Jr = sj[jj];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k]), qmax[k], swmin[k]);
+  }
+}
+
 template <class V, int IPL>
 __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
   using F = typename V::F;
@@ -160,13 +173,13 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
     __syncthreads();
     sj[tid] = rec;
     __syncthreads();
-#pragma unroll 2
-    for (int jj = 0; jj < kTJ; ++jj) {
-      const J Jr = sj[jj];
+    bool mine = false;
 #pragma unroll
-      for (int k = 0; k < IPL; ++k)
-        pair_step(I[k], Jr, eps2, jbase + jj == g[k], qmax[k], swmin[k]);
-    }
+    for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
+    if (__ballot(mine) != 0)
+      step_tile<V, 1, IPL>(sj, I, g, jbase, eps2, qmax, swmin);
+    else
+      step_tile<V, 0, IPL>(sj, I, g, jbase, eps2, qmax, swmin);
   }
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
@@ -193,11 +206,33 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce(StepArgs A) {
   A.dtc[q] = finish_dt(A.eta, qm, sm);
 }
 
+__global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
+  const int q = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= A.n_act) return;
+  double qm = 0.0, sm = __builtin_inf();
+  for (int s = lane; s < A.plan.n_slices; s += 64) {
+    const double *in = A.part + static_cast<int64_t>(s) * 2 * A.n_act;
+    qm = fmax(qm, in[q]);
+    sm = fmin(sm, in[A.n_act + q]);
+  }
+  qm = wave_max(qm);
+  sm = wave_min(sm);
+  if (lane == 0) A.dtc[q] = finish_dt(A.eta, qm, sm);
+}
+
 template <class V>
 hipError_t run(StepArgs &A, hipStream_t st) {
-  A.plan = plan_split(A.n_act, 1, A.n_jtiles, 2048);
-  hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices > 1) {
+  const int ipl = A.n_act >= 8192 ? 2 : 1;
+  A.plan = plan_split(A.n_act, ipl, A.n_jtiles, 2048);
+  if (ipl == 2)
+    hipLaunchKernelGGL((k_timestep<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.plan.n_slices >= kWaveReduceSlices) {
+    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL(k_timestep_reduce_wave, dim3(nb), dim3(kWG), 0, st, A);
+  } else if (A.plan.n_slices > 1) {
     const int nb = (A.n_act + kWG - 1) / kWG;
     hipLaunchKernelGGL(k_timestep_reduce, dim3(nb), dim3(kWG), 0, st, A);
   }
@@ -221,8 +256,8 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.part = c->part;
   A.dtc = dtc;
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
-  if (c->flags & TSBTS_FLAG_F64_SEPARATION) return run<MixSep64>(A, st);
-  return run<MixHiLo>(A, st);
+  if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
+  return run<MixSep64>(A, st);
 }
 
 }  // namespace tsbts

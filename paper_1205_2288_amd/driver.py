@@ -97,7 +97,7 @@ class TSBTS:
     precision / separation / newton select the force kernel (see Context)."""
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
-                 era=None, precision="mixed", separation="hilo", newton=True, context=None):
+                 era=None, precision="mixed", separation="f64", newton=False, context=None):
         self.n = n = int(np.asarray(m).size)
         self.eta = float(eta)
         self.passes = int(passes)

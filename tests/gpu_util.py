@@ -19,7 +19,7 @@ def summary(e):
             "p99": float(np.quantile(e, 0.99)), "max": float(e.max())}
 
 
-def make_ctx(n, eps, precision="mixed", separation="hilo", newton=True):
+def make_ctx(n, eps, precision="mixed", separation="f64", newton=False):
     from paper_1205_2288_amd import Context
     return Context(n, eps, precision=precision, separation=separation, newton=newton)
 

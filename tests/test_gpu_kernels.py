@@ -202,6 +202,49 @@ def test_history_hermite_prediction_and_snapshot(prec):
     ctx.close()
 
 
+def test_history_multi_tile_records():
+    # N spans several 8192-particle scan tiles; three block levels give 1, 2 or 4 records
+    # per particle after the era-start record; snapshots inside the era must equal the
+    # oracle's Hermite interpolation of the recorded states
+    n, eps, h = 20000, 1 / 64, 2.0 ** -8
+    r, v, m = plummer(n, 53)
+    a0, _ = oracle.force(r, m, eps)
+    lev = np.random.default_rng(3).integers(0, 3, n)
+    dt = h / 2.0 ** lev
+    ctx = make_ctx(n, eps, "fp64")
+    ctx.bind(r, v, m, a=a0, t_last=np.zeros(n), dt=dt)
+    rec = {j: [(0.0, r[:, j].copy(), v[:, j].copy(), a0[:, j].copy())] for j in range(n)}
+    ctx.history_begin()
+    t_last = np.zeros(n)
+    for tb in (h / 4, h / 2, 3 * h / 4, h):
+        act = np.flatnonzero(t_last + dt == tb).astype(np.int32)
+        ctx.predict(tb)
+        acc, _ = ctx.force(act, tb)
+        ctx.correct(act, tb, acc)
+        torch.cuda.synchronize()
+        rr, vv, aa = (x.cpu().numpy() for x in (ctx.r, ctx.v, ctx.a))
+        for j in act:
+            rec[j].append((tb, rr[:, j].copy(), vv[:, j].copy(), aa[:, j].copy()))
+        t_last[act] = tb
+    ctx.history_end()
+    assert all(len(rec[j]) == 1 + (1 << lev[j]) for j in range(n))
+    for T in (h / 8, 3 * h / 8, h / 2, 7 * h / 8):
+        rs, vs = ctx.snapshot(T)
+        rs, vs = rs.cpu().numpy(), vs.cpu().numpy()
+        for j in range(0, n, 97):
+            ts = [x[0] for x in rec[j]]
+            k = int(np.searchsorted(ts, T, side="right")) - 1
+            if ts[k] == T:
+                r_ref, v_ref = rec[j][k][1], rec[j][k][2]
+            else:
+                p0, p1 = rec[j][k], rec[j][k + 1]
+                r_ref, v_ref = oracle.hermite(p0[0], p0[1], p0[2], p0[3], p1[0], p1[1],
+                                              p1[2], p1[3], T)
+            assert np.allclose(rs[:, j], r_ref, rtol=0, atol=1e-14), (T, j)
+            assert np.allclose(vs[:, j], v_ref, rtol=0, atol=1e-13), (T, j)
+    ctx.close()
+
+
 def test_leapfrog_adjoint_elementwise():
     n, h = 300, 0.01
     ctx = make_ctx(n, 0.0, "fp64")
