@@ -69,6 +69,18 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
  * no-op. */
 int tsbts_destroy(tsbts_ctx *ctx);
 
+/* tuning parameters of tsbts_tune */
+#define TSBTS_TUNE_BLOCKS 1
+#define TSBTS_TUNE_IPL 2
+
+/* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
+ *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 2048)
+ *   TSBTS_TUNE_IPL:    target particles per lane for large active sets in the force and
+ *                      criterion kernels (0 = automatic, 1, 2 or 4)
+ * Results do not depend on these except through the order of float64 tile sums.
+ * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
+int tsbts_tune(tsbts_ctx *ctx, int param, int value);
+
 /* Attach the caller's particle state, used by predict / correct / timestep / snapshot /
  * history calls (Algorithm 2's per-particle data: positions, velocities, accelerations,
  * time of the last step and current block step).

@@ -52,6 +52,7 @@ _SIGS = {
     "tsbts_last_error": ([_p], ctypes.c_char_p),
     "tsbts_create": ([ctypes.POINTER(_p), _i64, _d, _int, _int], _int),
     "tsbts_destroy": ([_p], _int),
+    "tsbts_tune": ([_p, _int, _int], _int),
     "tsbts_bind_state": ([_p, _p, _p, _p, _p, _p, _p], _int),
     "tsbts_predict": ([_p, _d, _int, _p], _int),
     "tsbts_load_positions": ([_p, _p, _p, _d, _p], _int),
@@ -143,6 +144,14 @@ def tsbts_create(n: int, eps: float, precision: int, flags: int = 0):
 
 def tsbts_destroy(ctx):
     _check(None, lib.tsbts_destroy(ctx))
+
+
+TSBTS_TUNE_BLOCKS = 1
+TSBTS_TUNE_IPL = 2
+
+
+def tsbts_tune(ctx, param: int, value: int):
+    _check(ctx, lib.tsbts_tune(ctx, int(param), int(value)))
 
 
 def tsbts_bind_state(ctx, n, r, v, a, m, t_last, dt):

@@ -64,6 +64,15 @@ class Context:
         L.tsbts_bind_state(self.ctx, n, self.r, self.v, self.a, self.m, self.t_last, self.dt)
         return self
 
+    def tune(self, blocks=None, ipl=None):
+        """Launch-shape tuning (see tsbts_tune): workgroups per split launch, targets per
+        lane for large active sets (0 = automatic)."""
+        if blocks is not None:
+            L.tsbts_tune(self.ctx, L.TSBTS_TUNE_BLOCKS, blocks)
+        if ipl is not None:
+            L.tsbts_tune(self.ctx, L.TSBTS_TUNE_IPL, ipl)
+        return self
+
     def host_buffer(self, n, dtype):
         """Page-locked host staging buffer (for asynchronous copies)."""
         return torch.empty(n, dtype=dtype, pin_memory=True)

@@ -245,6 +245,23 @@ int tsbts_destroy(tsbts_ctx *c) {
   return TSBTS_OK;
 }
 
+int tsbts_tune(tsbts_ctx *c, int param, int value) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  switch (param) {
+    case TSBTS_TUNE_BLOCKS:
+      if (value < 64 || value > 65536) return fail(c, TSBTS_EINVAL, "blocks outside [64, 65536]");
+      c->tune_blocks = value;
+      return TSBTS_OK;
+    case TSBTS_TUNE_IPL:
+      if (value != 0 && value != 1 && value != 2 && value != 4)
+        return fail(c, TSBTS_EINVAL, "targets per lane must be 0, 1, 2 or 4");
+      c->tune_ipl = value;
+      return TSBTS_OK;
+    default:
+      return fail(c, TSBTS_EINVAL, "unknown tuning parameter %d", param);
+  }
+}
+
 int tsbts_bind_state(tsbts_ctx *c, double *r, double *v, double *a, const double *m,
                      double *t_last, double *dt) {
   if (check_ctx(c)) return TSBTS_EINVAL;

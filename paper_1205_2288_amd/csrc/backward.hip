@@ -52,6 +52,7 @@ struct BwdArgs {
   double eps2;
   double *part;
   double *gord;  // [4][npad] seeds in particle order (fused kernel)
+  int blocks;
 };
 
 template <class V, int NEWTON>
@@ -440,10 +441,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_all(BwdArgs A) {
 }
 
 SplitPlan plan_src(const BwdArgs &A) {
-  return plan_split(A.npad, 1, (A.n_act + kTJ - 1) / kTJ, 2048);
+  return plan_split(A.npad, 1, (A.n_act + kTJ - 1) / kTJ, A.blocks);
 }
-SplitPlan plan_tgt(const BwdArgs &A) { return plan_split(A.n_act, 1, A.npad / kTJ, 2048); }
-SplitPlan plan_all(const BwdArgs &A) { return plan_split(A.npad, 1, A.npad / kTJ, 2048); }
+SplitPlan plan_tgt(const BwdArgs &A) {
+  return plan_split(A.n_act, 1, A.npad / kTJ, A.blocks);
+}
+SplitPlan plan_all(const BwdArgs &A) { return plan_split(A.npad, 1, A.npad / kTJ, A.blocks); }
 
 template <int SCALE_R>
 void reduce_rows(BwdArgs &A, hipStream_t st) {
@@ -495,6 +498,7 @@ int64_t backward_partials_needed(const tsbts_ctx *c, int n_act) {
   A.n = c->n;
   A.npad = c->npad;
   A.n_act = n_act;
+  A.blocks = c->tune_blocks;
   int64_t need = 0;
   if (n_act == c->n) {
     const SplitPlan a = plan_all(A);
@@ -524,6 +528,7 @@ hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const do
   A.eps2 = c->eps * c->eps;
   A.part = c->part;
   A.gord = c->gord;
+  A.blocks = c->tune_blocks;
   if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st);
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION)

@@ -36,6 +36,8 @@ struct ForceArgs {
   double *part;  // [S][4][n_act] raw sums when S > 1
   double *acc;   // [3][n_act]
   double *pot;   // [n_act] or null
+  int blocks;    // workgroups a split launch aims for
+  int ipl;       // targets per lane
 };
 
 // ----- pair contributions -------------------------------------------------------------
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(kWG) void k_force_reduce_wave(ForceArgs A) {
 
 template <class V, int NEWTON, int IPL>
 hipError_t run(ForceArgs &A, hipStream_t st) {
-  A.plan = plan_split(A.n_act, IPL, A.n_jtiles, 2048);
+  A.plan = plan_split(A.n_act, IPL, A.n_jtiles, A.blocks);
   hipLaunchKernelGGL((k_force<V, NEWTON, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   if (A.plan.n_slices >= kWaveReduceSlices) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
@@ -237,7 +239,8 @@ hipError_t run(ForceArgs &A, hipStream_t st) {
 
 template <class V, int NEWTON>
 hipError_t pick_ipl(ForceArgs &A, hipStream_t st) {
-  if (A.n_act >= 8192) return run<V, NEWTON, 2>(A, st);
+  if (A.ipl == 4) return run<V, NEWTON, 4>(A, st);
+  if (A.ipl == 2) return run<V, NEWTON, 2>(A, st);
   return run<V, NEWTON, 1>(A, st);
 }
 
@@ -257,8 +260,8 @@ SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_bl
 
 int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
   const int64_t n_jtiles = c->npad / kTJ;
-  const int ipl = n_act >= 8192 ? 2 : 1;
-  const SplitPlan p = plan_split(n_act, ipl, n_jtiles, 2048);
+  // the criterion uses the same plan with 2 values per target instead of 4
+  const SplitPlan p = plan_split(n_act, targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
   int64_t need = p.n_slices > 1 ? static_cast<int64_t>(p.n_slices) * 4 * n_act : 0;
   return need;
 }
@@ -277,6 +280,8 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   A.part = c->part;
   A.acc = acc;
   A.pot = pot;
+  A.blocks = c->tune_blocks;
+  A.ipl = targets_per_lane(c, n_act);
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;

@@ -64,6 +64,9 @@ struct tsbts_ctx {
   double *epart = nullptr;
   int64_t epart_cap = 0;
   tsbts::History h;
+  // launch-shape tuning (tsbts_tune)
+  int tune_blocks = 2048;
+  int tune_ipl = 0;
   char err[512] = {0};
 };
 
@@ -138,6 +141,12 @@ struct SplitPlan {
 };
 
 SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_blocks);
+
+// Targets per lane of the force and criterion kernels for an active set of n_act.
+inline int targets_per_lane(const tsbts_ctx *c, int n_act) {
+  if (n_act < 8192) return 1;
+  return c->tune_ipl ? c->tune_ipl : 2;
+}
 
 // ------------------------------------------------------------------ launchers
 // Each returns a hipError_t from the launch (hipSuccess on success).

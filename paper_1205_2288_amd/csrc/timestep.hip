@@ -25,6 +25,8 @@ struct StepArgs {
   double eta;
   double *part;  // [S][2][n_act]: max q, min s*w
   double *dtc;
+  int blocks;
+  int ipl;
 };
 
 template <class V> struct StepRec;
@@ -223,9 +225,11 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
 
 template <class V>
 hipError_t run(StepArgs &A, hipStream_t st) {
-  const int ipl = A.n_act >= 8192 ? 2 : 1;
-  A.plan = plan_split(A.n_act, ipl, A.n_jtiles, 2048);
-  if (ipl == 2)
+  const int ipl = A.ipl;
+  A.plan = plan_split(A.n_act, ipl, A.n_jtiles, A.blocks);
+  if (ipl == 4)
+    hipLaunchKernelGGL((k_timestep<V, 4>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  else if (ipl == 2)
     hipLaunchKernelGGL((k_timestep<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   else
     hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
@@ -255,6 +259,8 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.eta = eta;
   A.part = c->part;
   A.dtc = dtc;
+  A.blocks = c->tune_blocks;
+  A.ipl = targets_per_lane(c, n_act);
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);
