@@ -201,6 +201,61 @@ int tsbts_energy(tsbts_ctx *ctx, const double *r, const double *v, const double 
 int tsbts_leapfrog_adjoint(tsbts_ctx *ctx, int phase, double h, const double *rbar,
                            double *vbar, double *abar, double *g_out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Native host scheduler (Algorithm 2 with Eq. blockcondition, Algorithm 1 and Algorithm 3).
+ * Block times are integers in ticks of 2^-20 and every step is a power of two of ticks.
+ * The scheduler keeps host copies of each particle's time, step and last criterion value
+ * and drives the entry points above; each block step synchronises the stream once (to
+ * read the criterion of the active set).  Readings of the paper it follows:
+ *   - admissible step = largest power of two <= mean of the criterion at the start and at
+ *     the end of the step, within [dt_min, dt_max] (Eq. blockcondition);
+ *   - first pass of an era: drop to the admissible step, or double at a multiple of twice
+ *     the step when that is admissible (the standard block-step scheme);
+ *   - later passes (Algorithm 1, as its prose describes it): even time: double, else keep,
+ *     else halve once; odd time: keep, else halve once; the end-of-step criterion comes
+ *     from the previous pass's values of the particle, linear in time between them, the
+ *     start value beyond the last one;
+ *   - every pass restarts from the era-start state; passes after the first interpolate
+ *     the non-active particles from the previous pass (tsbts_predict with history);
+ *   - fixed era: a multiple of dt_max; dynamic era (Algorithm 3): size = last minus first
+ *     next block time, clamped to [dt_max/8, dt_max] and rounded down to a power of two,
+ *     the era ending at the next multiple of it; particles whose next time is past the era
+ *     end are not advanced in that era.
+ * --------------------------------------------------------------------------------------- */
+
+/* Admissible step (ticks) for criterion values begin and end at the start and end of a
+ * step (Eq. blockcondition), within [dt_min, dt_max] (ticks, powers of two).  Host only. */
+int tsbts_sched_admissible(double begin, double end, int64_t dt_min, int64_t dt_max,
+                           int64_t *out);
+
+/* New step (ticks) of a particle with step dt at block time t_block (ticks, a multiple of
+ * dt) given its criterion value `begin` at t_block and the end values end_dt and end_2dt
+ * for the candidate steps dt and 2 dt: the first-pass rule when first_pass != 0, else
+ * Algorithm 1.  Host only; returns TSBTS_EINVAL for inconsistent arguments. */
+int tsbts_sched_rule(int first_pass, int64_t dt, int64_t t_block, double begin, double end_dt,
+                     double end_2dt, int64_t dt_min, int64_t dt_max, int64_t *out);
+
+/* Start a scheduled integration of the bound state at time 0 (Algorithm 2, step 1):
+ * sets t_last = 0, computes the accelerations of all particles (into the bound a), their
+ * criterion values and block steps (into the bound dt).  eta: accuracy parameter of
+ * Eq. nbdt; passes >= 1 (1 = no symmetrization); dt_min, dt_max: step bounds (powers of
+ * two, multiples of 2^-20); era > 0: fixed era size (a multiple of dt_max), era <= 0:
+ * dynamic era.  Allocates the scheduler's staging (pinned host and device buffers);
+ * synchronises the stream. */
+int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, double dt_max,
+                     double era, hipStream_t stream);
+
+/* Integrate one era with all its passes; *era_end (host, may be NULL) receives its end
+ * time.  The bound state then holds the final pass's state; particles are synchronised at
+ * era ends that are multiples of dt_max. */
+int tsbts_sched_era(tsbts_ctx *ctx, double *era_end, hipStream_t stream);
+
+/* Host copies of the scheduler state (each pointer may be NULL): t_ticks, dt_ticks [n]
+ * int64, dtc [n] float64 (last criterion values), stats [4] int64 (block steps, force
+ * calls, interactions, eras), *time (current era end). */
+int tsbts_sched_state(const tsbts_ctx *ctx, int64_t *t_ticks, int64_t *dt_ticks, double *dtc,
+                      int64_t *stats, double *time);
+
 #ifdef __cplusplus
 }
 #endif

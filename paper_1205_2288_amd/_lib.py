@@ -67,6 +67,12 @@ _SIGS = {
     "tsbts_snapshot": ([_p, _d, _p, _p, _p], _int),
     "tsbts_energy": ([_p, _p, _p, _p, _p, _p], _int),
     "tsbts_leapfrog_adjoint": ([_p, _int, _d, _p, _p, _p, _p, _p], _int),
+    "tsbts_sched_admissible": ([_d, _d, _i64, _i64, ctypes.POINTER(_i64)], _int),
+    "tsbts_sched_rule": ([_int, _i64, _i64, _d, _d, _d, _i64, _i64, ctypes.POINTER(_i64)],
+                         _int),
+    "tsbts_sched_init": ([_p, _d, _int, _d, _d, _d, _p], _int),
+    "tsbts_sched_era": ([_p, ctypes.POINTER(_d), _p], _int),
+    "tsbts_sched_state": ([_p, _p, _p, _p, _p, ctypes.POINTER(_d)], _int),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -230,3 +236,48 @@ def tsbts_leapfrog_adjoint(ctx, n, phase, h, rbar, vbar, abar, g_out, stream=Non
     _check(ctx, lib.tsbts_leapfrog_adjoint(
         ctx, int(phase), float(h), _f64(rbar, (3, n), "rbar"), _f64(vbar, (3, n), "vbar"),
         _f64(abar, (3, n), "abar"), _f64(g_out, (3, n), "g_out"), _stream(stream)))
+
+
+# ------------------------------------------------------------------ native scheduler
+
+def tsbts_sched_admissible(begin: float, end: float, dt_min: int, dt_max: int) -> int:
+    out = ctypes.c_int64()
+    _check(None, lib.tsbts_sched_admissible(float(begin), float(end), int(dt_min),
+                                            int(dt_max), ctypes.byref(out)))
+    return out.value
+
+
+def tsbts_sched_rule(first_pass: bool, dt: int, t_block: int, begin: float, end_dt: float,
+                     end_2dt: float, dt_min: int, dt_max: int) -> int:
+    out = ctypes.c_int64()
+    _check(None, lib.tsbts_sched_rule(int(bool(first_pass)), int(dt), int(t_block),
+                                      float(begin), float(end_dt), float(end_2dt),
+                                      int(dt_min), int(dt_max), ctypes.byref(out)))
+    return out.value
+
+
+def tsbts_sched_init(ctx, eta, passes, dt_min, dt_max, era, stream=None):
+    _check(ctx, lib.tsbts_sched_init(ctx, float(eta), int(passes), float(dt_min),
+                                     float(dt_max), float(era), _stream(stream)))
+
+
+def tsbts_sched_era(ctx, stream=None) -> float:
+    end = ctypes.c_double()
+    _check(ctx, lib.tsbts_sched_era(ctx, ctypes.byref(end), _stream(stream)))
+    return end.value
+
+
+def tsbts_sched_state(ctx, n):
+    """Host copies: (t_ticks int64[n], dt_ticks int64[n], dtc float64[n], stats int64[4],
+    time)."""
+    import numpy as np
+    t = np.empty(n, dtype=np.int64)
+    dt = np.empty(n, dtype=np.int64)
+    dtc = np.empty(n, dtype=np.float64)
+    stats = np.empty(4, dtype=np.int64)
+    time = ctypes.c_double()
+    _check(ctx, lib.tsbts_sched_state(ctx, ctypes.c_void_p(t.ctypes.data),
+                                      ctypes.c_void_p(dt.ctypes.data),
+                                      ctypes.c_void_p(dtc.ctypes.data),
+                                      ctypes.c_void_p(stats.ctypes.data), ctypes.byref(time)))
+    return t, dt, dtc, stats, time.value

@@ -226,6 +226,7 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
 int tsbts_destroy(tsbts_ctx *c) {
   if (!c) return TSBTS_OK;
   (void)hipDeviceSynchronize();
+  destroy_scheduler(c);
   dev_free(c->p64);
   dev_free(c->v64);
   dev_free(c->p32);

@@ -64,6 +64,8 @@ struct tsbts_ctx {
   double *epart = nullptr;
   int64_t epart_cap = 0;
   tsbts::History h;
+  // native host scheduler (tsbts_sched_*), owned
+  void *sched = nullptr;
   // launch-shape tuning (tsbts_tune)
   int tune_blocks = 2048;
   int tune_ipl = 0;
@@ -175,6 +177,9 @@ hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st);
 hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
                                    double *vbar, double *abar, double *g_out,
                                    hipStream_t st);
+
+// Free the native scheduler attached to a context (if any).
+void destroy_scheduler(tsbts_ctx *c);
 
 // Scratch needed by the split-j kernels for a given active-set size (float64 elements).
 int64_t partial_elems_needed(const tsbts_ctx *c, int n_act);

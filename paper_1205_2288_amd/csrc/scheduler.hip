@@ -1,0 +1,420 @@
+// Native host scheduler of the TSBTS integration: eras, passes and block steps
+// (Algorithm 2), the time-symmetry criterion (Eq. blockcondition), the symmetrization
+// rules (Algorithm 1) and the dynamic era size (Algorithm 3), driving the kernels of this
+// library with one host/device synchronisation per block step (to read the criterion).
+//
+// Times are integers in ticks of 2^-20; every step is a power of two of ticks.  Block
+// steps stay aligned (a step only doubles at a multiple of twice its size), so at any
+// block time T all particles of one level dt sit at floor(T/dt)*dt: the next block time
+// and the active set follow from per-level member lists in O(levels).
+//
+// Readings (shared with the reference scheduler used by the tests):
+//   admissible(b, e): largest power of two <= (b + e)/2, within [dt_min, dt_max];
+//   first pass: step <- min(step, admissible(b, b)), or twice the step at a multiple of
+//     twice the step when that is admissible;
+//   later passes: even time: double if admissible with the end value at t+2dt, else keep
+//     if admissible with the end value at t+dt, else halve; odd time: keep or halve.  End
+//     values come from the previous pass's criterion values of the particle, linear in
+//     time between stored values, the start value past the last one;
+//   dynamic era: size = (last - first next block time) clamped to [dt_max/8, dt_max],
+//     rounded down to a power of two; the era ends at the next multiple of the size.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tsbts {
+
+constexpr int kTickBits = 20;
+constexpr double kTick = 1.0 / (1 << kTickBits);
+constexpr int kMaxLevel = 40;
+
+int64_t admissible_ticks(double begin, double end, int64_t dt_min, int64_t dt_max) {
+  const double avg = 0.5 * (begin + end);
+  const double x = avg / kTick;
+  if (!std::isfinite(x) || x >= static_cast<double>(dt_max)) return dt_max;
+  if (x < 1.0) return dt_min;
+  int e = 0;
+  std::frexp(x, &e);  // x = f * 2^e, f in [0.5, 1)
+  const int64_t p2 = int64_t(1) << (e - 1);
+  return std::min(dt_max, std::max(dt_min, p2));
+}
+
+int64_t step_rule(int first_pass, int64_t dt, int64_t tb, double begin, double end_dt,
+                  double end_2dt, int64_t dt_min, int64_t dt_max) {
+  if (first_pass) {
+    const int64_t lvl = admissible_ticks(begin, begin, dt_min, dt_max);
+    if (lvl >= 2 * dt && tb % (2 * dt) == 0) return 2 * dt;
+    return std::min(dt, lvl);
+  }
+  const bool even = (tb / dt) % 2 == 0;
+  if (even && 2 * dt <= dt_max && 2 * dt <= admissible_ticks(begin, end_2dt, dt_min, dt_max))
+    return 2 * dt;
+  if (dt <= admissible_ticks(begin, end_dt, dt_min, dt_max)) return dt;
+  return std::max(dt / 2, dt_min);
+}
+
+namespace {
+
+int level_of(int64_t dt) {
+  int l = 0;
+  while ((int64_t(1) << l) < dt) ++l;
+  return l;
+}
+
+// Criterion values of one pass grouped by particle (time order kept).
+struct CritHistory {
+  std::vector<int32_t> pid;
+  std::vector<int64_t> t;
+  std::vector<double> c;
+  std::vector<int64_t> off;  // n + 1 after close()
+  std::vector<int64_t> gt;
+  std::vector<double> gc;
+
+  void clear() {
+    pid.clear();
+    t.clear();
+    c.clear();
+  }
+  void add(int32_t p, int64_t tt, double cc) {
+    pid.push_back(p);
+    t.push_back(tt);
+    c.push_back(cc);
+  }
+  void close(int64_t n) {
+    off.assign(n + 1, 0);
+    for (int32_t p : pid) ++off[p + 1];
+    for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    gt.resize(pid.size());
+    gc.resize(pid.size());
+    for (size_t r = 0; r < pid.size(); ++r) {
+      const int64_t d = fill[pid[r]]++;
+      gt[d] = t[r];
+      gc[d] = c[r];
+    }
+  }
+  // value of particle i at time tt, linear between stored values, fallback past the last
+  double value_at(int32_t i, int64_t tt, double fallback) const {
+    const int64_t lo = off[i], hi = off[i + 1];
+    // last record with time <= tt (the first record is at or before the era start)
+    int64_t a = lo, b = hi - 1;
+    while (a < b) {
+      const int64_t mid = (a + b + 1) >> 1;
+      if (gt[mid] <= tt) a = mid; else b = mid - 1;
+    }
+    const int64_t k = a;
+    if (gt[k] == tt) return gc[k];
+    if (k + 1 >= hi) return fallback;
+    const double w = static_cast<double>(tt - gt[k]) / static_cast<double>(gt[k + 1] - gt[k]);
+    return (1.0 - w) * gc[k] + w * gc[k + 1];
+  }
+};
+
+}  // namespace
+
+struct Scheduler {
+  int64_t n = 0;
+  double eta = 0.1;
+  int passes = 3;
+  int64_t dt_min = 1, dt_max = 1 << 14, era = 0;
+  std::vector<int64_t> t, dt;
+  std::vector<double> dtc;
+  int64_t time = 0;
+  // level member lists
+  std::vector<int32_t> mem[kMaxLevel + 1];
+  std::vector<int32_t> lvl, pos;
+  // criterion histories
+  CritHistory prev, cur;
+  bool have_prev = false;
+  // staging
+  int32_t *idx_h = nullptr;
+  double *dtc_h = nullptr, *dtn_h = nullptr;
+  int32_t *idx_d = nullptr;
+  double *acc_d = nullptr, *dtc_d = nullptr, *dtn_d = nullptr;
+  double *s0 = nullptr;  // era-start device copy: r, v, a (3n each), t_last, dt
+  std::vector<int64_t> s0_t, s0_dt;
+  std::vector<double> s0_dtc;
+  int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
+
+  void rebuild_levels() {
+    for (auto &m : mem) m.clear();
+    for (int64_t i = 0; i < n; ++i) {
+      const int l = level_of(dt[i]);
+      lvl[i] = l;
+      pos[i] = static_cast<int32_t>(mem[l].size());
+      mem[l].push_back(static_cast<int32_t>(i));
+    }
+  }
+  void move(int32_t i, int l) {
+    const int o = lvl[i];
+    if (o == l) return;
+    auto &src = mem[o];
+    const int32_t last = src.back();
+    src[pos[i]] = last;
+    pos[last] = pos[i];
+    src.pop_back();
+    lvl[i] = l;
+    pos[i] = static_cast<int32_t>(mem[l].size());
+    mem[l].push_back(i);
+  }
+  // next block time over occupied levels (members of a level share their time)
+  int64_t next_time() const {
+    int64_t best = INT64_MAX;
+    for (int l = 0; l <= kMaxLevel; ++l)
+      if (!mem[l].empty()) best = std::min(best, t[mem[l][0]] + (int64_t(1) << l));
+    return best;
+  }
+  int64_t era_end(int64_t t0) const {
+    if (era > 0) return t0 + era;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+      if (mem[l].empty()) continue;
+      const int64_t nx = t[mem[l][0]] + (int64_t(1) << l);
+      lo = std::min(lo, nx);
+      hi = std::max(hi, nx);
+    }
+    int64_t size = std::min(dt_max, std::max(dt_max / 8, hi - lo));
+    int64_t p2 = 1;
+    while (p2 * 2 <= size) p2 *= 2;
+    return (t0 / p2 + 1) * p2;
+  }
+};
+
+}  // namespace tsbts
+
+using tsbts::Scheduler;
+
+namespace {
+
+int sfail(tsbts_ctx *c, int st, const char *msg) {
+  snprintf(c->err, sizeof(c->err), "%s", msg);
+  return st;
+}
+
+#define SCHED_HIP(expr)                                                        \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess) {                                                    \
+      snprintf(c->err, sizeof(c->err), "%s: %s", #expr, hipGetErrorString(_e)); \
+      return TSBTS_EHIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+#define SCHED_CALL(expr)        \
+  do {                          \
+    int _s = (expr);            \
+    if (_s != TSBTS_OK) return _s; \
+  } while (0)
+
+// One pass of an era: block steps until the next block time passes T1.
+int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
+  const int64_t n = S.n;
+  S.cur.clear();
+  for (int64_t i = 0; i < n; ++i) S.cur.add(static_cast<int32_t>(i), S.t[i], S.dtc[i]);
+  SCHED_CALL(tsbts_history_begin(c, st));
+  for (;;) {
+    const int64_t tb = S.next_time();
+    if (tb > T1) break;
+    // active set: all members of the levels whose next time is tb
+    int32_t k = 0;
+    for (int l = 0; l <= tsbts::kMaxLevel; ++l) {
+      if (S.mem[l].empty() || S.t[S.mem[l][0]] + (int64_t(1) << l) != tb) continue;
+      std::copy(S.mem[l].begin(), S.mem[l].end(), S.idx_h + k);
+      k += static_cast<int32_t>(S.mem[l].size());
+    }
+    const double tbs = static_cast<double>(tb) * tsbts::kTick;
+    SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+    SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
+    SCHED_CALL(tsbts_force(c, S.idx_d, k, tbs, S.acc_d, nullptr, st));
+    SCHED_CALL(tsbts_correct(c, S.idx_d, k, tbs, S.acc_d, st));
+    SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_d, st));
+    SCHED_HIP(hipMemcpyAsync(S.dtc_h, S.dtc_d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    SCHED_HIP(hipStreamSynchronize(st));
+    for (int32_t q = 0; q < k; ++q) {
+      const int32_t i = S.idx_h[q];
+      const double b = S.dtc_h[q];
+      S.dtc[i] = b;
+      S.t[i] = tb;
+      S.cur.add(i, tb, b);
+      const int64_t d = S.dt[i];
+      double e1 = b, e2 = b;
+      if (p > 0) {
+        e1 = S.prev.value_at(i, tb + d, b);
+        e2 = S.prev.value_at(i, tb + 2 * d, b);
+      }
+      const int64_t nd = tsbts::step_rule(p == 0, d, tb, b, e1, e2, S.dt_min, S.dt_max);
+      S.dtn_h[q] = static_cast<double>(nd) * tsbts::kTick;
+      if (nd != d) {
+        S.dt[i] = nd;
+        S.move(i, tsbts::level_of(nd));
+      }
+    }
+    SCHED_HIP(hipMemcpyAsync(S.dtn_d, S.dtn_h, sizeof(double) * k, hipMemcpyHostToDevice, st));
+    SCHED_CALL(tsbts_set_dt(c, S.idx_d, k, S.dtn_d, st));
+    S.stats[0] += 1;
+    S.stats[1] += 1;
+    S.stats[2] += static_cast<int64_t>(k) * n;
+  }
+  SCHED_CALL(tsbts_history_end(c, st));
+  S.cur.close(n);
+  std::swap(S.prev, S.cur);
+  S.have_prev = true;
+  return TSBTS_OK;
+}
+
+void free_sched(Scheduler *S) {
+  if (!S) return;
+  if (S->idx_h) (void)hipHostFree(S->idx_h);
+  if (S->dtc_h) (void)hipHostFree(S->dtc_h);
+  if (S->dtn_h) (void)hipHostFree(S->dtn_h);
+  if (S->idx_d) (void)hipFree(S->idx_d);
+  if (S->acc_d) (void)hipFree(S->acc_d);
+  if (S->dtc_d) (void)hipFree(S->dtc_d);
+  if (S->dtn_d) (void)hipFree(S->dtn_d);
+  if (S->s0) (void)hipFree(S->s0);
+  delete S;
+}
+
+}  // namespace
+
+namespace tsbts {
+void destroy_scheduler(tsbts_ctx *c) {
+  free_sched(static_cast<Scheduler *>(c->sched));
+  c->sched = nullptr;
+}
+}  // namespace tsbts
+
+extern "C" {
+
+int tsbts_sched_admissible(double begin, double end, int64_t dt_min, int64_t dt_max,
+                           int64_t *out) {
+  if (!out || dt_min < 1 || dt_max < dt_min) return TSBTS_EINVAL;
+  *out = tsbts::admissible_ticks(begin, end, dt_min, dt_max);
+  return TSBTS_OK;
+}
+
+int tsbts_sched_rule(int first_pass, int64_t dt, int64_t t_block, double begin, double end_dt,
+                     double end_2dt, int64_t dt_min, int64_t dt_max, int64_t *out) {
+  if (!out || dt < 1 || dt_min < 1 || dt_max < dt_min || t_block % dt != 0) return TSBTS_EINVAL;
+  *out = tsbts::step_rule(first_pass, dt, t_block, begin, end_dt, end_2dt, dt_min, dt_max);
+  return TSBTS_OK;
+}
+
+int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double dt_max,
+                     double era, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  if (!c->r || !c->v || !c->a || !c->m || !c->t_last || !c->dt)
+    return sfail(c, TSBTS_ESTATE, "tsbts_sched_init: no particle state bound");
+  const double k_min = dt_min / tsbts::kTick, k_max = dt_max / tsbts::kTick;
+  if (!(eta > 0.0) || passes < 1 || k_min < 1.0 || k_max < k_min || k_min != std::floor(k_min) ||
+      k_max != std::floor(k_max) || k_max > double(int64_t(1) << tsbts::kMaxLevel))
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_init: invalid eta, passes or step bounds");
+  const int64_t imin = static_cast<int64_t>(k_min), imax = static_cast<int64_t>(k_max);
+  if ((imin & (imin - 1)) || (imax & (imax - 1)))
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_init: step bounds must be powers of two");
+  const double k_era = era / tsbts::kTick;
+  if (era > 0.0 && (k_era != std::floor(k_era) || static_cast<int64_t>(k_era) % imax != 0))
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_init: a fixed era must be a multiple of dt_max");
+  tsbts::destroy_scheduler(c);
+  Scheduler *S = new (std::nothrow) Scheduler();
+  if (!S) return TSBTS_ENOMEM;
+  c->sched = S;
+  const int64_t n = c->n;
+  S->n = n;
+  S->eta = eta;
+  S->passes = passes;
+  S->dt_min = imin;
+  S->dt_max = imax;
+  S->era = era > 0.0 ? static_cast<int64_t>(k_era) : 0;
+  S->t.assign(n, 0);
+  S->dt.assign(n, 0);
+  S->dtc.assign(n, 0.0);
+  S->lvl.assign(n, 0);
+  S->pos.assign(n, 0);
+  SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->idx_h), sizeof(int32_t) * n));
+  SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtc_h), sizeof(double) * n));
+  SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtn_h), sizeof(double) * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->idx_d), sizeof(int32_t) * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->acc_d), sizeof(double) * 3 * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->dtc_d), sizeof(double) * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->dtn_d), sizeof(double) * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->s0), sizeof(double) * 11 * n));
+  // Algorithm 2, step 1: forces, criterion and block steps of all particles at t = 0
+  for (int64_t i = 0; i < n; ++i) S->idx_h[i] = static_cast<int32_t>(i);
+  SCHED_HIP(hipMemcpyAsync(S->idx_d, S->idx_h, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  SCHED_HIP(hipMemsetAsync(c->t_last, 0, sizeof(double) * n, st));
+  SCHED_HIP(hipMemsetAsync(c->a, 0, sizeof(double) * 3 * n, st));
+  SCHED_HIP(hipMemsetAsync(c->dt, 0, sizeof(double) * n, st));
+  SCHED_CALL(tsbts_predict(c, 0.0, 0, st));
+  SCHED_CALL(tsbts_force(c, S->idx_d, static_cast<int32_t>(n), 0.0, c->a, nullptr, st));
+  // the force output has the same [3][n] layout as the bound accelerations
+  SCHED_CALL(tsbts_timestep(c, S->idx_d, static_cast<int32_t>(n), eta, S->dtc_d, st));
+  SCHED_HIP(hipMemcpyAsync(S->dtc_h, S->dtc_d, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  SCHED_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    S->dtc[i] = S->dtc_h[i];
+    S->dt[i] = tsbts::admissible_ticks(S->dtc[i], S->dtc[i], imin, imax);
+    S->dtn_h[i] = static_cast<double>(S->dt[i]) * tsbts::kTick;
+  }
+  SCHED_HIP(hipMemcpyAsync(c->dt, S->dtn_h, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  SCHED_HIP(hipStreamSynchronize(st));
+  S->rebuild_levels();
+  return TSBTS_OK;
+}
+
+int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  Scheduler *S = static_cast<Scheduler *>(c->sched);
+  if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_era: call tsbts_sched_init first");
+  const int64_t n = S->n;
+  const int64_t T0 = S->time;
+  const int64_t T1 = S->era_end(T0);
+  // era-start state: device copy and host mirrors
+  double *s0 = S->s0;
+  SCHED_HIP(hipMemcpyAsync(s0, c->r, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  SCHED_HIP(hipMemcpyAsync(s0 + 3 * n, c->v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  SCHED_HIP(hipMemcpyAsync(s0 + 6 * n, c->a, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  SCHED_HIP(hipMemcpyAsync(s0 + 9 * n, c->t_last, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  SCHED_HIP(hipMemcpyAsync(s0 + 10 * n, c->dt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  S->s0_t = S->t;
+  S->s0_dt = S->dt;
+  S->s0_dtc = S->dtc;
+  S->have_prev = false;
+  for (int p = 0; p < S->passes; ++p) {
+    if (p > 0) {
+      SCHED_HIP(hipMemcpyAsync(c->r, s0, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+      SCHED_HIP(hipMemcpyAsync(c->v, s0 + 3 * n, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+      SCHED_HIP(hipMemcpyAsync(c->a, s0 + 6 * n, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+      SCHED_HIP(hipMemcpyAsync(c->t_last, s0 + 9 * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      SCHED_HIP(hipMemcpyAsync(c->dt, s0 + 10 * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      S->t = S->s0_t;
+      S->dt = S->s0_dt;
+      S->dtc = S->s0_dtc;
+    }
+    S->rebuild_levels();
+    SCHED_CALL(run_pass(c, *S, p, T1, st));
+  }
+  S->time = T1;
+  S->stats[3] += 1;
+  if (era_end) *era_end = static_cast<double>(T1) * tsbts::kTick;
+  return TSBTS_OK;
+}
+
+int tsbts_sched_state(const tsbts_ctx *c, int64_t *t_ticks, int64_t *dt_ticks, double *dtc,
+                      int64_t *stats, double *time) {
+  if (!c || !c->sched) return TSBTS_EINVAL;
+  const Scheduler *S = static_cast<const Scheduler *>(c->sched);
+  if (t_ticks) std::copy(S->t.begin(), S->t.end(), t_ticks);
+  if (dt_ticks) std::copy(S->dt.begin(), S->dt.end(), dt_ticks);
+  if (dtc) std::copy(S->dtc.begin(), S->dtc.end(), dtc);
+  if (stats) std::copy(S->stats, S->stats + 4, stats);
+  if (time) *time = static_cast<double>(S->time) * tsbts::kTick;
+  return TSBTS_OK;
+}
+
+}  // extern "C"

@@ -259,3 +259,69 @@ class TSBTS:
 
     def close(self):
         self.ctx.close()
+
+
+class NativeTSBTS:
+    """The same integration with the block-step loop in the library's native scheduler
+    (tsbts_sched_*): one host/device synchronisation per block step and no Python in
+    the loop.  Same readings and results as TSBTS."""
+
+    def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
+                 era=None, precision="mixed", separation="f64", newton=False):
+        from . import _lib as L
+        self._L = L
+        self.n = n = int(np.asarray(m).size)
+        self.dt_max = to_ticks(dt_max)
+        self.ctx = Context(n, eps, precision=precision, separation=separation, newton=newton)
+        self.ctx.bind(r, v, m)
+        L.tsbts_sched_init(self.ctx.ctx, eta, passes, dt_min, dt_max,
+                           0.0 if era is None else era)
+        self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
+        self._host()
+        self.wall_s = 0.0
+
+    def _host(self):
+        t, dt, dtc, st, time_ = self._L.tsbts_sched_state(self.ctx.ctx, self.n)
+        self.t, self.dt, self.dtc = t, dt, dtc
+        self.time = to_ticks(time_)
+        self._stats = st
+
+    @property
+    def stats(self):
+        st = self._stats
+        return {"block_steps": int(st[0]), "force_calls": int(st[1]),
+                "interactions": int(st[2]), "eras": int(st[3]), "wall_s": self.wall_s}
+
+    def era_step(self) -> int:
+        end = self._L.tsbts_sched_era(self.ctx.ctx)
+        self._host()
+        return to_ticks(end)
+
+    def energy(self) -> float:
+        kw = self.ctx.energy(out=self._ek).cpu().numpy()
+        return float(kw[0] + kw[1])
+
+    def run(self, t_end: float, energy_every: float | None = None):
+        stop = to_ticks(t_end)
+        every = self.dt_max if energy_every is None else to_ticks(energy_every)
+        out = [(0.0, self.energy())]
+        t0 = time.perf_counter()
+        while self.time < stop:
+            T1 = self.era_step()
+            if T1 % every == 0:
+                if not np.all(self.t == T1):
+                    raise RuntimeError("particles not synchronised at a dt_max multiple")
+                out.append((T1 * TICK, self.energy()))
+        self.ctx.synchronize()
+        self.wall_s += time.perf_counter() - t0
+        return out
+
+    def state(self):
+        c = self.ctx
+        c.synchronize()
+        return {"r": c.r.cpu().numpy(), "v": c.v.cpu().numpy(), "a": c.a.cpu().numpy(),
+                "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
+                "time": self.time}
+
+    def close(self):
+        self.ctx.close()

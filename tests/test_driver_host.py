@@ -67,3 +67,41 @@ def test_one_pass_and_energy_series_match_oracle():
     prod = TSBTS(r, v, m, 1 / 64, context=FakeContext(64, 1 / 64), **kw)
     ref = OracleTSBTS(r, v, m, 1 / 64, **kw)
     assert prod.run(0.25) == ref.run(0.25)
+
+
+# ------------------------------------------------------------------ native scheduler rules
+def test_native_admissible_matches_oracle():
+    from paper_1205_2288_amd import _lib as L
+    rng = np.random.default_rng(1)
+    b = 2.0 ** rng.uniform(-24, 2, 3000)
+    e = b * 2.0 ** rng.uniform(-3, 3, 3000)
+    b[:20] = 2.0 ** -np.arange(20)
+    e[:20] = b[:20]
+    for x, y in zip(b, e):
+        assert L.tsbts_sched_admissible(x, y, 1, 1 << 14) == \
+            level_from_criterion(x, y, 1, 1 << 14)
+    assert L.tsbts_sched_admissible(np.inf, 1.0, 1, 1 << 14) == 1 << 14
+
+
+def test_native_rule_matches_oracle_rules():
+    from paper_1205_2288_amd import _lib as L
+    from oracle.tsbts import History
+    DT, DTMAX = 1 << 10, 1 << 14
+    rng = np.random.default_rng(2)
+    for trial in range(400):
+        dt = DT >> int(rng.integers(0, 3))
+        tb = dt * int(rng.integers(1, 16))
+        begin = dt * 2.0 ** -20 * 2.0 ** rng.uniform(-2, 3)
+        ends = {c: dt * 2.0 ** -20 * 2.0 ** rng.uniform(-2, 3) for c in (dt, 2 * dt)}
+        # oracle: previous-pass history holding exactly these end values
+        s = OracleTSBTS.__new__(OracleTSBTS)
+        s.n, s.dt_max, s.dt_min = 1, DTMAX, 1
+        s.dt = np.array([dt], dtype=np.int64)
+        h = History()
+        for t, c in ((0, begin), (tb + dt, ends[dt]), (tb + 2 * dt, ends[2 * dt])):
+            h.append([0], t, np.zeros((3, 1)), np.zeros((3, 1)), np.zeros((3, 1)), [c])
+        h.freeze(1)
+        first = trial % 3 == 0
+        ref = s._new_step(0, tb, begin, None if first else h)
+        got = L.tsbts_sched_rule(first, dt, tb, begin, ends[dt], ends[2 * dt], 1, DTMAX)
+        assert got == ref, (trial, dt, tb, begin, ends)

@@ -33,12 +33,14 @@ def _drift(series):
     return np.abs((e - e[0]) / e[0]).max()
 
 
+@pytest.mark.parametrize("native", [False, True])
 @pytest.mark.parametrize("passes", [1, 3])
-def test_shared_level_reduces_to_leapfrog(passes):
-    from paper_1205_2288_amd.driver import TSBTS
+def test_shared_level_reduces_to_leapfrog(passes, native):
+    from paper_1205_2288_amd.driver import TSBTS, NativeTSBTS
     r, v, m = plummer(64, 17)
     eps = 1 / 64
-    sim = TSBTS(r, v, m, eps, eta=1e9, passes=passes, era=1 / 8, precision="fp64")
+    cls = NativeTSBTS if native else TSBTS
+    sim = cls(r, v, m, eps, eta=1e9, passes=passes, era=1 / 8, precision="fp64")
     assert np.all(sim.dt == 1 << 14)
     sim.run(0.25)
     st = sim.state()
@@ -68,14 +70,36 @@ def test_plummer256_fp64_follows_oracle():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,eras", [("plummer256", 4), ("plummer4096", 3)])
+def test_native_scheduler_matches_python_scheduler(prec, name, eras):
+    from paper_1205_2288_amd.driver import TSBTS, NativeTSBTS
+    cfg = config(name)
+    r, v, m = cfg.ic()
+    kw = dict(eta=cfg.eta, passes=3, era=cfg.era, dt_max=cfg.dt_max, dt_min=cfg.dt_min,
+              precision=prec)
+    py = TSBTS(r, v, m, cfg.eps, **kw)
+    nat = NativeTSBTS(r, v, m, cfg.eps, **kw)
+    assert np.array_equal(py.dt, nat.dt) and np.array_equal(py.dtc, nat.dtc)
+    for _ in range(eras):
+        assert py.era_step() == nat.era_step()
+        a, b = py.state(), nat.state()
+        for key in ("t", "dt", "dtc", "r", "v", "a"):
+            assert np.array_equal(a[key], b[key]), key
+    assert py.stats["block_steps"] == nat.stats["block_steps"]
+    assert py.stats["interactions"] == nat.stats["interactions"]
+    py.close()
+    nat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["plummer256", "plummer256_1pass", "plummer4096_t1"])
 def test_energy_drift_within_twice_oracle(prec, name):
-    from paper_1205_2288_amd.driver import TSBTS
+    from paper_1205_2288_amd.driver import NativeTSBTS
     g = _golden(name)
     cfg = config(g["workload"])
     r, v, m = cfg.ic()
-    sim = TSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=g["passes"], era=cfg.era,
-                dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=prec)
+    sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=g["passes"], era=cfg.era,
+                      dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=prec)
     series = sim.run(g["t_end"])
     d = _drift(series)
     print(f"{name} {prec}: GPU drift {d:.3e}, oracle {g['max_rel_energy_error']:.3e}, "
@@ -93,12 +117,12 @@ def test_plummer4096_dynamic_era_t10_drift(prec):
     path = os.path.join(GOLDEN, "tsbts_plummer4096.json")
     if not os.path.exists(path):
         pytest.skip("oracle reference for the t=10 run not generated")
-    from paper_1205_2288_amd.driver import TSBTS
+    from paper_1205_2288_amd.driver import NativeTSBTS
     g = _golden("plummer4096")
     cfg = config("plummer4096")
     r, v, m = cfg.ic()
-    sim = TSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=None, dt_max=cfg.dt_max,
-                dt_min=cfg.dt_min, precision=prec)
+    sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=None, dt_max=cfg.dt_max,
+                      dt_min=cfg.dt_min, precision=prec)
     series = sim.run(cfg.t_end)
     d = _drift(series)
     print(f"plummer4096 t=10 {prec}: GPU drift {d:.3e}, oracle "
