@@ -74,7 +74,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
 #define TSBTS_TUNE_IPL 2
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
- *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 2048)
+ *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
  *   TSBTS_TUNE_IPL:    target particles per lane for large active sets in the force and
  *                      criterion kernels (0 = automatic, 1, 2 or 4)
  * Results do not depend on these except through the order of float64 tile sums.

@@ -204,6 +204,7 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
   if (!st && precision == TSBTS_MIXED) st = dev_alloc(c, &c->p32, P32_PLANES * c->npad);
   if (!st) st = dev_alloc(c, &c->gord, 4 * c->npad);
   if (!st) st = dev_alloc(c, &c->h.cnt, n);
+  if (!st) st = dev_alloc(c, &c->h.tsum, (n + 8191) / 8192);
   if (!st) st = dev_alloc(c, &c->h.off, n + 1);
   if (!st) st = dev_alloc(c, &c->h.cur, n);
   if (!st) {
@@ -242,6 +243,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   dev_free(c->h.off);
   dev_free(c->h.cur);
   dev_free(c->h.cnt);
+  dev_free(c->h.tsum);
   delete c;
   return TSBTS_OK;
 }

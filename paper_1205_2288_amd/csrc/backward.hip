@@ -450,7 +450,7 @@ SplitPlan plan_all(const BwdArgs &A) { return plan_split(A.npad, 1, A.npad / kTJ
 
 template <int SCALE_R>
 void reduce_rows(BwdArgs &A, hipStream_t st) {
-  if (A.plan.n_slices >= kWaveReduceSlices) {
+  if (use_wave_reduce(A.plan.n_slices, A.n)) {
     const int nb = static_cast<int>((A.n + kWG / 64 - 1) / (kWG / 64));
     hipLaunchKernelGGL(k_bwd_rows_reduce_wave<SCALE_R>, dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {
@@ -481,7 +481,7 @@ hipError_t run(BwdArgs &A, hipStream_t st) {
   A.plan = plan_tgt(A);
   A.n_ctiles = static_cast<int>(A.npad / kTJ);
   hipLaunchKernelGGL((k_bwd_tgt<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices >= kWaveReduceSlices) {
+  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL(k_bwd_tgt_reduce_wave, dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {

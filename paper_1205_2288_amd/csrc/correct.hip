@@ -80,53 +80,81 @@ __global__ __launch_bounds__(kWG) void k_history_begin(CorrectArgs p) {
   }
 }
 
-// Exclusive scan of cnt[0..n) into off[0..n] by one workgroup of 1024 threads walking
-// the array in tiles of 8192 counts: each thread owns 8 consecutive counts (coalesced
-// loads), waves scan their thread sums with shuffles, wave totals are combined through
-// LDS, and a running carry links the tiles.  Also resets the interpolation cursors.
+// Exclusive scan of cnt[0..n) into off[0..n] in tiles of 8192 counts, one workgroup of
+// 1024 threads per tile (8 consecutive counts per thread, coalesced): a first kernel sums
+// each tile, a second one scans each tile with the sum of the tiles before it as carry
+// (waves scan with shuffles, wave totals meet in LDS).  Integer sums are exact, so the
+// result does not depend on the order.  The second kernel also resets the interpolation
+// cursors to the group starts.
 constexpr int kScanWG = 1024;
 constexpr int kScanPer = 8;
-__global__ __launch_bounds__(kScanWG) void k_scan(const int32_t *cnt, int32_t *off,
-                                                  int32_t *cur, int64_t n) {
+constexpr int64_t kScanTile = static_cast<int64_t>(kScanWG) * kScanPer;
+
+__device__ __forceinline__ int block_sum_1024(int x, int *wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  if (lane == 0) wsum[w] = x;
+  __syncthreads();
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanWG / 64; ++k) s += wsum[k];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_sums(const int32_t *cnt, int64_t n,
+                                                       int32_t *tsum) {
+  __shared__ int wsum[kScanWG / 64];
+  const int64_t i0 = blockIdx.x * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanPer;
+  int local = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) local += i0 + e < n ? cnt[i0 + e] : 0;
+  const int s = block_sum_1024(local, wsum);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_tiles(const int32_t *cnt, int64_t n,
+                                                        const int32_t *tsum, int32_t *off,
+                                                        int32_t *cur) {
   __shared__ int wsum[kScanWG / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int carry = 0;
-  for (int64_t base = 0; base < n; base += kScanWG * kScanPer) {
-    const int64_t i0 = base + static_cast<int64_t>(t) * kScanPer;
-    int v[kScanPer];
-    int local = 0;
+  const int b = blockIdx.x;
+  int pre = 0;
+  for (int k = t; k < b; k += kScanWG) pre += tsum[k];
+  const int carry = block_sum_1024(pre, wsum);
+  const int64_t i0 = b * kScanTile + static_cast<int64_t>(t) * kScanPer;
+  int v[kScanPer];
+  int local = 0;
 #pragma unroll
-    for (int e = 0; e < kScanPer; ++e) {
-      v[e] = i0 + e < n ? cnt[i0 + e] : 0;
-      local += v[e];
-    }
-    int x = local;  // inclusive scan over the wave
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    int before = 0, total = 0;
-#pragma unroll
-    for (int k = 0; k < kScanWG / 64; ++k) {
-      before += k < w ? wsum[k] : 0;
-      total += wsum[k];
-    }
-    int run = carry + before + x - local;
-#pragma unroll
-    for (int e = 0; e < kScanPer; ++e) {
-      if (i0 + e < n) {
-        off[i0 + e] = run;
-        cur[i0 + e] = run;
-      }
-      run += v[e];
-    }
-    carry += total;
-    __syncthreads();
+  for (int e = 0; e < kScanPer; ++e) {
+    v[e] = i0 + e < n ? cnt[i0 + e] : 0;
+    local += v[e];
   }
-  if (t == 0) off[n] = carry;
+  int x = local;  // inclusive scan over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kScanWG / 64; ++k) {
+    before += k < w ? wsum[k] : 0;
+    total += wsum[k];
+  }
+  int run = carry + before + x - local;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) {
+    if (i0 + e < n) {
+      off[i0 + e] = run;
+      cur[i0 + e] = run;
+    }
+    run += v[e];
+  }
+  if (b == gridDim.x - 1 && t == 0) off[n] = carry + total;
 }
 
 struct ScatterArgs {
@@ -209,8 +237,11 @@ hipError_t launch_history_begin(tsbts_ctx *c, hipStream_t st) {
 }
 
 hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanWG), 0, st, c->h.cnt, c->h.off, c->h.cur,
-                     c->n);
+  const int ntiles = static_cast<int>((c->n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_sums, dim3(ntiles), dim3(kScanWG), 0, st, c->h.cnt, c->n,
+                     c->h.tsum);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanWG), 0, st, c->h.cnt, c->n,
+                     c->h.tsum, c->h.off, c->h.cur);
   ScatterArgs p;
   p.count = c->h.count;
   p.cap = c->h.cap;

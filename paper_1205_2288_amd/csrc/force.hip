@@ -184,6 +184,59 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   }
 }
 
+// Small active sets (n_act <= kSmallAct): one 256-particle j-tile per workgroup, one
+// source per lane, the targets broadcast from LDS; each pair is summed over the wave and
+// the 4 waves in a fixed order into one float64 partial per tile and target, which the
+// split-j reduction then combines.  Keeps every lane busy where an i-tile would leave all
+// but n_act lanes idle.
+template <class F>
+__device__ __forceinline__ F wave_sum_t(F x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
+  using F = typename V::F;
+  __shared__ typename V::I si[kSmallAct];
+  __shared__ int sg[kSmallAct];
+  __shared__ F red[kSmallAct][4][kWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tile = blockIdx.x;
+  const int64_t P = A.npad;
+  const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
+  const typename V::J J = V::load_j(A.p32, A.p64, P, j, Scale<V, NEWTON>::kMass);
+  if (tid < A.n_act) {
+    sg[tid] = A.idx[tid];
+    si[tid] = V::load_i(A.p32, A.p64, P, sg[tid]);
+  }
+  __syncthreads();
+  for (int q = 0; q < A.n_act; ++q) {
+    F ax = F(0), ay = F(0), az = F(0), pp = F(0);
+    pair_acc<V, NEWTON, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
+    ax = wave_sum_t(ax);
+    ay = wave_sum_t(ay);
+    az = wave_sum_t(az);
+    pp = wave_sum_t(pp);
+    if (lane == 0) {
+      red[q][0][w] = ax;
+      red[q][1][w] = ay;
+      red[q][2][w] = az;
+      red[q][3][w] = pp;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < 4 * A.n_act; t += kWG) {
+    const int q = t >> 2, c = t & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kWG / 64; ++ww) s += static_cast<double>(red[q][c][ww]);
+    A.part[(static_cast<int64_t>(tile) * 4 + c) * A.n_act + q] = s;
+  }
+}
+
 // Add the slices' partials in slice order and finish (scale, sign).
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_force_reduce(ForceArgs A) {
@@ -227,7 +280,7 @@ template <class V, int NEWTON, int IPL>
 hipError_t run(ForceArgs &A, hipStream_t st) {
   A.plan = plan_split(A.n_act, IPL, A.n_jtiles, A.blocks);
   hipLaunchKernelGGL((k_force<V, NEWTON, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices >= kWaveReduceSlices) {
+  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {
@@ -238,7 +291,25 @@ hipError_t run(ForceArgs &A, hipStream_t st) {
 }
 
 template <class V, int NEWTON>
+hipError_t run_small(ForceArgs &A, hipStream_t st) {
+  A.plan.n_itiles = 1;
+  A.plan.n_slices = A.n_jtiles;
+  A.plan.tiles_per_slice = 1;
+  A.plan.nblk = A.n_jtiles;
+  hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
+  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  } else {
+    const int nb = (A.n_act + kWG - 1) / kWG;
+    hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+template <class V, int NEWTON>
 hipError_t pick_ipl(ForceArgs &A, hipStream_t st) {
+  if (A.n_act <= kSmallAct) return run_small<V, NEWTON>(A, st);
   if (A.ipl == 4) return run<V, NEWTON, 4>(A, st);
   if (A.ipl == 2) return run<V, NEWTON, 2>(A, st);
   return run<V, NEWTON, 1>(A, st);
@@ -260,7 +331,9 @@ SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_bl
 
 int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
   const int64_t n_jtiles = c->npad / kTJ;
-  // the criterion uses the same plan with 2 values per target instead of 4
+  // small sets: one partial per j-tile; the criterion uses the same plans with 2 values
+  // per target instead of 4
+  if (n_act <= kSmallAct) return n_jtiles * 4 * n_act;
   const SplitPlan p = plan_split(n_act, targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
   int64_t need = p.n_slices > 1 ? static_cast<int64_t>(p.n_slices) * 4 * n_act : 0;
   return need;

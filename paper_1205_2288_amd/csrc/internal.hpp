@@ -37,6 +37,7 @@ struct History {
   int64_t hcap = 0, hcount = 0;
   bool valid = false;
   int32_t *cnt = nullptr;               // [n] records per particle in the current pass
+  int32_t *tsum = nullptr;              // per-tile sums of the offset scan
 };
 
 }  // namespace tsbts
@@ -67,7 +68,7 @@ struct tsbts_ctx {
   // native host scheduler (tsbts_sched_*), owned
   void *sched = nullptr;
   // launch-shape tuning (tsbts_tune)
-  int tune_blocks = 2048;
+  int tune_blocks = 8192;
   int tune_ipl = 0;
   char err[512] = {0};
 };
@@ -128,6 +129,15 @@ __device__ __forceinline__ double wave_min(double x) {
 // Split-j partials are combined by one thread per target when there are few slices and
 // by one wave per target (lanes striding over the slices) when there are many.
 constexpr int kWaveReduceSlices = 16;
+// ... but only for few targets: with many targets one thread per target reads the
+// partials coalesced, while one wave per target would touch a cache line per slice.
+constexpr int64_t kWaveReduceMaxTargets = 4096;
+__host__ __device__ inline bool use_wave_reduce(int n_slices, int64_t n_targets) {
+  return n_slices >= kWaveReduceSlices && n_targets <= kWaveReduceMaxTargets;
+}
+
+// Active sets up to this size use the j-parallel pair kernels (one source per lane).
+constexpr int kSmallAct = 32;
 
 __host__ __device__ constexpr int64_t round_up(int64_t x, int64_t q) {
   return (x + q - 1) / q * q;

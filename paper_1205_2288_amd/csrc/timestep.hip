@@ -116,7 +116,11 @@ __device__ __forceinline__ void pair_step(const StepRec<Fp64>::I &i, const StepR
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double ux = j.vx - i.vx, uy = j.vy - i.vy, uz = j.vz - i.vz;
   const double v2 = ux * ux + uy * uy + uz * uz;
-  double q = v2 / r2;
+  // v2 / r2 through the hardware reciprocal estimate and two Newton steps
+  double rr = __builtin_amdgcn_rcp(r2);
+  rr = fma(rr, fma(-r2, rr, 1.0), rr);
+  rr = fma(rr, fma(-r2, rr, 1.0), rr);
+  double q = v2 * rr;
   double sw = (r2 + eps2) * j.w;
   if (self) {
     q = 0.0;
@@ -196,6 +200,60 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
   }
 }
 
+// Small active sets: one j-tile per workgroup, one source per lane, targets from LDS;
+// wave-level max / min, then the 4 waves, into one partial per tile and target.
+template <class F>
+__device__ __forceinline__ F wave_max_t(F x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+template <class F>
+__device__ __forceinline__ F wave_min_t(F x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+template <class V>
+__global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
+  using F = typename V::F;
+  __shared__ typename StepRec<V>::I si[kSmallAct];
+  __shared__ int sg[kSmallAct];
+  __shared__ F red[kSmallAct][2][kWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tile = blockIdx.x;
+  const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
+  const F eps2 = static_cast<F>(A.eps2);
+  const typename StepRec<V>::J J = load_jv<V>(A, j);
+  if (tid < A.n_act) {
+    sg[tid] = A.idx[tid];
+    si[tid] = load_iv<V>(A, sg[tid]);
+  }
+  __syncthreads();
+  for (int q = 0; q < A.n_act; ++q) {
+    F qm = F(0);
+    F sm = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
+    pair_step(si[q], J, eps2, j == sg[q], qm, sm);
+    qm = wave_max_t(qm);
+    sm = wave_min_t(sm);
+    if (lane == 0) {
+      red[q][0][w] = qm;
+      red[q][1][w] = sm;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < 2 * A.n_act; t += kWG) {
+    const int q = t >> 1, c = t & 1;
+    double s = static_cast<double>(red[q][c][0]);
+#pragma unroll
+    for (int ww = 1; ww < kWG / 64; ++ww)
+      s = c == 0 ? fmax(s, static_cast<double>(red[q][c][ww]))
+                 : fmin(s, static_cast<double>(red[q][c][ww]));
+    A.part[(static_cast<int64_t>(tile) * 2 + c) * A.n_act + q] = s;
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_timestep_reduce(StepArgs A) {
   const int q = blockIdx.x * kWG + threadIdx.x;
   if (q >= A.n_act) return;
@@ -225,15 +283,22 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
 
 template <class V>
 hipError_t run(StepArgs &A, hipStream_t st) {
-  const int ipl = A.ipl;
-  A.plan = plan_split(A.n_act, ipl, A.n_jtiles, A.blocks);
-  if (ipl == 4)
-    hipLaunchKernelGGL((k_timestep<V, 4>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  else if (ipl == 2)
-    hipLaunchKernelGGL((k_timestep<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  else
-    hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (A.plan.n_slices >= kWaveReduceSlices) {
+  if (A.n_act <= kSmallAct) {
+    A.plan.n_itiles = 1;
+    A.plan.n_slices = A.n_jtiles;
+    A.plan.tiles_per_slice = 1;
+    A.plan.nblk = A.n_jtiles;
+    hipLaunchKernelGGL((k_timestep_small<V>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
+  } else {
+    A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
+    if (A.ipl == 4)
+      hipLaunchKernelGGL((k_timestep<V, 4>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+    else if (A.ipl == 2)
+      hipLaunchKernelGGL((k_timestep<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  }
+  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL(k_timestep_reduce_wave, dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {
