@@ -43,7 +43,7 @@ struct ForceArgs {
 // ----- pair contributions -------------------------------------------------------------
 // acc += m r^-3 d (times a constant scale), pot += m r^-1.
 
-template <class V, int NEWTON, int MASK>
+template <class V, int NEWTON, int MASK, int POT>
 __device__ __forceinline__ void pair_acc(const typename V::I &i, const typename V::J &j,
                                          float eps2, bool self, float &ax, float &ay,
                                          float &az, float &pp) {
@@ -61,10 +61,10 @@ __device__ __forceinline__ void pair_acc(const typename V::I &i, const typename 
   ax = fmaf(mr3, dx, ax);
   ay = fmaf(mr3, dy, ay);
   az = fmaf(mr3, dz, az);
-  pp += mr1;
+  if (POT) pp += mr1;
 }
 
-template <class V, int NEWTON, int MASK>
+template <class V, int NEWTON, int MASK, int POT>
 __device__ __forceinline__ void pair_acc(const typename V::I &i, const typename V::J &j,
                                          double eps2, bool self, double &ax, double &ay,
                                          double &az, double &pp) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ void pair_acc(const typename V::I &i, const typename 
   ax = fma(mr3, dx, ax);
   ay = fma(mr3, dy, ay);
   az = fma(mr3, dz, az);
-  pp += mr1;
+  if (POT) pp += mr1;
 }
 
 // Mass scale held in LDS and the final acceleration scale (see rsq_refined).
@@ -102,7 +102,7 @@ __device__ __forceinline__ void finish(const ForceArgs &A, int q, int64_t g, dou
   if (A.pot) A.pot[q] = -sp;
 }
 
-template <class V, int NEWTON, int MASK, int IPL, class F>
+template <class V, int NEWTON, int MASK, int POT, int IPL, class F>
 __device__ __forceinline__ void tile_loop(const typename V::J *sj, const typename V::I *I,
                                           const int *g, int64_t jbase, F eps2, F *fx, F *fy,
                                           F *fz, F *fp) {
@@ -111,12 +111,12 @@ __device__ __forceinline__ void tile_loop(const typename V::J *sj, const typenam
     const typename V::J J = sj[jj];
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
-      pair_acc<V, NEWTON, MASK>(I[k], J, eps2, MASK && (jbase + jj == g[k]), fx[k], fy[k],
+      pair_acc<V, NEWTON, MASK, POT>(I[k], J, eps2, MASK && (jbase + jj == g[k]), fx[k], fy[k],
                                 fz[k], fp[k]);
   }
 }
 
-template <class V, int NEWTON, int IPL>
+template <class V, int NEWTON, int POT, int IPL>
 __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   static_assert(kTJ == kWG, "one staged record per thread");
   using F = typename V::F;
@@ -157,9 +157,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
 #pragma unroll
     for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
     if (__ballot(mine) != 0)
-      tile_loop<V, NEWTON, 1, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
+      tile_loop<V, NEWTON, 1, POT, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
     else
-      tile_loop<V, NEWTON, 0, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
+      tile_loop<V, NEWTON, 0, POT, IPL>(sj, I, g, jbase, eps2, fx, fy, fz, fp);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       sx[k] += static_cast<double>(fx[k]);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
   __syncthreads();
   for (int q = 0; q < A.n_act; ++q) {
     F ax = F(0), ay = F(0), az = F(0), pp = F(0);
-    pair_acc<V, NEWTON, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
+    pair_acc<V, NEWTON, 1, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
     ax = wave_sum_t(ax);
     ay = wave_sum_t(ay);
     az = wave_sum_t(az);
@@ -279,7 +279,10 @@ __global__ __launch_bounds__(kWG) void k_force_reduce_wave(ForceArgs A) {
 template <class V, int NEWTON, int IPL>
 hipError_t run(ForceArgs &A, hipStream_t st) {
   A.plan = plan_split(A.n_act, IPL, A.n_jtiles, A.blocks);
-  hipLaunchKernelGGL((k_force<V, NEWTON, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  if (A.pot)
+    hipLaunchKernelGGL((k_force<V, NEWTON, 1, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_force<V, NEWTON, 0, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);

@@ -96,6 +96,30 @@ def test_force_full_size_sampled(name, prec):
     ctx.close()
 
 
+def test_sweep32768_error_histograms():
+    # one prediction + force call per active-set size, mixed and float64, 512 sampled
+    # targets against the oracle; histogram of log10 per-particle relative error in bins
+    # of 0.25 over [-12, -2] (printed), medians checked against the 1e-6 bar
+    cfg = config("sweep32768")
+    r, v, m = cfg.ic()
+    n = cfg.n
+    edges = np.arange(-12.0, -1.99, 0.25)
+    for prec in ("mixed", "fp64"):
+        ctx = make_ctx(n, cfg.eps, prec)
+        for k, n_act in enumerate([1, 8, 64, 512, 4096, 32768]):
+            idx = active_subset(n, n_act, cfg.seed + 1000 * k)
+            acc, _ = _run(ctx, r, v, m, idx)
+            take = np.sort(np.random.default_rng(k).choice(n_act, size=min(n_act, 512),
+                                                           replace=False))
+            a_ref, _ = oracle.force(r, m, cfg.eps, idx[take])
+            e = rel_err_vec(acc[:, take], a_ref)
+            h, _ = np.histogram(np.log10(np.maximum(e, 1e-300)), bins=edges)
+            print(f"hist {prec} n_act={n_act} median={np.median(e):.2e} max={e.max():.2e} "
+                  f"below={int((e < 1e-12).sum())} counts={h.tolist()}")
+            assert np.median(e) <= TOL[prec]["median"]
+        ctx.close()
+
+
 def test_force_out_of_order_and_bad_arguments():
     from paper_1205_2288_amd._lib import TsbtsError, TSBTS_ESTATE, TSBTS_EINVAL
     n = 100
