@@ -43,6 +43,40 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_FORCE = 20.0
 FLOPS_ADJOINT = 73.0
 FLOPS_ENERGY_PAIR = 12.0
+FLOPS_CRITERION = 20.0
+
+# HBM bytes per launch in the default (mixed) era step, from two rocprofv3 --pmc passes
+# over this workload: FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch, averaged over the
+# dispatches of one step (the same half / full mix the timing averages over), scaled by
+# what the same counters read for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x
+# 1.0).  Each entry names the sources the kernel is built from and their SHA-256 (first
+# 16 hex digits) when the counters were taken; if they differ now, traffic is null.
+COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC_KIB = {
+    "k_timestep": (153954.8, 65536.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
+                   "005451da9bedab7c"),
+    "k_force": (79676.0, 131072.0, ("force.hip", "pair.hpp", "internal.hpp"),
+                "cd5234b0a47c7eef"),
+    "k_bwd_all": (65044.3, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
+                  "66e90fe4d1f060a9"),
+    "k_energy_pairs": (23432.3, 4104.0, ("energy.hip", "internal.hpp"), "c7d943fafe6e5381"),
+}
+
+
+def traffic_bytes(kernel: str):
+    """Counter-measured HBM bytes per launch, or None if the kernel's sources changed."""
+    import hashlib
+    if kernel not in TRAFFIC_KIB:
+        return None
+    fetch, write, files, digest = TRAFFIC_KIB[kernel]
+    csrc = os.path.join(ROOT, "paper_1205_2288_amd", "csrc")
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != digest:
+        return None
+    return (fetch * COUNTER_SCALE["fetch"] + write * COUNTER_SCALE["write"]) * 1024.0
 
 
 class Timer:
@@ -218,8 +252,9 @@ def rooflines(ms, n, precision="mixed"):
     def entry(kernel, flops, ms_list, peak):
         t = float(np.sum(ms_list)) * 1e-3
         achieved = flops / t / 1e12
+        traffic = traffic_bytes(kernel) if precision == "mixed" else None
         return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "avg_launch_us": t / len(ms_list) * 1e6, "calls": len(ms_list),
                 "total_ms": t * 1e3}
 
@@ -228,7 +263,7 @@ def rooflines(ms, n, precision="mixed"):
                            ms["force_full"] + ms["force_half"], peak32)
     # the criterion kernel's calls alternate half / full active sets
     nts = len(ms["timestep"])
-    out["k_timestep"] = entry("k_timestep", 20.0 * n * (nts // 2) * (n + n // 2),
+    out["k_timestep"] = entry("k_timestep", FLOPS_CRITERION * n * (nts // 2) * (n + n // 2),
                               ms["timestep"], peak32)
     out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * len(ms["backward"]),
                              ms["backward"], peak32)

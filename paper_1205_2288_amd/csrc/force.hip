@@ -19,6 +19,7 @@
 // those tiles and the unmasked one elsewhere, so the mask costs nothing on almost every
 // tile and no large self term ever enters a float32 accumulator.
 #include "pair.hpp"
+#include <type_traits>
 
 namespace tsbts {
 namespace {
@@ -312,7 +313,10 @@ hipError_t run_small(ForceArgs &A, hipStream_t st) {
 
 template <class V, int NEWTON>
 hipError_t pick_ipl(ForceArgs &A, hipStream_t st) {
-  if (A.n_act <= kSmallAct) return run_small<V, NEWTON>(A, st);
+  // the float64 j-parallel kernel pays four float64 wave reductions per target, which
+  // beyond 16 targets cost more than the target-parallel kernel saves
+  const int small = std::is_same<V, Fp64>::value ? kSmallActFp64 : kSmallAct;
+  if (A.n_act <= small) return run_small<V, NEWTON>(A, st);
   if (A.ipl == 4) return run<V, NEWTON, 4>(A, st);
   if (A.ipl == 2) return run<V, NEWTON, 2>(A, st);
   return run<V, NEWTON, 1>(A, st);

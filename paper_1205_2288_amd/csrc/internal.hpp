@@ -138,6 +138,8 @@ __host__ __device__ inline bool use_wave_reduce(int n_slices, int64_t n_targets)
 
 // Active sets up to this size use the j-parallel pair kernels (one source per lane).
 constexpr int kSmallAct = 32;
+// ... and for the float64 force kernel up to this size.
+constexpr int kSmallActFp64 = 16;
 
 __host__ __device__ constexpr int64_t round_up(int64_t x, int64_t q) {
   return (x + q - 1) / q * q;

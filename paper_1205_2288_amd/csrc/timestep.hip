@@ -50,8 +50,11 @@ __device__ __forceinline__ typename StepRec<V>::J load_jv(const StepArgs &A, int
   const int64_t P = A.npad;
   r.p = V::load_j(A.p32, A.p64, P, j, 1.0f);
   if constexpr (sizeof(typename V::F) == 4) {
+    // the fourth lane carries eps^2 m_j^(-2/3), so s m_j^(-2/3) is one fma per pair (0
+    // when eps = 0, where the weight of a massless particle is infinite)
     r.v = make_float4(static_cast<float>(A.v64[j]), static_cast<float>(A.v64[P + j]),
-                      static_cast<float>(A.v64[2 * P + j]), 0.0f);
+                      static_cast<float>(A.v64[2 * P + j]),
+                      A.eps2 > 0.0 ? static_cast<float>(A.eps2) * V::weight(r.p) : 0.0f);
   } else {
     r.vx = A.v64[j];
     r.vy = A.v64[P + j];
@@ -81,7 +84,7 @@ __device__ __forceinline__ void pair_step(const StepRec<MixHiLo>::I &i,
   const float ux = j.v.x - i.vx, uy = j.v.y - i.vy, uz = j.v.z - i.vz;
   const float v2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
   float q = v2 * __builtin_amdgcn_rcpf(r2);
-  float sw = (r2 + eps2) * MixHiLo::weight(j.p);
+  float sw = fmaf(r2, MixHiLo::weight(j.p), j.v.w);
   if (self) {
     q = 0.0f;
     sw = __builtin_inff();
@@ -99,7 +102,7 @@ __device__ __forceinline__ void pair_step(const StepRec<MixSep64>::I &i,
   const float ux = j.v.x - i.vx, uy = j.v.y - i.vy, uz = j.v.z - i.vz;
   const float v2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
   float q = v2 * __builtin_amdgcn_rcpf(r2);
-  float sw = (r2 + eps2) * MixSep64::weight(j.p);
+  float sw = fmaf(r2, MixSep64::weight(j.p), j.v.w);
   if (self) {
     q = 0.0f;
     sw = __builtin_inff();

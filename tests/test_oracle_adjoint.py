@@ -80,3 +80,65 @@ def test_leapfrog_gradient_vs_finite_differences(oracle):
                 return adjoint.loss(rr, vv, mm, eps, h, steps, target)
             fd = (f(1) - f(-1)) / (2 * step)
             assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which
+
+
+def _levels_dt(n, h, seed, nlev=3):
+    rng = np.random.default_rng(seed)
+    return h * 2.0 ** rng.integers(0, nlev, size=n)
+
+
+def test_block_forward_schedule_and_shared_limit(oracle):
+    # the schedule: particle i is active exactly every dt_i; with one common step the
+    # block run is the shared-step leapfrog
+    n, eps, h = 12, 1.0 / 16, 1.0 / 64
+    r0, v0, m = plummer(n, 31)
+    dt = _levels_dt(n, h, 3)
+    _, _, trace = adjoint.block_forward(r0, v0, m, eps, dt, 8 * h)
+    assert [t for (t, *_rest) in trace] == [h * (s + 1) for s in range(8)]
+    for (t_b, act, *_rest) in trace:
+        expect = np.nonzero(np.mod(t_b, dt) == 0.0)[0]
+        assert np.array_equal(act, expect)
+    rb, vb, _ = adjoint.block_forward(r0, v0, m, eps, np.full(n, h), 8 * h)
+    rs, states = adjoint.forward(r0, v0, m, eps, h, 8)
+    assert np.array_equal(rb, rs) and np.array_equal(vb, states[-1][1])
+
+
+def test_block_gradient_vs_finite_differences(oracle):
+    n, eps, h = 14, 1.0 / 16, 1.0 / 64
+    t_end = 8 * h
+    r0, v0, m = plummer(n, 25, masses="loguniform")
+    dt = _levels_dt(n, h, 4)
+    rt, vt, _ = adjoint.block_forward(r0, v0, m, eps, dt, t_end)
+    rt = rt + 0.01 * gaussian((3, n), 7)
+    vt = vt + 0.01 * gaussian((3, n), 8)
+    L, gr, gv, gm = adjoint.block_gradient(r0, v0, m, eps, dt, t_end, rt, vt)
+    assert L == pytest.approx(adjoint.block_loss(r0, v0, m, eps, dt, t_end, rt, vt),
+                              rel=1e-15)
+    step = 1e-6
+    for trial in range(3):
+        dr = gaussian((3, n), 600 + trial)
+        dv = gaussian((3, n), 700 + trial)
+        dm = gaussian(n, 800 + trial) * m
+        for (g, d, which) in ((gr, dr, "r"), (gv, dv, "v"), (gm, dm, "m")):
+            def f(sgn):
+                rr = r0 + sgn * step * d if which == "r" else r0
+                vv = v0 + sgn * step * d if which == "v" else v0
+                mm = m + sgn * step * d if which == "m" else m
+                return adjoint.block_loss(rr, vv, mm, eps, dt, t_end, rt, vt)
+            fd = (f(1) - f(-1)) / (2 * step)
+            assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which
+
+
+def test_block_gradient_shared_limit(oracle):
+    # one common step: the block gradient must equal the shared-step gradient plus the
+    # velocity part of the loss (checked with a zero-weight velocity target)
+    n, eps, h = 10, 1.0 / 16, 1.0 / 64
+    r0, v0, m = plummer(n, 26)
+    dt = np.full(n, h)
+    rt = adjoint.forward(r0, v0, m, eps, h, 6)[0] + 0.01 * gaussian((3, n), 9)
+    v_end = adjoint.block_forward(r0, v0, m, eps, dt, 6 * h)[1]
+    Lb, gr_b, gv_b, gm_b = adjoint.block_gradient(r0, v0, m, eps, dt, 6 * h, rt, v_end)
+    Ls, gr_s, gv_s, gm_s = adjoint.gradient(r0, v0, m, eps, h, 6, rt)
+    assert Lb == pytest.approx(Ls, rel=1e-14)
+    for a, b in ((gr_b, gr_s), (gv_b, gv_s), (gm_b, gm_s)):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * np.abs(b).max())
