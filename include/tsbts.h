@@ -201,6 +201,25 @@ int tsbts_energy(tsbts_ctx *ctx, const double *r, const double *v, const double 
 int tsbts_leapfrog_adjoint(tsbts_ctx *ctx, int phase, double h, const double *rbar,
                            double *vbar, double *abar, double *g_out, hipStream_t stream);
 
+/* Reverse sweep of one block step of a fixed block schedule (Section 2's individual
+ * power-of-two steps in one pass: every particle predicted by the Taylor polynomial to
+ * t_block with h_j = t_block - t_last_j, the force on the active set, the leapfrog corrector
+ * r_i <- p_i, v_i <- v_i + dt_i (a_i + an_i)/2, a_i <- an_i on the active set).
+ * rbar, vbar, abar [3][n] float64 device: on entry the adjoint of the state after the block
+ * step, on exit (after phase 1) the adjoint of the state before it.  pbar [3][n] float64
+ * device: the adjoint of the predicted positions.  seeds [3][n_act] float64 device.
+ * The bound dt and t_last must hold the steps and the pre-step times of that block step.
+ *   phase 0 (idx [n_act] = the active set, sorted or not): pbar = 0 except
+ *           pbar_i = rbar_i;  seeds[:, q] = abar_i + (dt_i/2) vbar_i;
+ *           abar_i = (dt_i/2) vbar_i;  rbar_i = 0   (i = idx[q]).
+ *   then    tsbts_force_backward(idx, t_block, seeds, NULL, pbar, mbar) with the positions
+ *           predicted to t_block from the pre-step state (adds dL/dp into pbar).
+ *   phase 1 (every particle):  rbar += pbar;  vbar += h_j pbar;  abar += (h_j^2/2) pbar.
+ * idx and seeds are ignored in phase 1.  Not in the paper: gradients through the method. */
+int tsbts_block_adjoint(tsbts_ctx *ctx, int phase, const int32_t *idx, int32_t n_act,
+                        double t_block, double *rbar, double *vbar, double *abar,
+                        double *pbar, double *seeds, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------
  * Native host scheduler (Algorithm 2 with Eq. blockcondition, Algorithm 1 and Algorithm 3).
  * Block times are integers in ticks of 2^-20 and every step is a power of two of ticks.

@@ -67,6 +67,7 @@ _SIGS = {
     "tsbts_snapshot": ([_p, _d, _p, _p, _p], _int),
     "tsbts_energy": ([_p, _p, _p, _p, _p, _p], _int),
     "tsbts_leapfrog_adjoint": ([_p, _int, _d, _p, _p, _p, _p, _p], _int),
+    "tsbts_block_adjoint": ([_p, _int, _p, _int, _d, _p, _p, _p, _p, _p, _p], _int),
     "tsbts_sched_admissible": ([_d, _d, _i64, _i64, ctypes.POINTER(_i64)], _int),
     "tsbts_sched_rule": ([_int, _i64, _i64, _d, _d, _d, _i64, _i64, ctypes.POINTER(_i64)],
                          _int),
@@ -236,6 +237,15 @@ def tsbts_leapfrog_adjoint(ctx, n, phase, h, rbar, vbar, abar, g_out, stream=Non
     _check(ctx, lib.tsbts_leapfrog_adjoint(
         ctx, int(phase), float(h), _f64(rbar, (3, n), "rbar"), _f64(vbar, (3, n), "vbar"),
         _f64(abar, (3, n), "abar"), _f64(g_out, (3, n), "g_out"), _stream(stream)))
+
+
+def tsbts_block_adjoint(ctx, n, phase, active_idx, t_block, rbar, vbar, abar, pbar, seeds,
+                        stream=None):
+    k = 0 if active_idx is None else active_idx.numel()
+    _check(ctx, lib.tsbts_block_adjoint(
+        ctx, int(phase), _i32p(active_idx), k, float(t_block), _f64(rbar, (3, n), "rbar"),
+        _f64(vbar, (3, n), "vbar"), _f64(abar, (3, n), "abar"), _f64(pbar, (3, n), "pbar"),
+        _f64(seeds, None if seeds is None else (3, k), "seeds"), _stream(stream)))
 
 
 # ------------------------------------------------------------------ native scheduler

@@ -8,10 +8,17 @@
   each era from its checkpoint and sweeps it in reverse with the element-wise leapfrog
   adjoint kernel and the force adjoint kernel.
 
+* ``TsbtsBlockLeapfrog``: a run on a fixed block schedule (Section 2's individual
+  power-of-two steps, one pass, every particle predicted by its Taylor polynomial to each
+  block time, force and leapfrog corrector on the active set), all particles starting
+  together at t = 0.  Same checkpointing; the reverse sweep restores each block step's
+  pre-step state, predicts, and runs ``tsbts_block_adjoint`` around the force adjoint.
+
 All arithmetic runs in libtsbts kernels; torch provides the tensors and the graph.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from .context import Context
@@ -120,3 +127,126 @@ def _step(ctx: Context, every, acc, s: int, h: float):
 
 def tsbts_leapfrog(r0, v0, m, ctx: Context, h: float, steps: int, era: int = 16):
     return TsbtsLeapfrog.apply(r0, v0, m, ctx, h, steps, era)
+
+
+class BlockSchedule:
+    """Fixed block schedule: step dt_i = hmin * 2^level_i per particle, block times
+    (s + 1) * hmin for s = 0 .. K-1, K = t_end / hmin.  At block s the active set is
+    {i : level_i <= trailing zeros of s + 1} (particle i is due at every multiple of dt_i)."""
+
+    def __init__(self, ctx: Context, dt, t_end: float):
+        dt = np.asarray(dt.cpu().numpy() if isinstance(dt, torch.Tensor) else dt,
+                        dtype=np.float64).reshape(-1)
+        if dt.size != ctx.n or not np.all(dt > 0):
+            raise ValueError("dt must hold one positive step per particle")
+        self.hmin = float(dt.min())
+        lev = np.log2(dt / self.hmin)
+        self.level = np.rint(lev).astype(np.int64)
+        if not np.array_equal(self.hmin * 2.0 ** self.level, dt):
+            raise ValueError("every step must be the smallest step times a power of two")
+        k = t_end / self.hmin
+        self.K = int(round(k))
+        if self.K < 1 or self.K * self.hmin != t_end:
+            raise ValueError("t_end must be a positive multiple of the smallest step")
+        self.dt = dt
+        self.lmax = int(self.level.max())
+        self.sets = [ctx.idx(np.nonzero(self.level <= L)[0].astype(np.int32))
+                     for L in range(self.lmax + 1)]
+
+    def time(self, s: int) -> float:
+        return (s + 1) * self.hmin
+
+    def active(self, s: int):
+        b = s + 1
+        tz = (b & -b).bit_length() - 1
+        return self.sets[min(tz, self.lmax)]
+
+
+def _block_step(ctx: Context, sched: BlockSchedule, s: int, buf):
+    tb = sched.time(s)
+    idx = sched.active(s)
+    k = idx.numel()
+    acc = buf[:3 * k].view(3, k)
+    ctx.predict(tb)
+    ctx.force(idx, tb, with_pot=False, acc=acc)
+    ctx.correct(idx, tb, acc)
+
+
+class TsbtsBlockLeapfrog(torch.autograd.Function):
+    """(r, v) at t_end after a run on the fixed block schedule given by dt (per-particle
+    power-of-two steps), with a checkpoint every `era` block steps."""
+
+    @staticmethod
+    def forward(fctx, r0, v0, m, ctx: Context, dt, t_end: float, era: int):
+        n = ctx.n
+        dev = ctx.device
+        sched = BlockSchedule(ctx, dt, t_end)
+        r0, v0, m = (x.detach().contiguous() for x in (r0, v0, m))
+        ctx.bind(r0.clone(), v0.clone(), m.clone(),
+                 t_last=torch.zeros(n, dtype=torch.float64, device=dev),
+                 dt=torch.tensor(sched.dt, dtype=torch.float64, device=dev))
+        every = ctx.idx(torch.arange(n, dtype=torch.int32))
+        buf = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        acc = buf.view(3, n)
+        ctx.predict(0.0)
+        ctx.force(every, 0.0, with_pot=False, acc=acc)
+        ctx.a.copy_(acc)
+        checkpoints = []
+        for s in range(sched.K):
+            if s % era == 0:
+                checkpoints.append((s, ctx.r.clone(), ctx.v.clone(), ctx.a.clone(),
+                                    ctx.t_last.clone()))
+            _block_step(ctx, sched, s, buf)
+        fctx.tsbts = ctx
+        fctx.sched = sched
+        fctx.era = era
+        fctx.checkpoints = checkpoints
+        fctx.every = every
+        fctx.save_for_backward(m)
+        return ctx.r.clone(), ctx.v.clone()
+
+    @staticmethod
+    def backward(fctx, g_r, g_v):
+        ctx, sched, era = fctx.tsbts, fctx.sched, fctx.era
+        (m,) = fctx.saved_tensors
+        n = ctx.n
+        dev = ctx.device
+        z = lambda: torch.zeros((3, n), dtype=torch.float64, device=dev)  # noqa: E731
+        rbar = z() if g_r is None else g_r.contiguous().clone()
+        vbar = z() if g_v is None else g_v.contiguous().clone()
+        abar = z()
+        pbar = z()
+        mbar = torch.zeros(n, dtype=torch.float64, device=dev)
+        buf = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        seeds = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        first = fctx.checkpoints[0]
+        ctx.bind(first[1].clone(), first[2].clone(), m, a=first[3].clone(),
+                 t_last=first[4].clone(), dt=torch.tensor(sched.dt, dtype=torch.float64,
+                                                          device=dev))
+        state = (ctx.r, ctx.v, ctx.a, ctx.t_last)
+        for (s0, *ck) in reversed(fctx.checkpoints):
+            s1 = min(s0 + era, sched.K)
+            for dst, src in zip(state, ck):
+                dst.copy_(src)
+            pre = []
+            for s in range(s0, s1):
+                pre.append([x.clone() for x in state])
+                _block_step(ctx, sched, s, buf)
+            for s in range(s1 - 1, s0 - 1, -1):
+                for dst, src in zip(state, pre[s - s0]):
+                    dst.copy_(src)
+                tb = sched.time(s)
+                idx = sched.active(s)
+                k = idx.numel()
+                sd = seeds[:3 * k].view(3, k)
+                ctx.predict(tb)
+                ctx.block_adjoint(0, idx, tb, rbar, vbar, abar, pbar, sd)
+                ctx.force_backward(idx, tb, sd, None, pbar, mbar)
+                ctx.block_adjoint(1, None, tb, rbar, vbar, abar, pbar, None)
+        ctx.load_positions(first[1], m, 0.0)
+        ctx.force_backward(fctx.every, 0.0, abar, None, rbar, mbar)   # through a_0
+        return rbar, vbar, mbar, None, None, None, None
+
+
+def tsbts_block_leapfrog(r0, v0, m, ctx: Context, dt, t_end: float, era: int = 16):
+    return TsbtsBlockLeapfrog.apply(r0, v0, m, ctx, dt, t_end, era)

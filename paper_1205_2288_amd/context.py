@@ -171,6 +171,20 @@ class Context:
     def leapfrog_adjoint(self, phase, h, rbar, vbar, abar, g_out=None, stream=None):
         L.tsbts_leapfrog_adjoint(self.ctx, self.n, phase, h, rbar, vbar, abar, g_out, stream)
 
+    def block_adjoint(self, phase, active, t_block, rbar, vbar, abar, pbar, seeds,
+                      stream=None):
+        """Reverse of one block step of a fixed schedule (tsbts_block_adjoint); phase 1
+        needs neither the active set nor the seeds (pass None)."""
+        if active is None:
+            idx = None
+        elif isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+                and active.device.type == "cuda":
+            idx = active
+        else:
+            idx = self.idx(active)
+        L.tsbts_block_adjoint(self.ctx, self.n, phase, idx, t_block, rbar, vbar, abar, pbar,
+                              seeds, stream)
+
     # ---------------------------------------------------------------- lifetime
     def close(self):
         if getattr(self, "ctx", None) is not None:

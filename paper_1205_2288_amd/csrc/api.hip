@@ -448,4 +448,22 @@ int tsbts_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar
   return TSBTS_OK;
 }
 
+int tsbts_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int32_t n_act,
+                        double t_block, double *rbar, double *vbar, double *abar,
+                        double *pbar, double *seeds, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (phase != 0 && phase != 1) return fail(c, TSBTS_EINVAL, "phase must be 0 or 1");
+  if (!rbar || !vbar || !abar || !pbar)
+    return fail(c, TSBTS_EINVAL, "tsbts_block_adjoint: NULL array");
+  if (phase == 0) {
+    if (int s = check_active(c, idx, n_act)) return s;
+    if (!seeds) return fail(c, TSBTS_EINVAL, "seeds is NULL");
+  }
+  hipError_t e = launch_block_adjoint(c, phase, idx, n_act, t_block, rbar, vbar, abar, pbar,
+                                      seeds, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_block_adjoint launch");
+  return TSBTS_OK;
+}
+
 }  // extern "C"

@@ -194,6 +194,59 @@ __global__ __launch_bounds__(kWG) void k_lf_adjoint(int64_t len, int phase, doub
   }
 }
 
+// Reverse of one block step of a fixed block schedule.  Forward (Section 2, one pass):
+//   p_j = r_j + h_j v_j + h_j^2 a_j / 2 for every j, h_j = t_block - t_last_j;
+//   an_i = F_i(p) for i in the active set A;
+//   r_i <- p_i, v_i <- v_i + dt_i (a_i + an_i) / 2, a_i <- an_i for i in A.
+// Phase 0 (active set): seed_i = abar_i + dt_i vbar_i / 2 (the adjoint of an_i);
+// pbar_i = rbar_i (r_i' = p_i); abar_i = dt_i vbar_i / 2; rbar_i = 0.  pbar is zero
+// elsewhere (cleared by k_fill first).  Phase 1 (every particle, after the force adjoint
+// has added dL/dp into pbar): rbar += pbar, vbar += h pbar, abar += h^2 pbar / 2.
+__global__ __launch_bounds__(kWG) void k_fill(int64_t len, double *x, double v) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (e < len) x[e] = v;
+}
+
+struct BlockAdjArgs {
+  int64_t n;
+  const int32_t *idx;
+  int n_act;
+  double t_block;
+  const double *dt, *t_last;
+  double *rbar, *vbar, *abar, *pbar, *seeds;
+};
+
+__global__ __launch_bounds__(kWG) void k_block_adj_active(BlockAdjArgs A) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= A.n_act) return;
+  const int64_t i = A.idx[q];
+  const double half = 0.5 * A.dt[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t e = c * A.n + i;
+    const double vb = A.vbar[e];
+    A.seeds[static_cast<int64_t>(c) * A.n_act + q] = A.abar[e] + half * vb;
+    A.pbar[e] = A.rbar[e];
+    A.abar[e] = half * vb;
+    A.rbar[e] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_block_adj_predict(BlockAdjArgs A) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (j >= A.n) return;
+  const double h = A.t_block - A.t_last[j];
+  const double h2 = 0.5 * h * h;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t e = c * A.n + j;
+    const double pb = A.pbar[e];
+    A.rbar[e] += pb;
+    A.vbar[e] += h * pb;
+    A.abar[e] += h2 * pb;
+  }
+}
+
 CorrectArgs base_args(tsbts_ctx *c) {
   CorrectArgs p;
   p.n = c->n;
@@ -272,6 +325,36 @@ hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const doub
   const int nb = static_cast<int>((len + kWG - 1) / kWG);
   hipLaunchKernelGGL(k_lf_adjoint, dim3(nb), dim3(kWG), 0, st, len, phase, h, rbar, vbar,
                      abar, g_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
+                                double t_block, double *rbar, double *vbar, double *abar,
+                                double *pbar, double *seeds, hipStream_t st) {
+  BlockAdjArgs A;
+  A.n = c->n;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.t_block = t_block;
+  A.dt = c->dt;
+  A.t_last = c->t_last;
+  A.rbar = rbar;
+  A.vbar = vbar;
+  A.abar = abar;
+  A.pbar = pbar;
+  A.seeds = seeds;
+  if (phase == 0) {
+    const int64_t len = 3 * c->n;
+    hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>((len + kWG - 1) / kWG)), dim3(kWG),
+                       0, st, len, pbar, 0.0);
+    if (n_act > 0)
+      hipLaunchKernelGGL(k_block_adj_active, dim3((n_act + kWG - 1) / kWG), dim3(kWG), 0, st,
+                         A);
+  } else {
+    hipLaunchKernelGGL(k_block_adj_predict,
+                       dim3(static_cast<unsigned>((c->n + kWG - 1) / kWG)), dim3(kWG), 0, st,
+                       A);
+  }
   return hipGetLastError();
 }
 

@@ -189,6 +189,9 @@ hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st);
 hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
                                    double *vbar, double *abar, double *g_out,
                                    hipStream_t st);
+hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
+                                double t_block, double *rbar, double *vbar, double *abar,
+                                double *pbar, double *seeds, hipStream_t st);
 
 // Free the native scheduler attached to a context (if any).
 void destroy_scheduler(tsbts_ctx *c);

@@ -12,6 +12,10 @@ import torch
 import oracle
 
 
+def _np(x):
+    return x.detach().cpu().numpy() if isinstance(x, torch.Tensor) else x
+
+
 class FakeContext:
     def __init__(self, n, eps):
         self.n = n
@@ -23,7 +27,7 @@ class FakeContext:
     # ------------------------------------------------------------------ plumbing
     def bind(self, r, v, m, a=None, t_last=None, dt=None):
         n = self.n
-        f = lambda x, shape: torch.as_tensor(np.array(x, dtype=np.float64)).reshape(shape)  # noqa
+        f = lambda x, shape: torch.as_tensor(np.array(_np(x), dtype=np.float64)).reshape(shape)  # noqa
         self.r = f(r, (3, n))
         self.v = f(v, (3, n))
         self.m = f(m, (n,))
@@ -89,6 +93,44 @@ class FakeContext:
         if self.recording:
             self.records.append((idx.copy(), np.full(idx.size, t_block), r[:, idx].copy(),
                                  v[:, idx].copy(), a[:, idx].copy()))
+
+    def load_positions(self, r, m=None, t_label=0.0):
+        self.pred_r = np.array(_np(r), dtype=np.float64).reshape(3, self.n)
+        if m is not None:
+            self.m = torch.as_tensor(np.array(_np(m), dtype=np.float64)).reshape(self.n)
+        self.pred_t = t_label
+
+    def force_backward(self, active, t_block, grad_acc, grad_pot=None, grad_r=None,
+                       grad_m=None):
+        assert t_block == self.pred_t
+        idx = np.asarray(active, dtype=np.int32)
+        gp = None if grad_pot is None else torch.as_tensor(grad_pot).numpy()
+        gr, gm = oracle.force_backward(self.pred_r, self.m.numpy(), self.eps, idx,
+                                       torch.as_tensor(grad_acc).numpy(), gp)
+        if grad_r is None:
+            grad_r = torch.zeros((3, self.n), dtype=torch.float64)
+        if grad_m is None:
+            grad_m = torch.zeros(self.n, dtype=torch.float64)
+        grad_r += torch.from_numpy(gr)
+        grad_m += torch.from_numpy(gm)
+        return grad_r, grad_m
+
+    def block_adjoint(self, phase, active, t_block, rbar, vbar, abar, pbar, seeds):
+        dt, tl = self.dt.numpy(), self.t_last.numpy()
+        rb, vb, ab, pb = (x.numpy() for x in (rbar, vbar, abar, pbar))
+        if phase == 0:
+            idx = np.asarray(active, dtype=np.int64)
+            half = 0.5 * dt[idx]
+            seeds.numpy()[...] = ab[:, idx] + half * vb[:, idx]
+            pb[...] = 0.0
+            pb[:, idx] = rb[:, idx]
+            ab[:, idx] = half * vb[:, idx]
+            rb[:, idx] = 0.0
+        else:
+            h = t_block - tl
+            rb += pb
+            vb += h * pb
+            ab += 0.5 * h * h * pb
 
     def timestep(self, active, eta, dtc=None):
         idx = np.asarray(active, dtype=np.int32)

@@ -107,3 +107,146 @@ def test_adjoint8192_gradients_vs_finite_differences(prec):
             print(f"{prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} rel {rel:.2e}")
     assert worst <= 1e-5
     ref_ctx.close()
+
+
+# ---------------------------------------------------------------- fixed block schedule
+def _levels(n, h, seed, nlev=3):
+    rng = np.random.default_rng(seed)
+    return h * 2.0 ** rng.integers(0, nlev, size=n)
+
+
+def _block_grads(prec, r0, v0, m, eps, dt, t_end, era, rt, vt):
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_block_leapfrog
+    ctx = Context(m.size, eps, precision=prec)
+    r, v, mm = _t(r0, True), _t(v0, True), _t(m, True)
+    r_end, v_end = tsbts_block_leapfrog(r, v, mm, ctx, dt, t_end, era)
+    loss = ((r_end - _t(rt)) ** 2).sum() + ((v_end - _t(vt)) ** 2).sum()
+    loss.backward()
+    out = (float(loss.detach()), r.grad.cpu().numpy(), v.grad.cpu().numpy(),
+           mm.grad.cpu().numpy())
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("era", [5, 64])
+def test_block_leapfrog_gradient_matches_oracle(prec, era):
+    # 600 particles (two full 256-tiles and a ragged one), steps h, 2h, 4h, 16 block steps
+    n, eps, h = 600, 1 / 64, 1 / 128
+    t_end = 16 * h
+    r0, v0, m = plummer(n, 63, masses="loguniform")
+    dt = _levels(n, h, 8)
+    rt, vt, _ = oadj.block_forward(r0, v0, m, eps, dt, t_end)
+    rt = rt + 0.01 * gaussian((3, n), 21)
+    vt = vt + 0.01 * gaussian((3, n), 22)
+    Lr, rr, rv, rm = oadj.block_gradient(r0, v0, m, eps, dt, t_end, rt, vt)
+    L, gr, gv, gm = _block_grads(prec, r0, v0, m, eps, dt, t_end, era, rt, vt)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert L == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
+    for got, ref in ((gr, rr), (gv, rv), (gm, rm)):
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+
+
+def test_block_adjoint_phases_elementwise():
+    # the two element-wise phases against their definitions, on random adjoints
+    from paper_1205_2288_amd import Context
+    n, tb = 777, 0.75
+    r, v, m = plummer(n, 64)
+    rng = np.random.default_rng(3)
+    dt = 2.0 ** -rng.integers(2, 5, size=n)
+    t_last = tb - dt * rng.integers(0, 2, size=n) - dt * (rng.random(n) < 0.5) * 0.5
+    idx_np = np.sort(rng.choice(n, 123, replace=False)).astype(np.int32)
+    ctx = Context(n, 0.01, precision="fp64")
+    ctx.bind(r, v, m, t_last=t_last, dt=dt)
+    rb, vb, ab = (gaussian((3, n), 40 + k) for k in range(3))
+    R, V, A = _t(rb), _t(vb), _t(ab)
+    P = _t(gaussian((3, n), 50))          # garbage: phase 0 must clear it
+    S = torch.empty((3, idx_np.size), dtype=torch.float64, device="cuda")
+    ctx.block_adjoint(0, idx_np, tb, R, V, A, P, S)
+    torch.cuda.synchronize()
+    i = idx_np.astype(np.int64)
+    half = 0.5 * dt[i]
+    p_ref = np.zeros((3, n))
+    p_ref[:, i] = rb[:, i]
+    a_ref, r_ref = ab.copy(), rb.copy()
+    a_ref[:, i] = half * vb[:, i]
+    r_ref[:, i] = 0.0
+    assert np.allclose(S.cpu().numpy(), ab[:, i] + half * vb[:, i], rtol=0, atol=1e-15)
+    assert np.array_equal(P.cpu().numpy(), p_ref)
+    assert np.array_equal(A.cpu().numpy(), a_ref)
+    assert np.array_equal(R.cpu().numpy(), r_ref)
+    assert np.array_equal(V.cpu().numpy(), vb)
+    pb = gaussian((3, n), 60)
+    P.copy_(_t(pb))
+    ctx.block_adjoint(1, None, tb, R, V, A, P, None)
+    torch.cuda.synchronize()
+    hh = tb - t_last
+    assert np.array_equal(R.cpu().numpy(), r_ref + pb)
+    assert np.allclose(V.cpu().numpy(), vb + hh * pb, rtol=0, atol=1e-15)
+    assert np.allclose(A.cpu().numpy(), a_ref + 0.5 * hh * hh * pb, rtol=0, atol=1e-15)
+    ctx.close()
+
+
+def test_block_adjoint_bad_arguments():
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd._lib import TsbtsError, TSBTS_EINVAL
+    n = 50
+    r, v, m = plummer(n, 65)
+    ctx = Context(n, 0.01, precision="fp64")
+    ctx.bind(r, v, m, dt=np.full(n, 0.25))
+    z = lambda: torch.zeros((3, n), dtype=torch.float64, device="cuda")  # noqa: E731
+    R, V, A, P = z(), z(), z(), z()
+    with pytest.raises(TsbtsError) as e:
+        ctx.block_adjoint(2, None, 0.25, R, V, A, P, None)
+    assert e.value.status == TSBTS_EINVAL
+    with pytest.raises(TsbtsError) as e:
+        ctx.block_adjoint(0, None, 0.25, R, V, A, P, None)   # phase 0 needs the active set
+    assert e.value.status == TSBTS_EINVAL
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adjoint8192_block_schedule_vs_finite_differences(prec):
+    # the N=8192 workload on a three-level block schedule (h, 2h, 4h with h = 2^-8, 32
+    # block steps, checkpoints every 8): adjoint directional derivatives against central
+    # differences of the float64 GPU forward
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_block_leapfrog
+    cfg = config("adjoint8192")
+    n, eps, h = cfg.n, cfg.eps, 1 / 256
+    t_end, era = 32 * h, 8
+    r0, v0, m = cfg.ic()
+    dt = _levels(n, h, cfg.seed + 3)
+    ref = Context(n, eps, precision="fp64")
+
+    def fwd(rr, vv, mm):
+        with torch.no_grad():
+            return tsbts_block_leapfrog(_t(rr), _t(vv), _t(mm), ref, dt, t_end, 1 << 30)
+
+    r_fin, v_fin = fwd(r0, v0, m)
+    rt = r_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 8)
+    vt = v_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 9)
+
+    def loss(rr, vv, mm):
+        r_e, v_e = fwd(rr, vv, mm)
+        return float(((r_e - _t(rt)) ** 2).sum() + ((v_e - _t(vt)) ** 2).sum())
+
+    L, gr, gv, gm = _block_grads(prec, r0, v0, m, eps, dt, t_end, era, rt, vt)
+    step = 1e-6
+    worst = 0.0
+    for trial in range(2):
+        for which, g in (("r", gr), ("v", gv), ("m", gm)):
+            d = gaussian((3, n) if which != "m" else n, 950 + 10 * trial + len(which))
+            if which == "m":
+                d = d * m
+            def f(sgn):
+                return loss(r0 + sgn * step * d if which == "r" else r0,
+                            v0 + sgn * step * d if which == "v" else v0,
+                            m + sgn * step * d if which == "m" else m)
+            fd = (f(1) - f(-1)) / (2 * step)
+            rel = abs((g * d).sum() - fd) / abs(fd)
+            worst = max(worst, rel)
+            print(f"block {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} rel {rel:.2e}")
+    assert worst <= 1e-5
+    ref.close()
