@@ -196,7 +196,8 @@ def cpu_baseline(cfg, r, v, m, gpu_force_rows, target_s=12.0):
     import oracle
     n = cfg.n
     g = gaussian((3, n), cfg.seed + 7)
-    probe = np.arange(0, n, n // 64, dtype=np.int32)[:64]
+    # a probe large enough that thread start-up does not dominate its time
+    probe = np.arange(0, n, max(1, n // 1024), dtype=np.int32)[:1024]
     t0 = time.perf_counter()
     oracle.force(r, m, cfg.eps, probe)
     oracle.force_backward(r, m, cfg.eps, probe, g[:, probe])
