@@ -53,13 +53,13 @@ FLOPS_CRITERION = 20.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep": (153954.8, 65536.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
-                   "005451da9bedab7c"),
-    "k_force": (79676.0, 131072.0, ("force.hip", "pair.hpp", "internal.hpp"),
-                "cd5234b0a47c7eef"),
-    "k_bwd_all": (65044.3, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
-                  "66e90fe4d1f060a9"),
-    "k_energy_pairs": (23432.3, 4104.0, ("energy.hip", "internal.hpp"), "c7d943fafe6e5381"),
+    "k_timestep_scalar": (313264.5, 131072.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
+                          "8bc23251c01bb28d"),
+    "k_force_scalar": (40234.3, 65536.0, ("force.hip", "pair.hpp", "internal.hpp"),
+                       "23a897bdc9b82ef2"),
+    "k_bwd_all": (65047.9, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
+                  "a9e367996310b5fe"),
+    "k_energy_pairs": (23384.0, 4104.0, ("energy.hip", "internal.hpp"), "d87f03f843ecb1c5"),
 }
 
 
@@ -260,12 +260,14 @@ def rooflines(ms, n, precision="mixed"):
                 "total_ms": t * 1e3}
 
     nf, nh = len(ms["force_full"]), len(ms["force_half"])
-    out["k_force"] = entry("k_force", FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
-                           ms["force_full"] + ms["force_half"], peak32)
+    out["k_force_scalar"] = entry("k_force_scalar",
+                                  FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
+                                  ms["force_full"] + ms["force_half"], peak32)
     # the criterion kernel's calls alternate half / full active sets
     nts = len(ms["timestep"])
-    out["k_timestep"] = entry("k_timestep", FLOPS_CRITERION * n * (nts // 2) * (n + n // 2),
-                              ms["timestep"], peak32)
+    out["k_timestep_scalar"] = entry("k_timestep_scalar",
+                                     FLOPS_CRITERION * n * (nts // 2) * (n + n // 2),
+                                     ms["timestep"], peak32)
     out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * len(ms["backward"]),
                              ms["backward"], peak32)
     out["k_energy_pairs"] = entry("k_energy_pairs",

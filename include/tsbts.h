@@ -75,8 +75,10 @@ int tsbts_destroy(tsbts_ctx *ctx);
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
  *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
- *   TSBTS_TUNE_IPL:    target particles per lane for large active sets in the force and
- *                      criterion kernels (0 = automatic, 1, 2 or 4)
+ *   TSBTS_TUNE_IPL:    kernel form of the force and criterion (0 = automatic: the force,
+ *                      and the criterion from 8192 targets, read the j-particles through
+ *                      wave-uniform scalar loads; 1, 2 or 4 = the LDS-staged kernels with
+ *                      that many target particles per lane)
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);

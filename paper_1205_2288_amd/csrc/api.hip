@@ -297,8 +297,7 @@ int tsbts_load_positions(tsbts_ctx *c, const double *r, const double *m, double 
                          hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (!r || !m) return fail(c, TSBTS_EINVAL, "tsbts_load_positions: NULL array");
-  // velocities are zeroed so that tsbts_timestep sees a defined state
-  TSBTS_CHECK_HIP(c, hipMemsetAsync(c->v64, 0, 3 * c->npad * sizeof(double), stream));
+  // the kernel also zeroes the velocity planes, so tsbts_timestep sees a defined state
   hipError_t e = launch_load_positions(c, r, m, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_load_positions launch");
   c->pred_t = t_label;

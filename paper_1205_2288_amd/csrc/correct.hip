@@ -22,6 +22,7 @@ struct CorrectArgs {
   const double *acc_new;
   const double *p64;
   double *v64;
+  float *p32;  // mixed precision: float32 velocity planes refreshed too (else null)
   double *r, *v, *a, *t_last;
   int record;
   int64_t base;    // first free record slot
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(kWG) void k_correct(CorrectArgs p) {
     p.v[c * n + g] = vn;
     p.a[c * n + g] = an;
     p.v64[c * P + g] = vn;
+    if (p.p32) p.p32[(P32_VX + c) * P + g] = static_cast<float>(vn);
     st[c] = rn;
     st[c + 3] = vn;
     st[c + 6] = an;
@@ -253,6 +255,7 @@ CorrectArgs base_args(tsbts_ctx *c) {
   p.npad = c->npad;
   p.p64 = c->p64;
   p.v64 = c->v64;
+  p.p32 = c->precision == TSBTS_MIXED ? c->p32 : nullptr;
   p.r = c->r;
   p.v = c->v;
   p.a = c->a;

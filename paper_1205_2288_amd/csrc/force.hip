@@ -19,6 +19,7 @@
 // those tiles and the unmasked one elsewhere, so the mask costs nothing on almost every
 // tile and no large self term ever enters a float32 accumulator.
 #include "pair.hpp"
+#include <algorithm>
 #include <type_traits>
 
 namespace tsbts {
@@ -39,6 +40,7 @@ struct ForceArgs {
   double *pot;   // [n_act] or null
   int blocks;    // workgroups a split launch aims for
   int ipl;       // targets per lane
+  int scalar_j;  // j-particles through scalar loads (k_force_scalar)
 };
 
 // ----- pair contributions -------------------------------------------------------------
@@ -185,6 +187,61 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   }
 }
 
+// j-particles through scalar loads: the j index is the same on every lane, so the loads
+// of the j record from the predicted arrays are wave-uniform and become scalar loads; the
+// record then sits in SGPRs and the pair arithmetic takes it as scalar operands.  No LDS
+// staging and no barriers; one target per lane.  Same tiles of kTJ j-particles, same
+// self-pair vote and the same float32-in-tile / float64-across-tiles sums as k_force.
+template <class V, int NEWTON, int MASK, int POT, class F>
+__device__ __forceinline__ void scalar_tile(const ForceArgs &A, const typename V::I &I, int g,
+                                            int64_t jbase, F eps2, F &fx, F &fy, F &fz,
+                                            F &fp) {
+#pragma unroll 8
+  for (int jj = 0; jj < kTJ; ++jj) {
+    const typename V::J J =
+        V::load_j(A.p32, A.p64, A.npad, jbase + jj, Scale<V, NEWTON>::kMass);
+    pair_acc<V, NEWTON, MASK, POT>(I, J, eps2, MASK && (jbase + jj == g), fx, fy, fz, fp);
+  }
+}
+
+template <class V, int NEWTON, int POT>
+__global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
+  using F = typename V::F;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int itile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
+  const int q = itile * kWG + static_cast<int>(threadIdx.x);
+  const int g = A.idx[min(q, A.n_act - 1)];
+  const typename V::I I = V::load_i(A.p32, A.p64, A.npad, g);
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    F fx = F(0), fy = F(0), fz = F(0), fp = F(0);
+    if (__ballot(g >= jbase && g < jbase + kTJ) != 0)
+      scalar_tile<V, NEWTON, 1, POT>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+    else
+      scalar_tile<V, NEWTON, 0, POT>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+    sx += static_cast<double>(fx);
+    sy += static_cast<double>(fy);
+    sz += static_cast<double>(fz);
+    sp += static_cast<double>(fp);
+  }
+  if (q >= A.n_act) return;
+  if (A.plan.n_slices == 1) {
+    finish<V, NEWTON>(A, q, g, sx, sy, sz, sp);
+  } else {
+    double *out = A.part + static_cast<int64_t>(slice) * 4 * A.n_act;
+    out[q] = sx;
+    out[A.n_act + q] = sy;
+    out[2 * A.n_act + q] = sz;
+    out[3 * A.n_act + q] = sp;
+  }
+}
+
 // Small active sets (n_act <= kSmallAct): one 256-particle j-tile per workgroup, one
 // source per lane, the targets broadcast from LDS; each pair is summed over the wave and
 // the 4 waves in a fixed order into one float64 partial per tile and target, which the
@@ -277,6 +334,28 @@ __global__ __launch_bounds__(kWG) void k_force_reduce_wave(ForceArgs A) {
   if (lane == 0) finish<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp);
 }
 
+template <class V, int NEWTON>
+hipError_t launch_reduce(ForceArgs &A, hipStream_t st) {
+  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+    hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  } else if (A.plan.n_slices > 1) {
+    const int nb = (A.n_act + kWG - 1) / kWG;
+    hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+template <class V, int NEWTON>
+hipError_t run_scalar(ForceArgs &A, hipStream_t st) {
+  A.plan = plan_split(A.n_act, 1, A.n_jtiles, A.blocks);
+  if (A.pot)
+    hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 0>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  return launch_reduce<V, NEWTON>(A, st);
+}
+
 template <class V, int NEWTON, int IPL>
 hipError_t run(ForceArgs &A, hipStream_t st) {
   A.plan = plan_split(A.n_act, IPL, A.n_jtiles, A.blocks);
@@ -317,6 +396,7 @@ hipError_t pick_ipl(ForceArgs &A, hipStream_t st) {
   // beyond 16 targets cost more than the target-parallel kernel saves
   const int small = std::is_same<V, Fp64>::value ? kSmallActFp64 : kSmallAct;
   if (A.n_act <= small) return run_small<V, NEWTON>(A, st);
+  if (A.scalar_j) return run_scalar<V, NEWTON>(A, st);
   if (A.ipl == 4) return run<V, NEWTON, 4>(A, st);
   if (A.ipl == 2) return run<V, NEWTON, 2>(A, st);
   return run<V, NEWTON, 1>(A, st);
@@ -341,9 +421,14 @@ int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
   // small sets: one partial per j-tile; the criterion uses the same plans with 2 values
   // per target instead of 4
   if (n_act <= kSmallAct) return n_jtiles * 4 * n_act;
-  const SplitPlan p = plan_split(n_act, targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
-  int64_t need = p.n_slices > 1 ? static_cast<int64_t>(p.n_slices) * 4 * n_act : 0;
-  return need;
+  const SplitPlan pf =
+      plan_split(n_act, force_targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
+  const SplitPlan pc =
+      plan_split(n_act, criterion_targets_per_lane(c, n_act), n_jtiles,
+                 criterion_blocks(c, n_act));
+  const int64_t need_f = pf.n_slices > 1 ? static_cast<int64_t>(pf.n_slices) * 4 * n_act : 0;
+  const int64_t need_c = pc.n_slices > 1 ? static_cast<int64_t>(pc.n_slices) * 2 * n_act : 0;
+  return std::max(need_f, need_c);
 }
 
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
@@ -361,7 +446,8 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   A.acc = acc;
   A.pot = pot;
   A.blocks = c->tune_blocks;
-  A.ipl = targets_per_lane(c, n_act);
+  A.ipl = force_targets_per_lane(c, n_act);
+  A.scalar_j = force_scalar_j(c) ? 1 : 0;
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;

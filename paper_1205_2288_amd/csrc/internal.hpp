@@ -20,7 +20,7 @@ constexpr double kFar = 1.0e18;
 //   v64: [3][npad] float64: velocities at the predicted time
 //   p32: [8][npad] float32: x_hi, y_hi, z_hi, m, x_lo, y_lo, z_lo, w = m^(-2/3)
 enum { P64_X = 0, P64_M = 3, P64_W = 4, P64_PLANES = 5 };
-enum { P32_XH = 0, P32_M = 3, P32_XL = 4, P32_W = 7, P32_PLANES = 8 };
+enum { P32_XH = 0, P32_M = 3, P32_XL = 4, P32_W = 7, P32_VX = 8, P32_E = 11, P32_PLANES = 12 };
 // History record state planes: r(3), v(3), a(3)
 constexpr int kHistPlanes = 9;
 
@@ -158,8 +158,27 @@ SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_bl
 
 // Targets per lane of the force and criterion kernels for an active set of n_act.
 inline int targets_per_lane(const tsbts_ctx *c, int n_act) {
-  if (n_act < 8192) return 1;
-  return c->tune_ipl ? c->tune_ipl : 2;
+  if (c->tune_ipl) return c->tune_ipl;
+  return n_act < 8192 ? 1 : 2;
+}
+
+// The force kernel reads its j-particles through wave-uniform (scalar) loads unless a
+// targets-per-lane count was set, which selects the LDS-staged kernel.
+inline bool force_scalar_j(const tsbts_ctx *c) { return c->tune_ipl == 0; }
+inline int force_targets_per_lane(const tsbts_ctx *c, int n_act) {
+  return force_scalar_j(c) ? 1 : targets_per_lane(c, n_act);
+}
+// The criterion kernel likewise for large active sets (from 8192 targets; below that the
+// LDS-staged kernel with one target per lane measured faster); its scalar-load form holds
+// two targets per lane and is launched on twice the workgroups.
+inline bool criterion_scalar_j(const tsbts_ctx *c, int n_act) {
+  return force_scalar_j(c) && n_act >= 8192;
+}
+inline int criterion_targets_per_lane(const tsbts_ctx *c, int n_act) {
+  return criterion_scalar_j(c, n_act) ? 2 : targets_per_lane(c, n_act);
+}
+inline int criterion_blocks(const tsbts_ctx *c, int n_act) {
+  return criterion_scalar_j(c, n_act) ? 2 * c->tune_blocks : c->tune_blocks;
 }
 
 // ------------------------------------------------------------------ launchers

@@ -5,7 +5,7 @@
 // One thread per particle; float64 structure-of-arrays loads and stores, all coalesced.
 // Bandwidth-bound: per particle, Taylor reads r, v, a, t_last, dt, m (88 B) and writes the
 // float64 position/mass/weight planes (40 B), float64 velocities (24 B) and, in mixed
-// precision, the float32 hi/lo planes (32 B).
+// precision, the float32 hi/lo, mass, weight, velocity and eps^2-weight planes (48 B).
 #include "internal.hpp"
 
 namespace tsbts {
@@ -14,8 +14,9 @@ namespace {
 struct Out {
   double *p64;  // [5][npad]
   double *v64;  // [3][npad]
-  float *p32;   // [8][npad] or null
+  float *p32;   // [12][npad] or null
   int64_t npad;
+  double eps2;
 };
 
 __device__ __forceinline__ void store_particle(const Out &o, int64_t j, double x, double y,
@@ -44,6 +45,11 @@ __device__ __forceinline__ void store_particle(const Out &o, int64_t j, double x
     o.p32[(P32_XL + 2) * P + j] = l;
     o.p32[P32_M * P + j] = static_cast<float>(m);
     o.p32[P32_W * P + j] = static_cast<float>(w);
+    o.p32[(P32_VX + 0) * P + j] = static_cast<float>(vx);
+    o.p32[(P32_VX + 1) * P + j] = static_cast<float>(vy);
+    o.p32[(P32_VX + 2) * P + j] = static_cast<float>(vz);
+    // criterion term eps^2 m^(-2/3) (0 when eps = 0, where a massless weight is infinite)
+    o.p32[P32_E * P + j] = o.eps2 > 0.0 ? static_cast<float>(o.eps2 * w) : 0.0f;
   }
 }
 
@@ -215,6 +221,7 @@ Out make_out(tsbts_ctx *c) {
   o.v64 = c->v64;
   o.p32 = c->precision == TSBTS_MIXED ? c->p32 : nullptr;
   o.npad = c->npad;
+  o.eps2 = c->eps * c->eps;
   return o;
 }
 

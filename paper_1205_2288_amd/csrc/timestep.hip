@@ -27,6 +27,7 @@ struct StepArgs {
   double *dtc;
   int blocks;
   int ipl;
+  int scalar_j;  // j-particles through scalar loads (k_timestep_scalar)
 };
 
 template <class V> struct StepRec;
@@ -50,11 +51,10 @@ __device__ __forceinline__ typename StepRec<V>::J load_jv(const StepArgs &A, int
   const int64_t P = A.npad;
   r.p = V::load_j(A.p32, A.p64, P, j, 1.0f);
   if constexpr (sizeof(typename V::F) == 4) {
-    // the fourth lane carries eps^2 m_j^(-2/3), so s m_j^(-2/3) is one fma per pair (0
-    // when eps = 0, where the weight of a massless particle is infinite)
-    r.v = make_float4(static_cast<float>(A.v64[j]), static_cast<float>(A.v64[P + j]),
-                      static_cast<float>(A.v64[2 * P + j]),
-                      A.eps2 > 0.0 ? static_cast<float>(A.eps2) * V::weight(r.p) : 0.0f);
+    // float32 velocities, and in the fourth lane eps^2 m_j^(-2/3) so that s m_j^(-2/3) is
+    // one fma per pair (both planes written by the predictor)
+    r.v = make_float4(A.p32[(P32_VX + 0) * P + j], A.p32[(P32_VX + 1) * P + j],
+                      A.p32[(P32_VX + 2) * P + j], A.p32[P32_E * P + j]);
   } else {
     r.vx = A.v64[j];
     r.vy = A.v64[P + j];
@@ -203,6 +203,66 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
   }
 }
 
+// j-particles through scalar loads (wave-uniform j index): the j record comes straight
+// from the predicted planes into SGPRs, no LDS staging and no barriers.  Same tiles, vote
+// and partials as k_timestep.
+template <class V, int MASK, int IPL, class I, class F>
+__device__ __forceinline__ void scalar_step_tile(const StepArgs &A, const I *Ir, const int *g,
+                                                 int64_t jbase, F eps2, F *qmax, F *swmin) {
+#pragma unroll 4
+  for (int jj = 0; jj < kTJ; ++jj) {
+    const typename StepRec<V>::J Jr = load_jv<V>(A, jbase + jj);
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k]), qmax[k], swmin[k]);
+  }
+}
+
+template <class V, int IPL>
+__global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
+  using F = typename V::F;
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int itile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
+  const F eps2 = static_cast<F>(A.eps2);
+  typename StepRec<V>::I I[IPL];
+  int q[IPL], g[IPL];
+  F qmax[IPL], swmin[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    q[k] = (itile * IPL + k) * kWG + tid;
+    g[k] = A.idx[min(q[k], A.n_act - 1)];
+    I[k] = load_iv<V>(A, g[k]);
+    qmax[k] = F(0);
+    swmin[k] = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
+  }
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    bool mine = false;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
+    if (__ballot(mine) != 0)
+      scalar_step_tile<V, 1, IPL>(A, I, g, jbase, eps2, qmax, swmin);
+    else
+      scalar_step_tile<V, 0, IPL>(A, I, g, jbase, eps2, qmax, swmin);
+  }
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    if (q[k] >= A.n_act) continue;
+    if (A.plan.n_slices == 1) {
+      A.dtc[q[k]] = finish_dt(A.eta, qmax[k], swmin[k]);
+    } else {
+      double *out = A.part + static_cast<int64_t>(slice) * 2 * A.n_act;
+      out[q[k]] = qmax[k];
+      out[A.n_act + q[k]] = swmin[k];
+    }
+  }
+}
+
 // Small active sets: one j-tile per workgroup, one source per lane, targets from LDS;
 // wave-level max / min, then the 4 waves, into one partial per tile and target.
 template <class F>
@@ -292,6 +352,9 @@ hipError_t run(StepArgs &A, hipStream_t st) {
     A.plan.tiles_per_slice = 1;
     A.plan.nblk = A.n_jtiles;
     hipLaunchKernelGGL((k_timestep_small<V>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
+  } else if (A.scalar_j) {
+    A.plan = plan_split(A.n_act, 2, A.n_jtiles, A.blocks);
+    hipLaunchKernelGGL((k_timestep_scalar<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   } else {
     A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
     if (A.ipl == 4)
@@ -327,8 +390,9 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.eta = eta;
   A.part = c->part;
   A.dtc = dtc;
-  A.blocks = c->tune_blocks;
-  A.ipl = targets_per_lane(c, n_act);
+  A.blocks = criterion_blocks(c, n_act);
+  A.ipl = criterion_targets_per_lane(c, n_act);
+  A.scalar_j = criterion_scalar_j(c, n_act) ? 1 : 0;
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);

@@ -137,3 +137,43 @@ def test_force_out_of_order_and_bad_arguments():
         ctx.force(np.arange(n + 1, dtype=np.int32) % n, 0.25)  # more targets than particles
     assert e.value.status == TSBTS_EINVAL
     ctx.close()
+
+
+SHAPES = [(8192, 0), (64, 0), (65536, 0), (8192, 1), (8192, 2), (8192, 4), (512, 2),
+          (65536, 4)]
+
+
+@pytest.mark.parametrize("prec,sep", [("mixed", "f64"), ("mixed", "hilo"), ("fp64", "f64")])
+def test_launch_shapes_agree(prec, sep):
+    # every launch shape (scalar-load kernel with 64..65536 workgroups, LDS kernels with
+    # 1, 2, 4 targets per lane) against the oracle, and against the default shape up to
+    # the order of the float64 tile sums
+    n = 9000
+    r, v, m = plummer(n, 71, masses="loguniform")
+    ctx = make_ctx(n, 1 / 256, prec, sep)
+    sets = [np.arange(n, dtype=np.int32), active_subset(n, 8500, 1), active_subset(n, 300, 2),
+            active_subset(n, 33, 3)]
+    base = [_run(ctx, r, v, m, idx) for idx in sets]
+    refs = [oracle.force(r, m, 1 / 256, idx) for idx in sets]
+    for blocks, ipl in SHAPES:
+        ctx.tune(blocks=blocks, ipl=ipl)
+        for idx, (a0, p0), (ar, pr) in zip(sets, base, refs):
+            acc, pot = _run(ctx, r, v, m, idx)
+            ea = summary(rel_err_vec(acc, ar))
+            assert ea["median"] <= TOL[prec]["median"] and ea["max"] <= TOL[prec]["max"], \
+                (blocks, ipl, idx.size, ea)
+            ep = summary(rel_err(pot, pr))
+            assert ep["max"] <= TOL[prec]["max"], (blocks, ipl, idx.size, ep)
+            same = 1e-12 if prec == "fp64" else 1e-6
+            assert rel_err_vec(acc, a0).max() <= same, (blocks, ipl, idx.size)
+    ctx.close()
+
+
+def test_tune_rejects_bad_values():
+    from paper_1205_2288_amd._lib import TsbtsError, TSBTS_EINVAL
+    ctx = make_ctx(100, 0.01, "mixed")
+    for kw in ({"blocks": 63}, {"blocks": 65537}, {"ipl": 3}, {"ipl": -1}, {"ipl": 8}):
+        with pytest.raises(TsbtsError) as e:
+            ctx.tune(**kw)
+        assert e.value.status == TSBTS_EINVAL
+    ctx.close()

@@ -28,6 +28,30 @@ def test_timestep_matches_oracle(prec, sep, n, n_act):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_timestep_and_adjoint_launch_shapes(prec):
+    # criterion and force adjoint under every launch shape against the oracle
+    n, eps, eta = 9000, 1 / 256, 0.1
+    r, v, m = plummer(n, 72, masses="loguniform")
+    ctx = make_ctx(n, eps, prec)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    sets = [np.arange(n, dtype=np.int32), active_subset(n, 8500, 4), active_subset(n, 300, 5)]
+    for blocks, ipl in [(8192, 0), (64, 0), (65536, 0), (8192, 1), (8192, 2), (8192, 4)]:
+        ctx.tune(blocks=blocks, ipl=ipl)
+        for idx in sets:
+            dtc = ctx.timestep(idx, eta).cpu().numpy()
+            e = rel_err(dtc, oracle.timestep(r, v, m, eps, eta, idx))
+            assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), (blocks, ipl, idx.size)
+            g = gaussian((3, idx.size), 9)
+            gr, gm = ctx.force_backward(idx, 0.0, g)
+            rr, rm = oracle.force_backward(r, m, eps, idx, g)
+            tol = 1e-11 if prec == "fp64" else 2e-5
+            assert np.linalg.norm(gr.cpu().numpy() - rr) <= tol * np.linalg.norm(rr)
+            assert np.linalg.norm(gm.cpu().numpy() - rm) <= tol * np.linalg.norm(rm)
+    ctx.close()
+
+
 def test_timestep_three_body_by_hand():
     # particle 0 at rest, 1 at (1,0,0) moving (-2,0,0) with mass 1/4, 2 at (0,3,0), mass 1
     r = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 3.0], [0.0, 0.0, 0.0]])
