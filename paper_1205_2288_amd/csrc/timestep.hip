@@ -6,13 +6,16 @@
 // root and the 3/4 power are taken once per target.  No transcendental per pair in
 // float64 mode apart from the division; mixed mode uses the float32 reciprocal.
 // Same tiling and split-j scheme as the force kernel; the self pair is masked by index
-// in the tiles that hold some lane's own particle (wave-uniform vote), as in the force.
+// in the tiles that hold some lane's own particle (wave-uniform vote), as in the force,
+// and so are the padding particles of the last tile (at rest far away they would add a
+// tiny nonzero v^2/r^2, which matters when every real relative velocity is zero).
 #include "pair.hpp"
 
 namespace tsbts {
 namespace {
 
 struct StepArgs {
+  int64_t n;  // particles; j >= n are padding, excluded like the self pair
   const float *p32;
   const double *p64;
   const double *v64;
@@ -141,13 +144,14 @@ __device__ __forceinline__ double finish_dt(double eta, double qmax, double swmi
 
 template <class V, int MASK, int IPL, class J, class I, class F>
 __device__ __forceinline__ void step_tile(const J *sj, const I *Ir, const int *g, int64_t jbase,
-                                          F eps2, F *qmax, F *swmin) {
+                                          int64_t n, F eps2, F *qmax, F *swmin) {
 #pragma unroll 2
   for (int jj = 0; jj < kTJ; ++jj) {
     const J Jr = sj[jj];
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
-      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k]), qmax[k], swmin[k]);
+      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k] || jbase + jj >= n), qmax[k],
+                swmin[k]);
   }
 }
 
@@ -185,10 +189,10 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
     bool mine = false;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
-    if (__ballot(mine) != 0)
-      step_tile<V, 1, IPL>(sj, I, g, jbase, eps2, qmax, swmin);
+    if (__ballot(mine) != 0 || jbase + kTJ > A.n)
+      step_tile<V, 1, IPL>(sj, I, g, jbase, A.n, eps2, qmax, swmin);
     else
-      step_tile<V, 0, IPL>(sj, I, g, jbase, eps2, qmax, swmin);
+      step_tile<V, 0, IPL>(sj, I, g, jbase, A.n, eps2, qmax, swmin);
   }
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
@@ -214,7 +218,8 @@ __device__ __forceinline__ void scalar_step_tile(const StepArgs &A, const I *Ir,
     const typename StepRec<V>::J Jr = load_jv<V>(A, jbase + jj);
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
-      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k]), qmax[k], swmin[k]);
+      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k] || jbase + jj >= A.n), qmax[k],
+                swmin[k]);
   }
 }
 
@@ -245,7 +250,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
     bool mine = false;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
-    if (__ballot(mine) != 0)
+    if (__ballot(mine) != 0 || jbase + kTJ > A.n)
       scalar_step_tile<V, 1, IPL>(A, I, g, jbase, eps2, qmax, swmin);
     else
       scalar_step_tile<V, 0, IPL>(A, I, g, jbase, eps2, qmax, swmin);
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
   for (int q = 0; q < A.n_act; ++q) {
     F qm = F(0);
     F sm = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
-    pair_step(si[q], J, eps2, j == sg[q], qm, sm);
+    pair_step(si[q], J, eps2, j == sg[q] || j >= A.n, qm, sm);
     qm = wave_max_t(qm);
     sm = wave_min_t(sm);
     if (lane == 0) {
@@ -379,6 +384,7 @@ hipError_t run(StepArgs &A, hipStream_t st) {
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st) {
   StepArgs A;
+  A.n = c->n;
   A.p32 = c->p32;
   A.p64 = c->p64;
   A.v64 = c->v64;
