@@ -307,6 +307,33 @@ def force_variants(cfg, r, v, m, reps=5):
     return res
 
 
+def pass_cost(t_end=1.0):
+    """Wall-clock of the same integration with one pass (the plain block-step scheme) and
+    with three time-symmetrization passes, native scheduler, mixed precision: the GPU
+    counterpart of the paper's iteration-cost comparison (Section 6)."""
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    out = {}
+    for name in ("plummer256", "plummer4096"):
+        cfg = config(name)
+        r, v, m = cfg.ic()
+        res = {}
+        for passes in (1, 3):
+            sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=passes, era=cfg.era,
+                              dt_max=cfg.dt_max, dt_min=cfg.dt_min)
+            series = sim.run(t_end)
+            st = sim.stats
+            e0 = series[0][1]
+            res[passes] = {"wall_s": st["wall_s"], "block_steps": st["block_steps"],
+                           "interactions": st["interactions"], "eras": st["eras"],
+                           "drift": max(abs(e - e0) / abs(e0) for _, e in series),
+                           "us_per_block_step": st["wall_s"] / st["block_steps"] * 1e6}
+            sim.close()
+        out[name] = {"t_end": t_end, "one_pass": res[1], "three_passes": res[3],
+                     "wall_ratio": res[3]["wall_s"] / res[1]["wall_s"],
+                     "block_step_ratio": res[3]["block_steps"] / res[1]["block_steps"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +342,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-pass-cost", action="store_true")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -381,6 +409,8 @@ def main():
         out["force_variants"] = force_variants(cfg, r, v, m)
         out["sweep_mixed"] = sweep(cfg, r, v, m, "mixed")
         out["sweep_fp64"] = sweep(cfg, r, v, m, "fp64")
+    if not args.no_pass_cost:
+        out["pass_cost"] = pass_cost()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, r, v, m, gpu_force_rows(cfg, r, v, m))
     else:

@@ -74,16 +74,16 @@ __device__ __forceinline__ void pair_src(const typename V::I &row, const Col<V> 
   const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
   F y = inv_r<V, NEWTON>(s);
   if (MASK && self) y = F(0);
+  // 3 y^5 u + gp y^3 = y^3 (3 y^2 u + gp) and y^3 u + gp y = y (y^2 u + gp)
   const F y2 = y * y;
   const F y3 = y2 * y;
-  const F y5 = y3 * y2;
   const F u = fma(ex, F(c.g.x), fma(ey, F(c.g.y), ez * F(c.g.z)));
   const F gpc = F(c.g.w);
-  const F coef = -fma(F(3) * y5, u, gpc * y3);
-  acc[0] = fma(y3, F(c.g.x), fma(coef, ex, acc[0]));
-  acc[1] = fma(y3, F(c.g.y), fma(coef, ey, acc[1]));
-  acc[2] = fma(y3, F(c.g.z), fma(coef, ez, acc[2]));
-  acc[3] -= fma(y3, u, gpc * y);
+  const F coef = y3 * fma(F(3) * y2, u, gpc);
+  acc[0] = fma(y3, F(c.g.x), fma(-coef, ex, acc[0]));
+  acc[1] = fma(y3, F(c.g.y), fma(-coef, ey, acc[1]));
+  acc[2] = fma(y3, F(c.g.z), fma(-coef, ez, acc[2]));
+  acc[3] = fma(-y, fma(y2, u, gpc), acc[3]);
 }
 
 template <class V, int NEWTON, int MASK>
@@ -99,9 +99,9 @@ __device__ __forceinline__ void pair_tgt(const typename V::I &row, const typenam
   const F m = V::mass(j);
   const F y2 = y * y;
   const F my3 = m * (y2 * y);
-  const F my5 = my3 * y2;
   const F u = fma(ex, g[0], fma(ey, g[1], ez * g[2]));
-  const F coef = fma(F(3) * my5, u, -g[3] * my3);
+  // 3 m y^5 u - gp m y^3 = m y^3 (3 y^2 u - gp)
+  const F coef = my3 * fma(F(3) * y2, u, -g[3]);
   acc[0] = fma(-my3, g[0], fma(coef, ex, acc[0]));
   acc[1] = fma(-my3, g[1], fma(coef, ey, acc[1]));
   acc[2] = fma(-my3, g[2], fma(coef, ez, acc[2]));
@@ -121,21 +121,20 @@ __device__ __forceinline__ void pair_all(const typename V::I &row, const typenam
   if (MASK && self) y = F(0);
   const F y2 = y * y;
   const F y3 = y2 * y;
-  const F y5 = y3 * y2;
+  const F z = F(3) * y2;
   // source part: k pulls on target j
   const F gx = F(c.g.x), gy = F(c.g.y), gz = F(c.g.z), gpj = F(c.g.w);
   const F us = fma(ex, gx, fma(ey, gy, ez * gz));
-  const F cs = -fma(F(3) * y5, us, gpj * y3);
-  acc[0] = fma(y3, gx, fma(cs, ex, acc[0]));
-  acc[1] = fma(y3, gy, fma(cs, ey, acc[1]));
-  acc[2] = fma(y3, gz, fma(cs, ez, acc[2]));
-  acc[3] -= fma(y3, us, gpj * y);
+  const F cs = y3 * fma(z, us, gpj);
+  acc[0] = fma(y3, gx, fma(-cs, ex, acc[0]));
+  acc[1] = fma(y3, gy, fma(-cs, ey, acc[1]));
+  acc[2] = fma(y3, gz, fma(-cs, ez, acc[2]));
+  acc[3] = fma(-y, fma(y2, us, gpj), acc[3]);
   // target part: j pulls on target k
   const F m = V::mass(c.p);
   const F my3 = m * y3;
-  const F my5 = m * y5;
   const F ut = fma(ex, gk[0], fma(ey, gk[1], ez * gk[2]));
-  const F ct = fma(F(3) * my5, ut, -gk[3] * my3);
+  const F ct = my3 * fma(z, ut, -gk[3]);
   acc[4] = fma(-my3, gk[0], fma(ct, ex, acc[4]));
   acc[5] = fma(-my3, gk[1], fma(ct, ey, acc[5]));
   acc[6] = fma(-my3, gk[2], fma(ct, ez, acc[6]));
