@@ -53,6 +53,7 @@ struct BwdArgs {
   double *part;
   double *gord;  // [4][npad] seeds in particle order (fused kernel)
   int blocks;
+  int scalar_j;  // fused kernel reads its columns through scalar loads
 };
 
 template <class V, int NEWTON>
@@ -378,6 +379,18 @@ __global__ __launch_bounds__(kWG) void k_bwd_order(BwdArgs A) {
   }
 }
 
+// Column (g, gp) of the fused kernel read straight from the ordered seed planes.
+template <class V>
+__device__ __forceinline__ typename GradT<V>::T load_g(const BwdArgs &A, int64_t j) {
+  typename GradT<V>::T g;
+  const int64_t P = A.npad;
+  g.x = A.gord[j];
+  g.y = A.gord[P + j];
+  g.z = A.gord[2 * P + j];
+  g.w = A.gord[3 * P + j];
+  return g;
+}
+
 template <class V, int NEWTON, int MASK>
 __device__ __forceinline__ void all_tile(const typename V::I &row, const typename V::F gk[4],
                                          const ColAll<V> *sc, int64_t jbase, int64_t k,
@@ -439,6 +452,66 @@ __global__ __launch_bounds__(kWG) void k_bwd_all(BwdArgs A) {
   }
 }
 
+// The fused kernel with its columns read through wave-uniform (scalar) loads straight
+// from the predicted and seed planes: no LDS staging, no barriers; same tiles, vote and
+// sums as k_bwd_all.  Used in float64 mode, where it measured ~4% faster than the LDS
+// form at N = 131072; in mixed precision it measured ~6% slower (eight scalar streams per
+// column against a single staged record), so the LDS form stays the default there.
+template <class V, int NEWTON, int MASK>
+__device__ __forceinline__ void all_tile_scalar(const BwdArgs &A, const typename V::I &row,
+                                                const typename V::F gk[4], int64_t jbase,
+                                                int64_t k, typename V::F eps2,
+                                                typename V::F acc[7]) {
+#pragma unroll 4
+  for (int jj = 0; jj < kTJ; ++jj) {
+    ColAll<V> c;
+    c.p = V::load_j(A.p32, A.p64, A.npad, jbase + jj, 1.0f);
+    c.g = load_g<V>(A, jbase + jj);
+    pair_all<V, NEWTON, MASK>(row, gk, c, eps2, MASK && (jbase + jj == k), acc);
+  }
+}
+
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_bwd_all_scalar(BwdArgs A) {
+  using F = typename V::F;
+  const int tid = threadIdx.x;
+  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
+  const int rtile = L % A.plan.n_itiles;
+  const int slice = L / A.plan.n_itiles;
+  if (slice >= A.plan.n_slices) return;
+  const int jt0 = slice * A.plan.tiles_per_slice;
+  const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);
+  const int64_t P = A.npad;
+  const int64_t k = static_cast<int64_t>(rtile) * kWG + tid;  // row particle (< npad)
+  const typename V::I row = V::load_i(A.p32, A.p64, P, k);
+  const F gk[4] = {static_cast<F>(A.gord[k]), static_cast<F>(A.gord[P + k]),
+                   static_cast<F>(A.gord[2 * P + k]), static_cast<F>(A.gord[3 * P + k])};
+  const F eps2 = static_cast<F>(A.eps2);
+  double tot[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    F acc[7] = {F(0), F(0), F(0), F(0), F(0), F(0), F(0)};
+    if (__ballot(k >= jbase && k < jbase + kTJ) != 0)
+      all_tile_scalar<V, NEWTON, 1>(A, row, gk, jbase, k, eps2, acc);
+    else
+      all_tile_scalar<V, NEWTON, 0>(A, row, gk, jbase, k, eps2, acc);
+#pragma unroll
+    for (int e = 0; e < 7; ++e) tot[e] += static_cast<double>(acc[e]);
+  }
+  if (k >= A.n) return;
+  const double mk = A.p64[P64_M * P + k];
+  double out4[4] = {mk * tot[0] + tot[4], mk * tot[1] + tot[5], mk * tot[2] + tot[6], tot[3]};
+  if (A.plan.n_slices == 1) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) A.gr[e * A.n + k] += out4[e];
+    A.gm[k] += out4[3];
+  } else {
+    double *out = A.part + static_cast<int64_t>(slice) * 4 * A.n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e * A.n + k] = out4[e];
+  }
+}
+
 SplitPlan plan_src(const BwdArgs &A) {
   return plan_split(A.npad, 1, (A.n_act + kTJ - 1) / kTJ, A.blocks);
 }
@@ -467,7 +540,11 @@ hipError_t run(BwdArgs &A, hipStream_t st) {
                        dim3(kWG), 0, st, A);
     A.plan = plan_all(A);
     A.n_ctiles = static_cast<int>(A.npad / kTJ);
-    hipLaunchKernelGGL((k_bwd_all<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+    if (A.scalar_j)
+      hipLaunchKernelGGL((k_bwd_all_scalar<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st,
+                         A);
+    else
+      hipLaunchKernelGGL((k_bwd_all<V, NEWTON>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
     reduce_rows<0>(A, st);
     return hipGetLastError();
   }
@@ -528,6 +605,7 @@ hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const do
   A.part = c->part;
   A.gord = c->gord;
   A.blocks = c->tune_blocks;
+  A.scalar_j = force_scalar_j(c) && c->precision == TSBTS_FP64 ? 1 : 0;
   if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st);
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION)
