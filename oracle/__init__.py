@@ -6,15 +6,17 @@ never calls it, and it imports nothing from the product package.
 
 Contents
 --------
-* ``force``, ``energy``, ``timestep``, ``force_backward``: ctypes wrappers around the
-  plain C double loops in ``oracle.c`` (definitions cited there).
+* ``force``, ``energy``, ``timestep``, ``force_backward``, ``force_backward_rows``:
+  ctypes wrappers around the plain C double loops in ``oracle.c`` (definitions cited
+  there).
 * ``taylor``: the predictor of Section 2 (second-order positions, first-order
   velocities).
 * ``hermite``: the cubic Hermite interpolant used as the time-symmetric interpolation of
   stored era data (Section 2, second pass onwards).
 * ``leapfrog_shared``: the self-starting leapfrog of Section 2 with one shared step.
 * ``tsbts``: the era / pass / block-step driver (Algorithms 1-3).
-* ``adjoint``: reverse-mode gradient through a shared-step leapfrog run.
+* ``adjoint``: reverse-mode gradients through a shared-step leapfrog run and through a
+  run on a fixed block schedule.
 
 Parity status of each function is recorded in its docstring; every one is pinned by the
 CPU-only tests under ``tests/`` (closed forms, invariants, brute force, finite
@@ -61,6 +63,8 @@ def _load():
         lib.oracle_timestep.argtypes = [i64, _d, _d, _d, _d, _d, _d, _d, dbl, dbl, _i, i64, _d]
         lib.oracle_force_backward.argtypes = [i64, _d, _d, _d, _d, dbl, _i, i64,
                                               _d, _d, _d, _d, _d, _d, _d, _d]
+        lib.oracle_force_backward_rows.argtypes = [i64, _d, _d, _d, _d, dbl, _i, i64,
+                                                   _d, _d, _d, _d, _i, i64, _d, _d]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -143,6 +147,32 @@ def timestep(r, v, m, eps, eta, idx=None):
     lib.oracle_timestep(n, _p(r[0]), _p(r[1]), _p(r[2]), _p(v[0]), _p(v[1]), _p(v[2]),
                         _p(m), float(eps), float(eta), _pi(idx), idx.size, _p(out))
     return out
+
+
+def force_backward_rows(r, m, eps, idx, g_acc, rows, g_pot=None):
+    """``force_backward`` evaluated for the listed rows only: (dL/dr [3, len(rows)],
+    dL/dm [len(rows)]), at O(len(rows) N) cost.  Same per-row loops as the full function
+    (pinned to it element by element, tests/test_oracle_adjoint.py)."""
+    lib = _load()
+    r = _soa(r, "r")
+    n = r.shape[1]
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    idx = _idx(idx, n)
+    rows = _idx(rows, n)
+    g_acc = _soa(g_acc, "g_acc")
+    if g_acc.shape[1] != idx.size:
+        raise ValueError("g_acc must have shape (3, n_act)")
+    gp = None
+    if g_pot is not None:
+        gp = np.ascontiguousarray(g_pot, dtype=np.float64)
+    out_r = np.zeros((3, rows.size))
+    out_m = np.zeros(rows.size)
+    lib.oracle_force_backward_rows(n, _p(r[0]), _p(r[1]), _p(r[2]), _p(m), float(eps),
+                                   _pi(idx), idx.size, _p(g_acc[0]), _p(g_acc[1]),
+                                   _p(g_acc[2]),
+                                   _p(gp) if gp is not None else ctypes.cast(None, _d),
+                                   _pi(rows), rows.size, _p(out_r), _p(out_m))
+    return out_r, out_m
 
 
 def force_backward(r, m, eps, idx, g_acc, g_pot=None):

@@ -132,6 +132,65 @@ void oracle_timestep(int64_t n, const double *x, const double *y, const double *
  *     dL/dr_k += -sum_j m_j T(d) g_k + gp_k sum_j m_j s^(-3/2) d
  *
  * The loops below evaluate these sums literally, one pair at a time. */
+
+/* source term of row k: sum over the listed targets c != k (adds to out[0..3]) */
+static void bwd_source_row(int64_t k, const double *x, const double *y, const double *z,
+                           const double *m, double eps2, const int32_t *idx, int64_t nact,
+                           const double *gax, const double *gay, const double *gaz,
+                           const double *gp, double out[4])
+{
+    double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+    for (int64_t q = 0; q < nact; ++q) {
+        const int64_t c = idx[q];
+        if (c == k) continue;
+        const double dx = x[k] - x[c];
+        const double dy = y[k] - y[c];
+        const double dz = z[k] - z[c];
+        const double s = dx * dx + dy * dy + dz * dz + eps2;
+        const double rinv = 1.0 / sqrt(s);
+        const double r3 = rinv * rinv * rinv;
+        const double r5 = r3 * rinv * rinv;
+        const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
+        const double g2 = gp ? gp[q] : 0.0;
+        sx += r3 * gax[q] - 3.0 * r5 * dg * dx + g2 * r3 * dx;
+        sy += r3 * gay[q] - 3.0 * r5 * dg * dy + g2 * r3 * dy;
+        sz += r3 * gaz[q] - 3.0 * r5 * dg * dz + g2 * r3 * dz;
+        sm += dg * r3 - g2 * rinv;
+    }
+    out[0] += m[k] * sx;
+    out[1] += m[k] * sy;
+    out[2] += m[k] * sz;
+    out[3] += sm;
+}
+
+/* target term of the listed target q (particle k = idx[q]): sum over all sources j != k */
+static void bwd_target_row(int64_t q, int64_t n, const double *x, const double *y,
+                           const double *z, const double *m, double eps2, const int32_t *idx,
+                           const double *gax, const double *gay, const double *gaz,
+                           const double *gp, double out[3])
+{
+    const int64_t k = idx[q];
+    const double g2 = gp ? gp[q] : 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == k) continue;
+        const double dx = x[k] - x[j];
+        const double dy = y[k] - y[j];
+        const double dz = z[k] - z[j];
+        const double s = dx * dx + dy * dy + dz * dz + eps2;
+        const double rinv = 1.0 / sqrt(s);
+        const double r3 = rinv * rinv * rinv;
+        const double r5 = r3 * rinv * rinv;
+        const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
+        sx += -m[j] * (r3 * gax[q] - 3.0 * r5 * dg * dx) + g2 * m[j] * r3 * dx;
+        sy += -m[j] * (r3 * gay[q] - 3.0 * r5 * dg * dy) + g2 * m[j] * r3 * dy;
+        sz += -m[j] * (r3 * gaz[q] - 3.0 * r5 * dg * dz) + g2 * m[j] * r3 * dz;
+    }
+    out[0] += sx;
+    out[1] += sy;
+    out[2] += sz;
+}
+
 void oracle_force_backward(int64_t n, const double *x, const double *y, const double *z,
                            const double *m, double eps, const int32_t *idx, int64_t nact,
                            const double *gax, const double *gay, const double *gaz,
@@ -142,52 +201,53 @@ void oracle_force_backward(int64_t n, const double *x, const double *y, const do
     /* source terms: every particle k against every target c */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < n; ++k) {
-        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
-        for (int64_t q = 0; q < nact; ++q) {
-            const int64_t c = idx[q];
-            if (c == k) continue;
-            const double dx = x[k] - x[c];
-            const double dy = y[k] - y[c];
-            const double dz = z[k] - z[c];
-            const double s = dx * dx + dy * dy + dz * dz + eps2;
-            const double rinv = 1.0 / sqrt(s);
-            const double r3 = rinv * rinv * rinv;
-            const double r5 = r3 * rinv * rinv;
-            const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
-            const double g2 = gp ? gp[q] : 0.0;
-            sx += r3 * gax[q] - 3.0 * r5 * dg * dx + g2 * r3 * dx;
-            sy += r3 * gay[q] - 3.0 * r5 * dg * dy + g2 * r3 * dy;
-            sz += r3 * gaz[q] - 3.0 * r5 * dg * dz + g2 * r3 * dz;
-            sm += dg * r3 - g2 * rinv;
-        }
-        grx[k] += m[k] * sx;
-        gry[k] += m[k] * sy;
-        grz[k] += m[k] * sz;
-        gm[k] += sm;
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        bwd_source_row(k, x, y, z, m, eps2, idx, nact, gax, gay, gaz, gp, o);
+        grx[k] += o[0];
+        gry[k] += o[1];
+        grz[k] += o[2];
+        gm[k] += o[3];
     }
     /* target terms: every listed target k against every source j */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t q = 0; q < nact; ++q) {
         const int64_t k = idx[q];
-        const double g2 = gp ? gp[q] : 0.0;
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == k) continue;
-            const double dx = x[k] - x[j];
-            const double dy = y[k] - y[j];
-            const double dz = z[k] - z[j];
-            const double s = dx * dx + dy * dy + dz * dz + eps2;
-            const double rinv = 1.0 / sqrt(s);
-            const double r3 = rinv * rinv * rinv;
-            const double r5 = r3 * rinv * rinv;
-            const double dg = dx * gax[q] + dy * gay[q] + dz * gaz[q];
-            sx += -m[j] * (r3 * gax[q] - 3.0 * r5 * dg * dx) + g2 * m[j] * r3 * dx;
-            sy += -m[j] * (r3 * gay[q] - 3.0 * r5 * dg * dy) + g2 * m[j] * r3 * dy;
-            sz += -m[j] * (r3 * gaz[q] - 3.0 * r5 * dg * dz) + g2 * m[j] * r3 * dz;
+        double o[3] = {0.0, 0.0, 0.0};
+        bwd_target_row(q, n, x, y, z, m, eps2, idx, gax, gay, gaz, gp, o);
+        grx[k] += o[0];
+        gry[k] += o[1];
+        grz[k] += o[2];
+    }
+}
+
+/* The same gradient for the listed rows only: out_r[3][nrows], out_m[nrows] (written, not
+ * accumulated) for particles rows[0..nrows), each the source term of its row plus, when
+ * the row is a listed target, its target term. */
+void oracle_force_backward_rows(int64_t n, const double *x, const double *y, const double *z,
+                                const double *m, double eps, const int32_t *idx, int64_t nact,
+                                const double *gax, const double *gay, const double *gaz,
+                                const double *gp, const int32_t *rows, int64_t nrows,
+                                double *out_r, double *out_m)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t k = rows[t];
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        bwd_source_row(k, x, y, z, m, eps2, idx, nact, gax, gay, gaz, gp, o);
+        double src[3] = {o[0], o[1], o[2]};
+        for (int64_t q = 0; q < nact; ++q) {
+            if (idx[q] != k) continue;
+            double tg[3] = {0.0, 0.0, 0.0};
+            bwd_target_row(q, n, x, y, z, m, eps2, idx, gax, gay, gaz, gp, tg);
+            src[0] += tg[0];
+            src[1] += tg[1];
+            src[2] += tg[2];
         }
-        grx[k] += sx;
-        gry[k] += sy;
-        grz[k] += sz;
+        out_r[t] = src[0];
+        out_r[nrows + t] = src[1];
+        out_r[2 * nrows + t] = src[2];
+        out_m[t] = o[3];
     }
 }
 

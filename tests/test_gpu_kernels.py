@@ -138,24 +138,51 @@ def test_backward_matches_oracle(prec, sep, n, n_act, eps, with_gp):
     ctx.close()
 
 
-def test_backward_full_size_identities():
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_backward_full_size_identities_and_sampled_rows(prec):
+    # the N=131072 workload in the launch configuration the benchmark times (every
+    # particle active: the fused kernel; half of them: the source / target kernels)
     cfg = config("plummer131k")
     r, v, m = cfg.ic()
     n = cfg.n
-    ctx = make_ctx(n, cfg.eps, "mixed")
+    ctx = make_ctx(n, cfg.eps, prec)
     ctx.bind(r, v, m)
     ctx.predict(0.0)
-    idx = np.arange(n, dtype=np.int32)
-    ga = gaussian((3, n), 21)
-    acc, pot = ctx.force(idx, 0.0)
-    gr, gm = ctx.force_backward(idx, 0.0, ga)
-    gr, gm = gr.cpu().numpy(), gm.cpu().numpy()
-    # translation invariance: sum over particles of dL/dr vanishes
-    assert np.abs(gr.sum(axis=1)).max() <= 1e-5 * np.abs(gr).sum()
-    # Euler: sum m dL/dm = sum g . a (acceleration homogeneous of degree one in m)
-    euler = (acc.cpu().numpy() * ga).sum()
-    assert (m * gm).sum() == pytest.approx(euler, rel=1e-5)
-    # sampled rows against the oracle (sources only: rows k with the full target set)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    rows = np.sort(np.random.default_rng(8).choice(n, 96, replace=False)).astype(np.int32)
+    for idx in (np.arange(n, dtype=np.int32), active_subset(n, n // 2, cfg.seed + 11)):
+        ga = gaussian((3, idx.size), 21)
+        acc, pot = ctx.force(idx, 0.0)
+        gr, gm = ctx.force_backward(idx, 0.0, ga)
+        gr, gm = gr.cpu().numpy(), gm.cpu().numpy()
+        # translation invariance: sum over particles of dL/dr vanishes
+        assert np.abs(gr.sum(axis=1)).max() <= 1e-5 * np.abs(gr).sum()
+        # Euler: sum m dL/dm = sum g . a (acceleration homogeneous of degree one in m)
+        euler = (acc.cpu().numpy() * ga).sum()
+        assert (m * gm).sum() == pytest.approx(euler, rel=1e-5)
+        # sampled rows against the oracle's row-restricted gradient
+        rr, rm = oracle.force_backward_rows(r, m, cfg.eps, idx, ga, rows)
+        assert np.linalg.norm(gr[:, rows] - rr) <= tol * np.linalg.norm(rr), idx.size
+        assert np.linalg.norm(gm[rows] - rm) <= tol * np.linalg.norm(rm), idx.size
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_timestep_full_size_sampled(prec):
+    # the criterion at N=131072 in the benchmark's launch configuration, full and half
+    # active sets, sampled targets against the oracle
+    cfg = config("plummer131k")
+    r, v, m = cfg.ic()
+    n = cfg.n
+    ctx = make_ctx(n, cfg.eps, prec)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    for idx in (np.arange(n, dtype=np.int32), active_subset(n, n // 2, cfg.seed + 11)):
+        dtc = ctx.timestep(idx, cfg.eta).cpu().numpy()
+        take = np.sort(np.random.default_rng(9).choice(idx.size, 256, replace=False))
+        ref = oracle.timestep(r, v, m, cfg.eps, cfg.eta, idx[take])
+        e = rel_err(dtc[take], ref)
+        assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), summary(e)
     ctx.close()
 
 

@@ -142,3 +142,17 @@ def test_block_gradient_shared_limit(oracle):
     assert Lb == pytest.approx(Ls, rel=1e-14)
     for a, b in ((gr_b, gr_s), (gv_b, gv_s), (gm_b, gm_s)):
         assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("n_act", [1, 40, 97])
+def test_force_backward_rows_equal_full(oracle, n_act):
+    # the row-restricted gradient is the full one's rows, element by element (the same
+    # per-row loops; the full function is pinned by finite differences above)
+    n, eps = 97, 1.0 / 32
+    r, _, m = plummer(n, 33, masses="loguniform")
+    idx = active_subset(n, n_act, 4)
+    ga, gp = gaussian((3, n_act), 5), gaussian(n_act, 6)
+    gr, gm = oracle.force_backward(r, m, eps, idx, ga, gp)
+    rows = np.array([0, 5, 17, 96, 40, 41], dtype=np.int32)
+    rr, rm = oracle.force_backward_rows(r, m, eps, idx, ga, rows, gp)
+    assert np.array_equal(rr, gr[:, rows]) and np.array_equal(rm, gm[rows])
