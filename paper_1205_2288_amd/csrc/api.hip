@@ -8,7 +8,7 @@
 #include <cstring>
 #include <new>
 
-#include "internal.hpp"
+#include "correct.hpp"
 
 namespace tsbts {
 int64_t backward_partials_needed(const tsbts_ctx *c, int n_act);
@@ -466,3 +466,32 @@ int tsbts_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int32_t n_a
 }
 
 }  // extern "C"
+
+namespace tsbts {
+
+// Force on the active set followed by its corrector, in the same launches: the corrector
+// of each target runs where its force is finished (end of the force kernel, or its split-j
+// reduction).  Same checks and history bookkeeping as tsbts_force + tsbts_correct; used by
+// the native scheduler, whose block steps need nothing between the two.
+int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                  double *acc, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
+  if (int s = check_pred(c, t_block)) return s;
+  if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  if (c->h.recording) {
+    const int64_t need = c->h.count + n_act;
+    if (need >= (int64_t(1) << 31))
+      return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
+    if (int s = grow_log(c, need, stream)) return s;
+  }
+  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  hipError_t e = launch_force(c, idx, n_act, acc, nullptr, stream, &corr);
+  if (e != hipSuccess) return hip_fail(c, e, "force + corrector launch");
+  if (c->h.recording) c->h.count += n_act;
+  return TSBTS_OK;
+}
+
+}  // namespace tsbts

@@ -9,60 +9,16 @@
 // slot offset[particle] + rank: the records end up grouped by particle and in time order
 // (a stable counting sort).  Predictions of later passes walk these groups with a
 // per-particle cursor that only moves forward.
-#include "internal.hpp"
+#include "correct.hpp"
 
 namespace tsbts {
 namespace {
 
-struct CorrectArgs {
-  int64_t n, npad;
-  const int32_t *idx;
-  int n_act;
-  double tb;
-  const double *acc_new;
-  const double *p64;
-  double *v64;
-  float *p32;  // mixed precision: float32 velocity planes refreshed too (else null)
-  double *r, *v, *a, *t_last;
-  int record;
-  int64_t base;    // first free record slot
-  int64_t cap;
-  int32_t *pid, *rank, *cnt;
-  double *rt, *rs;
-};
-
 __global__ __launch_bounds__(kWG) void k_correct(CorrectArgs p) {
   const int q = blockIdx.x * kWG + threadIdx.x;
   if (q >= p.n_act) return;
-  const int64_t g = p.idx[q];
-  const int64_t n = p.n, P = p.npad;
-  const double h = p.tb - p.t_last[g];
-  double st[9];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double an = p.acc_new[c * p.n_act + q];
-    const double rn = p.p64[c * P + g];  // predicted position = r + v h + a h^2/2
-    const double vn = p.v[c * n + g] + 0.5 * (p.a[c * n + g] + an) * h;
-    p.r[c * n + g] = rn;
-    p.v[c * n + g] = vn;
-    p.a[c * n + g] = an;
-    p.v64[c * P + g] = vn;
-    if (p.p32) p.p32[(P32_VX + c) * P + g] = static_cast<float>(vn);
-    st[c] = rn;
-    st[c + 3] = vn;
-    st[c + 6] = an;
-  }
-  p.t_last[g] = p.tb;
-  if (p.record) {
-    const int64_t slot = p.base + q;
-    p.pid[slot] = static_cast<int32_t>(g);
-    const int32_t k = p.cnt[g];
-    p.rank[slot] = k;
-    p.cnt[g] = k + 1;
-    p.rt[slot] = p.tb;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) p.rs[c * p.cap + slot] = st[c];
-  }
+  const double an[3] = {p.acc_new[q], p.acc_new[p.n_act + q], p.acc_new[2 * p.n_act + q]};
+  correct_one(p, q, p.idx[q], an);
 }
 
 // First record of every particle: its state at its own last time.
@@ -273,13 +229,19 @@ CorrectArgs base_args(tsbts_ctx *c) {
 
 }  // namespace
 
-hipError_t launch_correct(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
-                          const double *acc_new, hipStream_t st) {
+CorrectArgs correct_args(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                         const double *acc_new) {
   CorrectArgs p = base_args(c);
   p.idx = idx;
   p.n_act = n_act;
   p.tb = t_block;
   p.acc_new = acc_new;
+  return p;
+}
+
+hipError_t launch_correct(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                          const double *acc_new, hipStream_t st) {
+  CorrectArgs p = correct_args(c, idx, n_act, t_block, acc_new);
   const int nb = (n_act + kWG - 1) / kWG;
   hipLaunchKernelGGL(k_correct, dim3(nb), dim3(kWG), 0, st, p);
   return hipGetLastError();
@@ -328,6 +290,13 @@ hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const doub
   const int nb = static_cast<int>((len + kWG - 1) / kWG);
   hipLaunchKernelGGL(k_lf_adjoint, dim3(nb), dim3(kWG), 0, st, len, phase, h, rbar, vbar,
                      abar, g_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *x, int64_t len, double v, hipStream_t st) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>((len + kWG - 1) / kWG)), dim3(kWG), 0,
+                     st, len, x, v);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 // lane's own particle: a wave-uniform vote picks a masked copy of the inner loop for
 // those tiles and the unmasked one elsewhere, so the mask costs nothing on almost every
 // tile and no large self term ever enters a float32 accumulator.
+#include "correct.hpp"
 #include "pair.hpp"
 #include <algorithm>
 #include <type_traits>
@@ -41,6 +42,8 @@ struct ForceArgs {
   int blocks;    // workgroups a split launch aims for
   int ipl;       // targets per lane
   int scalar_j;  // j-particles through scalar loads (k_force_scalar)
+  int correct;   // apply the corrector to each target as its force is finished
+  CorrectArgs corr;
 };
 
 // ----- pair contributions -------------------------------------------------------------
@@ -99,10 +102,12 @@ template <class V, int NEWTON>
 __device__ __forceinline__ void finish(const ForceArgs &A, int q, int64_t g, double sx,
                                        double sy, double sz, double sp) {
   const double k = Scale<V, NEWTON>::kAcc;
-  A.acc[q] = k * sx;
-  A.acc[A.n_act + q] = k * sy;
-  A.acc[2 * A.n_act + q] = k * sz;
+  const double an[3] = {k * sx, k * sy, k * sz};
+  A.acc[q] = an[0];
+  A.acc[A.n_act + q] = an[1];
+  A.acc[2 * A.n_act + q] = an[2];
   if (A.pot) A.pot[q] = -sp;
+  if (A.correct) correct_one(A.corr, q, g, an);
 }
 
 template <class V, int NEWTON, int MASK, int POT, int IPL, class F>
@@ -432,8 +437,10 @@ int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
 }
 
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
-                        double *pot, hipStream_t st) {
+                        double *pot, hipStream_t st, const CorrectArgs *corr) {
   ForceArgs A;
+  A.correct = corr ? 1 : 0;
+  if (corr) A.corr = *corr;
   A.p32 = c->p32;
   A.p64 = c->p64;
   A.npad = c->npad;

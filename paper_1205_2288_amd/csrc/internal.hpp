@@ -190,8 +190,14 @@ hipError_t launch_load_positions(tsbts_ctx *c, const double *r, const double *m,
 hipError_t launch_snapshot(tsbts_ctx *c, double T, double *r_out, double *v_out,
                            hipStream_t st);
 
+struct CorrectArgs;
+// Force on the active set and its corrector in the same launches (checked like the two
+// entry points; returns a status code).
+int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                  double *acc, hipStream_t stream);
+// With corr, every target's corrector (correct_one) runs where its force is final.
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
-                        double *pot, hipStream_t st);
+                        double *pot, hipStream_t st, const CorrectArgs *corr = nullptr);
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st);
 hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const double *ga,
@@ -208,6 +214,8 @@ hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st);
 hipError_t launch_leapfrog_adjoint(tsbts_ctx *c, int phase, double h, const double *rbar,
                                    double *vbar, double *abar, double *g_out,
                                    hipStream_t st);
+// x[0 .. len) = v with a fill kernel (no memset node if a caller captures the stream).
+hipError_t launch_fill(double *x, int64_t len, double v, hipStream_t st);
 hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
                                 double t_block, double *rbar, double *vbar, double *abar,
                                 double *pbar, double *seeds, hipStream_t st);

@@ -132,10 +132,13 @@ struct Scheduler {
   CritHistory prev, cur;
   bool have_prev = false;
   // staging
+  // pinned host buffers; the criterion and the step updates cross the link without a
+  // copy: the kernels write dtc_h and read dtn_h through their device mappings
   int32_t *idx_h = nullptr;
   double *dtc_h = nullptr, *dtn_h = nullptr;
+  double *dtc_hd = nullptr, *dtn_hd = nullptr;  // device views of dtc_h, dtn_h
   int32_t *idx_d = nullptr;
-  double *acc_d = nullptr, *dtc_d = nullptr, *dtn_d = nullptr;
+  double *acc_d = nullptr;
   double *s0 = nullptr;  // era-start device copy: r, v, a (3n each), t_last, dt
   std::vector<int64_t> s0_t, s0_dt;
   std::vector<double> s0_dtc;
@@ -230,10 +233,8 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
     SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
     SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
-    SCHED_CALL(tsbts_force(c, S.idx_d, k, tbs, S.acc_d, nullptr, st));
-    SCHED_CALL(tsbts_correct(c, S.idx_d, k, tbs, S.acc_d, st));
-    SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_d, st));
-    SCHED_HIP(hipMemcpyAsync(S.dtc_h, S.dtc_d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st));
+    SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     SCHED_HIP(hipStreamSynchronize(st));
     for (int32_t q = 0; q < k; ++q) {
       const int32_t i = S.idx_h[q];
@@ -254,8 +255,8 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
         S.move(i, tsbts::level_of(nd));
       }
     }
-    SCHED_HIP(hipMemcpyAsync(S.dtn_d, S.dtn_h, sizeof(double) * k, hipMemcpyHostToDevice, st));
-    SCHED_CALL(tsbts_set_dt(c, S.idx_d, k, S.dtn_d, st));
+    // dtn_h is rewritten only after the next synchronisation, when this kernel has run
+    SCHED_CALL(tsbts_set_dt(c, S.idx_d, k, S.dtn_hd, st));
     S.stats[0] += 1;
     S.stats[1] += 1;
     S.stats[2] += static_cast<int64_t>(k) * n;
@@ -274,8 +275,6 @@ void free_sched(Scheduler *S) {
   if (S->dtn_h) (void)hipHostFree(S->dtn_h);
   if (S->idx_d) (void)hipFree(S->idx_d);
   if (S->acc_d) (void)hipFree(S->acc_d);
-  if (S->dtc_d) (void)hipFree(S->dtc_d);
-  if (S->dtn_d) (void)hipFree(S->dtn_d);
   if (S->s0) (void)hipFree(S->s0);
   delete S;
 }
@@ -339,22 +338,21 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->idx_h), sizeof(int32_t) * n));
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtc_h), sizeof(double) * n));
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtn_h), sizeof(double) * n));
+  SCHED_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&S->dtc_hd), S->dtc_h, 0));
+  SCHED_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&S->dtn_hd), S->dtn_h, 0));
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->idx_d), sizeof(int32_t) * n));
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->acc_d), sizeof(double) * 3 * n));
-  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->dtc_d), sizeof(double) * n));
-  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->dtn_d), sizeof(double) * n));
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->s0), sizeof(double) * 11 * n));
   // Algorithm 2, step 1: forces, criterion and block steps of all particles at t = 0
   for (int64_t i = 0; i < n; ++i) S->idx_h[i] = static_cast<int32_t>(i);
   SCHED_HIP(hipMemcpyAsync(S->idx_d, S->idx_h, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-  SCHED_HIP(hipMemsetAsync(c->t_last, 0, sizeof(double) * n, st));
-  SCHED_HIP(hipMemsetAsync(c->a, 0, sizeof(double) * 3 * n, st));
-  SCHED_HIP(hipMemsetAsync(c->dt, 0, sizeof(double) * n, st));
+  SCHED_HIP(tsbts::launch_fill(c->t_last, n, 0.0, st));
+  SCHED_HIP(tsbts::launch_fill(c->a, 3 * n, 0.0, st));
+  SCHED_HIP(tsbts::launch_fill(c->dt, n, 0.0, st));
   SCHED_CALL(tsbts_predict(c, 0.0, 0, st));
   SCHED_CALL(tsbts_force(c, S->idx_d, static_cast<int32_t>(n), 0.0, c->a, nullptr, st));
   // the force output has the same [3][n] layout as the bound accelerations
-  SCHED_CALL(tsbts_timestep(c, S->idx_d, static_cast<int32_t>(n), eta, S->dtc_d, st));
-  SCHED_HIP(hipMemcpyAsync(S->dtc_h, S->dtc_d, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  SCHED_CALL(tsbts_timestep(c, S->idx_d, static_cast<int32_t>(n), eta, S->dtc_hd, st));
   SCHED_HIP(hipStreamSynchronize(st));
   for (int64_t i = 0; i < n; ++i) {
     S->dtc[i] = S->dtc_h[i];
