@@ -53,13 +53,14 @@ FLOPS_CRITERION = 20.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (313264.5, 131072.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
-                          "8bc23251c01bb28d"),
-    "k_force_scalar": (40234.3, 65536.0, ("force.hip", "pair.hpp", "internal.hpp"),
-                       "23a897bdc9b82ef2"),
-    "k_bwd_all": (65047.9, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
-                  "a9e367996310b5fe"),
-    "k_energy_pairs": (23384.0, 4104.0, ("energy.hip", "internal.hpp"), "d87f03f843ecb1c5"),
+    "k_timestep_scalar": (313244.3, 131072.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
+                          "062b879bc45c617e"),
+    "k_force_scalar": (40641.0, 65536.0,
+                       ("force.hip", "pair.hpp", "internal.hpp", "correct.hpp"),
+                       "c2aca8a949640384"),
+    "k_bwd_all": (65025.9, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
+                  "15d0ce57f04ef531"),
+    "k_energy_pairs": (23390.4, 4104.0, ("energy.hip", "internal.hpp"), "b8d560950cc12f53"),
 }
 
 
