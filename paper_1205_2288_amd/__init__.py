@@ -7,9 +7,11 @@ N-body method of Kaplan & Saygin (arXiv 1205.2288).
   the O(N^2) float64 energy and the force adjoint - all hand-written HIP kernels.
 * ``_lib``: ctypes binding with the C names.
 * ``Context``: device-resident state and convenience wrappers.
-* ``driver.TSBTS``: host-side era / pass / block-step scheduler (Algorithms 1-3).
-* ``autograd``: torch.autograd Functions over the force adjoint and a checkpointed
-  shared-step leapfrog.
+* ``driver.TSBTS``: host-side era / pass / block-step scheduler (Algorithms 1-3) in
+  Python; ``driver.NativeTSBTS``: the same loop in the library (tsbts_sched_*).
+* ``autograd``: torch.autograd Functions over the force adjoint, a checkpointed
+  shared-step leapfrog and a run on a fixed block schedule.
+* ``experiments``: era-size / iteration and fixed / dynamic era energy-error studies.
 """
 from .context import Context  # noqa: F401
 

@@ -1,0 +1,137 @@
+"""Era-size and iteration studies of the method at GPU speed (the paper's Section 3 tests
+of era size and iteration count, and Section 4's fixed versus dynamic era), on seeded
+Plummer spheres with the native scheduler.
+
+Each run integrates one sphere and samples the relative energy error
+|E(t) - E(0)| / |E(0)| (float64 O(N^2) energy) at a fixed interval.  A run is summarised
+by its largest error, its final error and the growth ratio err(t_end) / err(t_end / 2),
+taken on the running maximum of the error: about 2 for a linearly growing error, about
+sqrt(2) for a random walk, about 1 once the error has saturated.
+
+The paper's own initial conditions and curves are not published, and its runs last
+1000 time units; these studies use fresh seeded spheres and shorter runs, so only the
+trends compare (larger eras with too few passes drift linearly; more passes or smaller
+eras keep the error in a random walk; dynamic eras perform like the best fixed era).
+
+    python -m paper_1205_2288_amd.experiments era --n 100 --t-end 100 --seeds 3
+    python -m paper_1205_2288_amd.experiments dynamic --n 100 --t-end 100 --seeds 10
+
+Each finished run prints one JSON line (progress and result); the last line is a summary.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def _plummer(n: int, seed: int):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from workloads import plummer
+    return plummer(n, seed)
+
+
+def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
+                     era: float | None, dt_max: float, t_end: float, every: float,
+                     precision: str = "fp64") -> dict:
+    """One integration; era=None selects the dynamic era (Algorithm 3)."""
+    from .driver import NativeTSBTS
+    r, v, m = _plummer(n, seed)
+    sim = NativeTSBTS(r, v, m, eps, eta=eta, passes=passes, era=era, dt_max=dt_max,
+                      precision=precision)
+    t0 = time.perf_counter()
+    series = sim.run(t_end, energy_every=every)
+    wall = time.perf_counter() - t0
+    st = sim.stats
+    sim.close()
+    e0 = series[0][1]
+    t = np.array([p[0] for p in series])
+    err = np.array([abs(p[1] - e0) / abs(e0) for p in series])
+    run_max = np.maximum.accumulate(err)
+    half = run_max[np.searchsorted(t, 0.5 * t_end)]
+    growth = float(run_max[-1] / half) if half > 0 else math.nan
+    return {"n": n, "seed": seed, "passes": passes, "era": era if era else "dynamic",
+            "eta": eta, "eps": eps, "dt_max": dt_max, "t_end": t_end,
+            "max_err": float(err.max()), "final_err": float(err[-1]), "growth": growth,
+            "block_steps": st["block_steps"], "eras": st["eras"], "wall_s": wall,
+            "series_t": t.tolist(), "series_err": err.tolist()}
+
+
+def era_study(n=100, seeds=3, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
+              eras=(1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4), passes=(3, 5), every=1.0,
+              seed0=1205, out=sys.stdout):
+    """Fixed era sizes x pass counts x initial conditions (Section 3, fixed-era tests)."""
+    rows = []
+    for k in range(seeds):
+        for p in passes:
+            for era in eras:
+                res = energy_error_run(n, seed0 + k, eps, eta, p, era, dt_max, t_end, every)
+                rows.append(res)
+                _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
+    summary = {}
+    for p in passes:
+        for era in eras:
+            sel = [r for r in rows if r["passes"] == p and r["era"] == era]
+            summary[f"passes={p} era={era:g}"] = {
+                "median_max_err": float(np.median([r["max_err"] for r in sel])),
+                "median_growth": float(np.median([r["growth"] for r in sel])),
+                "median_block_steps": float(np.median([r["block_steps"] for r in sel]))}
+    _emit(out, {"study": "era", "n": n, "t_end": t_end, "seeds": seeds, "summary": summary})
+    return rows, summary
+
+
+def dynamic_era_study(n=100, seeds=10, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
+                      passes=3, every=1.0, seed0=2205, out=sys.stdout):
+    """Fixed era (= dt_max) against the dynamic era (Section 4), same initial conditions."""
+    rows = []
+    for k in range(seeds):
+        pair = {}
+        for era in (dt_max, None):
+            res = energy_error_run(n, seed0 + k, eps, eta, passes, era, dt_max, t_end, every)
+            pair["fixed" if era else "dynamic"] = res
+            _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
+        rows.append(pair)
+    better = sum(1 for p in rows if p["dynamic"]["final_err"] < p["fixed"]["final_err"])
+    summary = {
+        "dynamic_smaller_final_err_fraction": better / len(rows),
+        "median_final_err_fixed": float(np.median([p["fixed"]["final_err"] for p in rows])),
+        "median_final_err_dynamic": float(np.median([p["dynamic"]["final_err"] for p in rows])),
+        "wall_ratio_dynamic_to_fixed": float(sum(p["dynamic"]["wall_s"] for p in rows)
+                                             / sum(p["fixed"]["wall_s"] for p in rows))}
+    _emit(out, {"study": "dynamic", "n": n, "t_end": t_end, "seeds": seeds,
+                "summary": summary})
+    return rows, summary
+
+
+def _emit(out, obj):
+    out.write(json.dumps(obj) + "\n")
+    out.flush()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("study", choices=["era", "dynamic"])
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--seeds", type=int, default=3)
+    ap.add_argument("--t-end", type=float, default=100.0)
+    ap.add_argument("--eta", type=float, default=0.1)
+    ap.add_argument("--eps", type=float, default=0.01)
+    ap.add_argument("--passes", type=int, nargs="+", default=None)
+    args = ap.parse_args(argv)
+    if args.study == "era":
+        era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta, eps=args.eps,
+                  passes=tuple(args.passes or (3, 5)))
+    else:
+        dynamic_era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta,
+                          eps=args.eps, passes=(args.passes or [3])[0])
+
+
+if __name__ == "__main__":
+    main()

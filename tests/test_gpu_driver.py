@@ -130,3 +130,24 @@ def test_plummer4096_dynamic_era_t10_drift(prec):
           f"{sim.stats['wall_s']:.1f} s")
     assert d <= 2.0 * g["max_rel_energy_error"]
     sim.close()
+
+
+def test_experiments_module_small():
+    # the era-size / dynamic-era study drivers on a tiny sphere: structure, finiteness,
+    # and block steps proportional to the pass count
+    import io
+    import json
+    from paper_1205_2288_amd import experiments as ex
+    buf = io.StringIO()
+    rows, summary = ex.era_study(n=32, seeds=1, t_end=0.5, eras=(1 / 64, 1 / 16),
+                                 passes=(1, 3), every=0.25, out=buf)
+    assert len(rows) == 4 and len(summary) == 4
+    lines = [json.loads(x) for x in buf.getvalue().splitlines()]
+    assert lines[-1]["study"] == "era"
+    for r in rows:
+        assert np.isfinite(r["max_err"]) and 0.0 <= r["final_err"] <= r["max_err"]
+    by = {(r["passes"], r["era"]): r["block_steps"] for r in rows}
+    for era in (1 / 64, 1 / 16):
+        assert 2.5 <= by[(3, era)] / by[(1, era)] <= 3.5
+    rows, summary = ex.dynamic_era_study(n=32, seeds=2, t_end=0.5, every=0.25, out=buf)
+    assert 0.0 <= summary["dynamic_smaller_final_err_fraction"] <= 1.0
