@@ -72,6 +72,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
 /* tuning parameters of tsbts_tune */
 #define TSBTS_TUNE_BLOCKS 1
 #define TSBTS_TUNE_IPL 2
+#define TSBTS_TUNE_CHUNK 3
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
  *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
@@ -79,6 +80,9 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      and the criterion from 8192 targets, read the j-particles through
  *                      wave-uniform scalar loads; 1, 2 or 4 = the LDS-staged kernels with
  *                      that many target particles per lane)
+ *   TSBTS_TUNE_CHUNK:  j-particles per split unit of the scalar-load kernels (0 =
+ *                      automatic: 64 when 256-particle units would give fewer than 512
+ *                      workgroups, else 256; or 64, 256)
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);

@@ -155,6 +155,7 @@ def tsbts_destroy(ctx):
 
 TSBTS_TUNE_BLOCKS = 1
 TSBTS_TUNE_IPL = 2
+TSBTS_TUNE_CHUNK = 3
 
 
 def tsbts_tune(ctx, param: int, value: int):

@@ -64,13 +64,16 @@ class Context:
         L.tsbts_bind_state(self.ctx, n, self.r, self.v, self.a, self.m, self.t_last, self.dt)
         return self
 
-    def tune(self, blocks=None, ipl=None):
-        """Launch-shape tuning (see tsbts_tune): workgroups per split launch, targets per
-        lane for large active sets (0 = automatic)."""
+    def tune(self, blocks=None, ipl=None, chunk=None):
+        """Launch-shape tuning (see tsbts_tune): workgroups per split launch, kernel form
+        (0 = scalar-load kernels, 1/2/4 = LDS kernels with that many targets per lane), j
+        per split unit of the scalar-load kernels (0 = automatic, 64, 256)."""
         if blocks is not None:
             L.tsbts_tune(self.ctx, L.TSBTS_TUNE_BLOCKS, blocks)
         if ipl is not None:
             L.tsbts_tune(self.ctx, L.TSBTS_TUNE_IPL, ipl)
+        if chunk is not None:
+            L.tsbts_tune(self.ctx, L.TSBTS_TUNE_CHUNK, chunk)
         return self
 
     def host_buffer(self, n, dtype):

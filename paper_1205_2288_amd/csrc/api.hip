@@ -260,6 +260,11 @@ int tsbts_tune(tsbts_ctx *c, int param, int value) {
         return fail(c, TSBTS_EINVAL, "targets per lane must be 0, 1, 2 or 4");
       c->tune_ipl = value;
       return TSBTS_OK;
+    case TSBTS_TUNE_CHUNK:
+      if (value != 0 && value != 64 && value != 256)
+        return fail(c, TSBTS_EINVAL, "j chunk must be 0, 64 or 256");
+      c->tune_chunk = value;
+      return TSBTS_OK;
     default:
       return fail(c, TSBTS_EINVAL, "unknown tuning parameter %d", param);
   }

@@ -42,6 +42,7 @@ struct ForceArgs {
   int blocks;    // workgroups a split launch aims for
   int ipl;       // targets per lane
   int scalar_j;  // j-particles through scalar loads (k_force_scalar)
+  int chunk;     // j-particles per split unit of k_force_scalar
   int correct;   // apply the corrector to each target as its force is finished
   CorrectArgs corr;
 };
@@ -197,19 +198,20 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
 // record then sits in SGPRs and the pair arithmetic takes it as scalar operands.  No LDS
 // staging and no barriers; one target per lane.  Same tiles of kTJ j-particles, same
 // self-pair vote and the same float32-in-tile / float64-across-tiles sums as k_force.
-template <class V, int NEWTON, int MASK, int POT, class F>
+template <class V, int NEWTON, int MASK, int POT, int CH, class F>
 __device__ __forceinline__ void scalar_tile(const ForceArgs &A, const typename V::I &I, int g,
                                             int64_t jbase, F eps2, F &fx, F &fy, F &fz,
                                             F &fp) {
 #pragma unroll 8
-  for (int jj = 0; jj < kTJ; ++jj) {
+  for (int jj = 0; jj < CH; ++jj) {
     const typename V::J J =
         V::load_j(A.p32, A.p64, A.npad, jbase + jj, Scale<V, NEWTON>::kMass);
     pair_acc<V, NEWTON, MASK, POT>(I, J, eps2, MASK && (jbase + jj == g), fx, fy, fz, fp);
   }
 }
 
-template <class V, int NEWTON, int POT>
+// Split units of CH j-particles (A.n_jtiles counts them here).
+template <class V, int NEWTON, int POT, int CH>
 __global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
   using F = typename V::F;
   const int L = xcd_linear(blockIdx.x, A.plan.nblk);
@@ -224,12 +226,12 @@ __global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
   const typename V::I I = V::load_i(A.p32, A.p64, A.npad, g);
   double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
   for (int jt = jt0; jt < jt1; ++jt) {
-    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const int64_t jbase = static_cast<int64_t>(jt) * CH;
     F fx = F(0), fy = F(0), fz = F(0), fp = F(0);
-    if (__ballot(g >= jbase && g < jbase + kTJ) != 0)
-      scalar_tile<V, NEWTON, 1, POT>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+    if (__ballot(g >= jbase && g < jbase + CH) != 0)
+      scalar_tile<V, NEWTON, 1, POT, CH>(A, I, g, jbase, eps2, fx, fy, fz, fp);
     else
-      scalar_tile<V, NEWTON, 0, POT>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+      scalar_tile<V, NEWTON, 0, POT, CH>(A, I, g, jbase, eps2, fx, fy, fz, fp);
     sx += static_cast<double>(fx);
     sy += static_cast<double>(fy);
     sz += static_cast<double>(fz);
@@ -353,11 +355,20 @@ hipError_t launch_reduce(ForceArgs &A, hipStream_t st) {
 
 template <class V, int NEWTON>
 hipError_t run_scalar(ForceArgs &A, hipStream_t st) {
+  A.n_jtiles = static_cast<int>(A.npad / A.chunk);
   A.plan = plan_split(A.n_act, 1, A.n_jtiles, A.blocks);
-  if (A.pot)
-    hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  else
-    hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 0>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+  const dim3 grid(A.plan.nblk), block(kWG);
+  if (A.chunk == kChunkSmall) {
+    if (A.pot)
+      hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 1, kChunkSmall>), grid, block, 0, st, A);
+    else
+      hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 0, kChunkSmall>), grid, block, 0, st, A);
+  } else {
+    if (A.pot)
+      hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 1, kTJ>), grid, block, 0, st, A);
+    else
+      hipLaunchKernelGGL((k_force_scalar<V, NEWTON, 0, kTJ>), grid, block, 0, st, A);
+  }
   return launch_reduce<V, NEWTON>(A, st);
 }
 
@@ -427,10 +438,13 @@ int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
   // per target instead of 4
   if (n_act <= kSmallAct) return n_jtiles * 4 * n_act;
   const SplitPlan pf =
-      plan_split(n_act, force_targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
-  const SplitPlan pc =
-      plan_split(n_act, criterion_targets_per_lane(c, n_act), n_jtiles,
-                 criterion_blocks(c, n_act));
+      force_scalar_j(c)
+          ? plan_split(n_act, 1, c->npad / scalar_chunk(c, n_act, 1), c->tune_blocks)
+          : plan_split(n_act, force_targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
+  const int ipl_c = criterion_targets_per_lane(c, n_act);
+  const int64_t units_c =
+      criterion_scalar_j(c, n_act) ? c->npad / scalar_chunk(c, n_act, ipl_c) : n_jtiles;
+  const SplitPlan pc = plan_split(n_act, ipl_c, units_c, criterion_blocks(c, n_act));
   const int64_t need_f = pf.n_slices > 1 ? static_cast<int64_t>(pf.n_slices) * 4 * n_act : 0;
   const int64_t need_c = pc.n_slices > 1 ? static_cast<int64_t>(pc.n_slices) * 2 * n_act : 0;
   return std::max(need_f, need_c);
@@ -455,6 +469,7 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   A.blocks = c->tune_blocks;
   A.ipl = force_targets_per_lane(c, n_act);
   A.scalar_j = force_scalar_j(c) ? 1 : 0;
+  A.chunk = scalar_chunk(c, n_act, 1);
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;

@@ -70,6 +70,7 @@ struct tsbts_ctx {
   // launch-shape tuning (tsbts_tune)
   int tune_blocks = 8192;
   int tune_ipl = 0;
+  int tune_chunk = 0;  // j-particles per split unit of the scalar-load kernels (0: automatic)
   char err[512] = {0};
 };
 
@@ -168,17 +169,27 @@ inline bool force_scalar_j(const tsbts_ctx *c) { return c->tune_ipl == 0; }
 inline int force_targets_per_lane(const tsbts_ctx *c, int n_act) {
   return force_scalar_j(c) ? 1 : targets_per_lane(c, n_act);
 }
-// The criterion kernel likewise for large active sets (from 8192 targets; below that the
-// LDS-staged kernel with one target per lane measured faster); its scalar-load form holds
-// two targets per lane and is launched on twice the workgroups.
+// j-particles per split unit of the scalar-load kernels: whole tiles of kTJ, or quarter
+// tiles when whole tiles would give too few workgroups to fill the chip (small N or small
+// active sets), so that the j-range splits over 4x more workgroups.
+constexpr int kChunkSmall = 64;
+inline int scalar_chunk(const tsbts_ctx *c, int n_act, int ipl) {
+  if (c->tune_chunk) return c->tune_chunk;
+  const int64_t itiles = (n_act + ipl * kWG - 1) / (ipl * kWG);
+  return itiles * (c->npad / kTJ) < 512 ? kChunkSmall : kTJ;
+}
+// The criterion kernel likewise for large active sets (from 8192 targets, two targets per
+// lane, twice the workgroups) and for small launches (one target per lane, quarter-tile
+// units); in between the LDS-staged kernel with one target per lane measured faster.
 inline bool criterion_scalar_j(const tsbts_ctx *c, int n_act) {
-  return force_scalar_j(c) && n_act >= 8192;
+  return force_scalar_j(c) && (n_act >= 8192 || scalar_chunk(c, n_act, 1) == kChunkSmall);
 }
 inline int criterion_targets_per_lane(const tsbts_ctx *c, int n_act) {
-  return criterion_scalar_j(c, n_act) ? 2 : targets_per_lane(c, n_act);
+  if (!criterion_scalar_j(c, n_act)) return targets_per_lane(c, n_act);
+  return n_act >= 8192 ? 2 : 1;
 }
 inline int criterion_blocks(const tsbts_ctx *c, int n_act) {
-  return criterion_scalar_j(c, n_act) ? 2 * c->tune_blocks : c->tune_blocks;
+  return criterion_scalar_j(c, n_act) && n_act >= 8192 ? 2 * c->tune_blocks : c->tune_blocks;
 }
 
 // ------------------------------------------------------------------ launchers

@@ -31,6 +31,7 @@ struct StepArgs {
   int blocks;
   int ipl;
   int scalar_j;  // j-particles through scalar loads (k_timestep_scalar)
+  int chunk;     // j-particles per split unit of k_timestep_scalar
 };
 
 template <class V> struct StepRec;
@@ -210,11 +211,11 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
 // j-particles through scalar loads (wave-uniform j index): the j record comes straight
 // from the predicted planes into SGPRs, no LDS staging and no barriers.  Same tiles, vote
 // and partials as k_timestep.
-template <class V, int MASK, int IPL, class I, class F>
+template <class V, int MASK, int IPL, int CH, class I, class F>
 __device__ __forceinline__ void scalar_step_tile(const StepArgs &A, const I *Ir, const int *g,
                                                  int64_t jbase, F eps2, F *qmax, F *swmin) {
 #pragma unroll 4
-  for (int jj = 0; jj < kTJ; ++jj) {
+  for (int jj = 0; jj < CH; ++jj) {
     const typename StepRec<V>::J Jr = load_jv<V>(A, jbase + jj);
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
@@ -223,7 +224,8 @@ __device__ __forceinline__ void scalar_step_tile(const StepArgs &A, const I *Ir,
   }
 }
 
-template <class V, int IPL>
+// Split units of CH j-particles (A.n_jtiles counts them here).
+template <class V, int IPL, int CH>
 __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
   using F = typename V::F;
   const int tid = threadIdx.x;
@@ -246,14 +248,14 @@ __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
     swmin[k] = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
   }
   for (int jt = jt0; jt < jt1; ++jt) {
-    const int64_t jbase = static_cast<int64_t>(jt) * kTJ;
+    const int64_t jbase = static_cast<int64_t>(jt) * CH;
     bool mine = false;
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + kTJ);
-    if (__ballot(mine) != 0 || jbase + kTJ > A.n)
-      scalar_step_tile<V, 1, IPL>(A, I, g, jbase, eps2, qmax, swmin);
+    for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + CH);
+    if (__ballot(mine) != 0 || jbase + CH > A.n)
+      scalar_step_tile<V, 1, IPL, CH>(A, I, g, jbase, eps2, qmax, swmin);
     else
-      scalar_step_tile<V, 0, IPL>(A, I, g, jbase, eps2, qmax, swmin);
+      scalar_step_tile<V, 0, IPL, CH>(A, I, g, jbase, eps2, qmax, swmin);
   }
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
@@ -358,8 +360,17 @@ hipError_t run(StepArgs &A, hipStream_t st) {
     A.plan.nblk = A.n_jtiles;
     hipLaunchKernelGGL((k_timestep_small<V>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
   } else if (A.scalar_j) {
-    A.plan = plan_split(A.n_act, 2, A.n_jtiles, A.blocks);
-    hipLaunchKernelGGL((k_timestep_scalar<V, 2>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
+    A.n_jtiles = static_cast<int>(A.npad / A.chunk);
+    A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
+    const dim3 grid(A.plan.nblk), block(kWG);
+    if (A.ipl == 2 && A.chunk == kTJ)
+      hipLaunchKernelGGL((k_timestep_scalar<V, 2, kTJ>), grid, block, 0, st, A);
+    else if (A.ipl == 2)
+      hipLaunchKernelGGL((k_timestep_scalar<V, 2, kChunkSmall>), grid, block, 0, st, A);
+    else if (A.chunk == kTJ)
+      hipLaunchKernelGGL((k_timestep_scalar<V, 1, kTJ>), grid, block, 0, st, A);
+    else
+      hipLaunchKernelGGL((k_timestep_scalar<V, 1, kChunkSmall>), grid, block, 0, st, A);
   } else {
     A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
     if (A.ipl == 4)
@@ -399,6 +410,7 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.blocks = criterion_blocks(c, n_act);
   A.ipl = criterion_targets_per_lane(c, n_act);
   A.scalar_j = criterion_scalar_j(c, n_act) ? 1 : 0;
+  A.chunk = scalar_chunk(c, n_act, A.ipl);
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);

@@ -37,12 +37,14 @@ def test_timestep_and_adjoint_launch_shapes(prec):
     ctx.bind(r, v, m)
     ctx.predict(0.0)
     sets = [np.arange(n, dtype=np.int32), active_subset(n, 8500, 4), active_subset(n, 300, 5)]
-    for blocks, ipl in [(8192, 0), (64, 0), (65536, 0), (8192, 1), (8192, 2), (8192, 4)]:
-        ctx.tune(blocks=blocks, ipl=ipl)
+    for blocks, ipl, chunk in [(8192, 0, 0), (64, 0, 0), (65536, 0, 0), (8192, 0, 64),
+                               (8192, 0, 256), (8192, 1, 0), (8192, 2, 0), (8192, 4, 0)]:
+        ctx.tune(blocks=blocks, ipl=ipl, chunk=chunk)
         for idx in sets:
             dtc = ctx.timestep(idx, eta).cpu().numpy()
             e = rel_err(dtc, oracle.timestep(r, v, m, eps, eta, idx))
-            assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), (blocks, ipl, idx.size)
+            assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), (blocks, ipl, chunk,
+                                                                    idx.size)
             g = gaussian((3, idx.size), 9)
             gr, gm = ctx.force_backward(idx, 0.0, g)
             rr, rm = oracle.force_backward(r, m, eps, idx, g)
