@@ -53,14 +53,14 @@ FLOPS_CRITERION = 20.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (313244.3, 131072.0, ("timestep.hip", "pair.hpp", "internal.hpp"),
-                          "062b879bc45c617e"),
-    "k_force_scalar": (40641.0, 65536.0,
-                       ("force.hip", "pair.hpp", "internal.hpp", "correct.hpp"),
-                       "c2aca8a949640384"),
-    "k_bwd_all": (65025.9, 65536.0, ("backward.hip", "pair.hpp", "internal.hpp"),
-                  "15d0ce57f04ef531"),
-    "k_energy_pairs": (23390.4, 4104.0, ("energy.hip", "internal.hpp"), "b8d560950cc12f53"),
+    "k_timestep_scalar": (313247.7, 131072.0,
+        ("timestep.hip", "pair.hpp", "internal.hpp"), "832cd4d21931c1b7"),
+    "k_force_scalar": (40786.5, 65536.0,
+        ("force.hip", "pair.hpp", "internal.hpp", "correct.hpp"), "2b7eb0ee7d0f41e1"),
+    "k_bwd_all": (65026.4, 65536.0,
+        ("backward.hip", "pair.hpp", "internal.hpp"), "cc45e862ec197fc7"),
+    "k_energy_pairs": (23313.8, 4104.0,
+        ("energy.hip", "internal.hpp"), "00f2544f23a5b12a"),
 }
 
 
