@@ -124,13 +124,22 @@ def main(argv=None):
     ap.add_argument("--eta", type=float, default=0.1)
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--passes", type=int, nargs="+", default=None)
+    ap.add_argument("--eras", type=float, nargs="+", default=None,
+                    help="fixed era sizes of the era study (default 1/64 ... 1/4)")
+    ap.add_argument("--seed0", type=int, default=None, help="first sphere's seed")
+    ap.add_argument("--every", type=float, default=1.0, help="energy sampling interval")
     args = ap.parse_args(argv)
     if args.study == "era":
+        kw = {} if args.eras is None else {"eras": tuple(args.eras)}
+        if args.seed0 is not None:
+            kw["seed0"] = args.seed0
         era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta, eps=args.eps,
-                  passes=tuple(args.passes or (3, 5)))
+                  passes=tuple(args.passes or (3, 5)), every=args.every, **kw)
     else:
+        kw = {} if args.seed0 is None else {"seed0": args.seed0}
         dynamic_era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta,
-                          eps=args.eps, passes=(args.passes or [3])[0])
+                          eps=args.eps, passes=(args.passes or [3])[0], every=args.every,
+                          **kw)
 
 
 if __name__ == "__main__":
