@@ -238,7 +238,7 @@ class TSBTS:
         energy_every (default dt_max), where every particle is synchronised."""
         stop = to_ticks(t_end)
         every = self.dt_max if energy_every is None else to_ticks(energy_every)
-        out = [(0.0, self.energy())]
+        out = [(self.time * TICK, self.energy())]
         t0 = time.perf_counter()
         while self.time < stop:
             T1 = self.era_step()
@@ -304,7 +304,7 @@ class NativeTSBTS:
     def run(self, t_end: float, energy_every: float | None = None):
         stop = to_ticks(t_end)
         every = self.dt_max if energy_every is None else to_ticks(energy_every)
-        out = [(0.0, self.energy())]
+        out = [(self.time * TICK, self.energy())]
         t0 = time.perf_counter()
         while self.time < stop:
             T1 = self.era_step()

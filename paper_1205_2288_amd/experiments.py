@@ -47,7 +47,16 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
     sim = NativeTSBTS(r, v, m, eps, eta=eta, passes=passes, era=era, dt_max=dt_max,
                       precision=precision)
     t0 = time.perf_counter()
-    series = sim.run(t_end, energy_every=every)
+    series = []
+    t_mark = 0.0
+    while t_mark < t_end:
+        # integrate in segments of at most 25 time units, reporting progress on stderr
+        t_mark = min(t_end, t_mark + max(every, 25.0))
+        seg = sim.run(t_mark, energy_every=every)
+        series.extend(seg if not series else seg[1:])
+        print(f"n={n} seed={seed} passes={passes} era={era} t={t_mark:g} "
+              f"steps={sim.stats['block_steps']} wall={time.perf_counter() - t0:.1f}s",
+              file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     st = sim.stats
     sim.close()
