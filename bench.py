@@ -349,7 +349,7 @@ def main():
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
