@@ -102,10 +102,14 @@ class Timer:
 
 
 class EraBench:
-    def __init__(self, cfg, r, v, m, precision, h=2.0 ** -10, seed=0):
+    """fused=True: the variant that takes the criterion before the corrector, in the same
+    pass over the pairs as the force (tsbts_force_criterion)."""
+
+    def __init__(self, cfg, r, v, m, precision, h=2.0 ** -10, seed=0, fused=False):
         from paper_1205_2288_amd import Context
         n = cfg.n
         self.n, self.h = n, h
+        self.fused = fused
         self.ctx = c = Context(n, cfg.eps, precision=precision)
         fine = active_subset(n, n // 2, cfg.seed + 11)
         dt = np.full(n, h)
@@ -140,6 +144,12 @@ class EraBench:
             for tb, idx, acc, dtc in ((h / 2, self.idx_fine, self.acc_fine, self.dtc_fine),
                                       (h, self.idx_all, self.acc_all, self.dtc_all)):
                 t("predict", c.predict, tb, use_history=p > 0)
+                if self.fused:
+                    t("force_criterion_full" if idx is self.idx_all else
+                      "force_criterion_half", c.force_criterion, idx, tb, self.eta,
+                      with_pot=False, acc=acc, dtc=dtc)
+                    t("correct", c.correct, idx, tb, acc)
+                    continue
                 t("force_full" if idx is self.idx_all else "force_half", c.force, idx, tb,
                   with_pot=False, acc=acc)
                 t("correct", c.correct, idx, tb, acc)
@@ -412,6 +422,16 @@ def main():
         out["sweep_fp64"] = sweep(cfg, r, v, m, "fp64")
     if not args.no_pass_cost:
         out["pass_cost"] = pass_cost()
+    if not args.no_sweep:
+        bf = EraBench(cfg, r, v, m, "mixed", fused=True)
+        stepsf = max(2, args.steps // 2)
+        wallf, msf = time_steps(bf, stepsf, 1)
+        out["criterion_before_corrector"] = {
+            "ms_per_step": wallf / stepsf * 1e3,
+            "value": bf.interactions * stepsf / wallf,
+            "speedup_vs_paper_order": (wall / args.steps) / (wallf / stepsf),
+            "breakdown_us": {k: float(np.mean(x)) * 1e3 for k, x in msf.items()}}
+        bf.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, r, v, m, gpu_force_rows(cfg, r, v, m))
     else:

@@ -169,6 +169,16 @@ int tsbts_correct(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
 int tsbts_timestep(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active, double eta,
                    double *dtc, hipStream_t stream);
 
+/* Force, potential and time-step criterion of the active set in one pass over the pairs:
+ * a variant of Algorithm 2's order in which the criterion is taken before the corrector,
+ * with the predicted velocities of the active particles (the paper takes it after the
+ * corrector, with their corrected velocities; positions are the same either way).
+ * acc, pot as tsbts_force (pot may be NULL); dtc [n_active] as tsbts_timestep.  Needs a
+ * prediction at t_block; errors as tsbts_force and tsbts_timestep. */
+int tsbts_force_criterion(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                          double t_block, double eta, double *acc, double *pot, double *dtc,
+                          hipStream_t stream);
+
 /* Scatter new block steps: dt[active_idx[k]] = dt_new[k] (dt_new device [n_active]). */
 int tsbts_set_dt(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
                  const double *dt_new, hipStream_t stream);
@@ -269,6 +279,17 @@ int tsbts_sched_rule(int first_pass, int64_t dt, int64_t t_block, double begin, 
  * synchronises the stream. */
 int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, double dt_max,
                      double era, hipStream_t stream);
+
+/* options of tsbts_sched_option */
+#define TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR 1
+
+/* Scheduler option (host only; applies from the next block step):
+ *   TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR: 0 = the paper's order, criterion after the
+ *     corrector (default); 1 = criterion with the predicted velocities, in the same pass
+ *     over the pairs as the force (tsbts_force_criterion).
+ * Returns TSBTS_ESTATE before tsbts_sched_init, TSBTS_EINVAL for an unknown option or
+ * value. */
+int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);
 
 /* Integrate one era with all its passes; *era_end (host, may be NULL) receives its end
  * time.  The bound state then holds the final pass's state; particles are synchronised at

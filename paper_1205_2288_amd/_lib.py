@@ -57,6 +57,8 @@ _SIGS = {
     "tsbts_predict": ([_p, _d, _int, _p], _int),
     "tsbts_load_positions": ([_p, _p, _p, _d, _p], _int),
     "tsbts_force": ([_p, _p, _i32, _d, _p, _p, _p], _int),
+    "tsbts_force_criterion": ([_p, _p, _i32, _d, _d, _p, _p, _p, _p], _int),
+    "tsbts_sched_option": ([_p, _int, _int], _int),
     "tsbts_force_backward": ([_p, _p, _i32, _d, _p, _p, _p, _p, _p], _int),
     "tsbts_correct": ([_p, _p, _i32, _d, _p, _p], _int),
     "tsbts_timestep": ([_p, _p, _i32, _d, _p, _p], _int),
@@ -156,6 +158,7 @@ def tsbts_destroy(ctx):
 TSBTS_TUNE_BLOCKS = 1
 TSBTS_TUNE_IPL = 2
 TSBTS_TUNE_CHUNK = 3
+TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR = 1
 
 
 def tsbts_tune(ctx, param: int, value: int):
@@ -175,6 +178,14 @@ def tsbts_predict(ctx, t_block, use_history=False, stream=None):
 def tsbts_load_positions(ctx, n, r, m, t_label=0.0, stream=None):
     _check(ctx, lib.tsbts_load_positions(ctx, _f64(r, (3, n), "r"), _f64(m, (n,), "m"),
                                          float(t_label), _stream(stream)))
+
+
+def tsbts_force_criterion(ctx, active_idx, t_block, eta, acc, pot, dtc, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_force_criterion(ctx, _i32p(active_idx), k, float(t_block),
+                                          float(eta), _f64(acc, (3, k), "acc"),
+                                          _f64(pot, (k,), "pot"), _f64(dtc, (k,), "dtc"),
+                                          _stream(stream)))
 
 
 def tsbts_force(ctx, active_idx, t_block, acc, pot=None, stream=None):
@@ -265,6 +276,10 @@ def tsbts_sched_rule(first_pass: bool, dt: int, t_block: int, begin: float, end_
                                       float(begin), float(end_dt), float(end_2dt),
                                       int(dt_min), int(dt_max), ctypes.byref(out)))
     return out.value
+
+
+def tsbts_sched_option(ctx, option, value):
+    _check(ctx, lib.tsbts_sched_option(ctx, int(option), int(value)))
 
 
 def tsbts_sched_init(ctx, eta, passes, dt_min, dt_max, era, stream=None):

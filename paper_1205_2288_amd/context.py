@@ -116,6 +116,23 @@ class Context:
         L.tsbts_force(self.ctx, idx, t_block, acc, pot if with_pot else None, stream)
         return acc, pot
 
+    def force_criterion(self, active, t_block, eta, with_pot=True, acc=None, pot=None,
+                        dtc=None, stream=None):
+        """Force, potential and criterion in one pass, the criterion with the predicted
+        velocities (tsbts_force_criterion).  Returns (acc, pot, dtc)."""
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        k = idx.numel()
+        if acc is None:
+            acc = torch.empty((3, k), dtype=torch.float64, device=self.device)
+        if with_pot and pot is None:
+            pot = torch.empty(k, dtype=torch.float64, device=self.device)
+        if dtc is None:
+            dtc = torch.empty(k, dtype=torch.float64, device=self.device)
+        L.tsbts_force_criterion(self.ctx, idx, t_block, eta, acc, pot if with_pot else None,
+                                dtc, stream)
+        return acc, (pot if with_pot else None), dtc
+
     def force_backward(self, active, t_block, grad_acc, grad_pot=None, grad_r=None,
                        grad_m=None, stream=None):
         idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \

@@ -212,8 +212,9 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
     st = dev_alloc(c, &c->epart, c->epart_cap);
   }
   if (!st) {
-    const int64_t need = std::max(partial_elems_needed(c, static_cast<int>(n)),
-                                  backward_partials_needed(c, static_cast<int>(n)));
+    const int64_t need = std::max({partial_elems_needed(c, static_cast<int>(n)),
+                                   backward_partials_needed(c, static_cast<int>(n)),
+                                   fused_partials_needed(c, static_cast<int>(n))});
     st = ensure_part(c, need);
   }
   if (st) {
@@ -319,6 +320,20 @@ int tsbts_force(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
   hipError_t e = launch_force(c, idx, n_act, acc, pot, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_force launch");
+  return TSBTS_OK;
+}
+
+int tsbts_force_criterion(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                          double eta, double *acc, double *pot, double *dtc,
+                          hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
+  if (int s = check_pred(c, t_block)) return s;
+  if (int s = ensure_part(c, fused_partials_needed(c, n_act))) return s;
+  hipError_t e = launch_fused(c, idx, n_act, eta, acc, pot, dtc, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_force_criterion launch");
   return TSBTS_OK;
 }
 
@@ -495,6 +510,29 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
   const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
   hipError_t e = launch_force(c, idx, n_act, acc, nullptr, stream, &corr);
   if (e != hipSuccess) return hip_fail(c, e, "force + corrector launch");
+  if (c->h.recording) c->h.count += n_act;
+  return TSBTS_OK;
+}
+
+// The fused force + criterion with the corrector in its reduction (the native
+// scheduler's block step when the criterion is taken before the corrector).
+int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                            double eta, double *acc, double *dtc, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
+  if (int s = check_pred(c, t_block)) return s;
+  if (int s = ensure_part(c, fused_partials_needed(c, n_act))) return s;
+  if (c->h.recording) {
+    const int64_t need = c->h.count + n_act;
+    if (need >= (int64_t(1) << 31))
+      return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
+    if (int s = grow_log(c, need, stream)) return s;
+  }
+  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  hipError_t e = launch_fused(c, idx, n_act, eta, acc, nullptr, dtc, stream, &corr);
+  if (e != hipSuccess) return hip_fail(c, e, "force + criterion + corrector launch");
   if (c->h.recording) c->h.count += n_act;
   return TSBTS_OK;
 }

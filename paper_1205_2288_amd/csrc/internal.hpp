@@ -202,6 +202,14 @@ hipError_t launch_snapshot(tsbts_ctx *c, double T, double *r_out, double *v_out,
                            hipStream_t st);
 
 struct CorrectArgs;
+// Force, potential and criterion (with the predicted velocities) in one pass; with corr,
+// the corrector runs in its reduction.
+int64_t fused_partials_needed(const tsbts_ctx *c, int n_act);
+hipError_t launch_fused(tsbts_ctx *c, const int32_t *idx, int n_act, double eta, double *acc,
+                        double *pot, double *dtc, hipStream_t st,
+                        const CorrectArgs *corr = nullptr);
+int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                            double eta, double *acc, double *dtc, hipStream_t stream);
 // Force on the active set and its corrector in the same launches (checked like the two
 // entry points; returns a status code).
 int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,

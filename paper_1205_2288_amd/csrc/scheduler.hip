@@ -143,6 +143,7 @@ struct Scheduler {
   std::vector<int64_t> s0_t, s0_dt;
   std::vector<double> s0_dtc;
   int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
+  int crit_before = 0;  // criterion with the predicted velocities, fused with the force
 
   void rebuild_levels() {
     for (auto &m : mem) m.clear();
@@ -233,8 +234,13 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
     SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
     SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
-    SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st));
-    SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
+    if (S.crit_before) {
+      SCHED_CALL(tsbts::force_criterion_correct(c, S.idx_d, k, tbs, S.eta, S.acc_d, S.dtc_hd,
+                                                st));
+    } else {
+      SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st));
+      SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
+    }
     SCHED_HIP(hipStreamSynchronize(st));
     for (int32_t q = 0; q < k; ++q) {
       const int32_t i = S.idx_h[q];
@@ -400,6 +406,17 @@ int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
   S->time = T1;
   S->stats[3] += 1;
   if (era_end) *era_end = static_cast<double>(T1) * tsbts::kTick;
+  return TSBTS_OK;
+}
+
+int tsbts_sched_option(tsbts_ctx *c, int option, int value) {
+  if (!c) return TSBTS_EINVAL;
+  Scheduler *S = static_cast<Scheduler *>(c->sched);
+  if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_option: call tsbts_sched_init first");
+  if (option != TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR)
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_option: unknown option");
+  if (value != 0 && value != 1) return sfail(c, TSBTS_EINVAL, "option value must be 0 or 1");
+  S->crit_before = value;
   return TSBTS_OK;
 }
 

@@ -267,8 +267,13 @@ class NativeTSBTS:
     the loop.  Same readings and results as TSBTS."""
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
-                 era=None, precision="mixed", separation="f64", newton=False):
+                 era=None, precision="mixed", separation="f64", newton=False,
+                 criterion="after"):
+        """criterion: "after" the corrector (the paper's order) or "before" it, with the
+        predicted velocities, in the same pass over the pairs as the force."""
         from . import _lib as L
+        if criterion not in ("after", "before"):
+            raise ValueError("criterion must be 'after' or 'before'")
         self._L = L
         self.n = n = int(np.asarray(m).size)
         self.dt_max = to_ticks(dt_max)
@@ -276,6 +281,8 @@ class NativeTSBTS:
         self.ctx.bind(r, v, m)
         L.tsbts_sched_init(self.ctx.ctx, eta, passes, dt_min, dt_max,
                            0.0 if era is None else era)
+        if criterion == "before":
+            L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR, 1)
         self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
         self._host()
         self.wall_s = 0.0
