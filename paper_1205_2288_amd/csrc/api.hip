@@ -331,8 +331,17 @@ int tsbts_force_criterion(tsbts_ctx *c, const int32_t *idx, int32_t n_act, doubl
   if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
   if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
   if (int s = check_pred(c, t_block)) return s;
-  if (int s = ensure_part(c, fused_partials_needed(c, n_act))) return s;
-  hipError_t e = launch_fused(c, idx, n_act, eta, acc, pot, dtc, stream);
+  hipError_t e;
+  if (n_act <= kSmallAct) {
+    // small sets: the j-parallel criterion and force kernels, criterion first, on the same
+    // predicted state (same definition as the fused pass, fewer idle lanes)
+    if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+    e = launch_timestep(c, idx, n_act, eta, dtc, stream);
+    if (e == hipSuccess) e = launch_force(c, idx, n_act, acc, pot, stream);
+  } else {
+    if (int s = ensure_part(c, fused_partials_needed(c, n_act))) return s;
+    e = launch_fused(c, idx, n_act, eta, acc, pot, dtc, stream);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_force_criterion launch");
   return TSBTS_OK;
 }
@@ -523,7 +532,9 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
   if (int s = check_active(c, idx, n_act)) return s;
   if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
   if (int s = check_pred(c, t_block)) return s;
-  if (int s = ensure_part(c, fused_partials_needed(c, n_act))) return s;
+  if (int s = ensure_part(c, std::max(fused_partials_needed(c, n_act),
+                                      partial_elems_needed(c, n_act))))
+    return s;
   if (c->h.recording) {
     const int64_t need = c->h.count + n_act;
     if (need >= (int64_t(1) << 31))
@@ -531,7 +542,15 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
     if (int s = grow_log(c, need, stream)) return s;
   }
   const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
-  hipError_t e = launch_fused(c, idx, n_act, eta, acc, nullptr, dtc, stream, &corr);
+  hipError_t e;
+  if (n_act <= kSmallAct) {
+    // small sets: the criterion on the predicted state first, then the force with the
+    // corrector (the corrector rewrites the velocities the criterion reads)
+    e = launch_timestep(c, idx, n_act, eta, dtc, stream);
+    if (e == hipSuccess) e = launch_force(c, idx, n_act, acc, nullptr, stream, &corr);
+  } else {
+    e = launch_fused(c, idx, n_act, eta, acc, nullptr, dtc, stream, &corr);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "force + criterion + corrector launch");
   if (c->h.recording) c->h.count += n_act;
   return TSBTS_OK;
