@@ -53,14 +53,15 @@ FLOPS_CRITERION = 20.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (313247.7, 131072.0,
-        ("timestep.hip", "pair.hpp", "internal.hpp"), "832cd4d21931c1b7"),
-    "k_force_scalar": (40786.5, 65536.0,
-        ("force.hip", "pair.hpp", "internal.hpp", "correct.hpp"), "2b7eb0ee7d0f41e1"),
-    "k_bwd_all": (65026.4, 65536.0,
-        ("backward.hip", "pair.hpp", "internal.hpp"), "cc45e862ec197fc7"),
-    "k_energy_pairs": (23313.8, 4104.0,
-        ("energy.hip", "internal.hpp"), "00f2544f23a5b12a"),
+    "k_timestep_scalar": (313277.0, 131072.0,
+        ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp"), "08eebd53e86dfdfb"),
+    "k_force_scalar": (40750.7, 65536.0,
+        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
+        "67ba1a56ff01859d"),
+    "k_bwd_all": (64964.3, 65536.0,
+        ("backward.hip", "pair.hpp", "internal.hpp"), "248afc0475cd86fb"),
+    "k_energy_pairs": (22007.1, 4104.0,
+        ("energy.hip", "internal.hpp"), "1c85c27126d2c652"),
 }
 
 
