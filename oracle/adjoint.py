@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import force, force_backward
+from . import force, force_backward, hermite
 
 
 def forward(r0, v0, m, eps, h, nsteps):
@@ -145,6 +145,195 @@ def block_gradient(r0, v0, m, eps, dt, t_end, r_target, v_target):
         rbar += pbar
         vbar += hh * pbar
         abar += 0.5 * hh * hh * pbar
+    gr, gm = force_backward(np.asarray(r0, dtype=np.float64), m, eps,
+                            np.arange(n, dtype=np.int32), abar)
+    return L, rbar + gr, vbar, mbar + gm
+
+
+# ----------------------------------------------------------------------------------------
+# Fixed block schedule with eras and passes (Section 2's time-symmetric scheme on a given
+# schedule).  The run is cut into eras of length `era` (a multiple of the largest step, so
+# every particle is due at each era end).  Each era is integrated `passes` times from its
+# start state.  A pass records, per particle, the era-start state and the state after each
+# of its steps (t, r, v, a).  In the first pass every particle is Taylor-predicted to the
+# block time; from the second pass on the active particles are still Taylor-predicted from
+# their own state (their leapfrog position) and every other particle is taken from the
+# previous pass's records: the record itself at a stored time, otherwise the cubic Hermite
+# interpolant between the two records that bracket the block time.  The era ends with the
+# last pass's state.  With passes = 1 this is ``block_forward``.
+
+
+def _records_new(r, v, a, t0):
+    """Per-particle lists of (t, r, v, a), starting with the era-start state."""
+    return [[(t0, r[:, j].copy(), v[:, j].copy(), a[:, j].copy())] for j in range(r.shape[1])]
+
+
+def _bracket(recs_j, t):
+    """Index of the last record with time <= t (at least 0)."""
+    k = 0
+    while k + 1 < len(recs_j) and recs_j[k + 1][0] <= t:
+        k += 1
+    return k
+
+
+def _era_times(dt, t_end, era):
+    dt = np.asarray(dt, dtype=np.float64)
+    hmin = float(dt.min())
+    assert era % float(dt.max()) == 0.0, "the era must be a multiple of the largest step"
+    n_era = int(round(t_end / era))
+    assert n_era * era == t_end, "t_end must be a multiple of the era"
+    per = int(round(era / hmin))
+    return [(e * era, [e * era + hmin * (s + 1) for s in range(per)]) for e in range(n_era)]
+
+
+def _pass(state, m, eps, dt, times, prev):
+    """One pass over an era's block times from `state` (modified in place); prev = the
+    previous pass's records or None.  Returns (records, steps) with steps[s] = (t_b, act,
+    pre-step r, v, a, t_last, interpolated: list of (j, k, exact))."""
+    r, v, a, t_last = state
+    recs = _records_new(r, v, a, float(t_last[0]))
+    steps = []
+    for t_b in times:
+        act = np.nonzero(t_last + dt == t_b)[0].astype(np.int32)
+        hh = t_b - t_last
+        p = r + v * hh + 0.5 * a * hh * hh
+        interp = []
+        if prev is not None:
+            is_act = np.zeros(dt.size, dtype=bool)
+            is_act[act] = True
+            for j in np.nonzero(~is_act)[0]:
+                k = _bracket(prev[j], t_b)
+                tk, rk, vk, ak = prev[j][k]
+                if tk == t_b:
+                    p[:, j] = rk
+                    interp.append((j, k, True))
+                elif k + 1 < len(prev[j]):
+                    t1, r1, v1, a1 = prev[j][k + 1]
+                    p[:, j] = hermite(tk, rk, vk, ak, t1, r1, v1, a1, t_b)[0]
+                    interp.append((j, k, False))
+        steps.append((t_b, act, r.copy(), v.copy(), a.copy(), t_last.copy(), interp))
+        an, _ = force(p, m, eps, act)
+        r[:, act] = p[:, act]
+        v[:, act] = v[:, act] + 0.5 * dt[act] * (a[:, act] + an)
+        a[:, act] = an
+        t_last[act] = t_b
+        for q, i in enumerate(act):
+            recs[i].append((t_b, r[:, i].copy(), v[:, i].copy(), a[:, i].copy()))
+    return recs, steps
+
+
+def era_forward(r0, v0, m, eps, dt, t_end, era, passes):
+    """(r_end, v_end, eras); eras[e] = (era-start state, [(records, steps) per pass])."""
+    m = np.asarray(m, dtype=np.float64)
+    dt = np.asarray(dt, dtype=np.float64)
+    r = np.array(r0, dtype=np.float64)
+    v = np.array(v0, dtype=np.float64)
+    a, _ = force(r, m, eps)
+    t_last = np.zeros(dt.size)
+    out = []
+    for T0, times in _era_times(dt, t_end, era):
+        start = (r.copy(), v.copy(), a.copy(), t_last.copy())
+        prev = None
+        passes_log = []
+        for _ in range(passes):
+            r, v, a, t_last = (x.copy() for x in start)
+            recs, steps = _pass((r, v, a, t_last), m, eps, dt, times, prev)
+            passes_log.append((recs, steps))
+            prev = recs
+        out.append((start, passes_log))
+    return r, v, out
+
+
+def era_loss(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
+    r, v, _ = era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    return float(((r - r_target) ** 2).sum() + ((v - v_target) ** 2).sum())
+
+
+def _hermite_weights(t0, t1, t):
+    """Weights of (r0, v0, r1, v1) in the interpolated position: the interpolant is
+    linear in the stored values, so each weight is the interpolant of a unit value."""
+    one, zero = np.ones(1), np.zeros(1)
+    return tuple(float(hermite(t0, *ends[:3], t1, *ends[3:], t)[0][0]) for ends in (
+        (one, zero, zero, zero, zero, zero), (zero, one, zero, zero, zero, zero),
+        (zero, zero, zero, one, zero, zero), (zero, zero, zero, zero, one, zero)))
+
+
+def era_gradient(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
+    """(L, dL/dr0, dL/dv0, dL/dm) for L = |r_end - r_target|^2 + |v_end - v_target|^2, by
+    the chain rule in reverse: eras last to first, within an era passes last to first.
+    A pass's end state only reaches later passes through its records, so the reverse of
+    pass p starts from the adjoints of pass p's records (added to the state adjoint at the
+    block step that wrote each record) and hands the adjoints of the previous pass's
+    records on to it; every pass starts from the era-start state, whose adjoint is the sum
+    over the passes (plus the adjoints of the era-start records)."""
+    m = np.asarray(m, dtype=np.float64)
+    dt = np.asarray(dt, dtype=np.float64)
+    n = m.size
+    r_end, v_end, eras = era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    L = float(((r_end - r_target) ** 2).sum() + ((v_end - v_target) ** 2).sum())
+    rbar = 2.0 * (r_end - r_target)
+    vbar = 2.0 * (v_end - v_target)
+    abar = np.zeros_like(rbar)
+    mbar = np.zeros(n)
+    for start, passes_log in reversed(eras):
+        sr, sv, sa = np.zeros_like(rbar), np.zeros_like(rbar), np.zeros_like(rbar)
+        rec_bar = None  # adjoints [(R, V)] of the records of the pass being reversed
+        for p in range(len(passes_log) - 1, -1, -1):
+            recs, steps = passes_log[p]
+            prev = passes_log[p - 1][0] if p > 0 else None
+            prev_bar = None if prev is None else [
+                [[np.zeros(3), np.zeros(3)] for _ in rj] for rj in prev]
+            if p < len(passes_log) - 1:
+                rb, vb, ab = np.zeros_like(rbar), np.zeros_like(rbar), np.zeros_like(rbar)
+            else:
+                rb, vb, ab = rbar, vbar, abar
+            for (t_b, act, r, v, a, t_last, interp) in reversed(steps):
+                if rec_bar is not None:
+                    for i in act:
+                        k = [q for q, rec in enumerate(recs[i]) if rec[0] == t_b][0]
+                        rb[:, i] += rec_bar[i][k][0]
+                        vb[:, i] += rec_bar[i][k][1]
+                hh = t_b - t_last
+                p_pos = r + v * hh + 0.5 * a * hh * hh
+                if prev is not None:
+                    for (j, k, exact) in interp:
+                        if exact:
+                            p_pos[:, j] = prev[j][k][1]
+                        else:
+                            tk, rk, vk, ak = prev[j][k]
+                            t1, r1, v1, a1 = prev[j][k + 1]
+                            p_pos[:, j] = hermite(tk, rk, vk, ak, t1, r1, v1, a1, t_b)[0]
+                seed = ab[:, act] + 0.5 * dt[act] * vb[:, act]
+                pbar = np.zeros_like(rb)
+                pbar[:, act] = rb[:, act]
+                ab[:, act] = 0.5 * dt[act] * vb[:, act]
+                rb[:, act] = 0.0
+                gr, gm = force_backward(p_pos, m, eps, act, seed)
+                pbar += gr
+                mbar += gm
+                for (j, k, exact) in interp:
+                    if exact:
+                        prev_bar[j][k][0] += pbar[:, j]
+                    else:
+                        w_r0, w_v0, w_r1, w_v1 = _hermite_weights(prev[j][k][0],
+                                                                  prev[j][k + 1][0], t_b)
+                        prev_bar[j][k][0] += w_r0 * pbar[:, j]
+                        prev_bar[j][k][1] += w_v0 * pbar[:, j]
+                        prev_bar[j][k + 1][0] += w_r1 * pbar[:, j]
+                        prev_bar[j][k + 1][1] += w_v1 * pbar[:, j]
+                    pbar[:, j] = 0.0
+                rb += pbar
+                vb += hh * pbar
+                ab += 0.5 * hh * hh * pbar
+            if rec_bar is not None:
+                for j in range(n):
+                    rb[:, j] += rec_bar[j][0][0]
+                    vb[:, j] += rec_bar[j][0][1]
+            sr += rb
+            sv += vb
+            sa += ab
+            rec_bar = prev_bar
+        rbar, vbar, abar = sr, sv, sa
     gr, gm = force_backward(np.asarray(r0, dtype=np.float64), m, eps,
                             np.arange(n, dtype=np.int32), abar)
     return L, rbar + gr, vbar, mbar + gm

@@ -3,7 +3,10 @@
 The force adjoint is checked against central finite differences of the oracle force
 (a different code path: only the forward loops), and against two exact identities:
 translation invariance (the gradient summed over particles vanishes) and Euler's theorem
-(acceleration and potential are homogeneous of degree one in the masses)."""
+(acceleration and potential are homogeneous of degree one in the masses).  The gradients
+through runs (shared step, fixed block schedule, eras with several passes) are checked
+against central finite differences of the oracle runs, and the multi-pass run itself
+against the era driver of `oracle.tsbts` on the same fixed schedule."""
 import numpy as np
 import pytest
 
@@ -156,3 +159,67 @@ def test_force_backward_rows_equal_full(oracle, n_act):
     rows = np.array([0, 5, 17, 96, 40, 41], dtype=np.int32)
     rr, rm = oracle.force_backward_rows(r, m, eps, idx, ga, rows, gp)
     assert np.array_equal(rr, gr[:, rows]) and np.array_equal(rm, gm[rows])
+
+
+# ---------------------------------------------------------------- eras and passes
+def test_era_forward_matches_the_era_driver(oracle):
+    # the fixed-schedule multi-pass run is the era driver's run when the criterion hands
+    # every particle its own fixed step (two independent codings of Section 2's passes)
+    from oracle.tsbts import OracleTSBTS, TICK
+    n, eps, h = 16, 1.0 / 16, 1.0 / 64
+    r0, v0, m = plummer(n, 41)
+    dt = _levels_dt(n, h, 5)
+    for passes in (1, 3):
+        r, v, _ = adjoint.era_forward(r0, v0, m, eps, dt, 16 * h, 8 * h, passes)
+        sim = OracleTSBTS(r0, v0, m, eps, passes=passes, dt_max=4 * h, era=8 * h,
+                          criterion=lambda rr, vv, idx: dt[idx])
+        sim.run(16 * h)
+        assert np.all(sim.dt * TICK == dt)
+        assert np.allclose(r, sim.r, rtol=0, atol=1e-13)
+        assert np.allclose(v, sim.v, rtol=0, atol=1e-12)
+
+
+def test_era_forward_passes_change_the_run(oracle):
+    # later passes interpolate the non-active particles, so the result moves (by the
+    # interpolation error, small but far above rounding); one pass is the block run
+    n, eps, h = 16, 1.0 / 16, 1.0 / 64
+    r0, v0, m = plummer(n, 42)
+    dt = _levels_dt(n, h, 6)
+    r1, v1, _ = adjoint.era_forward(r0, v0, m, eps, dt, 16 * h, 8 * h, 1)
+    rb, vb, _ = adjoint.block_forward(r0, v0, m, eps, dt, 16 * h)
+    assert np.array_equal(r1, rb) and np.array_equal(v1, vb)
+    r2, _, _ = adjoint.era_forward(r0, v0, m, eps, dt, 16 * h, 8 * h, 2)
+    r3, _, _ = adjoint.era_forward(r0, v0, m, eps, dt, 16 * h, 8 * h, 3)
+    assert 1e-10 < np.abs(r2 - r1).max() < 1e-4
+    assert 1e-12 < np.abs(r3 - r2).max() < np.abs(r2 - r1).max()
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_era_gradient_vs_finite_differences(oracle, passes):
+    n, eps, h = 10, 1.0 / 16, 1.0 / 64
+    t_end, era = 16 * h, 8 * h
+    r0, v0, m = plummer(n, 27, masses="loguniform")
+    dt = _levels_dt(n, h, 7)
+    rt, vt, _ = adjoint.era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    rt = rt + 0.01 * gaussian((3, n), 17)
+    vt = vt + 0.01 * gaussian((3, n), 18)
+    L, gr, gv, gm = adjoint.era_gradient(r0, v0, m, eps, dt, t_end, era, passes, rt, vt)
+    assert L == pytest.approx(
+        adjoint.era_loss(r0, v0, m, eps, dt, t_end, era, passes, rt, vt), rel=1e-15)
+    if passes == 1:
+        ref = adjoint.block_gradient(r0, v0, m, eps, dt, t_end, rt, vt)
+        for a, b in zip((L, gr, gv, gm), ref):
+            assert np.array_equal(a, b)
+    step = 1e-6
+    for trial in range(2):
+        dr = gaussian((3, n), 610 + trial)
+        dv = gaussian((3, n), 710 + trial)
+        dm = gaussian(n, 810 + trial) * m
+        for (g, d, which) in ((gr, dr, "r"), (gv, dv, "v"), (gm, dm, "m")):
+            def f(sgn):
+                rr = r0 + sgn * step * d if which == "r" else r0
+                vv = v0 + sgn * step * d if which == "v" else v0
+                mm = m + sgn * step * d if which == "m" else m
+                return adjoint.era_loss(rr, vv, mm, eps, dt, t_end, era, passes, rt, vt)
+            fd = (f(1) - f(-1)) / (2 * step)
+            assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which
