@@ -110,7 +110,8 @@ int tsbts_bind_state(tsbts_ctx *ctx, double *r, double *v, double *a, const doub
  *     passes;
  *   - otherwise it is Taylor-predicted.
  * Requires bound state.  use_history requires a completed history (else TSBTS_ESTATE).
- * Within one pass successive t_block values must not decrease. */
+ * The interpolation keeps a per-particle cursor into the history that follows t_block in
+ * either direction (forward within a pass, backward in a reverse sweep). */
 int tsbts_predict(tsbts_ctx *ctx, double t_block, int use_history, hipStream_t stream);
 
 /* Load explicit positions r [3][n] and masses m [n] (float64) into the context's particle
@@ -235,6 +236,57 @@ int tsbts_leapfrog_adjoint(tsbts_ctx *ctx, int phase, double h, const double *rb
 int tsbts_block_adjoint(tsbts_ctx *ctx, int phase, const int32_t *idx, int32_t n_act,
                         double t_block, double *rbar, double *vbar, double *abar,
                         double *pbar, double *seeds, hipStream_t stream);
+
+/* Adjoints through the passes of an era (not in the paper: gradients through the method).
+ * From the second pass on, tsbts_predict(t_block, use_history=1) takes each non-active
+ * particle from the finished history of the previous pass (Section 2's time-symmetric
+ * interpolation).  A reverse sweep over such a pass needs the transposes of that map and
+ * of the recording of a pass's states; the four calls below provide them.  The records
+ * of a finished history are numbered as tsbts_history_layout reports them: particle j's
+ * records are off[j] .. off[j+1]-1, in time order, the first one its state when the
+ * recording began.  A record adjoint array hbar [6][n_records] float64 (device) holds the
+ * adjoints of the stored positions (rows 0-2) and velocities (rows 3-5). */
+
+/* Size and numbering of the finished history: *n_records (host) = number of records;
+ * off [n+1] int32 and t [n_records] float64 (device, either may be NULL = not copied) get
+ * the per-particle offsets and the record times.  Asynchronous copies on `stream`.
+ * TSBTS_ESTATE without a finished history. */
+int tsbts_history_layout(tsbts_ctx *ctx, int64_t *n_records, int32_t *off, double *t,
+                         hipStream_t stream);
+
+/* Adjoint of the interpolation in tsbts_predict(t_block, use_history=1) for the bound
+ * state and the current finished history (the same one the prediction used).  For every
+ * particle j that the prediction took from the history:
+ *   - a record k at exactly t_block:  hbar[0..2][k] += pbar_j;
+ *   - else the bracketing records k, k+1 (times t0 < t_block < t1, h = t1 - t0):
+ *       hbar[0..2][k]   += H00 pbar_j,   hbar[3..5][k]   += h H10 pbar_j,
+ *       hbar[0..2][k+1] += H01 pbar_j,   hbar[3..5][k+1] += h H11 pbar_j
+ *     (the cubic Hermite weights of tsbts_predict);
+ * and sets pbar_j = 0.  Active and Taylor-predicted particles keep their pbar.
+ * pbar [3][n] float64 device (adjoint of the predicted positions, e.g. after
+ * tsbts_force_backward); hbar [6][n_records] float64 device, accumulated; n_records must
+ * be the history's record count (else TSBTS_EINVAL). */
+int tsbts_interp_adjoint(tsbts_ctx *ctx, double t_block, double *pbar, double *hbar,
+                         int64_t n_records, hipStream_t stream);
+
+/* Adds the adjoints of the records that the particles active_idx [n_active] received at
+ * t_block into the state adjoint: rbar_i += hbar[0..2][k], vbar_i += hbar[3..5][k] for
+ * the record k of particle i with time t_block (particles without one are skipped).
+ * off [n+1], t [n_records] (device) describe a history as tsbts_history_layout copied
+ * them; hbar [6][n_records] is that history's record adjoint; rbar, vbar [3][n] float64
+ * device.  In a reverse sweep it is called before the block step that wrote the records
+ * is undone, and with every particle at the era start for the first records.  No
+ * duplicates in active_idx. */
+int tsbts_record_adjoint(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                         double t_block, const int32_t *off, const double *t,
+                         int64_t n_records, const double *hbar, double *rbar, double *vbar,
+                         hipStream_t stream);
+
+/* rbar_acc += rbar, vbar_acc += vbar, abar_acc += abar, all [3][n] float64 device: every
+ * pass restarts from the era-start state, whose adjoint is the sum over the passes. */
+int tsbts_adjoint_accumulate(tsbts_ctx *ctx, const double *rbar, const double *vbar,
+                             const double *abar, double *rbar_acc, double *vbar_acc,
+                             double *abar_acc, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------
  * Native host scheduler (Algorithm 2 with Eq. blockcondition, Algorithm 1 and Algorithm 3).

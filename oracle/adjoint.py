@@ -249,7 +249,7 @@ def era_loss(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
     return float(((r - r_target) ** 2).sum() + ((v - v_target) ** 2).sum())
 
 
-def _hermite_weights(t0, t1, t):
+def hermite_weights(t0, t1, t):
     """Weights of (r0, v0, r1, v1) in the interpolated position: the interpolant is
     linear in the stored values, so each weight is the interpolant of a unit value."""
     one, zero = np.ones(1), np.zeros(1)
@@ -315,7 +315,7 @@ def era_gradient(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
                     if exact:
                         prev_bar[j][k][0] += pbar[:, j]
                     else:
-                        w_r0, w_v0, w_r1, w_v1 = _hermite_weights(prev[j][k][0],
+                        w_r0, w_v0, w_r1, w_v1 = hermite_weights(prev[j][k][0],
                                                                   prev[j][k + 1][0], t_b)
                         prev_bar[j][k][0] += w_r0 * pbar[:, j]
                         prev_bar[j][k][1] += w_v0 * pbar[:, j]

@@ -70,6 +70,10 @@ _SIGS = {
     "tsbts_energy": ([_p, _p, _p, _p, _p, _p], _int),
     "tsbts_leapfrog_adjoint": ([_p, _int, _d, _p, _p, _p, _p, _p], _int),
     "tsbts_block_adjoint": ([_p, _int, _p, _int, _d, _p, _p, _p, _p, _p, _p], _int),
+    "tsbts_history_layout": ([_p, ctypes.POINTER(_i64), _p, _p, _p], _int),
+    "tsbts_interp_adjoint": ([_p, _d, _p, _p, _i64, _p], _int),
+    "tsbts_record_adjoint": ([_p, _p, _i32, _d, _p, _p, _i64, _p, _p, _p, _p], _int),
+    "tsbts_adjoint_accumulate": ([_p, _p, _p, _p, _p, _p, _p, _p], _int),
     "tsbts_sched_admissible": ([_d, _d, _i64, _i64, ctypes.POINTER(_i64)], _int),
     "tsbts_sched_rule": ([_int, _i64, _i64, _d, _d, _d, _i64, _i64, ctypes.POINTER(_i64)],
                          _int),
@@ -258,6 +262,44 @@ def tsbts_block_adjoint(ctx, n, phase, active_idx, t_block, rbar, vbar, abar, pb
         ctx, int(phase), _i32p(active_idx), k, float(t_block), _f64(rbar, (3, n), "rbar"),
         _f64(vbar, (3, n), "vbar"), _f64(abar, (3, n), "abar"), _f64(pbar, (3, n), "pbar"),
         _f64(seeds, None if seeds is None else (3, k), "seeds"), _stream(stream)))
+
+
+def tsbts_history_layout(ctx, n, off=None, t=None, stream=None) -> int:
+    """Number of records of the finished history; copies its offsets / times when given
+    (off int32 [n+1], t float64 [n_records])."""
+    count = ctypes.c_int64()
+    _check(ctx, lib.tsbts_history_layout(ctx, ctypes.byref(count), None, None, None))
+    n_rec = count.value
+    if off is not None or t is not None:
+        _check(ctx, lib.tsbts_history_layout(
+            ctx, ctypes.byref(count), _ptr(off, torch.int32, (n + 1,), "off"),
+            _f64(t, (n_rec,), "t"), _stream(stream)))
+    return n_rec
+
+
+def tsbts_interp_adjoint(ctx, n, n_records, t_block, pbar, hbar, stream=None):
+    _check(ctx, lib.tsbts_interp_adjoint(ctx, float(t_block), _f64(pbar, (3, n), "pbar"),
+                                         _f64(hbar, (6, n_records), "hbar"), int(n_records),
+                                         _stream(stream)))
+
+
+def tsbts_record_adjoint(ctx, n, active_idx, t_block, off, t, hbar, rbar, vbar,
+                         stream=None):
+    n_rec = t.numel()
+    _check(ctx, lib.tsbts_record_adjoint(
+        ctx, _i32p(active_idx), active_idx.numel(), float(t_block),
+        _ptr(off, torch.int32, (n + 1,), "off"), _f64(t, (n_rec,), "t"), n_rec,
+        _f64(hbar, (6, n_rec), "hbar"), _f64(rbar, (3, n), "rbar"),
+        _f64(vbar, (3, n), "vbar"), _stream(stream)))
+
+
+def tsbts_adjoint_accumulate(ctx, n, rbar, vbar, abar, rbar_acc, vbar_acc, abar_acc,
+                             stream=None):
+    _check(ctx, lib.tsbts_adjoint_accumulate(
+        ctx, _f64(rbar, (3, n), "rbar"), _f64(vbar, (3, n), "vbar"),
+        _f64(abar, (3, n), "abar"), _f64(rbar_acc, (3, n), "rbar_acc"),
+        _f64(vbar_acc, (3, n), "vbar_acc"), _f64(abar_acc, (3, n), "abar_acc"),
+        _stream(stream)))
 
 
 # ------------------------------------------------------------------ native scheduler

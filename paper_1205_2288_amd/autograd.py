@@ -13,6 +13,12 @@
   block time, force and leapfrog corrector on the active set), all particles starting
   together at t = 0.  Same checkpointing; the reverse sweep restores each block step's
   pre-step state, predicts, and runs ``tsbts_block_adjoint`` around the force adjoint.
+* ``TsbtsEraLeapfrog``: the same fixed schedule cut into eras, each integrated with
+  several passes (Section 2's time-symmetric scheme: from the second pass on the
+  non-active particles are interpolated from the previous pass's stored states).  The
+  reverse sweep of a pass also moves the adjoints of interpolated positions into the
+  adjoints of the previous pass's records (``tsbts_interp_adjoint``) and adds those back
+  at the block steps that wrote them (``tsbts_record_adjoint``).
 
 All arithmetic runs in libtsbts kernels; torch provides the tensors and the graph.
 """
@@ -162,12 +168,12 @@ class BlockSchedule:
         return self.sets[min(tz, self.lmax)]
 
 
-def _block_step(ctx: Context, sched: BlockSchedule, s: int, buf):
+def _block_step(ctx: Context, sched: BlockSchedule, s: int, buf, use_history=False):
     tb = sched.time(s)
     idx = sched.active(s)
     k = idx.numel()
     acc = buf[:3 * k].view(3, k)
-    ctx.predict(tb)
+    ctx.predict(tb, use_history)
     ctx.force(idx, tb, with_pot=False, acc=acc)
     ctx.correct(idx, tb, acc)
 
@@ -250,3 +256,143 @@ class TsbtsBlockLeapfrog(torch.autograd.Function):
 
 def tsbts_block_leapfrog(r0, v0, m, ctx: Context, dt, t_end: float, era: int = 16):
     return TsbtsBlockLeapfrog.apply(r0, v0, m, ctx, dt, t_end, era)
+
+
+def _state(ctx: Context):
+    return (ctx.r, ctx.v, ctx.a, ctx.t_last)
+
+
+def _restore(ctx: Context, saved):
+    for dst, src in zip(_state(ctx), saved):
+        dst.copy_(src)
+
+
+def _era_pass(ctx: Context, sched: BlockSchedule, s0: int, s1: int, buf, use_history: bool,
+              record: bool, pre=None):
+    """Block steps s0 .. s1-1 of one pass; record = keep its states as the next pass's
+    interpolation source; pre = list receiving each step's pre-step state."""
+    if record:
+        ctx.history_begin()
+    for s in range(s0, s1):
+        if pre is not None:
+            pre.append([x.clone() for x in _state(ctx)])
+        _block_step(ctx, sched, s, buf, use_history)
+    if record:
+        ctx.history_end()
+
+
+class TsbtsEraLeapfrog(torch.autograd.Function):
+    """(r, v) at t_end after a run on a fixed block schedule cut into eras of length `era`
+    (a multiple of the largest step), each era integrated `passes` times from its start
+    state: the first pass Taylor-predicts every particle, later passes take the
+    non-active particles from the previous pass's stored states by cubic Hermite
+    interpolation (Section 2's time-symmetric scheme on a given schedule).  The forward
+    keeps the era-start states; the backward sweeps each era's passes in reverse,
+    recomputing the interpolation source of each pass from the era start."""
+
+    @staticmethod
+    def forward(fctx, r0, v0, m, ctx: Context, dt, t_end: float, era: float, passes: int):
+        n = ctx.n
+        dev = ctx.device
+        sched = BlockSchedule(ctx, dt, t_end)
+        per = era / sched.hmin
+        if passes < 1:
+            raise ValueError("passes must be >= 1")
+        if era % float(sched.dt.max()) != 0.0 or per != int(per) or sched.K % int(per):
+            raise ValueError("era must be a multiple of the largest step and divide t_end")
+        per = int(per)
+        r0, v0, m = (x.detach().contiguous() for x in (r0, v0, m))
+        ctx.bind(r0.clone(), v0.clone(), m.clone(),
+                 t_last=torch.zeros(n, dtype=torch.float64, device=dev),
+                 dt=torch.tensor(sched.dt, dtype=torch.float64, device=dev))
+        every = ctx.idx(torch.arange(n, dtype=torch.int32))
+        buf = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        acc = buf.view(3, n)
+        ctx.predict(0.0)
+        ctx.force(every, 0.0, with_pot=False, acc=acc)
+        ctx.a.copy_(acc)
+        starts = []
+        for s0 in range(0, sched.K, per):
+            start = [x.clone() for x in _state(ctx)]
+            starts.append(start)
+            ctx.history_clear()
+            for p in range(passes):
+                if p:
+                    _restore(ctx, start)
+                _era_pass(ctx, sched, s0, s0 + per, buf, p > 0, p < passes - 1)
+        ctx.history_clear()
+        fctx.tsbts = ctx
+        fctx.sched = sched
+        fctx.per = per
+        fctx.passes = passes
+        fctx.starts = starts
+        fctx.every = every
+        fctx.save_for_backward(m)
+        return ctx.r.clone(), ctx.v.clone()
+
+    @staticmethod
+    def backward(fctx, g_r, g_v):
+        ctx, sched, per, passes = fctx.tsbts, fctx.sched, fctx.per, fctx.passes
+        (m,) = fctx.saved_tensors
+        n = ctx.n
+        dev = ctx.device
+        z = lambda: torch.zeros((3, n), dtype=torch.float64, device=dev)  # noqa: E731
+        rbar = z() if g_r is None else g_r.contiguous().clone()
+        vbar = z() if g_v is None else g_v.contiguous().clone()
+        abar = z()
+        pbar = z()
+        mbar = torch.zeros(n, dtype=torch.float64, device=dev)
+        buf = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        seeds = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        first = fctx.starts[0]
+        ctx.bind(first[0].clone(), first[1].clone(), m, a=first[2].clone(),
+                 t_last=first[3].clone(),
+                 dt=torch.tensor(sched.dt, dtype=torch.float64, device=dev))
+        for e in range(len(fctx.starts) - 1, -1, -1):
+            start = fctx.starts[e]
+            s0 = e * per
+            t0 = s0 * sched.hmin
+            acc_r, acc_v, acc_a = z(), z(), z()
+            later = None   # (layout, record adjoint) of the pass after the one reversed
+            for p in range(passes - 1, -1, -1):
+                # interpolation source of pass p: pass p-1, rebuilt from the era start
+                ctx.history_clear()
+                for q in range(p):
+                    _restore(ctx, start)
+                    _era_pass(ctx, sched, s0, s0 + per, buf, q > 0, True)
+                if p:
+                    layout = ctx.history_layout()
+                    hbar = torch.zeros((6, layout[0]), dtype=torch.float64, device=dev)
+                _restore(ctx, start)
+                pre = []
+                _era_pass(ctx, sched, s0, s0 + per, buf, p > 0, False, pre)
+                rb, vb, ab = (rbar, vbar, abar) if p == passes - 1 else (z(), z(), z())
+                for s in range(s0 + per - 1, s0 - 1, -1):
+                    _restore(ctx, pre[s - s0])
+                    tb = sched.time(s)
+                    idx = sched.active(s)
+                    k = idx.numel()
+                    sd = seeds[:3 * k].view(3, k)
+                    if later is not None:
+                        ctx.record_adjoint(idx, tb, later[0], later[1], rb, vb)
+                    ctx.predict(tb, p > 0)
+                    ctx.block_adjoint(0, idx, tb, rb, vb, ab, pbar, sd)
+                    ctx.force_backward(idx, tb, sd, None, pbar, mbar)
+                    if p:
+                        ctx.interp_adjoint(tb, pbar, hbar)
+                    ctx.block_adjoint(1, None, tb, rb, vb, ab, pbar, None)
+                if later is not None:
+                    ctx.record_adjoint(fctx.every, t0, later[0], later[1], rb, vb)
+                ctx.adjoint_accumulate(rb, vb, ab, acc_r, acc_v, acc_a)
+                later = (layout, hbar) if p else None
+            rbar, vbar, abar = acc_r, acc_v, acc_a
+            _restore(ctx, start)
+        ctx.history_clear()
+        ctx.load_positions(first[0], m, 0.0)
+        ctx.force_backward(fctx.every, 0.0, abar, None, rbar, mbar)   # through a_0
+        return rbar, vbar, mbar, None, None, None, None, None
+
+
+def tsbts_era_leapfrog(r0, v0, m, ctx: Context, dt, t_end: float, era: float,
+                       passes: int = 3):
+    return TsbtsEraLeapfrog.apply(r0, v0, m, ctx, dt, t_end, era, passes)

@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "libtsbts.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "predict.hip", "force.hip", "timestep.hip", "correct.hip",
-           "energy.hip", "backward.hip", "scheduler.hip", "fused.hip"]
+           "energy.hip", "backward.hip", "scheduler.hip", "fused.hip",
+           "hist_adjoint.hip"]
 
 ARCH = os.environ.get("TSBTS_OFFLOAD_ARCH", "gfx950")
 

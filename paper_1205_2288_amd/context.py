@@ -173,6 +173,33 @@ class Context:
     def history_clear(self):
         L.tsbts_history_clear(self.ctx)
 
+    def history_layout(self, stream=None):
+        """(n_records, off int32 [n+1], t float64 [n_records]) of the finished history,
+        copied to new device tensors."""
+        n_rec = L.tsbts_history_layout(self.ctx, self.n)
+        off = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        t = torch.empty(n_rec, dtype=torch.float64, device=self.device)
+        L.tsbts_history_layout(self.ctx, self.n, off, t, stream)
+        return n_rec, off, t
+
+    def interp_adjoint(self, t_block, pbar, hbar, stream=None):
+        """Move the adjoint of interpolated predicted positions into the record adjoint
+        hbar [6][n_records] of the finished history (tsbts_interp_adjoint)."""
+        L.tsbts_interp_adjoint(self.ctx, self.n, hbar.shape[1], t_block, pbar, hbar, stream)
+
+    def record_adjoint(self, active, t_block, layout, hbar, rbar, vbar, stream=None):
+        """Add the adjoints of the records written at t_block (history `layout` as
+        returned by history_layout) into rbar, vbar (tsbts_record_adjoint)."""
+        idx = active if isinstance(active, torch.Tensor) and active.dtype == torch.int32 \
+            and active.device.type == "cuda" else self.idx(active)
+        _, off, t = layout
+        L.tsbts_record_adjoint(self.ctx, self.n, idx, t_block, off, t, hbar, rbar, vbar,
+                               stream)
+
+    def adjoint_accumulate(self, rbar, vbar, abar, rbar_acc, vbar_acc, abar_acc, stream=None):
+        L.tsbts_adjoint_accumulate(self.ctx, self.n, rbar, vbar, abar, rbar_acc, vbar_acc,
+                                   abar_acc, stream)
+
     def snapshot(self, T, stream=None):
         r = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
         v = torch.empty((3, self.n), dtype=torch.float64, device=self.device)

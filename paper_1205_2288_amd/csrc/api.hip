@@ -494,6 +494,63 @@ int tsbts_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int32_t n_a
   return TSBTS_OK;
 }
 
+int tsbts_history_layout(tsbts_ctx *c, int64_t *n_records, int32_t *off, double *t,
+                         hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!n_records) return fail(c, TSBTS_EINVAL, "n_records is NULL");
+  if (!c->h.valid) return fail(c, TSBTS_ESTATE, "no finished history");
+  *n_records = c->h.hcount;
+  if (off)
+    TSBTS_CHECK_HIP(c, hipMemcpyAsync(off, c->h.off, (c->n + 1) * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, stream));
+  if (t && c->h.hcount > 0)
+    TSBTS_CHECK_HIP(c, hipMemcpyAsync(t, c->h.ht, c->h.hcount * sizeof(double),
+                                      hipMemcpyDeviceToDevice, stream));
+  return TSBTS_OK;
+}
+
+int tsbts_interp_adjoint(tsbts_ctx *c, double t_block, double *pbar, double *hbar,
+                         int64_t n_records, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (!pbar || !hbar) return fail(c, TSBTS_EINVAL, "tsbts_interp_adjoint: NULL array");
+  if (!c->h.valid) return fail(c, TSBTS_ESTATE, "no finished history");
+  if (n_records != c->h.hcount)
+    return fail(c, TSBTS_EINVAL, "n_records=%lld differs from the history's %lld records",
+                static_cast<long long>(n_records), static_cast<long long>(c->h.hcount));
+  if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
+  hipError_t e = launch_interp_adjoint(c, t_block, pbar, hbar, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_interp_adjoint launch");
+  return TSBTS_OK;
+}
+
+int tsbts_record_adjoint(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                         const int32_t *off, const double *t, int64_t n_records,
+                         const double *hbar, double *rbar, double *vbar, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!off || !hbar || !rbar || !vbar || (n_records > 0 && !t))
+    return fail(c, TSBTS_EINVAL, "tsbts_record_adjoint: NULL array");
+  if (n_records < 0) return fail(c, TSBTS_EINVAL, "n_records < 0");
+  if (n_records == 0) return TSBTS_OK;
+  hipError_t e = launch_record_adjoint(c, idx, n_act, t_block, off, t, n_records, hbar, rbar,
+                                       vbar, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_record_adjoint launch");
+  return TSBTS_OK;
+}
+
+int tsbts_adjoint_accumulate(tsbts_ctx *c, const double *rbar, const double *vbar,
+                             const double *abar, double *rbar_acc, double *vbar_acc,
+                             double *abar_acc, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (!rbar || !vbar || !abar || !rbar_acc || !vbar_acc || !abar_acc)
+    return fail(c, TSBTS_EINVAL, "tsbts_adjoint_accumulate: NULL array");
+  hipError_t e = launch_accumulate3(3 * c->n, rbar, vbar, abar, rbar_acc, vbar_acc, abar_acc,
+                                    stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_adjoint_accumulate launch");
+  return TSBTS_OK;
+}
+
 }  // extern "C"
 
 namespace tsbts {

@@ -238,6 +238,16 @@ hipError_t launch_fill(double *x, int64_t len, double v, hipStream_t st);
 hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
                                 double t_block, double *rbar, double *vbar, double *abar,
                                 double *pbar, double *seeds, hipStream_t st);
+// Adjoints of the passes of an era (hist_adjoint.hip).
+hipError_t launch_interp_adjoint(tsbts_ctx *c, double t_block, double *pbar, double *hbar,
+                                 hipStream_t st);
+hipError_t launch_record_adjoint(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                                 const int32_t *off, const double *ht, int64_t n_records,
+                                 const double *hbar, double *rbar, double *vbar,
+                                 hipStream_t st);
+hipError_t launch_accumulate3(int64_t len, const double *x0, const double *x1,
+                              const double *x2, double *y0, double *y1, double *y2,
+                              hipStream_t st);
 
 // Free the native scheduler attached to a context (if any).
 void destroy_scheduler(tsbts_ctx *c);

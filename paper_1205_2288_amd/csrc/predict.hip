@@ -6,7 +6,7 @@
 // Bandwidth-bound: per particle, Taylor reads r, v, a, t_last, dt, m (88 B) and writes the
 // float64 position/mass/weight planes (40 B), float64 velocities (24 B) and, in mixed
 // precision, the float32 hi/lo, mass, weight, velocity and eps^2-weight planes (48 B).
-#include "internal.hpp"
+#include "hermite.hpp"
 
 namespace tsbts {
 namespace {
@@ -59,26 +59,6 @@ __device__ __forceinline__ void store_pad(const Out &o, int64_t j) {
   store_particle(o, j, kFar, kFar, kFar, 0.0, 0.0, 0.0, 0.0);
 }
 
-// Cubic Hermite interpolation between records (t0; r0, v0, a0) and (t1; r1, v1, a1).
-// Positions use (r, v) at both ends and velocities (v, a):
-//   tau = (t - t0)/h, H00 = 2tau^3 - 3tau^2 + 1, H10 = tau^3 - 2tau^2 + tau,
-//   H01 = -2tau^3 + 3tau^2, H11 = tau^3 - tau^2.
-struct Herm {
-  double h00, h10h, h01, h11h;
-  __device__ Herm(double t0, double t1, double t) {
-    const double h = t1 - t0;
-    const double tau = (t - t0) / h;
-    const double tau2 = tau * tau, tau3 = tau2 * tau;
-    h00 = 2.0 * tau3 - 3.0 * tau2 + 1.0;
-    h10h = (tau3 - 2.0 * tau2 + tau) * h;
-    h01 = -2.0 * tau3 + 3.0 * tau2;
-    h11h = (tau3 - tau2) * h;
-  }
-  __device__ double operator()(double p0, double d0, double p1, double d1) const {
-    return h00 * p0 + h10h * d0 + h01 * p1 + h11h * d1;
-  }
-};
-
 // Records of particle j in the finished history: times ht[k], state planes hs[c*hcap+k]
 // (c = 0..2 position, 3..5 velocity, 6..8 acceleration).
 __device__ __forceinline__ void from_records(const double *ht, const double *hs, int64_t hcap,
@@ -123,9 +103,12 @@ __global__ __launch_bounds__(kWG) void k_predict(PredictArgs p) {
   double s[6];
   bool done = false;
   if (p.use_hist && !active) {
-    const int hi = p.off[j + 1];
+    // the cursor follows the block time in either direction (a reverse sweep predicts
+    // at decreasing times); it stops at the particle's first record
+    const int lo = p.off[j], hi = p.off[j + 1];
     int k = p.cur[j];
     const int k0 = k;
+    while (k > lo && p.ht[k] > p.tb) --k;
     while (k + 1 < hi && p.ht[k + 1] <= p.tb) ++k;
     if (k != k0) p.cur[j] = k;
     const bool exact = (p.ht[k] == p.tb);

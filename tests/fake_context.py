@@ -10,6 +10,7 @@ import numpy as np
 import torch
 
 import oracle
+from oracle import adjoint as oadj
 
 
 def _np(x):
@@ -163,6 +164,49 @@ class FakeContext:
             "off": np.concatenate([[0], np.cumsum(np.bincount(pid, minlength=self.n))]),
         }
         self.recording = False
+
+    def history_clear(self):
+        self.hist = None
+        self.recording = False
+
+    def history_layout(self):
+        h = self.hist
+        return (h["t"].size, torch.as_tensor(h["off"].astype(np.int32)),
+                torch.as_tensor(h["t"].copy()))
+
+    def interp_adjoint(self, t_block, pbar, hbar):
+        h = self.hist
+        tl, dt = self.t_last.numpy(), self.dt.numpy()
+        pb, hb = pbar.numpy(), hbar.numpy()
+        for j in np.flatnonzero(tl + dt != t_block):
+            lo, hi = h["off"][j], h["off"][j + 1]
+            ks = [k for k in range(lo, hi) if h["t"][k] <= t_block]
+            k = ks[-1] if ks else lo
+            if h["t"][k] == t_block:
+                hb[0:3, k] += pb[:, j]
+            elif k + 1 < hi:
+                w = oadj.hermite_weights(h["t"][k], h["t"][k + 1], t_block)
+                hb[0:3, k] += w[0] * pb[:, j]
+                hb[3:6, k] += w[1] * pb[:, j]
+                hb[0:3, k + 1] += w[2] * pb[:, j]
+                hb[3:6, k + 1] += w[3] * pb[:, j]
+            else:
+                continue
+            pb[:, j] = 0.0
+
+    def record_adjoint(self, active, t_block, layout, hbar, rbar, vbar):
+        _, off, t = (np.asarray(_np(x)) for x in layout)
+        hb, rb, vb = hbar.numpy(), rbar.numpy(), vbar.numpy()
+        for i in np.asarray(_np(active), dtype=np.int64):
+            for k in range(off[i], off[i + 1]):
+                if t[k] == t_block:
+                    rb[:, i] += hb[0:3, k]
+                    vb[:, i] += hb[3:6, k]
+
+    def adjoint_accumulate(self, rbar, vbar, abar, rbar_acc, vbar_acc, abar_acc):
+        rbar_acc += rbar
+        vbar_acc += vbar
+        abar_acc += abar
 
     def energy(self, r=None, v=None, m=None, out=None):
         k, w = oracle.energy(self.r.numpy(), self.v.numpy(), self.m.numpy(), self.eps)

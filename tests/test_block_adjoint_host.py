@@ -12,7 +12,8 @@ import torch
 from oracle import adjoint as oadj
 from workloads import plummer, gaussian
 from fake_context import FakeContext
-from paper_1205_2288_amd.autograd import BlockSchedule, tsbts_block_leapfrog
+from paper_1205_2288_amd.autograd import (BlockSchedule, tsbts_block_leapfrog,
+                                          tsbts_era_leapfrog)
 
 
 def _dt(n, h, seed, nlev=3):
@@ -65,3 +66,39 @@ def test_block_leapfrog_gradient_matches_oracle(era):
     assert float(loss.detach()) == pytest.approx(L, rel=1e-13)
     for got, ref in ((r.grad, gr), (v.grad, gv), (mm.grad, gm)):
         assert np.allclose(got.numpy(), ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_era_leapfrog_gradient_matches_oracle(passes):
+    # eras with several passes: the reverse sweep's bookkeeping (rebuilt interpolation
+    # sources, record adjoints handed from pass to pass, era-start sums) against the
+    # oracle's reverse-mode gradient through the same schedule
+    n, eps, h = 12, 1.0 / 16, 1.0 / 64
+    t_end, era = 16 * h, 8 * h
+    r0, v0, m = plummer(n, 28, masses="loguniform")
+    dt = _dt(n, h, 6)
+    rt, vt, _ = oadj.era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    rt = rt + 0.01 * gaussian((3, n), 13)
+    vt = vt + 0.01 * gaussian((3, n), 14)
+    L, gr, gv, gm = oadj.era_gradient(r0, v0, m, eps, dt, t_end, era, passes, rt, vt)
+    ctx = FakeContext(n, eps)
+    r = torch.tensor(r0, requires_grad=True)
+    v = torch.tensor(v0, requires_grad=True)
+    mm = torch.tensor(m, requires_grad=True)
+    r_end, v_end = tsbts_era_leapfrog(r, v, mm, ctx, dt, t_end, era, passes)
+    loss = ((r_end - torch.tensor(rt)) ** 2).sum() + ((v_end - torch.tensor(vt)) ** 2).sum()
+    loss.backward()
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-13)
+    for got, ref in ((r.grad, gr), (v.grad, gv), (mm.grad, gm)):
+        assert np.allclose(got.numpy(), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("era", [3.0 / 64, 4.0 / 64 + 1.0 / 128])
+def test_era_leapfrog_rejects_bad_eras(era):
+    n, h = 6, 1.0 / 64
+    dt = np.full(n, h)
+    dt[0] = 4 * h
+    r0, v0, m = plummer(n, 3)
+    with pytest.raises(ValueError):
+        tsbts_era_leapfrog(torch.tensor(r0), torch.tensor(v0), torch.tensor(m),
+                           FakeContext(n, 0.1), dt, 16 * h, era, 2)

@@ -6,6 +6,9 @@
   reverse-mode gradient (small sphere), and, at the N=8192 / 64 steps / 16-step era
   workload, with central finite differences of the float64 GPU forward along random
   directions to 1e-5 relative.
+* TsbtsBlockLeapfrog / TsbtsEraLeapfrog (fixed block schedule; eras with several passes
+  and time-symmetric interpolation): the same two checks, plus the history adjoint
+  kernels against their definitions and the predictor's history cursor run backwards.
 """
 import numpy as np
 import pytest
@@ -248,5 +251,212 @@ def test_adjoint8192_block_schedule_vs_finite_differences(prec):
             rel = abs((g * d).sum() - fd) / abs(fd)
             worst = max(worst, rel)
             print(f"block {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} rel {rel:.2e}")
+    assert worst <= 1e-5
+    ref.close()
+
+
+# ---------------------------------------------------------------- eras with several passes
+def _era_grads(prec, r0, v0, m, eps, dt, t_end, era, passes, rt, vt):
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_era_leapfrog
+    ctx = Context(m.size, eps, precision=prec)
+    r, v, mm = _t(r0, True), _t(v0, True), _t(m, True)
+    r_end, v_end = tsbts_era_leapfrog(r, v, mm, ctx, dt, t_end, era, passes)
+    loss = ((r_end - _t(rt)) ** 2).sum() + ((v_end - _t(vt)) ** 2).sum()
+    loss.backward()
+    out = (float(loss.detach()), r.grad.cpu().numpy(), v.grad.cpu().numpy(),
+           mm.grad.cpu().numpy(), r_end.detach().cpu().numpy(), v_end.detach().cpu().numpy())
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("passes", [2, 3])
+def test_era_leapfrog_gradient_matches_oracle(prec, passes):
+    # 300 particles (a full 256-tile and a ragged one), steps h, 2h, 4h, two eras of 8h
+    n, eps, h = 300, 1 / 64, 1 / 128
+    t_end, era = 16 * h, 8 * h
+    r0, v0, m = plummer(n, 66, masses="loguniform")
+    dt = _levels(n, h, 9)
+    r_ref, v_ref, _ = oadj.era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    rt = r_ref + 0.01 * gaussian((3, n), 23)
+    vt = v_ref + 0.01 * gaussian((3, n), 24)
+    Lr, rr, rv, rm = oadj.era_gradient(r0, v0, m, eps, dt, t_end, era, passes, rt, vt)
+    L, gr, gv, gm, r_end, v_end = _era_grads(prec, r0, v0, m, eps, dt, t_end, era, passes,
+                                             rt, vt)
+    fwd_tol = 1e-12 if prec == "fp64" else 1e-6
+    assert np.abs(r_end - r_ref).max() <= fwd_tol * np.abs(r_ref).max()
+    assert np.abs(v_end - v_ref).max() <= fwd_tol * np.abs(v_ref).max() * 10
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert L == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
+    for got, ref in ((gr, rr), (gv, rv), (gm, rm)):
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+
+
+def _history_pass(ctx, dt, h, steps):
+    """Record one pass of `steps` block steps of size h from the bound state."""
+    ctx.history_begin()
+    for s in range(1, steps + 1):
+        tb = s * h
+        act = np.flatnonzero(np.mod(tb, dt) == 0.0).astype(np.int32)
+        ctx.predict(tb)
+        acc = ctx.force(act, tb, with_pot=False)[0]
+        ctx.correct(act, tb, acc)
+    ctx.history_end()
+
+
+def test_interp_and_record_adjoint_elementwise():
+    # the two history adjoint kernels against their definitions (oracle Hermite weights)
+    from paper_1205_2288_amd import Context
+    n, eps, h = 777, 1 / 64, 1 / 64
+    r0, v0, m = plummer(n, 67)
+    dt = _levels(n, h, 10)
+    ctx = Context(n, eps, precision="fp64")
+    ctx.bind(r0, v0, m, dt=dt)
+    _history_pass(ctx, dt, h, 8)
+    n_rec, off_t, t_t = ctx.history_layout()
+    off, t = off_t.cpu().numpy(), t_t.cpu().numpy()
+    counts = np.diff(off)
+    assert n_rec == off[-1] == int((1 + 8 * h / dt).sum())
+    assert np.array_equal(counts, (1 + 8 * h / dt).astype(np.int64))
+    for j in (0, 1, n - 1):
+        assert np.array_equal(t[off[j]:off[j + 1]], dt[j] * np.arange(counts[j]))
+    # back at the era start: at t_b the particles with dt == t_b are active; the others
+    # are interpolated (exact at stored times, Hermite otherwise)
+    ctx.bind(r0, v0, m, dt=dt)
+    for tb in (h, 2 * h, 3 * h, 6 * h):
+        pb = gaussian((3, n), 70 + int(tb / h))
+        P = _t(pb)
+        hb0 = gaussian((6, n_rec), 80 + int(tb / h))
+        Hb = _t(hb0)
+        ctx.interp_adjoint(tb, P, Hb)
+        torch.cuda.synchronize()
+        hb_ref, pb_ref = hb0.copy(), pb.copy()
+        for j in range(n):
+            if dt[j] == tb:
+                continue
+            lo, hi = off[j], off[j + 1]
+            k = lo + int(np.searchsorted(t[lo:hi], tb, side="right")) - 1
+            if t[k] == tb:
+                hb_ref[0:3, k] += pb[:, j]
+            else:
+                w = oadj.hermite_weights(t[k], t[k + 1], tb)
+                hb_ref[0:3, k] += w[0] * pb[:, j]
+                hb_ref[3:6, k] += w[1] * pb[:, j]
+                hb_ref[0:3, k + 1] += w[2] * pb[:, j]
+                hb_ref[3:6, k + 1] += w[3] * pb[:, j]
+            pb_ref[:, j] = 0.0
+        assert np.array_equal(P.cpu().numpy(), pb_ref)
+        assert np.allclose(Hb.cpu().numpy(), hb_ref, rtol=1e-15, atol=1e-15)
+    # record injection at a stored time of a random subset
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(n, 200, replace=False)).astype(np.int32)
+    hb = gaussian((6, n_rec), 90)
+    rb, vb = gaussian((3, n), 91), gaussian((3, n), 92)
+    R, V = _t(rb), _t(vb)
+    for tb in (4 * h, 0.0):
+        ctx.record_adjoint(idx, tb, (n_rec, off_t, t_t), _t(hb), R, V)
+        for i in idx:
+            ks = np.flatnonzero(t[off[i]:off[i + 1]] == tb)
+            if ks.size:
+                k = off[i] + ks[0]
+                rb[:, i] += hb[0:3, k]
+                vb[:, i] += hb[3:6, k]
+    torch.cuda.synchronize()
+    assert np.array_equal(R.cpu().numpy(), rb)
+    assert np.array_equal(V.cpu().numpy(), vb)
+    ctx.close()
+
+
+def test_predict_history_cursor_both_directions():
+    # predictions from the history at decreasing block times (a reverse sweep) equal the
+    # ones made going forward, bit for bit
+    from paper_1205_2288_amd import Context
+    n, eps, h = 500, 1 / 64, 1 / 64
+    r0, v0, m = plummer(n, 68)
+    dt = _levels(n, h, 11)
+    ctx = Context(n, eps, precision="mixed")
+    ctx.bind(r0, v0, m, dt=dt)
+    _history_pass(ctx, dt, h, 8)
+    ctx.bind(r0, v0, m, dt=dt)
+    every = np.arange(n, dtype=np.int32)
+    fwd = {}
+    for s in range(1, 8):
+        ctx.predict(s * h, True)
+        fwd[s] = ctx.force(every, s * h)[0].cpu().numpy()
+    for s in (7, 5, 2, 1, 6, 3):
+        ctx.predict(s * h, True)
+        assert np.array_equal(ctx.force(every, s * h)[0].cpu().numpy(), fwd[s]), s
+    ctx.close()
+
+
+def test_history_adjoint_bad_arguments():
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd._lib import TsbtsError, TSBTS_EINVAL, TSBTS_ESTATE
+    n, h = 64, 1 / 64
+    r, v, m = plummer(n, 69)
+    dt = np.full(n, h)
+    ctx = Context(n, 0.01, precision="fp64")
+    ctx.bind(r, v, m, dt=dt)
+    P = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(TsbtsError) as e:
+        ctx.history_layout()
+    assert e.value.status == TSBTS_ESTATE
+    with pytest.raises(TsbtsError) as e:
+        ctx.interp_adjoint(h, P, torch.zeros((6, 1), dtype=torch.float64, device="cuda"))
+    assert e.value.status == TSBTS_ESTATE
+    _history_pass(ctx, dt, h, 2)
+    n_rec = ctx.history_layout()[0]
+    assert n_rec == 3 * n
+    with pytest.raises(TsbtsError) as e:   # record adjoint sized for another history
+        ctx.interp_adjoint(h, P, torch.zeros((6, n_rec - 1), dtype=torch.float64,
+                                             device="cuda"))
+    assert e.value.status == TSBTS_EINVAL
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adjoint8192_era_passes_vs_finite_differences(prec):
+    # the N=8192 workload on the three-level schedule cut into eras of 8h with three
+    # passes each (4 eras, 96 block-step evaluations per forward run): adjoint
+    # directional derivatives against central differences of the float64 GPU forward
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_era_leapfrog
+    cfg = config("adjoint8192")
+    n, eps, h = cfg.n, cfg.eps, 1 / 256
+    t_end, era, passes = 32 * h, 8 * h, 3
+    r0, v0, m = cfg.ic()
+    dt = _levels(n, h, cfg.seed + 3)
+    ref = Context(n, eps, precision="fp64")
+
+    def fwd(rr, vv, mm):
+        with torch.no_grad():
+            return tsbts_era_leapfrog(_t(rr), _t(vv), _t(mm), ref, dt, t_end, era, passes)
+
+    r_fin, v_fin = fwd(r0, v0, m)
+    rt = r_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 18)
+    vt = v_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 19)
+
+    def loss(rr, vv, mm):
+        r_e, v_e = fwd(rr, vv, mm)
+        return float(((r_e - _t(rt)) ** 2).sum() + ((v_e - _t(vt)) ** 2).sum())
+
+    L, gr, gv, gm, _, _ = _era_grads(prec, r0, v0, m, eps, dt, t_end, era, passes, rt, vt)
+    step = 1e-6
+    worst = 0.0
+    for trial in range(2):
+        for which, g in (("r", gr), ("v", gv), ("m", gm)):
+            d = gaussian((3, n) if which != "m" else n, 960 + 10 * trial + len(which))
+            if which == "m":
+                d = d * m
+            def f(sgn):
+                return loss(r0 + sgn * step * d if which == "r" else r0,
+                            v0 + sgn * step * d if which == "v" else v0,
+                            m + sgn * step * d if which == "m" else m)
+            fd = (f(1) - f(-1)) / (2 * step)
+            rel = abs((g * d).sum() - fd) / abs(fd)
+            worst = max(worst, rel)
+            print(f"era passes {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} "
+                  f"rel {rel:.2e}")
     assert worst <= 1e-5
     ref.close()
