@@ -73,6 +73,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
 #define TSBTS_TUNE_BLOCKS 1
 #define TSBTS_TUNE_IPL 2
 #define TSBTS_TUNE_CHUNK 3
+#define TSBTS_TUNE_SYMMETRIC 4
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
  *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
@@ -83,6 +84,13 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *   TSBTS_TUNE_CHUNK:  j-particles per split unit of the scalar-load kernels (0 =
  *                      automatic: 64 when 256-particle units would give fewer than 512
  *                      workgroups, else 256; or 64, 256)
+ *   TSBTS_TUNE_SYMMETRIC: when every particle is a target (n_active = n), evaluate each
+ *                      unordered pair once for both of its particles (0 = never, 1 =
+ *                      always, 2 = automatic: mixed precision from 32768 particles;
+ *                      default 2).  The criterion (maxima and minima) is then
+ *                      bit-identical; sums are combined in another fixed order.  The
+ *                      first such call on a context allocates its work list and partial
+ *                      buffers.
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);

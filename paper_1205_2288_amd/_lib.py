@@ -162,6 +162,7 @@ def tsbts_destroy(ctx):
 TSBTS_TUNE_BLOCKS = 1
 TSBTS_TUNE_IPL = 2
 TSBTS_TUNE_CHUNK = 3
+TSBTS_TUNE_SYMMETRIC = 4
 TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR = 1
 
 

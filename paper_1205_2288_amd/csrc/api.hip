@@ -9,6 +9,7 @@
 #include <new>
 
 #include "correct.hpp"
+#include "sym.hpp"
 
 namespace tsbts {
 int64_t backward_partials_needed(const tsbts_ctx *c, int n_act);
@@ -235,6 +236,8 @@ int tsbts_destroy(tsbts_ctx *c) {
   dev_free(c->part);
   dev_free(c->epart);
   dev_free(c->gord);
+  if (c->sym_items) (void)hipFree(c->sym_items);
+  if (c->sym_part) (void)hipFree(c->sym_part);
   dev_free(c->h.pid);
   dev_free(c->h.rank);
   dev_free(c->h.t);
@@ -265,6 +268,10 @@ int tsbts_tune(tsbts_ctx *c, int param, int value) {
       if (value != 0 && value != 64 && value != 256)
         return fail(c, TSBTS_EINVAL, "j chunk must be 0, 64 or 256");
       c->tune_chunk = value;
+      return TSBTS_OK;
+    case TSBTS_TUNE_SYMMETRIC:
+      if (value < 0 || value > 2) return fail(c, TSBTS_EINVAL, "symmetric must be 0, 1 or 2");
+      c->tune_sym = value;
       return TSBTS_OK;
     default:
       return fail(c, TSBTS_EINVAL, "unknown tuning parameter %d", param);
@@ -386,6 +393,10 @@ int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, 
   if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
   if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  if (sym_enabled(c, n_act)) {
+    if (int s = sym_prepare(c, 2, c->precision == TSBTS_FP64 ? 8 : 4))
+      return fail(c, s, "symmetric criterion: work list or partials not allocated");
+  }
   hipError_t e = launch_timestep(c, idx, n_act, eta, dtc, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_timestep launch");
   return TSBTS_OK;

@@ -111,6 +111,62 @@ __device__ __forceinline__ void pair_step(const StepRec<Fp64>::I &i, const StepR
   swmin = fmin(swmin, sw);
 }
 
+// Both directions of one pair for the symmetric all-targets kernel: the row particle i
+// gets the terms pair_step gives it against j, and the column particle j the terms
+// pair_step would give it against i (cq, cs).  The separation and the velocity difference
+// only change sign between the two directions, so r^2, v^2 and q are the same values and
+// every result equals the gather kernel's bit for bit.  wi, ei: i's weight m^(-2/3) and
+// eps^2 m^(-2/3) (mixed precision) or its weight alone (float64).
+template <class V>
+__device__ __forceinline__ void pair_step_sym(const typename StepRec<V>::I &i, float wi,
+                                              float ei, const typename StepRec<V>::J &j,
+                                              float eps2, bool skip, float &qmax,
+                                              float &swmin, float &cq, float &cs) {
+  float dx, dy, dz;
+  V::sep(i.p, j.p, dx, dy, dz);
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const float ux = j.v.x - i.vx, uy = j.v.y - i.vy, uz = j.v.z - i.vz;
+  const float v2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+  float q = v2 * __builtin_amdgcn_rcpf(r2);
+  float sw = fmaf(r2, V::weight(j.p), j.v.w);
+  float swj = fmaf(r2, wi, ei);
+  if (skip) {
+    q = 0.0f;
+    sw = __builtin_inff();
+    swj = __builtin_inff();
+  }
+  qmax = fmaxf(qmax, q);
+  swmin = fminf(swmin, sw);
+  cq = fmaxf(cq, q);
+  cs = fminf(cs, swj);
+}
+
+__device__ __forceinline__ void pair_step_sym(const StepRec<Fp64>::I &i, double wi, double,
+                                              const StepRec<Fp64>::J &j, double eps2,
+                                              bool skip, double &qmax, double &swmin,
+                                              double &cq, double &cs) {
+  double dx, dy, dz;
+  Fp64::sep(i.p, j.p, dx, dy, dz);
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ux = j.vx - i.vx, uy = j.vy - i.vy, uz = j.vz - i.vz;
+  const double v2 = ux * ux + uy * uy + uz * uz;
+  double rr = __builtin_amdgcn_rcp(r2);
+  rr = fma(rr, fma(-r2, rr, 1.0), rr);
+  rr = fma(rr, fma(-r2, rr, 1.0), rr);
+  double q = v2 * rr;
+  double sw = (r2 + eps2) * j.w;
+  double swj = (r2 + eps2) * wi;
+  if (skip) {
+    q = 0.0;
+    sw = __builtin_inf();
+    swj = __builtin_inf();
+  }
+  qmax = fmax(qmax, q);
+  swmin = fmin(swmin, sw);
+  cq = fmax(cq, q);
+  cs = fmin(cs, swj);
+}
+
 __device__ __forceinline__ double finish_dt(double eta, double qmax, double swmin) {
   const double tcol = qmax > 0.0 ? sqrt(1.0 / qmax) : __builtin_inf();
   const double tff = pow(swmin, 0.75);

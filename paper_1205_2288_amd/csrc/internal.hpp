@@ -71,6 +71,14 @@ struct tsbts_ctx {
   int tune_blocks = 8192;
   int tune_ipl = 0;
   int tune_chunk = 0;  // j-particles per split unit of the scalar-load kernels (0: automatic)
+  int tune_sym = 2;    // symmetric all-targets kernels: 0 off, 1 on, 2 automatic
+  // symmetric all-targets kernels: work items (int4) and partials
+  void *sym_items = nullptr;
+  int sym_items_n = 0;
+  int64_t sym_items_npad = 0;
+  int sym_chunk = 0;
+  void *sym_part = nullptr;
+  int64_t sym_part_bytes = 0;
   char err[512] = {0};
 };
 
@@ -238,6 +246,10 @@ hipError_t launch_fill(double *x, int64_t len, double v, hipStream_t st);
 hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
                                 double t_block, double *rbar, double *vbar, double *abar,
                                 double *pbar, double *seeds, hipStream_t st);
+// Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.
+struct SymPlan;
+hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,
+                               int n_act, double eta, double *dtc, hipStream_t st);
 // Adjoints of the passes of an era (hist_adjoint.hip).
 hipError_t launch_interp_adjoint(tsbts_ctx *c, double t_block, double *pbar, double *hbar,
                                  hipStream_t st);

@@ -1,0 +1,96 @@
+// Host side of the symmetric all-targets kernels: work items and partial buffers.
+#include <algorithm>
+#include <vector>
+
+#include "sym.hpp"
+
+namespace tsbts {
+namespace {
+
+int sym_chunk(int64_t npad) {
+  const int64_t n_rtiles = (npad + kSymWaveRows - 1) / kSymWaveRows;
+  // about kSymTargetItems items over the upper triangle, whole column tiles of 64
+  const int64_t cols = (npad * n_rtiles / 2 + kSymTargetItems - 1) / kSymTargetItems;
+  int64_t chunk = std::max<int64_t>(64, (cols + 63) / 64 * 64);
+  chunk = std::min<int64_t>(chunk, (npad + 63) / 64 * 64);
+  return static_cast<int>(chunk);
+}
+
+}  // namespace
+
+bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
+  if (n_act != c->n) return false;
+  if (c->tune_sym == 0) return false;
+  if (c->tune_sym == 1) return true;
+  // automatic: mixed precision only (the float64 records do not fit the scalar registers
+  // of a column batch, and the symmetric float64 criterion measured slower)
+  return c->n >= kSymMinN && c->precision != TSBTS_FP64;
+}
+
+int sym_prepare(tsbts_ctx *c, int nv, int vbytes) {
+  const int64_t npad = c->npad;
+  const int chunk = sym_chunk(npad);
+  const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
+  if (c->sym_items_npad != npad || c->sym_chunk != chunk) {
+    std::vector<int4> items;
+    for (int R = 0; R < n_rtiles; ++R) {
+      int s = 0;
+      for (int64_t j0 = static_cast<int64_t>(R) * kSymWaveRows; j0 < npad; j0 += chunk, ++s)
+        items.push_back(make_int4(R, static_cast<int>(j0),
+                                  static_cast<int>(std::min<int64_t>(j0 + chunk, npad)), s));
+    }
+    if (c->sym_items) (void)hipFree(c->sym_items);
+    c->sym_items = nullptr;
+    c->sym_items_n = 0;
+    c->sym_items_npad = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&c->sym_items), items.size() * sizeof(int4)) !=
+        hipSuccess) {
+      c->sym_items = nullptr;
+      return TSBTS_ENOMEM;
+    }
+    if (hipMemcpy(c->sym_items, items.data(), items.size() * sizeof(int4),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return TSBTS_EHIP;
+    c->sym_items_n = static_cast<int>(items.size());
+    c->sym_items_npad = npad;
+    c->sym_chunk = chunk;
+  }
+  const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
+  const int max_slots = sym_slots(npad, 0, chunk);
+  const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows +
+                         static_cast<int64_t>(n_rtiles) * npad) * nv * vbytes;
+  if (bytes > c->sym_part_bytes) {
+    (void)hipDeviceSynchronize();
+    if (c->sym_part) (void)hipFree(c->sym_part);
+    c->sym_part = nullptr;
+    c->sym_part_bytes = 0;
+    if (hipMalloc(&c->sym_part, bytes) != hipSuccess) {
+      c->sym_part = nullptr;
+      return TSBTS_ENOMEM;
+    }
+    c->sym_part_bytes = bytes;
+  }
+  return TSBTS_OK;
+}
+
+bool sym_plan(const tsbts_ctx *c, int nv, int vbytes, SymPlan *p) {
+  const int64_t npad = c->npad;
+  if (!c->sym_items || c->sym_items_npad != npad) return false;
+  const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
+  const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
+  const int max_slots = sym_slots(npad, 0, c->sym_chunk);
+  const int64_t row_bytes = static_cast<int64_t>(max_slots) * npad_rows * nv * vbytes;
+  const int64_t bytes = row_bytes + static_cast<int64_t>(n_rtiles) * npad * nv * vbytes;
+  if (bytes > c->sym_part_bytes) return false;
+  p->items = static_cast<const int4 *>(c->sym_items);
+  p->n_items = c->sym_items_n;
+  p->n_rtiles = n_rtiles;
+  p->chunk = c->sym_chunk;
+  p->max_slots = max_slots;
+  p->npad_rows = npad_rows;
+  p->row_part = c->sym_part;
+  p->col_part = static_cast<char *>(c->sym_part) + row_bytes;
+  return true;
+}
+
+}  // namespace tsbts

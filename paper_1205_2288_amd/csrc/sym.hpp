@@ -1,0 +1,62 @@
+// Symmetric evaluation of the all-targets pair sums.
+//
+// When every particle is a target, each unordered pair {k, j} enters two rows: k's sum
+// over j and j's sum over k, with the same separation, distance and reciprocal powers.
+// The symmetric kernels evaluate each pair once.  The upper triangle of the pair matrix is
+// cut into wave work items: a row tile of kSymWaveRows particles (kSymRows per lane)
+// against a contiguous range of columns at or right of the tile's first particle.  A
+// lane accumulates the row side of its particles in registers.  The column side of each
+// column j is first combined over the lane's rows in registers, then over the 64 lanes
+// through a wave-private LDS transposition of kSymBlock columns at a time, and written
+// once per (row tile, column) to a partial.  A reduction kernel combines, for each
+// particle, the row partials of its own row tile's items and the column partials of all
+// row tiles at or above it, in a fixed order.  Pairs with j <= k inside the diagonal
+// block, padding rows and padding columns are masked (wave-uniform choice of the masked
+// loop, as in the gather kernels).
+#pragma once
+
+#include "internal.hpp"
+
+namespace tsbts {
+
+constexpr int kSymRows = 4;                        // rows per lane
+constexpr int kSymWaveRows = 64 * kSymRows;        // rows of one work item
+constexpr int kSymBlock = 16;                      // columns per LDS transposition
+constexpr int kSymLdsStride = 65;                  // LDS entries per column (one pad)
+constexpr int kSymMinN = 32768;                    // automatic use from this many particles
+constexpr int kSymTargetItems = 32768;             // work items aimed at by the column chunk
+
+struct SymPlan {
+  const int4 *items;  // (row tile, first column, end column, slot of the row tile)
+  int n_items;
+  int n_rtiles;       // row tiles of kSymWaveRows
+  int chunk;          // columns per work item (multiple of 64)
+  int max_slots;      // items of row tile 0 (the most of any row tile)
+  int64_t npad_rows;  // n_rtiles * kSymWaveRows
+  void *row_part;     // [max_slots][NV][npad_rows]
+  void *col_part;     // [n_rtiles][NV][npad]
+};
+
+// Work items of a row tile: those covering columns [R * kSymWaveRows, npad) in chunks.
+__host__ __device__ inline int sym_slots(int64_t npad, int R, int chunk) {
+  const int64_t cols = npad - static_cast<int64_t>(R) * kSymWaveRows;
+  return static_cast<int>((cols + chunk - 1) / chunk);
+}
+
+// Make the LDS writes of this wave visible to its other lanes and keep the compiler from
+// moving LDS accesses across this point (LDS operations of one wave execute in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Whether the symmetric kernels serve a call with n_act targets (all particles).
+bool sym_enabled(const tsbts_ctx *c, int64_t n_act);
+// Items and partial buffers for NV values of vbytes bytes per partial entry: allocates
+// (host set-up, synchronous) and returns a status.
+int sym_prepare(tsbts_ctx *c, int nv, int vbytes);
+// The plan if sym_prepare has provided for (nv, vbytes); false otherwise (no allocation).
+bool sym_plan(const tsbts_ctx *c, int nv, int vbytes, SymPlan *plan);
+
+}  // namespace tsbts

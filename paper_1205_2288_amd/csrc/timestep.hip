@@ -10,6 +10,7 @@
 // and so are the padding particles of the last tile (at rest far away they would add a
 // tiny nonzero v^2/r^2, which matters when every real relative velocity is zero).
 #include "criterion.hpp"
+#include "sym.hpp"
 
 namespace tsbts {
 namespace {
@@ -285,6 +286,11 @@ hipError_t run(StepArgs &A, hipStream_t st) {
 
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st) {
+  if (sym_enabled(c, n_act)) {
+    SymPlan plan;
+    if (sym_plan(c, 2, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
+      return launch_timestep_sym(c, plan, idx, n_act, eta, dtc, st);
+  }
   StepArgs A;
   A.n = c->n;
   A.p32 = c->p32;

@@ -1,0 +1,208 @@
+// Time-step criterion (Eq. nbdt of Section 2) when every particle is a target: each
+// unordered pair is evaluated once for both of its particles (symmetric all-targets
+// scheme of sym.hpp).  The per-pair terms are the gather kernels' (pair_step_sym), and
+// maxima and minima do not depend on the order in which they are taken, so the result
+// equals the gather kernels' bit for bit.  Partials: [slot][2][rows] and [row tile][2][n]
+// of max v^2/r^2 and min s m^(-2/3), in the kernel's float type.
+#include "criterion.hpp"
+#include "sym.hpp"
+
+namespace tsbts {
+namespace {
+
+struct StepSymArgs {
+  int64_t n, npad;
+  const float *p32;
+  const double *p64;
+  const double *v64;
+  double eps2;
+  SymPlan plan;
+  const int32_t *idx;
+  int n_act;
+  double eta;
+  double *dtc;
+};
+
+// A row particle's weights in the column role (see pair_step_sym).
+template <class V>
+__device__ __forceinline__ void col_weights(const StepSymArgs &A, int64_t k,
+                                            typename V::F &w, typename V::F &e) {
+  if constexpr (sizeof(typename V::F) == 4) {
+    w = A.p32[P32_W * A.npad + k];
+    e = A.p32[P32_E * A.npad + k];
+  } else {
+    w = A.p64[P64_W * A.npad + k];
+    e = 0.0;
+  }
+}
+
+template <class F>
+__device__ __forceinline__ F inf_of() {
+  if constexpr (sizeof(F) == 4) return __builtin_inff();
+  else return __builtin_inf();
+}
+
+// kSymBlock columns starting at jb against the lane's kSymRows rows; the column values of
+// column jb + c go to L[(c * kSymLdsStride + lane) * 2 + {0, 1}].
+template <class V, int MASK>
+__device__ __forceinline__ void sym_block(const StepSymArgs &A,
+                                          const typename StepRec<V>::I (&rows)[kSymRows],
+                                          const typename V::F (&wr)[kSymRows],
+                                          const typename V::F (&er)[kSymRows],
+                                          const int (&k)[kSymRows], int64_t jb,
+                                          typename V::F eps2, typename V::F (&qmax)[kSymRows],
+                                          typename V::F (&swmin)[kSymRows], typename V::F *L,
+                                          int lane) {
+  using F = typename V::F;
+  // unrolled so that the column records of consecutive columns merge into wide scalar loads
+#pragma unroll 8
+  for (int c = 0; c < kSymBlock; ++c) {
+    const int64_t j = jb + c;
+    const typename StepRec<V>::J Jr = load_jv<V>(A, j);
+    F cq = F(0), cs = inf_of<F>();
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r) {
+      const bool skip = MASK && (j <= k[r] || j >= A.n || k[r] >= A.n);
+      if constexpr (sizeof(F) == 4)
+        pair_step_sym<V>(rows[r], wr[r], er[r], Jr, eps2, skip, qmax[r], swmin[r], cq, cs);
+      else
+        pair_step_sym(rows[r], wr[r], er[r], Jr, eps2, skip, qmax[r], swmin[r], cq, cs);
+    }
+    L[(c * kSymLdsStride + lane) * 2] = cq;
+    L[(c * kSymLdsStride + lane) * 2 + 1] = cs;
+  }
+}
+
+// The particle planes and the partials come as separate restrict-qualified arguments:
+// with stores to the partials inside the column loop, only the no-alias guarantee lets the
+// compiler keep the column records on scalar loads.
+template <class V>
+__global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
+                                                      const float *__restrict__ p32,
+                                                      const double *__restrict__ p64,
+                                                      const double *__restrict__ v64,
+                                                      typename V::F *__restrict__ col_part,
+                                                      typename V::F *__restrict__ row_part) {
+  using F = typename V::F;
+  StepSymArgs A = A0;
+  A.p32 = p32;
+  A.p64 = p64;
+  A.v64 = v64;
+  __shared__ F lds[kWG / 64][kSymBlock * kSymLdsStride * 2];
+  // the wave index is uniform over the wave: say so, so that the work item and the column
+  // index are scalar and the column records arrive through scalar loads
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = blockIdx.x * (kWG / 64) + wv;
+  if (item >= A.plan.n_items) return;  // whole wave; the kernel has no workgroup barrier
+  const int4 it = A.plan.items[item];
+  const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
+  typename StepRec<V>::I rows[kSymRows];
+  F wr[kSymRows], er[kSymRows], qmax[kSymRows], swmin[kSymRows];
+  int k[kSymRows];  // row particles (fewer than 2^31)
+#pragma unroll
+  for (int r = 0; r < kSymRows; ++r) {
+    k[r] = static_cast<int>(row0) + r * 64 + lane;
+    const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
+    rows[r] = load_iv<V>(A, kk);
+    col_weights<V>(A, kk, wr[r], er[r]);
+    qmax[r] = F(0);
+    swmin[r] = inf_of<F>();
+  }
+  const F eps2 = static_cast<F>(A.eps2);
+  F *L = lds[wv];
+  F *colq = col_part + static_cast<int64_t>(it.x) * 2 * A.npad;
+  F *cols = colq + A.npad;
+  const bool rows_pad = row0 + kSymWaveRows > A.n;
+  for (int64_t jb = it.y; jb < it.z; jb += kSymBlock) {
+    if (rows_pad || jb < row0 + kSymWaveRows || jb + kSymBlock > A.n)
+      sym_block<V, 1>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
+    else
+      sym_block<V, 0>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
+    wave_lds_sync();
+    // column c = lane & 15 over the 16 lanes' entries of this lane's quarter, then the
+    // four quarters
+    const int c = lane & 15, quarter = lane >> 4;
+    F cq = F(0), cs = inf_of<F>();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = (c * kSymLdsStride + quarter * 16 + i) * 2;
+      cq = fmax(cq, L[e]);
+      cs = fmin(cs, L[e + 1]);
+    }
+    cq = fmax(cq, __shfl_xor(cq, 16, 64));
+    cs = fmin(cs, __shfl_xor(cs, 16, 64));
+    cq = fmax(cq, __shfl_xor(cq, 32, 64));
+    cs = fmin(cs, __shfl_xor(cs, 32, 64));
+    if (lane < 16) {
+      colq[jb + c] = cq;
+      cols[jb + c] = cs;
+    }
+    wave_lds_sync();
+  }
+  F *rq = row_part + static_cast<int64_t>(it.w) * 2 * A.plan.npad_rows;
+  F *rs = rq + A.plan.npad_rows;
+#pragma unroll
+  for (int r = 0; r < kSymRows; ++r) {
+    rq[k[r]] = qmax[r];
+    rs[k[r]] = swmin[r];
+  }
+}
+
+// Target q (particle p = idx[q]): its row tile's row partials in slot order, then the
+// column partials of the row tiles 0 .. its own.
+template <class V>
+__global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
+  using F = typename V::F;
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q >= A.n_act) return;
+  const int64_t p = A.idx[q];
+  const int R = static_cast<int>(p / kSymWaveRows);
+  const int slots = sym_slots(A.npad, R, A.plan.chunk);
+  double qm = 0.0, sm = __builtin_inf();
+  const F *rp = static_cast<const F *>(A.plan.row_part);
+  for (int s = 0; s < slots; ++s) {
+    qm = fmax(qm, static_cast<double>(rp[(2 * s) * A.plan.npad_rows + p]));
+    sm = fmin(sm, static_cast<double>(rp[(2 * s + 1) * A.plan.npad_rows + p]));
+  }
+  const F *cp = static_cast<const F *>(A.plan.col_part);
+  for (int t = 0; t <= R; ++t) {
+    qm = fmax(qm, static_cast<double>(cp[(2 * t) * A.npad + p]));
+    sm = fmin(sm, static_cast<double>(cp[(2 * t + 1) * A.npad + p]));
+  }
+  A.dtc[q] = finish_dt(A.eta, qm, sm);
+}
+
+template <class V>
+hipError_t run(StepSymArgs &A, hipStream_t st) {
+  const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
+  using F = typename V::F;
+  hipLaunchKernelGGL((k_timestep_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, A.v64,
+                     static_cast<F *>(A.plan.col_part), static_cast<F *>(A.plan.row_part));
+  hipLaunchKernelGGL((k_timestep_sym_reduce<V>), dim3((A.n_act + kWG - 1) / kWG), dim3(kWG),
+                     0, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,
+                               int n_act, double eta, double *dtc, hipStream_t st) {
+  StepSymArgs A;
+  A.n = c->n;
+  A.npad = c->npad;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.v64 = c->v64;
+  A.eps2 = c->eps * c->eps;
+  A.plan = plan;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.eta = eta;
+  A.dtc = dtc;
+  if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
+  if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
+  return run<MixSep64>(A, st);
+}
+
+}  // namespace tsbts
