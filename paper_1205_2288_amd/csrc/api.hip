@@ -75,6 +75,14 @@ int check_bound(tsbts_ctx *c) {
   return TSBTS_OK;
 }
 
+// Work list and partials of the symmetric all-targets force, when it serves the call.
+int prepare_force_sym(tsbts_ctx *c, int32_t n_act) {
+  if (!force_sym_applies(c, n_act)) return TSBTS_OK;
+  if (int s = sym_prepare(c, 4, 8, 4))
+    return fail(c, s, "symmetric force: work list or partials not allocated");
+  return TSBTS_OK;
+}
+
 int check_pred(tsbts_ctx *c, double t_block) {
   if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
   if (c->pred_t != t_block)
@@ -325,6 +333,7 @@ int tsbts_force(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
   if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  if (int s = prepare_force_sym(c, n_act)) return s;
   hipError_t e = launch_force(c, idx, n_act, acc, pot, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_force launch");
   return TSBTS_OK;
@@ -394,7 +403,8 @@ int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, 
   if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
   if (sym_enabled(c, n_act)) {
-    if (int s = sym_prepare(c, 2, c->precision == TSBTS_FP64 ? 8 : 4))
+    const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
+    if (int s = sym_prepare(c, 2, vb, vb))
       return fail(c, s, "symmetric criterion: work list or partials not allocated");
   }
   hipError_t e = launch_timestep(c, idx, n_act, eta, dtc, stream);
@@ -584,6 +594,7 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
       return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
     if (int s = grow_log(c, need, stream)) return s;
   }
+  if (int s = prepare_force_sym(c, n_act)) return s;
   const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
   hipError_t e = launch_force(c, idx, n_act, acc, nullptr, stream, &corr);
   if (e != hipSuccess) return hip_fail(c, e, "force + corrector launch");

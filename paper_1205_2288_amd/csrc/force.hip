@@ -20,6 +20,7 @@
 // tile and no large self term ever enters a float32 accumulator.
 #include "correct.hpp"
 #include "force_pair.hpp"
+#include "sym.hpp"
 #include <algorithm>
 #include <type_traits>
 
@@ -400,6 +401,11 @@ int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
 
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr) {
+  if (force_sym_applies(c, n_act)) {
+    SymPlan plan;
+    if (sym_plan(c, 4, 8, 4, &plan))
+      return launch_force_sym(c, plan, idx, n_act, acc, pot, st, corr);
+  }
   ForceArgs A;
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;

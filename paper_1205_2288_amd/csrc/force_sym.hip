@@ -1,0 +1,219 @@
+// Softened force and potential (Section 2 force law, Plummer softening; Algorithm 2,
+// step 5) when every particle is a target: each unordered pair once for both particles
+// (symmetric all-targets scheme of sym.hpp).  For the pair k < j with d = r_j - r_k and
+// y = (|d|^2 + eps^2)^(-1/2), row k gets m_j y^3 d and m_j y, column j gets -m_k y^3 d and
+// m_k y.  Mixed precision without the Newton step: float32 pair arithmetic on the float64
+// separation (or the hi/lo one), float32 sums over a column tile of 64 (rows) or over one
+// work item's rows (columns), float64 across them, combined in a fixed order.  The
+// corrector can be applied as each target is finished, as in the gather kernels.
+#include "correct.hpp"
+#include "force_pair.hpp"
+#include "sym.hpp"
+
+namespace tsbts {
+namespace {
+
+constexpr int kFBlock = 8;  // columns per LDS transposition (4 values each)
+
+struct ForceSymArgs {
+  int64_t n, npad;
+  const float *p32;
+  const double *p64;
+  float eps2;
+  SymPlan plan;
+  const int32_t *idx;
+  int n_act;
+  double *acc;  // [3][n_act]
+  double *pot;  // [n_act] or null
+  int correct;
+  CorrectArgs corr;
+};
+
+// Both directions of pair (row i, column j): row sums (ax, ay, az, pp), column sums
+// (cx, cy, cz, cp).
+template <class V, int POT>
+__device__ __forceinline__ void pair_acc_sym(const typename V::I &i, float mi,
+                                             const typename V::J &j, float eps2, bool skip,
+                                             float &ax, float &ay, float &az, float &pp,
+                                             float &cx, float &cy, float &cz, float &cp) {
+  float dx, dy, dz;
+  V::sep(i, j, dx, dy, dz);
+  const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  float y = rsq_f32(s);
+  if (skip) y = 0.0f;
+  const float y3 = y * (y * y);
+  const float mj = V::mass(j);
+  const float mj3 = mj * y3;
+  const float mi3 = mi * y3;
+  ax = fmaf(mj3, dx, ax);
+  ay = fmaf(mj3, dy, ay);
+  az = fmaf(mj3, dz, az);
+  cx = fmaf(-mi3, dx, cx);
+  cy = fmaf(-mi3, dy, cy);
+  cz = fmaf(-mi3, dz, cz);
+  if (POT) {
+    pp = fmaf(mj, y, pp);
+    cp = fmaf(mi, y, cp);
+  }
+}
+
+template <class V, int POT, int MASK>
+__device__ __forceinline__ void force_block(const ForceSymArgs &A,
+                                            const typename V::I (&rows)[kSymRows],
+                                            const float (&mr)[kSymRows],
+                                            const int (&k)[kSymRows], int64_t jb,
+                                            float (&a)[kSymRows][4], float *L, int lane) {
+#pragma unroll 8
+  for (int c = 0; c < kFBlock; ++c) {
+    const int64_t j = jb + c;
+    const typename V::J Jr = V::load_j(A.p32, A.p64, A.npad, j, 1.0f);
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f, cp = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r) {
+      const bool skip = MASK && (j <= k[r] || j >= A.n || k[r] >= A.n);
+      pair_acc_sym<V, POT>(rows[r], mr[r], Jr, A.eps2, skip, a[r][0], a[r][1], a[r][2],
+                           a[r][3], cx, cy, cz, cp);
+    }
+    float *e = L + (c * kSymLdsStride + lane) * 4;
+    e[0] = cx;
+    e[1] = cy;
+    e[2] = cz;
+    e[3] = cp;
+  }
+}
+
+template <class V, int POT>
+__global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
+                                                   const float *__restrict__ p32,
+                                                   const double *__restrict__ p64,
+                                                   float *__restrict__ col_part,
+                                                   double *__restrict__ row_part) {
+  __shared__ float lds[kWG / 64][kFBlock * kSymLdsStride * 4];
+  ForceSymArgs A = A0;
+  A.p32 = p32;
+  A.p64 = p64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = blockIdx.x * (kWG / 64) + wv;
+  if (item >= A.plan.n_items) return;  // whole wave; the kernel has no workgroup barrier
+  const int4 it = A.plan.items[item];
+  const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
+  typename V::I rows[kSymRows];
+  float mr[kSymRows];
+  int k[kSymRows];
+  double tot[kSymRows][4];
+#pragma unroll
+  for (int r = 0; r < kSymRows; ++r) {
+    k[r] = static_cast<int>(row0) + r * 64 + lane;
+    const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
+    rows[r] = V::load_i(A.p32, A.p64, A.npad, kk);
+    mr[r] = A.p32[P32_M * A.npad + kk];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tot[r][v] = 0.0;
+  }
+  float *L = lds[wv];
+  float *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
+  const bool rows_pad = row0 + kSymWaveRows > A.n;
+  for (int64_t jt = it.y; jt < it.z; jt += 64) {
+    float a[kSymRows][4];
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[r][v] = 0.0f;
+    for (int64_t jb = jt; jb < jt + 64; jb += kFBlock) {
+      if (rows_pad || jb < row0 + kSymWaveRows || jb + kFBlock > A.n)
+        force_block<V, POT, 1>(A, rows, mr, k, jb, a, L, lane);
+      else
+        force_block<V, POT, 0>(A, rows, mr, k, jb, a, L, lane);
+      wave_lds_sync();
+      float cs[4];
+      sym_col_sums<kFBlock, 4>(L, lane, cs);
+      if (lane < kFBlock) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cpart[v * A.npad + jb + lane] = cs[v];
+      }
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tot[r][v] += static_cast<double>(a[r][v]);
+  }
+  double *rp = row_part + static_cast<int64_t>(it.w) * 4 * A.plan.npad_rows;
+#pragma unroll
+  for (int r = 0; r < kSymRows; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rp[v * A.plan.npad_rows + k[r]] = tot[r][v];
+}
+
+// Particle p (target q = inv[p]): the row partials of its row tile in slot order, then
+// the column partials of the row tiles 0 .. its own; then acc, pot and the corrector.
+__global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (p >= A.n) return;
+  const int q = A.plan.inv[p];
+  if (q < 0 || q >= A.n_act) return;  // not in the list
+  const int R = static_cast<int>(p / kSymWaveRows);
+  const int slots = sym_slots(A.npad, R, A.plan.chunk);
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  const double *rp = static_cast<const double *>(A.plan.row_part);
+  for (int s = 0; s < slots; ++s)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
+  const float *cp = static_cast<const float *>(A.plan.col_part);
+  for (int u = 0; u <= R; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
+  const double an[3] = {t[0], t[1], t[2]};
+  A.acc[q] = an[0];
+  A.acc[A.n_act + q] = an[1];
+  A.acc[2 * A.n_act + q] = an[2];
+  if (A.pot) A.pot[q] = -t[3];
+  if (A.correct) correct_one(A.corr, q, p, an);
+}
+
+template <class V>
+hipError_t run(ForceSymArgs &A, hipStream_t st) {
+  const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
+  float *cp = static_cast<float *>(A.plan.col_part);
+  double *rp = static_cast<double *>(A.plan.row_part);
+  if (A.pot)
+    hipLaunchKernelGGL((k_force_sym<V, 1>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, cp,
+                       rp);
+  else
+    hipLaunchKernelGGL((k_force_sym<V, 0>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, cp,
+                       rp);
+  launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  hipLaunchKernelGGL(k_force_sym_reduce, dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
+                     dim3(kWG), 0, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool force_sym_applies(const tsbts_ctx *c, int64_t n_act) {
+  return sym_enabled(c, n_act) && c->precision != TSBTS_FP64 &&
+         (c->flags & TSBTS_FLAG_NEWTON) == 0;
+}
+
+hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
+                            double *acc, double *pot, hipStream_t st,
+                            const CorrectArgs *corr) {
+  ForceSymArgs A;
+  A.n = c->n;
+  A.npad = c->npad;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.eps2 = static_cast<float>(c->eps * c->eps);
+  A.plan = plan;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.acc = acc;
+  A.pot = pot;
+  A.correct = corr ? 1 : 0;
+  if (corr) A.corr = *corr;
+  if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
+  return run<MixSep64>(A, st);
+}
+
+}  // namespace tsbts

@@ -250,6 +250,11 @@ hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int
 struct SymPlan;
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,
                                int n_act, double eta, double *dtc, hipStream_t st);
+// Symmetric all-targets force (force_sym.hip): whether it serves the call, and its launch.
+bool force_sym_applies(const tsbts_ctx *c, int64_t n_act);
+hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
+                            double *acc, double *pot, hipStream_t st,
+                            const CorrectArgs *corr);
 // Adjoints of the passes of an era (hist_adjoint.hip).
 hipError_t launch_interp_adjoint(tsbts_ctx *c, double t_block, double *pbar, double *hbar,
                                  hipStream_t st);

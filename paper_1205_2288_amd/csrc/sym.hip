@@ -18,6 +18,26 @@ int sym_chunk(int64_t npad) {
 
 }  // namespace
 
+__global__ __launch_bounds__(kWG) void k_sym_inverse(const int32_t *idx, int n_act,
+                                                     int32_t *inv) {
+  const int q = blockIdx.x * kWG + threadIdx.x;
+  if (q < n_act) inv[idx[q]] = q;
+}
+
+__global__ __launch_bounds__(kWG) void k_sym_inverse_clear(int64_t n, int32_t *inv) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (p < n) inv[p] = -1;
+}
+
+hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act, int64_t n,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_sym_inverse_clear, dim3(static_cast<unsigned>((n + kWG - 1) / kWG)),
+                     dim3(kWG), 0, st, n, plan.inv);
+  hipLaunchKernelGGL(k_sym_inverse, dim3((n_act + kWG - 1) / kWG), dim3(kWG), 0, st, idx, n_act,
+                     plan.inv);
+  return hipGetLastError();
+}
+
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
   if (n_act != c->n) return false;
   if (c->tune_sym == 0) return false;
@@ -27,7 +47,7 @@ bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
   return c->n >= kSymMinN && c->precision != TSBTS_FP64;
 }
 
-int sym_prepare(tsbts_ctx *c, int nv, int vbytes) {
+int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
   const int64_t npad = c->npad;
   const int chunk = sym_chunk(npad);
   const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
@@ -57,8 +77,9 @@ int sym_prepare(tsbts_ctx *c, int nv, int vbytes) {
   }
   const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
   const int max_slots = sym_slots(npad, 0, chunk);
-  const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows +
-                         static_cast<int64_t>(n_rtiles) * npad) * nv * vbytes;
+  const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows * row_bytes +
+                         static_cast<int64_t>(n_rtiles) * npad * col_bytes) * nv +
+                        npad * static_cast<int64_t>(sizeof(int32_t));
   if (bytes > c->sym_part_bytes) {
     (void)hipDeviceSynchronize();
     if (c->sym_part) (void)hipFree(c->sym_part);
@@ -73,14 +94,15 @@ int sym_prepare(tsbts_ctx *c, int nv, int vbytes) {
   return TSBTS_OK;
 }
 
-bool sym_plan(const tsbts_ctx *c, int nv, int vbytes, SymPlan *p) {
+bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *p) {
   const int64_t npad = c->npad;
   if (!c->sym_items || c->sym_items_npad != npad) return false;
   const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
   const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
   const int max_slots = sym_slots(npad, 0, c->sym_chunk);
-  const int64_t row_bytes = static_cast<int64_t>(max_slots) * npad_rows * nv * vbytes;
-  const int64_t bytes = row_bytes + static_cast<int64_t>(n_rtiles) * npad * nv * vbytes;
+  const int64_t rows = static_cast<int64_t>(max_slots) * npad_rows * nv * row_bytes;
+  const int64_t cols = static_cast<int64_t>(n_rtiles) * npad * nv * col_bytes;
+  const int64_t bytes = rows + cols + npad * static_cast<int64_t>(sizeof(int32_t));
   if (bytes > c->sym_part_bytes) return false;
   p->items = static_cast<const int4 *>(c->sym_items);
   p->n_items = c->sym_items_n;
@@ -89,7 +111,10 @@ bool sym_plan(const tsbts_ctx *c, int nv, int vbytes, SymPlan *p) {
   p->max_slots = max_slots;
   p->npad_rows = npad_rows;
   p->row_part = c->sym_part;
-  p->col_part = static_cast<char *>(c->sym_part) + row_bytes;
+  p->col_part = static_cast<char *>(c->sym_part) + rows;
+  // the inverse permutation sits at the end of the buffer
+  p->inv = reinterpret_cast<int32_t *>(static_cast<char *>(c->sym_part) + c->sym_part_bytes -
+                                       npad * static_cast<int64_t>(sizeof(int32_t)));
   return true;
 }
 

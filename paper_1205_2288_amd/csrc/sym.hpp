@@ -35,7 +35,14 @@ struct SymPlan {
   int64_t npad_rows;  // n_rtiles * kSymWaveRows
   void *row_part;     // [max_slots][NV][npad_rows]
   void *col_part;     // [n_rtiles][NV][npad]
+  int32_t *inv;       // [npad]: position of each particle in the active list
 };
+
+// inv[idx[q]] = q, -1 for particles not in the list (a list with repeated entries): the
+// reductions run over particles in order (coalesced partial reads) and write each result
+// to its place in the active list.
+hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act, int64_t n,
+                              hipStream_t st);
 
 // Work items of a row tile: those covering columns [R * kSymWaveRows, npad) in chunks.
 __host__ __device__ inline int sym_slots(int64_t npad, int R, int chunk) {
@@ -51,12 +58,35 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Column sums of one transposition block: L holds, for each of the BLK columns c, the
+// NV values of every lane at (c * kSymLdsStride + lane) * NV.  Lane l adds the BLK
+// entries of column l % BLK in part l / BLK, then the parts are added across lanes; lanes
+// l < BLK return column l's sums (float, in this fixed order).
+template <int BLK, int NV>
+__device__ __forceinline__ void sym_col_sums(const float *L, int lane, float out[NV]) {
+  const int c = lane % BLK, part = lane / BLK;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < BLK; ++i) {
+    const float *e = L + (c * kSymLdsStride + part * BLK + i) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] += e[v];
+  }
+#pragma unroll
+  for (int off = BLK; off < 64; off <<= 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] += __shfl_xor(out[v], off, 64);
+  }
+}
+
 // Whether the symmetric kernels serve a call with n_act targets (all particles).
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act);
-// Items and partial buffers for NV values of vbytes bytes per partial entry: allocates
-// (host set-up, synchronous) and returns a status.
-int sym_prepare(tsbts_ctx *c, int nv, int vbytes);
-// The plan if sym_prepare has provided for (nv, vbytes); false otherwise (no allocation).
-bool sym_plan(const tsbts_ctx *c, int nv, int vbytes, SymPlan *plan);
+// Items and partial buffers for NV values per particle, row partials of row_bytes and
+// column partials of col_bytes bytes per value: allocates (host set-up, synchronous) and
+// returns a status.
+int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes);
+// The plan if sym_prepare has provided for these sizes; false otherwise (no allocation).
+bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *plan);
 
 }  // namespace tsbts

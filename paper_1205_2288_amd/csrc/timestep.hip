@@ -288,7 +288,8 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
                            double *dtc, hipStream_t st) {
   if (sym_enabled(c, n_act)) {
     SymPlan plan;
-    if (sym_plan(c, 2, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
+    const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
+    if (sym_plan(c, 2, vb, vb, &plan))
       return launch_timestep_sym(c, plan, idx, n_act, eta, dtc, st);
   }
   StepArgs A;

@@ -149,14 +149,15 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
   }
 }
 
-// Target q (particle p = idx[q]): its row tile's row partials in slot order, then the
+// Particle p (target q = inv[p]): its row tile's row partials in slot order, then the
 // column partials of the row tiles 0 .. its own.
 template <class V>
 __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   using F = typename V::F;
-  const int q = blockIdx.x * kWG + threadIdx.x;
-  if (q >= A.n_act) return;
-  const int64_t p = A.idx[q];
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (p >= A.n) return;
+  const int q = A.plan.inv[p];
+  if (q < 0 || q >= A.n_act) return;  // not in the list
   const int R = static_cast<int>(p / kSymWaveRows);
   const int slots = sym_slots(A.npad, R, A.plan.chunk);
   double qm = 0.0, sm = __builtin_inf();
@@ -179,8 +180,9 @@ hipError_t run(StepSymArgs &A, hipStream_t st) {
   using F = typename V::F;
   hipLaunchKernelGGL((k_timestep_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, A.v64,
                      static_cast<F *>(A.plan.col_part), static_cast<F *>(A.plan.row_part));
-  hipLaunchKernelGGL((k_timestep_sym_reduce<V>), dim3((A.n_act + kWG - 1) / kWG), dim3(kWG),
-                     0, st, A);
+  launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  hipLaunchKernelGGL((k_timestep_sym_reduce<V>), dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
+                     dim3(kWG), 0, st, A);
   return hipGetLastError();
 }
 

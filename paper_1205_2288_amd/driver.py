@@ -268,9 +268,10 @@ class NativeTSBTS:
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
                  era=None, precision="mixed", separation="f64", newton=False,
-                 criterion="after"):
+                 criterion="after", tune=None):
         """criterion: "after" the corrector (the paper's order) or "before" it, with the
-        predicted velocities, in the same pass over the pairs as the force."""
+        predicted velocities, in the same pass over the pairs as the force.  tune: keyword
+        arguments of Context.tune, applied before the first force evaluation."""
         from . import _lib as L
         if criterion not in ("after", "before"):
             raise ValueError("criterion must be 'after' or 'before'")
@@ -278,6 +279,8 @@ class NativeTSBTS:
         self.n = n = int(np.asarray(m).size)
         self.dt_max = to_ticks(dt_max)
         self.ctx = Context(n, eps, precision=precision, separation=separation, newton=newton)
+        if tune:
+            self.ctx.tune(**tune)
         self.ctx.bind(r, v, m)
         L.tsbts_sched_init(self.ctx.ctx, eta, passes, dt_min, dt_max,
                            0.0 if era is None else era)

@@ -117,3 +117,87 @@ def test_plummer131k_symmetric_criterion(prec):
     e = rel_err(out[1][np.argsort(idx)][sample], oracle.timestep(r, v, m, eps, eta, sample))
     assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), summary(e)
     ctx.close()
+
+
+# ---------------------------------------------------------------- force and potential
+from gpu_util import rel_err_vec  # noqa: E402
+
+
+@pytest.mark.parametrize("sep", ["f64", "hilo"])
+@pytest.mark.parametrize("n", [3, 300, 700, 1100, 5000])
+def test_symmetric_force_matches_gather_and_oracle(sep, n):
+    eps = 1 / 256
+    r, v, m = _state(n, 3400 + n)
+    ctx = make_ctx(n, eps, "mixed", sep)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _perm(n, n + 1)
+    ctx.tune(symmetric=0)
+    a0, p0 = (x.cpu().numpy() for x in ctx.force(idx, 0.0))
+    ctx.tune(symmetric=1)
+    a1, p1 = (x.cpu().numpy() for x in ctx.force(idx, 0.0))
+    a2, p2 = (x.cpu().numpy() for x in ctx.force(idx, 0.0))
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)   # fixed order
+    ra, rp = oracle.force(r, m, eps, idx)
+    e = rel_err_vec(a1, ra)
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
+    assert rel_err(p1, rp).max() <= 1e-5
+    # same sums as the gather kernel up to float32 rounding of the partial sums
+    assert np.median(rel_err_vec(a1, a0)) <= 1e-6
+    ctx.close()
+
+
+def test_symmetric_kernels_in_native_runs():
+    # whole runs of the native scheduler (all-particle block steps at every era end use
+    # the symmetric force with the corrector in its reduction, and the symmetric
+    # criterion) against the same runs on the gather kernels: the criterion is the same
+    # function of the state and the forces differ only by rounding, so the schedules and
+    # the energy errors agree
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    n, eps = 2048, 1 / 256
+    r, v, m = plummer(n, 3500)
+    runs = []
+    for sym in (0, 1):
+        sim = NativeTSBTS(r, v, m, eps, passes=3, era=1 / 64, dt_max=1 / 64,
+                          tune={"symmetric": sym})
+        series = sim.run(0.25)
+        e0 = series[0][1]
+        runs.append((sim.stats["block_steps"], abs(series[-1][1] - e0) / abs(e0),
+                     sim.ctx.r.cpu().numpy().copy()))
+        sim.close()
+    print(f"native runs N={n}: gather {runs[0][0]} block steps, drift {runs[0][1]:.3e}; "
+          f"symmetric {runs[1][0]} block steps, drift {runs[1][1]:.3e}")
+    assert abs(runs[0][0] - runs[1][0]) <= 0.01 * runs[0][0]
+    assert abs(runs[0][1] - runs[1][1]) <= 0.05 * runs[0][1] + 1e-9
+    assert np.abs(runs[0][2] - runs[1][2]).max() <= 1e-5
+
+
+def test_plummer131k_symmetric_force():
+    cfg = config("plummer131k")
+    n, eps = cfg.n, cfg.eps
+    r, v, m = cfg.ic()
+    ctx = make_ctx(n, eps, "mixed")
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _perm(n, 9)
+    acc = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    out, ms = {}, {}
+    for sym in (0, 1):
+        ctx.tune(symmetric=sym)
+        ctx.force(idx, 0.0, with_pot=False, acc=acc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ctx.force(idx, 0.0, with_pot=False, acc=acc)
+        torch.cuda.synchronize()
+        ms[sym] = (time.perf_counter() - t0) / 3 * 1e3
+        out[sym] = acc.cpu().numpy().copy()
+    print(f"plummer131k mixed force, all targets: gather {ms[0]:.2f} ms, "
+          f"symmetric {ms[1]:.2f} ms")
+    order = np.argsort(idx)
+    sample = np.arange(0, n, n // 256)
+    ra, _ = oracle.force(r, m, eps, sample.astype(np.int32))
+    e = rel_err_vec(out[1][:, order][:, sample], ra)
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
+    assert np.median(rel_err_vec(out[1], out[0])) <= 1e-6
+    ctx.close()
