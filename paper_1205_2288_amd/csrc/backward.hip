@@ -16,6 +16,7 @@
 // (the adjoint seeds are first put in particle order).  The self pair is masked by index,
 // only in tiles that can contain it (wave-uniform vote).
 #include "pair.hpp"
+#include "sym.hpp"
 
 namespace tsbts {
 namespace {
@@ -532,12 +533,16 @@ void reduce_rows(BwdArgs &A, hipStream_t st) {
 }
 
 template <class V, int NEWTON>
-hipError_t run(BwdArgs &A, hipStream_t st) {
+hipError_t run(BwdArgs &A, hipStream_t st, tsbts_ctx *c) {
   if (A.n_act == A.n) {
     // every particle is active (the active set is a permutation of all particles)
     const int64_t cnt = A.n_act + (A.npad - A.n);
     hipLaunchKernelGGL(k_bwd_order, dim3(static_cast<unsigned>((cnt + kWG - 1) / kWG)),
                        dim3(kWG), 0, st, A);
+    if (bwd_sym_applies(c, A.n_act)) {
+      SymPlan plan;
+      if (sym_plan(c, 4, 8, 4, &plan)) return launch_bwd_sym(c, plan, A.gr, A.gm, st);
+    }
     A.plan = plan_all(A);
     A.n_ctiles = static_cast<int>(A.npad / kTJ);
     if (A.scalar_j)
@@ -606,11 +611,11 @@ hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const do
   A.gord = c->gord;
   A.blocks = c->tune_blocks;
   A.scalar_j = force_scalar_j(c) && c->precision == TSBTS_FP64 ? 1 : 0;
-  if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st);
+  if (c->precision == TSBTS_FP64) return run<Fp64, 0>(A, st, c);
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION)
-    return newton ? run<MixHiLo, 1>(A, st) : run<MixHiLo, 0>(A, st);
-  return newton ? run<MixSep64, 1>(A, st) : run<MixSep64, 0>(A, st);
+    return newton ? run<MixHiLo, 1>(A, st, c) : run<MixHiLo, 0>(A, st, c);
+  return newton ? run<MixSep64, 1>(A, st, c) : run<MixSep64, 0>(A, st, c);
 }
 
 }  // namespace tsbts

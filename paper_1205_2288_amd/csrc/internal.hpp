@@ -255,6 +255,10 @@ bool force_sym_applies(const tsbts_ctx *c, int64_t n_act);
 hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
                             double *acc, double *pot, hipStream_t st,
                             const CorrectArgs *corr);
+// Symmetric all-targets force adjoint (backward_sym.hip), after the seeds are ordered.
+bool bwd_sym_applies(const tsbts_ctx *c, int64_t n_act);
+hipError_t launch_bwd_sym(tsbts_ctx *c, const SymPlan &plan, double *gr, double *gm,
+                          hipStream_t st);
 // Adjoints of the passes of an era (hist_adjoint.hip).
 hipError_t launch_interp_adjoint(tsbts_ctx *c, double t_block, double *pbar, double *hbar,
                                  hipStream_t st);

@@ -79,7 +79,7 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
   const int max_slots = sym_slots(npad, 0, chunk);
   const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows * row_bytes +
                          static_cast<int64_t>(n_rtiles) * npad * col_bytes) * nv +
-                        npad * static_cast<int64_t>(sizeof(int32_t));
+                        npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
   if (bytes > c->sym_part_bytes) {
     (void)hipDeviceSynchronize();
     if (c->sym_part) (void)hipFree(c->sym_part);
@@ -102,7 +102,8 @@ bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan 
   const int max_slots = sym_slots(npad, 0, c->sym_chunk);
   const int64_t rows = static_cast<int64_t>(max_slots) * npad_rows * nv * row_bytes;
   const int64_t cols = static_cast<int64_t>(n_rtiles) * npad * nv * col_bytes;
-  const int64_t bytes = rows + cols + npad * static_cast<int64_t>(sizeof(int32_t));
+  const int64_t bytes = rows + cols + npad * static_cast<int64_t>(4 * sizeof(float) +
+                                                                 sizeof(int32_t));
   if (bytes > c->sym_part_bytes) return false;
   p->items = static_cast<const int4 *>(c->sym_items);
   p->n_items = c->sym_items_n;
@@ -112,9 +113,11 @@ bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan 
   p->npad_rows = npad_rows;
   p->row_part = c->sym_part;
   p->col_part = static_cast<char *>(c->sym_part) + rows;
-  // the inverse permutation sits at the end of the buffer
-  p->inv = reinterpret_cast<int32_t *>(static_cast<char *>(c->sym_part) + c->sym_part_bytes -
-                                       npad * static_cast<int64_t>(sizeof(int32_t)));
+  // the staged values and the inverse permutation sit at the end of the buffer
+  char *end = static_cast<char *>(c->sym_part) + c->sym_part_bytes;
+  p->inv = reinterpret_cast<int32_t *>(end - npad * static_cast<int64_t>(sizeof(int32_t)));
+  p->aux = reinterpret_cast<float *>(end - npad * static_cast<int64_t>(sizeof(int32_t) +
+                                                                      4 * sizeof(float)));
   return true;
 }
 

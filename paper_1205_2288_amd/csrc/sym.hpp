@@ -35,6 +35,7 @@ struct SymPlan {
   int64_t npad_rows;  // n_rtiles * kSymWaveRows
   void *row_part;     // [max_slots][NV][npad_rows]
   void *col_part;     // [n_rtiles][NV][npad]
+  float *aux;         // [4][npad]: per-particle float32 values a kernel stages (seeds)
   int32_t *inv;       // [npad]: position of each particle in the active list
 };
 

@@ -201,3 +201,68 @@ def test_plummer131k_symmetric_force():
     assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
     assert np.median(rel_err_vec(out[1], out[0])) <= 1e-6
     ctx.close()
+
+
+# ---------------------------------------------------------------- force adjoint
+@pytest.mark.parametrize("sep", ["f64", "hilo"])
+@pytest.mark.parametrize("n", [3, 300, 700, 5000])
+@pytest.mark.parametrize("with_gp", [False, True])
+def test_symmetric_adjoint_matches_gather_and_oracle(sep, n, with_gp):
+    eps = 1 / 256
+    r, v, m = _state(n, 3600 + n)
+    ctx = make_ctx(n, eps, "mixed", sep)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _perm(n, n + 2)
+    g = gaussian((3, n), 11)
+    gp = gaussian(n, 12) if with_gp else None
+    out = {}
+    for sym in (0, 1, 1):
+        ctx.tune(symmetric=sym)
+        gr = torch.full((3, n), 0.5, dtype=torch.float64, device="cuda")   # accumulates
+        gm = torch.full((n,), 0.25, dtype=torch.float64, device="cuda")
+        ctx.force_backward(idx, 0.0, g, gp, gr, gm)
+        res = (gr.cpu().numpy() - 0.5, gm.cpu().numpy() - 0.25)
+        if sym in out:
+            assert all(np.array_equal(a, b) for a, b in zip(res, out[sym]))   # fixed order
+        out[sym] = res
+    rr, rm = oracle.force_backward(r, m, eps, idx, g, gp)
+    for got, ref in ((out[1][0], rr), (out[1][1], rm)):
+        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+    for got, ref in zip(out[1], out[0]):
+        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+    ctx.close()
+
+
+def test_plummer131k_symmetric_adjoint():
+    cfg = config("plummer131k")
+    n, eps = cfg.n, cfg.eps
+    r, v, m = cfg.ic()
+    ctx = make_ctx(n, eps, "mixed")
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _perm(n, 13)
+    g = torch.tensor(gaussian((3, n), 14), dtype=torch.float64, device="cuda")
+    out, ms = {}, {}
+    for sym in (0, 1):
+        ctx.tune(symmetric=sym)
+        gr = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        gm = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.force_backward(idx, 0.0, g, None, gr, gm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            ctx.force_backward(idx, 0.0, g, None, gr, gm)
+        torch.cuda.synchronize()
+        ms[sym] = (time.perf_counter() - t0) / 2 * 1e3
+        out[sym] = (gr.cpu().numpy() / 3, gm.cpu().numpy() / 3)
+    print(f"plummer131k mixed adjoint, all targets: gather {ms[0]:.2f} ms, "
+          f"symmetric {ms[1]:.2f} ms")
+    for got, ref in zip(out[1], out[0]):
+        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+    # sampled rows against the oracle
+    rows = np.arange(0, n, n // 128).astype(np.int32)
+    rr, rm = oracle.force_backward_rows(r, m, eps, idx, g.cpu().numpy(), rows)
+    for got, ref in ((out[1][0][:, rows], rr), (out[1][1][rows], rm)):
+        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+    ctx.close()
