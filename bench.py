@@ -44,6 +44,13 @@ FLOPS_FORCE = 20.0
 FLOPS_ADJOINT = 73.0
 FLOPS_ENERGY_PAIR = 12.0
 FLOPS_CRITERION = 20.0
+# symmetric all-targets kernels, per unordered pair (FMA = 2): criterion 26 (separation 3,
+# r^2 5, velocity difference 3, v^2 5, v^2/r^2 2, two free-fall terms 4, two maxima and two
+# minima 4); force 26 (separation 3, s 6, 1/sqrt(s) 1, y^3 2, two mass factors 2, row and
+# column sums 12); adjoint 64 (see DESIGN)
+FLOPS_CRITERION_SYM = 26.0
+FLOPS_FORCE_SYM = 26.0
+FLOPS_ADJOINT_SYM = 64.0
 
 # HBM bytes per launch in the default (mixed) era step, from two rocprofv3 --pmc passes
 # over this workload: FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch, averaged over the
@@ -106,12 +113,14 @@ class EraBench:
     """fused=True: the variant that takes the criterion before the corrector, in the same
     pass over the pairs as the force (tsbts_force_criterion)."""
 
-    def __init__(self, cfg, r, v, m, precision, h=2.0 ** -10, seed=0, fused=False):
+    def __init__(self, cfg, r, v, m, precision, h=2.0 ** -10, seed=0, fused=False,
+                 symmetric=2):
         from paper_1205_2288_amd import Context
         n = cfg.n
         self.n, self.h = n, h
         self.fused = fused
         self.ctx = c = Context(n, cfg.eps, precision=precision)
+        c.tune(symmetric=symmetric)
         fine = active_subset(n, n // 2, cfg.seed + 11)
         dt = np.full(n, h)
         dt[fine] = h / 2
@@ -154,7 +163,8 @@ class EraBench:
                 t("force_full" if idx is self.idx_all else "force_half", c.force, idx, tb,
                   with_pot=False, acc=acc)
                 t("correct", c.correct, idx, tb, acc)
-                t("timestep", c.timestep, idx, self.eta, dtc=dtc)
+                t("timestep_full" if idx is self.idx_all else "timestep_half", c.timestep,
+                  idx, self.eta, dtc=dtc)
             t("history_end", c.history_end)
         t("energy", c.energy, out=self.kw)
         self.gr.zero_()
@@ -253,14 +263,17 @@ def gpu_force_rows(cfg, r, v, m):
     return out
 
 
-def rooflines(ms, n, precision="mixed"):
+def rooflines(ms, n, precision="mixed", symmetric=True):
     """Roofline entries per kernel from HIP-event times of their calls in the timed steps.
 
     Each entry: algorithmic TFLOP/s = (flops per unit x units per call) / mean call time.
-    Units per call: force n_act*N interactions; criterion n_act*N pairs; adjoint N^2
-    interactions (all active); energy N(N-1)/2 pairs."""
+    Gather kernels (active subsets): force n_act*N interactions, criterion n_act*N pairs.
+    Symmetric all-targets kernels (every particle active, mixed precision from N = 32768):
+    N(N-1)/2 unordered pairs, each evaluated once for both particles.  Energy N(N-1)/2
+    pairs.  The events enclose each call's reduction kernels too."""
     peak32 = PEAK_FP32_TFLOPS if precision == "mixed" else PEAK_FP64_TFLOPS
     out = {}
+    pairs = n * (n - 1) / 2
 
     def entry(kernel, flops, ms_list, peak):
         t = float(np.sum(ms_list)) * 1e-3
@@ -272,18 +285,31 @@ def rooflines(ms, n, precision="mixed"):
                 "total_ms": t * 1e3}
 
     nf, nh = len(ms["force_full"]), len(ms["force_half"])
-    out["k_force_scalar"] = entry("k_force_scalar",
-                                  FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
-                                  ms["force_full"] + ms["force_half"], peak32)
-    # the criterion kernel's calls alternate half / full active sets
-    nts = len(ms["timestep"])
+    tf, th = len(ms["timestep_full"]), len(ms["timestep_half"])
+    nb = len(ms["backward"])
+    out["k_force_scalar"] = entry("k_force_scalar", FLOPS_FORCE * n * (n // 2) * nh,
+                                  ms["force_half"], peak32)
     out["k_timestep_scalar"] = entry("k_timestep_scalar",
-                                     FLOPS_CRITERION * n * (nts // 2) * (n + n // 2),
-                                     ms["timestep"], peak32)
-    out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * len(ms["backward"]),
-                             ms["backward"], peak32)
+                                     FLOPS_CRITERION * n * (n // 2) * th,
+                                     ms["timestep_half"], peak32)
+    if symmetric:
+        out["k_force_sym"] = entry("k_force_sym", FLOPS_FORCE_SYM * pairs * nf,
+                                   ms["force_full"], peak32)
+        out["k_timestep_sym"] = entry("k_timestep_sym", FLOPS_CRITERION_SYM * pairs * tf,
+                                      ms["timestep_full"], peak32)
+        out["k_bwd_sym"] = entry("k_bwd_sym", FLOPS_ADJOINT_SYM * pairs * nb,
+                                 ms["backward"], peak32)
+    else:
+        out["k_force_scalar"] = entry("k_force_scalar",
+                                      FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
+                                      ms["force_full"] + ms["force_half"], peak32)
+        out["k_timestep_scalar"] = entry("k_timestep_scalar",
+                                         FLOPS_CRITERION * n * (tf * n + th * (n // 2)),
+                                         ms["timestep_full"] + ms["timestep_half"], peak32)
+        out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * nb, ms["backward"],
+                                 peak32)
     out["k_energy_pairs"] = entry("k_energy_pairs",
-                                  FLOPS_ENERGY_PAIR * n * (n - 1) / 2 * len(ms["energy"]),
+                                  FLOPS_ENERGY_PAIR * pairs * len(ms["energy"]),
                                   ms["energy"], PEAK_FP64_TFLOPS)
     return out
 
@@ -433,6 +459,16 @@ def main():
             "speedup_vs_paper_order": (wall / args.steps) / (wallf / stepsf),
             "breakdown_us": {k: float(np.mean(x)) * 1e3 for k, x in msf.items()}}
         bf.close()
+        # the same era step on the gather kernels only (symmetric all-targets kernels off)
+        bg = EraBench(cfg, r, v, m, "mixed", symmetric=0)
+        wallg, msg = time_steps(bg, stepsf, 1)
+        out["gather_kernels_only"] = {
+            "ms_per_step": wallg / stepsf * 1e3,
+            "value": bg.interactions * stepsf / wallg,
+            "speedup_of_symmetric": (wallg / stepsf) / (wall / args.steps),
+            "rooflines": rooflines(msg, n, symmetric=False),
+            "breakdown_us": {k: float(np.mean(x)) * 1e3 for k, x in msg.items()}}
+        bg.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, r, v, m, gpu_force_rows(cfg, r, v, m))
     else:
