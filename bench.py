@@ -60,15 +60,24 @@ FLOPS_ADJOINT_SYM = 64.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (313277.0, 131072.0,
-        ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp"), "08eebd53e86dfdfb"),
-    "k_force_scalar": (40750.7, 65536.0,
-        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
-        "67ba1a56ff01859d"),
-    "k_bwd_all": (64964.3, 65536.0,
-        ("backward.hip", "pair.hpp", "internal.hpp"), "248afc0475cd86fb"),
-    "k_energy_pairs": (22007.1, 4104.0,
-        ("energy.hip", "internal.hpp"), "1c85c27126d2c652"),
+    "k_timestep_scalar": (411308.8, 131072.0,
+        ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
+        "73b1678449491c76"),
+    "k_force_scalar": (50979.5, 65536.0,
+        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp"),
+        "959ae23cabae0ed8"),
+    "k_timestep_sym": (424665.3, 332259.5,
+        ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
+        "fa1d61a5d662c90f"),
+    "k_force_sym": (311024.0, 790087.9,
+        ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
+        "4489612d30c1f9d3"),
+    "k_bwd_sym": (609883.8, 792229.5,
+        ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
+        "6e36e9d052bf6676"),
+    "k_energy_pairs": (23349.4, 4104.0,
+        ("energy.hip", "internal.hpp"),
+        "fdf7af56d3adecd9"),
 }
 
 
