@@ -151,21 +151,27 @@ def block_gradient(r0, v0, m, eps, dt, t_end, r_target, v_target):
 
 
 # ----------------------------------------------------------------------------------------
-# Fixed block schedule with eras and passes (Section 2's time-symmetric scheme on a given
-# schedule).  The run is cut into eras of length `era` (a multiple of the largest step, so
-# every particle is due at each era end).  Each era is integrated `passes` times from its
-# start state.  A pass records, per particle, the era-start state and the state after each
+# Block schedules with eras and passes (Section 2's time-symmetric scheme on a given
+# schedule).  A schedule lists the initial steps and, per era and pass, the block steps
+# (t_b, active set, the active particles' steps after the step).  Each era is integrated
+# once per listed pass from its start state (positions, velocities, accelerations, times
+# and steps).  A pass records, per particle, its era-start state and the state after each
 # of its steps (t, r, v, a).  In the first pass every particle is Taylor-predicted to the
 # block time; from the second pass on the active particles are still Taylor-predicted from
 # their own state (their leapfrog position) and every other particle is taken from the
 # previous pass's records: the record itself at a stored time, otherwise the cubic Hermite
-# interpolant between the two records that bracket the block time.  The era ends with the
-# last pass's state.  With passes = 1 this is ``block_forward``.
+# interpolant between the two records that bracket the block time, otherwise (no record
+# after the block time) its Taylor prediction.  The era ends with the last pass's state.
+# The steps are taken as given (a recorded schedule is replayed; its choice by the
+# criterion is not differentiated).  The fixed schedule (every particle keeps dt_i, eras
+# of a multiple of the largest step) is one such schedule; with one pass per era it is
+# ``block_forward``.
 
 
-def _records_new(r, v, a, t0):
+def _records_new(r, v, a, t_last):
     """Per-particle lists of (t, r, v, a), starting with the era-start state."""
-    return [[(t0, r[:, j].copy(), v[:, j].copy(), a[:, j].copy())] for j in range(r.shape[1])]
+    return [[(float(t_last[j]), r[:, j].copy(), v[:, j].copy(), a[:, j].copy())]
+            for j in range(r.shape[1])]
 
 
 def _bracket(recs_j, t):
@@ -176,25 +182,37 @@ def _bracket(recs_j, t):
     return k
 
 
-def _era_times(dt, t_end, era):
+def fixed_schedule(dt, t_end, era, passes):
+    """The fixed block schedule (particle i due at every multiple of dt_i) cut into eras of
+    length `era` (a multiple of the largest step), `passes` passes per era."""
     dt = np.asarray(dt, dtype=np.float64)
     hmin = float(dt.min())
     assert era % float(dt.max()) == 0.0, "the era must be a multiple of the largest step"
     n_era = int(round(t_end / era))
     assert n_era * era == t_end, "t_end must be a multiple of the era"
     per = int(round(era / hmin))
-    return [(e * era, [e * era + hmin * (s + 1) for s in range(per)]) for e in range(n_era)]
+    eras = []
+    for e in range(n_era):
+        steps = []
+        for s in range(per):
+            t_b = e * era + hmin * (s + 1)
+            act = np.nonzero(np.mod(t_b, dt) == 0.0)[0].astype(np.int32)
+            steps.append((t_b, act, dt[act].copy()))
+        eras.append({"passes": [steps] * passes})
+    return {"dt0": dt.copy(), "eras": eras}
 
 
-def _pass(state, m, eps, dt, times, prev):
-    """One pass over an era's block times from `state` (modified in place); prev = the
-    previous pass's records or None.  Returns (records, steps) with steps[s] = (t_b, act,
-    pre-step r, v, a, t_last, interpolated: list of (j, k, exact))."""
-    r, v, a, t_last = state
-    recs = _records_new(r, v, a, float(t_last[0]))
-    steps = []
-    for t_b in times:
-        act = np.nonzero(t_last + dt == t_b)[0].astype(np.int32)
+def _pass(state, m, eps, steps, prev):
+    """One pass over an era's block steps from `state` = (r, v, a, t_last, dt), modified in
+    place; prev = the previous pass's records or None.  Returns (records, log) with
+    log[s] = (t_b, act, pre-step r, v, a, t_last, interpolated: list of (j, k, exact))."""
+    r, v, a, t_last, dt = state
+    recs = _records_new(r, v, a, t_last)
+    log = []
+    for (t_b, act, dt_new) in steps:
+        act = np.asarray(act, dtype=np.int32)
+        due = np.nonzero(t_last + dt == t_b)[0]
+        assert np.array_equal(np.sort(act), due), "schedule inconsistent with the steps"
         hh = t_b - t_last
         p = r + v * hh + 0.5 * a * hh * hh
         interp = []
@@ -211,42 +229,54 @@ def _pass(state, m, eps, dt, times, prev):
                     t1, r1, v1, a1 = prev[j][k + 1]
                     p[:, j] = hermite(tk, rk, vk, ak, t1, r1, v1, a1, t_b)[0]
                     interp.append((j, k, False))
-        steps.append((t_b, act, r.copy(), v.copy(), a.copy(), t_last.copy(), interp))
+        log.append((t_b, act, r.copy(), v.copy(), a.copy(), t_last.copy(), interp))
         an, _ = force(p, m, eps, act)
+        h = hh[act]
         r[:, act] = p[:, act]
-        v[:, act] = v[:, act] + 0.5 * dt[act] * (a[:, act] + an)
+        v[:, act] = v[:, act] + 0.5 * h * (a[:, act] + an)
         a[:, act] = an
         t_last[act] = t_b
-        for q, i in enumerate(act):
+        dt[act] = dt_new
+        for i in act:
             recs[i].append((t_b, r[:, i].copy(), v[:, i].copy(), a[:, i].copy()))
-    return recs, steps
+    return recs, log
 
 
-def era_forward(r0, v0, m, eps, dt, t_end, era, passes):
-    """(r_end, v_end, eras); eras[e] = (era-start state, [(records, steps) per pass])."""
+def schedule_forward(r0, v0, m, eps, schedule):
+    """(r_end, v_end, eras); eras[e] = (era-start state, [(records, log) per pass])."""
     m = np.asarray(m, dtype=np.float64)
-    dt = np.asarray(dt, dtype=np.float64)
     r = np.array(r0, dtype=np.float64)
     v = np.array(v0, dtype=np.float64)
     a, _ = force(r, m, eps)
+    dt = np.array(schedule["dt0"], dtype=np.float64)
     t_last = np.zeros(dt.size)
     out = []
-    for T0, times in _era_times(dt, t_end, era):
-        start = (r.copy(), v.copy(), a.copy(), t_last.copy())
+    for era in schedule["eras"]:
+        start = (r.copy(), v.copy(), a.copy(), t_last.copy(), dt.copy())
         prev = None
         passes_log = []
-        for _ in range(passes):
-            r, v, a, t_last = (x.copy() for x in start)
-            recs, steps = _pass((r, v, a, t_last), m, eps, dt, times, prev)
-            passes_log.append((recs, steps))
+        for steps in era["passes"]:
+            r, v, a, t_last, dt = (x.copy() for x in start)
+            recs, log = _pass((r, v, a, t_last, dt), m, eps, steps, prev)
+            passes_log.append((recs, log))
             prev = recs
         out.append((start, passes_log))
     return r, v, out
 
 
-def era_loss(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
-    r, v, _ = era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+def schedule_loss(r0, v0, m, eps, schedule, r_target, v_target):
+    r, v, _ = schedule_forward(r0, v0, m, eps, schedule)
     return float(((r - r_target) ** 2).sum() + ((v - v_target) ** 2).sum())
+
+
+def era_forward(r0, v0, m, eps, dt, t_end, era, passes):
+    """The fixed schedule cut into eras (see ``fixed_schedule``)."""
+    return schedule_forward(r0, v0, m, eps, fixed_schedule(dt, t_end, era, passes))
+
+
+def era_loss(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
+    return schedule_loss(r0, v0, m, eps, fixed_schedule(dt, t_end, era, passes), r_target,
+                         v_target)
 
 
 def hermite_weights(t0, t1, t):
@@ -259,6 +289,12 @@ def hermite_weights(t0, t1, t):
 
 
 def era_gradient(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
+    """``schedule_gradient`` on the fixed schedule cut into eras."""
+    return schedule_gradient(r0, v0, m, eps, fixed_schedule(dt, t_end, era, passes),
+                             r_target, v_target)
+
+
+def schedule_gradient(r0, v0, m, eps, schedule, r_target, v_target):
     """(L, dL/dr0, dL/dv0, dL/dm) for L = |r_end - r_target|^2 + |v_end - v_target|^2, by
     the chain rule in reverse: eras last to first, within an era passes last to first.
     A pass's end state only reaches later passes through its records, so the reverse of
@@ -267,9 +303,8 @@ def era_gradient(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
     records on to it; every pass starts from the era-start state, whose adjoint is the sum
     over the passes (plus the adjoints of the era-start records)."""
     m = np.asarray(m, dtype=np.float64)
-    dt = np.asarray(dt, dtype=np.float64)
     n = m.size
-    r_end, v_end, eras = era_forward(r0, v0, m, eps, dt, t_end, era, passes)
+    r_end, v_end, eras = schedule_forward(r0, v0, m, eps, schedule)
     L = float(((r_end - r_target) ** 2).sum() + ((v_end - v_target) ** 2).sum())
     rbar = 2.0 * (r_end - r_target)
     vbar = 2.0 * (v_end - v_target)
@@ -303,10 +338,11 @@ def era_gradient(r0, v0, m, eps, dt, t_end, era, passes, r_target, v_target):
                             tk, rk, vk, ak = prev[j][k]
                             t1, r1, v1, a1 = prev[j][k + 1]
                             p_pos[:, j] = hermite(tk, rk, vk, ak, t1, r1, v1, a1, t_b)[0]
-                seed = ab[:, act] + 0.5 * dt[act] * vb[:, act]
+                h = hh[act]  # the active particles' steps
+                seed = ab[:, act] + 0.5 * h * vb[:, act]
                 pbar = np.zeros_like(rb)
                 pbar[:, act] = rb[:, act]
-                ab[:, act] = 0.5 * dt[act] * vb[:, act]
+                ab[:, act] = 0.5 * h * vb[:, act]
                 rb[:, act] = 0.0
                 gr, gm = force_backward(p_pos, m, eps, act, seed)
                 pbar += gr

@@ -102,7 +102,10 @@ class OracleTSBTS:
     """Plain FP64 TSBTS integration (oracle).  State arrays are (3, N) / (N,)."""
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
-                 era=None, criterion=None):
+                 era=None, criterion=None, record_schedule=False):
+        """record_schedule: keep the block steps taken (``self.schedule``: initial steps
+        and, per era and pass, (t_b, active set, new steps of the active set), in time
+        units) so that the same schedule can be replayed."""
         self.n = int(np.asarray(m).size)
         self.m = np.array(m, dtype=np.float64)
         self.eps = float(eps)
@@ -122,6 +125,8 @@ class OracleTSBTS:
                             for c in self.dtc], dtype=np.int64)
         self.time = 0
         self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0}
+        self.schedule = ({"dt0": self.dt * TICK, "eras": []} if record_schedule else None)
+        self._log = None
 
     # ------------------------------------------------------------------ criterion
     def _criterion(self, r, v, idx):
@@ -224,6 +229,8 @@ class OracleTSBTS:
             hist.append(idx, tb, self.r[:, idx], self.v[:, idx], self.a[:, idx], dtc)
             for k, i in enumerate(idx):
                 self.dt[i] = self._new_step(int(i), tb, float(dtc[k]), prev)
+            if self._log is not None:
+                self._log.append((tb * TICK, idx.copy(), self.dt[idx] * TICK))
             self.stats["block_steps"] += 1
             self.stats["force_calls"] += 1
             self.stats["interactions"] += int(idx.size) * self.n
@@ -235,12 +242,20 @@ class OracleTSBTS:
         T1 = self._era_end(T0)
         saved = [x.copy() for x in (self.r, self.v, self.a, self.t, self.dt, self.dtc)]
         prev = None
+        era_rec = None
+        if self.schedule is not None:
+            era_rec = {"passes": []}
+            self.schedule["eras"].append(era_rec)
         for p in range(self.passes):
             if p > 0:
                 for dst, src in zip((self.r, self.v, self.a, self.t, self.dt, self.dtc),
                                     saved):
                     dst[...] = src
+            if era_rec is not None:
+                self._log = []
+                era_rec["passes"].append(self._log)
             prev = self._pass(T1, prev)
+        self._log = None
         self.last_history = prev
         self.time = T1
         self.stats["eras"] += 1

@@ -223,3 +223,47 @@ def test_era_gradient_vs_finite_differences(oracle, passes):
                 return adjoint.era_loss(rr, vv, mm, eps, dt, t_end, era, passes, rt, vt)
             fd = (f(1) - f(-1)) / (2 * step)
             assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which
+
+
+# ---------------------------------------------------------------- recorded schedules
+def _recorded(n, seed, passes, era, t_end):
+    from oracle.tsbts import OracleTSBTS
+    r0, v0, m = plummer(n, seed)
+    sim = OracleTSBTS(r0, v0, m, 1.0 / 64, passes=passes, dt_max=1.0 / 64, era=era,
+                      record_schedule=True)
+    sim.run(t_end)
+    return r0, v0, m, sim
+
+
+@pytest.mark.parametrize("passes,era", [(1, None), (3, None), (3, 1.0 / 32)])
+def test_schedule_replay_matches_the_era_driver(oracle, passes, era):
+    # the era driver's own steps (criterion, Algorithm 1, dynamic or fixed eras), replayed
+    # by the schedule run, give the driver's end state
+    r0, v0, m, sim = _recorded(20, 43, passes, era, 0.25)
+    levels = {float(d) for e in sim.schedule["eras"] for p in e["passes"]
+              for (_, _, dts) in p for d in dts}
+    assert len(levels) >= 3     # a schedule with several step levels
+    assert all(len(e["passes"]) == passes for e in sim.schedule["eras"])
+    r, v, _ = adjoint.schedule_forward(r0, v0, m, 1.0 / 64, sim.schedule)
+    assert np.array_equal(r, sim.r) and np.array_equal(v, sim.v)
+
+
+def test_schedule_gradient_vs_finite_differences(oracle):
+    r0, v0, m, sim = _recorded(10, 44, 3, None, 0.125)
+    eps, sched = 1.0 / 64, sim.schedule
+    rt = sim.r + 0.01 * gaussian((3, 10), 19)
+    vt = sim.v + 0.01 * gaussian((3, 10), 20)
+    L, gr, gv, gm = adjoint.schedule_gradient(r0, v0, m, eps, sched, rt, vt)
+    step = 1e-6
+    for trial in range(2):
+        dr = gaussian((3, 10), 620 + trial)
+        dv = gaussian((3, 10), 720 + trial)
+        dm = gaussian(10, 820 + trial) * m
+        for (g, d, which) in ((gr, dr, "r"), (gv, dv, "v"), (gm, dm, "m")):
+            def f(sgn):
+                rr = r0 + sgn * step * d if which == "r" else r0
+                vv = v0 + sgn * step * d if which == "v" else v0
+                mm = m + sgn * step * d if which == "m" else m
+                return adjoint.schedule_loss(rr, vv, mm, eps, sched, rt, vt)
+            fd = (f(1) - f(-1)) / (2 * step)
+            assert (g * d).sum() == pytest.approx(fd, rel=2e-6, abs=1e-10), which
