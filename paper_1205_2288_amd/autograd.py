@@ -13,12 +13,14 @@
   block time, force and leapfrog corrector on the active set), all particles starting
   together at t = 0.  Same checkpointing; the reverse sweep restores each block step's
   pre-step state, predicts, and runs ``tsbts_block_adjoint`` around the force adjoint.
-* ``TsbtsEraLeapfrog``: the same fixed schedule cut into eras, each integrated with
-  several passes (Section 2's time-symmetric scheme: from the second pass on the
-  non-active particles are interpolated from the previous pass's stored states).  The
-  reverse sweep of a pass also moves the adjoints of interpolated positions into the
-  adjoints of the previous pass's records (``tsbts_interp_adjoint``) and adds those back
-  at the block steps that wrote them (``tsbts_record_adjoint``).
+* ``TsbtsScheduleLeapfrog``: a run on a given block schedule with eras and several passes
+  (Section 2's time-symmetric scheme: from the second pass on the non-active particles
+  are interpolated from the previous pass's stored states), e.g. the schedule the
+  criterion chose in a run of ``driver.TSBTS(record_schedule=True)``, replayed; or the
+  fixed schedule cut into eras (``tsbts_era_leapfrog``).  The reverse sweep of a pass
+  also moves the adjoints of interpolated positions into the adjoints of the previous
+  pass's records (``tsbts_interp_adjoint``) and adds those back at the block steps that
+  wrote them (``tsbts_record_adjoint``).
 
 All arithmetic runs in libtsbts kernels; torch provides the tensors and the graph.
 """
@@ -259,7 +261,7 @@ def tsbts_block_leapfrog(r0, v0, m, ctx: Context, dt, t_end: float, era: int = 1
 
 
 def _state(ctx: Context):
-    return (ctx.r, ctx.v, ctx.a, ctx.t_last)
+    return (ctx.r, ctx.v, ctx.a, ctx.t_last, ctx.dt)
 
 
 def _restore(ctx: Context, saved):
@@ -267,44 +269,100 @@ def _restore(ctx: Context, saved):
         dst.copy_(src)
 
 
-def _era_pass(ctx: Context, sched: BlockSchedule, s0: int, s1: int, buf, use_history: bool,
-              record: bool, pre=None):
-    """Block steps s0 .. s1-1 of one pass; record = keep its states as the next pass's
+def fixed_schedule(dt, t_end: float, era: float, passes: int):
+    """The fixed block schedule (particle i due at every multiple of dt_i, steps kept) cut
+    into eras of length `era` (a multiple of the largest step that divides t_end), as a
+    schedule for tsbts_schedule_leapfrog."""
+    dt = np.asarray(dt.cpu().numpy() if isinstance(dt, torch.Tensor) else dt,
+                    dtype=np.float64).reshape(-1)
+    if dt.size == 0 or not np.all(dt > 0):
+        raise ValueError("dt must hold one positive step per particle")
+    hmin = float(dt.min())
+    level = np.rint(np.log2(dt / hmin))
+    if not np.array_equal(hmin * 2.0 ** level, dt):
+        raise ValueError("every step must be the smallest step times a power of two")
+    per = era / hmin
+    n_era = t_end / era if era > 0 else 0.0
+    if (passes < 1 or era <= 0 or era % float(dt.max()) != 0.0 or per != int(per)
+            or n_era != int(n_era) or n_era < 1):
+        raise ValueError("era must be a multiple of the largest step and divide t_end; "
+                         "passes >= 1")
+    eras = []
+    for e in range(int(n_era)):
+        steps = []
+        for k in range(int(per)):
+            tb = e * era + hmin * (k + 1)
+            act = np.flatnonzero(np.mod(tb, dt) == 0.0).astype(np.int32)
+            steps.append((tb, act, dt[act].copy()))
+        eras.append({"passes": [steps] * passes})
+    return {"dt0": dt.copy(), "eras": eras}
+
+
+class _DeviceSchedule:
+    """A schedule ({"dt0": steps, "eras": [{"passes": [[(t_b, active, new steps), ...]]}]},
+    as recorded by driver.TSBTS(record_schedule=True)) with its index and step arrays on the
+    device."""
+
+    def __init__(self, ctx: Context, schedule):
+        dev = ctx.device
+        self.dt0 = torch.tensor(np.asarray(schedule["dt0"], dtype=np.float64), device=dev)
+        if self.dt0.numel() != ctx.n:
+            raise ValueError("the schedule's initial steps must cover every particle")
+        cache = {}
+        self.eras = []
+        for era in schedule["eras"]:
+            passes = []
+            for steps in era["passes"]:
+                dev_steps = []
+                for (tb, act, dtn) in steps:
+                    key = id(act)
+                    if key not in cache:
+                        cache[key] = (ctx.idx(np.asarray(act, dtype=np.int32)), act)
+                    dev_steps.append((float(tb), cache[key][0],
+                                      torch.tensor(np.asarray(dtn, dtype=np.float64),
+                                                   device=dev)))
+                passes.append(dev_steps)
+            if not passes:
+                raise ValueError("every era needs at least one pass")
+            self.eras.append(passes)
+
+
+def _sched_pass(ctx: Context, steps, buf, use_history: bool, record: bool, pre=None):
+    """One pass over the listed block steps; record = keep its states as the next pass's
     interpolation source; pre = list receiving each step's pre-step state."""
     if record:
         ctx.history_begin()
-    for s in range(s0, s1):
+    for (tb, idx, dtn) in steps:
         if pre is not None:
             pre.append([x.clone() for x in _state(ctx)])
-        _block_step(ctx, sched, s, buf, use_history)
+        k = idx.numel()
+        acc = buf[:3 * k].view(3, k)
+        ctx.predict(tb, use_history)
+        ctx.force(idx, tb, with_pot=False, acc=acc)
+        ctx.correct(idx, tb, acc)
+        ctx.set_dt(idx, dtn)
     if record:
         ctx.history_end()
 
 
-class TsbtsEraLeapfrog(torch.autograd.Function):
-    """(r, v) at t_end after a run on a fixed block schedule cut into eras of length `era`
-    (a multiple of the largest step), each era integrated `passes` times from its start
-    state: the first pass Taylor-predicts every particle, later passes take the
-    non-active particles from the previous pass's stored states by cubic Hermite
-    interpolation (Section 2's time-symmetric scheme on a given schedule).  The forward
-    keeps the era-start states; the backward sweeps each era's passes in reverse,
-    recomputing the interpolation source of each pass from the era start."""
+class TsbtsScheduleLeapfrog(torch.autograd.Function):
+    """(r, v) at the end of a run on a given block schedule with eras and passes (Section
+    2's time-symmetric scheme): each era is integrated once per listed pass from its start
+    state; the first pass Taylor-predicts every particle, later passes take the non-active
+    particles from the previous pass's stored states (cubic Hermite interpolation).  The
+    schedule (block times, active sets, steps) is replayed, not re-chosen: its choice by
+    the criterion is piecewise constant and not differentiated.  The forward keeps the
+    era-start states; the backward sweeps each era's passes in reverse, recomputing the
+    interpolation source of each pass from the era start."""
 
     @staticmethod
-    def forward(fctx, r0, v0, m, ctx: Context, dt, t_end: float, era: float, passes: int):
+    def forward(fctx, r0, v0, m, ctx: Context, sched: _DeviceSchedule):
         n = ctx.n
         dev = ctx.device
-        sched = BlockSchedule(ctx, dt, t_end)
-        per = era / sched.hmin
-        if passes < 1:
-            raise ValueError("passes must be >= 1")
-        if era % float(sched.dt.max()) != 0.0 or per != int(per) or sched.K % int(per):
-            raise ValueError("era must be a multiple of the largest step and divide t_end")
-        per = int(per)
         r0, v0, m = (x.detach().contiguous() for x in (r0, v0, m))
         ctx.bind(r0.clone(), v0.clone(), m.clone(),
                  t_last=torch.zeros(n, dtype=torch.float64, device=dev),
-                 dt=torch.tensor(sched.dt, dtype=torch.float64, device=dev))
+                 dt=sched.dt0.clone())
         every = ctx.idx(torch.arange(n, dtype=torch.int32))
         buf = torch.empty(3 * n, dtype=torch.float64, device=dev)
         acc = buf.view(3, n)
@@ -312,19 +370,17 @@ class TsbtsEraLeapfrog(torch.autograd.Function):
         ctx.force(every, 0.0, with_pot=False, acc=acc)
         ctx.a.copy_(acc)
         starts = []
-        for s0 in range(0, sched.K, per):
+        for passes in sched.eras:
             start = [x.clone() for x in _state(ctx)]
             starts.append(start)
             ctx.history_clear()
-            for p in range(passes):
+            for p, steps in enumerate(passes):
                 if p:
                     _restore(ctx, start)
-                _era_pass(ctx, sched, s0, s0 + per, buf, p > 0, p < passes - 1)
+                _sched_pass(ctx, steps, buf, p > 0, p < len(passes) - 1)
         ctx.history_clear()
         fctx.tsbts = ctx
         fctx.sched = sched
-        fctx.per = per
-        fctx.passes = passes
         fctx.starts = starts
         fctx.every = every
         fctx.save_for_backward(m)
@@ -332,7 +388,7 @@ class TsbtsEraLeapfrog(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, g_r, g_v):
-        ctx, sched, per, passes = fctx.tsbts, fctx.sched, fctx.per, fctx.passes
+        ctx, sched = fctx.tsbts, fctx.sched
         (m,) = fctx.saved_tensors
         n = ctx.n
         dev = ctx.device
@@ -346,31 +402,32 @@ class TsbtsEraLeapfrog(torch.autograd.Function):
         seeds = torch.empty(3 * n, dtype=torch.float64, device=dev)
         first = fctx.starts[0]
         ctx.bind(first[0].clone(), first[1].clone(), m, a=first[2].clone(),
-                 t_last=first[3].clone(),
-                 dt=torch.tensor(sched.dt, dtype=torch.float64, device=dev))
-        for e in range(len(fctx.starts) - 1, -1, -1):
-            start = fctx.starts[e]
-            s0 = e * per
-            t0 = s0 * sched.hmin
+                 t_last=first[3].clone(), dt=first[4].clone())
+        for e in range(len(sched.eras) - 1, -1, -1):
+            passes, start = sched.eras[e], fctx.starts[e]
+            P = len(passes)
+            # each particle's first record of a pass is its era-start state, at its own time
+            t_start = start[3].cpu().numpy()
+            groups = [(float(t), ctx.idx(np.flatnonzero(t_start == t).astype(np.int32)))
+                      for t in np.unique(t_start)]
             acc_r, acc_v, acc_a = z(), z(), z()
             later = None   # (layout, record adjoint) of the pass after the one reversed
-            for p in range(passes - 1, -1, -1):
+            for p in range(P - 1, -1, -1):
                 # interpolation source of pass p: pass p-1, rebuilt from the era start
                 ctx.history_clear()
                 for q in range(p):
                     _restore(ctx, start)
-                    _era_pass(ctx, sched, s0, s0 + per, buf, q > 0, True)
+                    _sched_pass(ctx, passes[q], buf, q > 0, True)
                 if p:
                     layout = ctx.history_layout()
                     hbar = torch.zeros((6, layout[0]), dtype=torch.float64, device=dev)
                 _restore(ctx, start)
                 pre = []
-                _era_pass(ctx, sched, s0, s0 + per, buf, p > 0, False, pre)
-                rb, vb, ab = (rbar, vbar, abar) if p == passes - 1 else (z(), z(), z())
-                for s in range(s0 + per - 1, s0 - 1, -1):
-                    _restore(ctx, pre[s - s0])
-                    tb = sched.time(s)
-                    idx = sched.active(s)
+                _sched_pass(ctx, passes[p], buf, p > 0, False, pre)
+                rb, vb, ab = (rbar, vbar, abar) if p == P - 1 else (z(), z(), z())
+                for s in range(len(passes[p]) - 1, -1, -1):
+                    _restore(ctx, pre[s])
+                    tb, idx, _ = passes[p][s]
                     k = idx.numel()
                     sd = seeds[:3 * k].view(3, k)
                     if later is not None:
@@ -382,7 +439,8 @@ class TsbtsEraLeapfrog(torch.autograd.Function):
                         ctx.interp_adjoint(tb, pbar, hbar)
                     ctx.block_adjoint(1, None, tb, rb, vb, ab, pbar, None)
                 if later is not None:
-                    ctx.record_adjoint(fctx.every, t0, later[0], later[1], rb, vb)
+                    for (t0, gidx) in groups:
+                        ctx.record_adjoint(gidx, t0, later[0], later[1], rb, vb)
                 ctx.adjoint_accumulate(rb, vb, ab, acc_r, acc_v, acc_a)
                 later = (layout, hbar) if p else None
             rbar, vbar, abar = acc_r, acc_v, acc_a
@@ -390,9 +448,16 @@ class TsbtsEraLeapfrog(torch.autograd.Function):
         ctx.history_clear()
         ctx.load_positions(first[0], m, 0.0)
         ctx.force_backward(fctx.every, 0.0, abar, None, rbar, mbar)   # through a_0
-        return rbar, vbar, mbar, None, None, None, None, None
+        return rbar, vbar, mbar, None, None
+
+
+def tsbts_schedule_leapfrog(r0, v0, m, ctx: Context, schedule):
+    """Differentiable run on a recorded block schedule (see TsbtsScheduleLeapfrog)."""
+    return TsbtsScheduleLeapfrog.apply(r0, v0, m, ctx, _DeviceSchedule(ctx, schedule))
 
 
 def tsbts_era_leapfrog(r0, v0, m, ctx: Context, dt, t_end: float, era: float,
                        passes: int = 3):
-    return TsbtsEraLeapfrog.apply(r0, v0, m, ctx, dt, t_end, era, passes)
+    """Differentiable run on the fixed block schedule dt cut into eras of length `era`
+    with `passes` passes each (see fixed_schedule)."""
+    return tsbts_schedule_leapfrog(r0, v0, m, ctx, fixed_schedule(dt, t_end, era, passes))

@@ -97,8 +97,14 @@ class TSBTS:
     precision / separation / newton select the force kernel (see Context)."""
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
-                 era=None, precision="mixed", separation="f64", newton=False, context=None):
+                 era=None, precision="mixed", separation="f64", newton=False, context=None,
+                 record_schedule=False):
+        """record_schedule: keep the block steps taken in ``self.schedule`` (initial steps
+        and, per era and pass, (t_b, active set, new steps of the active set), in time
+        units), the input of autograd.tsbts_schedule_leapfrog."""
         self.n = n = int(np.asarray(m).size)
+        self.schedule = {"dt0": None, "eras": []} if record_schedule else None
+        self._log = None
         self.eta = float(eta)
         self.passes = int(passes)
         self.dt_max = to_ticks(dt_max)
@@ -147,6 +153,8 @@ class TSBTS:
         self.dt[:] = admissible(self.dtc, self.dtc, self.dt_min, self.dt_max)
         c.dt.copy_(torch.from_numpy(self.dt * TICK))
         c.synchronize()
+        if self.schedule is not None:
+            self.schedule["dt0"] = self.dt * TICK
 
     # ------------------------------------------------------------------ step rules
     def _new_steps(self, idx, tb, begin, prev: CriterionHistory | None):
@@ -205,6 +213,8 @@ class TSBTS:
             dtn = self._dtn_d[:k]
             dtn.copy_(self._dtn_h[:k], non_blocking=True)
             c.set_dt(d_idx, dtn)
+            if self._log is not None:
+                self._log.append((tbs, idx.copy(), new * TICK))
             self.stats["block_steps"] += 1
             self.stats["force_calls"] += 1
             self.stats["interactions"] += k * self.n
@@ -218,13 +228,21 @@ class TSBTS:
         saved_dev = [x.clone() for x in (c.r, c.v, c.a, c.t_last, c.dt)]
         saved_host = [x.copy() for x in (self.t, self.dt, self.dtc)]
         prev = None
+        era_rec = None
+        if self.schedule is not None:
+            era_rec = {"passes": []}
+            self.schedule["eras"].append(era_rec)
         for p in range(self.passes):
             if p > 0:
                 for dst, src in zip((c.r, c.v, c.a, c.t_last, c.dt), saved_dev):
                     dst.copy_(src)
                 for dst, src in zip((self.t, self.dt, self.dtc), saved_host):
                     dst[...] = src
+            if era_rec is not None:
+                self._log = []
+                era_rec["passes"].append(self._log)
             prev = self._pass(p, T1, prev)
+        self._log = None
         self.time = T1
         self.stats["eras"] += 1
         return T1

@@ -13,7 +13,7 @@ from oracle import adjoint as oadj
 from workloads import plummer, gaussian
 from fake_context import FakeContext
 from paper_1205_2288_amd.autograd import (BlockSchedule, tsbts_block_leapfrog,
-                                          tsbts_era_leapfrog)
+                                          tsbts_era_leapfrog, tsbts_schedule_leapfrog)
 
 
 def _dt(n, h, seed, nlev=3):
@@ -102,3 +102,30 @@ def test_era_leapfrog_rejects_bad_eras(era):
     with pytest.raises(ValueError):
         tsbts_era_leapfrog(torch.tensor(r0), torch.tensor(v0), torch.tensor(m),
                            FakeContext(n, 0.1), dt, 16 * h, era, 2)
+
+
+@pytest.mark.parametrize("passes,era", [(1, None), (3, None), (2, 1.0 / 32)])
+def test_recorded_schedule_gradient_matches_oracle(passes, era):
+    # a schedule chosen by the criterion (the oracle's era driver, dynamic or fixed eras),
+    # replayed: end state and gradient against the oracle's replay of the same schedule
+    from oracle.tsbts import OracleTSBTS
+    n, eps = 12, 1.0 / 64
+    r0, v0, m = plummer(n, 45, masses="loguniform")
+    sim = OracleTSBTS(r0, v0, m, eps, passes=passes, dt_max=1.0 / 64, era=era,
+                      record_schedule=True)
+    sim.run(0.125)
+    sched = sim.schedule
+    rt = sim.r + 0.01 * gaussian((3, n), 15)
+    vt = sim.v + 0.01 * gaussian((3, n), 16)
+    L, gr, gv, gm = oadj.schedule_gradient(r0, v0, m, eps, sched, rt, vt)
+    ctx = FakeContext(n, eps)
+    r = torch.tensor(r0, requires_grad=True)
+    v = torch.tensor(v0, requires_grad=True)
+    mm = torch.tensor(m, requires_grad=True)
+    r_end, v_end = tsbts_schedule_leapfrog(r, v, mm, ctx, sched)
+    assert np.array_equal(r_end.detach().numpy(), sim.r)
+    loss = ((r_end - torch.tensor(rt)) ** 2).sum() + ((v_end - torch.tensor(vt)) ** 2).sum()
+    loss.backward()
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-13)
+    for got, ref in ((r.grad, gr), (v.grad, gv), (mm.grad, gm)):
+        assert np.allclose(got.numpy(), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())

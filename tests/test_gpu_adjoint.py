@@ -460,3 +460,90 @@ def test_adjoint8192_era_passes_vs_finite_differences(prec):
                   f"rel {rel:.2e}")
     assert worst <= 1e-5
     ref.close()
+
+
+# ---------------------------------------------------------------- recorded schedules
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_recorded_schedule_gradient_matches_oracle(prec):
+    # a schedule chosen by the criterion in the oracle's era driver (dynamic eras, three
+    # passes), replayed on the GPU: end state and gradient against the oracle's replay
+    from oracle.tsbts import OracleTSBTS
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_schedule_leapfrog
+    n, eps = 100, 1 / 64
+    r0, v0, m = plummer(n, 70, masses="loguniform")
+    sim = OracleTSBTS(r0, v0, m, eps, passes=3, dt_max=1 / 64, record_schedule=True)
+    sim.run(1 / 32)
+    sched = sim.schedule
+    rt = sim.r + 0.01 * gaussian((3, n), 25)
+    vt = sim.v + 0.01 * gaussian((3, n), 26)
+    Lr, rr, rv, rm = oadj.schedule_gradient(r0, v0, m, eps, sched, rt, vt)
+    ctx = Context(n, eps, precision=prec)
+    r, v, mm = _t(r0, True), _t(v0, True), _t(m, True)
+    r_end, v_end = tsbts_schedule_leapfrog(r, v, mm, ctx, sched)
+    fwd_tol = 1e-12 if prec == "fp64" else 1e-6
+    assert np.abs(r_end.detach().cpu().numpy() - sim.r).max() <= fwd_tol
+    loss = ((r_end - _t(rt)) ** 2).sum() + ((v_end - _t(vt)) ** 2).sum()
+    loss.backward()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert float(loss.detach()) == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
+    for got, ref in ((r.grad, rr), (v.grad, rv), (mm.grad, rm)):
+        got = got.cpu().numpy()
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    ctx.close()
+
+
+def test_driver_schedule_replay_and_finite_differences():
+    # the GPU driver records the schedule it chose (N = 2048, three passes, dynamic eras);
+    # replaying it reproduces the run bit for bit, and the replay's gradient matches
+    # central differences of the replayed float64 forward
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.driver import TSBTS
+    from paper_1205_2288_amd.autograd import tsbts_schedule_leapfrog
+    n, eps = 2048, 1 / 256
+    r0, v0, m = plummer(n, 71)
+    drv = TSBTS(r0, v0, m, eps, passes=3, dt_max=1 / 64, precision="fp64",
+                record_schedule=True)
+    drv.run(1 / 64)
+    sched = drv.schedule
+    steps = sum(len(p) for e in sched["eras"] for p in e["passes"])
+    st = drv.state()
+    drv.close()
+    ctx = Context(n, eps, precision="fp64")
+
+    def fwd(rr, vv, mm):
+        with torch.no_grad():
+            return tsbts_schedule_leapfrog(_t(rr), _t(vv), _t(mm), ctx, sched)
+
+    r_e, v_e = fwd(r0, v0, m)
+    assert np.array_equal(r_e.cpu().numpy(), st["r"])
+    assert np.array_equal(v_e.cpu().numpy(), st["v"])
+    rt = st["r"] + 0.01 * gaussian((3, n), 27)
+    vt = st["v"] + 0.01 * gaussian((3, n), 28)
+
+    def loss(rr, vv, mm):
+        a, b = fwd(rr, vv, mm)
+        return float(((a - _t(rt)) ** 2).sum() + ((b - _t(vt)) ** 2).sum())
+
+    r, v, mm = _t(r0, True), _t(v0, True), _t(m, True)
+    a, b = tsbts_schedule_leapfrog(r, v, mm, ctx, sched)
+    ((a - _t(rt)) ** 2).sum().add(((b - _t(vt)) ** 2).sum()).backward()
+    grads = {"r": r.grad.cpu().numpy(), "v": v.grad.cpu().numpy(), "m": mm.grad.cpu().numpy()}
+    step = 1e-6
+    worst = 0.0
+    for which in ("r", "v", "m"):
+        d = gaussian((3, n) if which != "m" else n, 990 + len(which))
+        if which == "m":
+            d = d * m
+        fd = (loss(r0 + step * d if which == "r" else r0, v0 + step * d if which == "v" else v0,
+                   m + step * d if which == "m" else m)
+              - loss(r0 - step * d if which == "r" else r0,
+                     v0 - step * d if which == "v" else v0,
+                     m - step * d if which == "m" else m)) / (2 * step)
+        g = (grads[which] * d).sum()
+        rel = abs(g - fd) / abs(fd)
+        worst = max(worst, rel)
+        print(f"driver schedule ({steps} block steps, {len(sched['eras'])} eras) {which}: "
+              f"adjoint {g:.10e} fd {fd:.10e} rel {rel:.2e}")
+    assert worst <= 1e-5
+    ctx.close()
