@@ -342,11 +342,16 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
 
 /* options of tsbts_sched_option */
 #define TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR 1
+#define TSBTS_SCHED_PREDICT_ON_LOAD 2
 
 /* Scheduler option (host only; applies from the next block step):
  *   TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR: 0 = the paper's order, criterion after the
  *     corrector (default); 1 = criterion with the predicted velocities, in the same pass
  *     over the pairs as the force (tsbts_force_criterion).
+ *   TSBTS_SCHED_PREDICT_ON_LOAD: 1 = for active sets of at most 32 particles (16 in
+ *     float64) the predictor's work is done by the force kernel as it loads its sources
+ *     (one launch less per block step, same results bit for bit); 0 = separate predictor
+ *     (default).  Not combined with the option above.
  * Returns TSBTS_ESTATE before tsbts_sched_init, TSBTS_EINVAL for an unknown option or
  * value. */
 int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);

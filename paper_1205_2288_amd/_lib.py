@@ -164,6 +164,7 @@ TSBTS_TUNE_IPL = 2
 TSBTS_TUNE_CHUNK = 3
 TSBTS_TUNE_SYMMETRIC = 4
 TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR = 1
+TSBTS_SCHED_PREDICT_ON_LOAD = 2
 
 
 def tsbts_tune(ctx, param: int, value: int):

@@ -606,6 +606,38 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
   return TSBTS_OK;
 }
 
+// Prediction and force with the corrector for a small active set, the sources predicted
+// as the force kernel loads them (one launch less than tsbts_predict + force_correct, same
+// results).  Same checks and history bookkeeping as tsbts_predict + force_correct.
+int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                            int use_history, double *acc, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (int s = check_active(c, idx, n_act)) return s;
+  if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
+  if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
+  if (n_act > small_act_limit(c))
+    return fail(c, TSBTS_EINVAL, "prediction on load serves at most %d targets",
+                small_act_limit(c));
+  if (use_history && !c->h.valid)
+    return fail(c, TSBTS_ESTATE, "use_history requested without a finished history");
+  if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
+  if (c->h.recording) {
+    const int64_t need = c->h.count + n_act;
+    if (need >= (int64_t(1) << 31))
+      return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
+    if (int s = grow_log(c, need, stream)) return s;
+  }
+  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  hipError_t e = launch_force_predicted(c, idx, n_act, t_block, use_history ? 1 : 0, acc,
+                                        nullptr, stream, &corr);
+  if (e != hipSuccess) return hip_fail(c, e, "prediction + force + corrector launch");
+  c->pred_t = t_block;
+  c->have_pred = true;
+  if (c->h.recording) c->h.count += n_act;
+  return TSBTS_OK;
+}
+
 // The fused force + criterion with the corrector in its reduction (the native
 // scheduler's block step when the criterion is taken before the corrector).
 int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,

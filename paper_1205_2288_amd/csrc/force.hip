@@ -20,6 +20,7 @@
 // tile and no large self term ever enters a float32 accumulator.
 #include "correct.hpp"
 #include "force_pair.hpp"
+#include "predict.hpp"
 #include "sym.hpp"
 #include <algorithm>
 #include <type_traits>
@@ -251,6 +252,108 @@ __global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
   }
 }
 
+// Source record of a policy built from a particle's predicted position and mass: the
+// values V::load_j reads back from the planes the predictor stores for it.
+template <class V>
+__device__ __forceinline__ typename V::J j_from_state(double x, double y, double z, double m,
+                                                      float ms) {
+  typename V::J r;
+  if constexpr (std::is_same<V, Fp64>::value) {
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.m = m;
+  } else if constexpr (std::is_same<V, MixSep64>::value) {
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.m = static_cast<float>(m) * ms;
+    r.w = static_cast<float>(ff_weight(m));
+  } else {
+    float hx, lx, hy, ly, hz, lz;
+    split_hilo(x, hx, lx);
+    split_hilo(y, hy, ly);
+    split_hilo(z, hz, lz);
+    r.a = make_float4(hx, hy, hz, static_cast<float>(m) * ms);
+    r.b = make_float4(lx, ly, lz, static_cast<float>(ff_weight(m)));
+  }
+  return r;
+}
+
+template <class V>
+__device__ __forceinline__ typename V::I i_from_state(double x, double y, double z) {
+  typename V::I r;
+  if constexpr (std::is_same<V, MixHiLo>::value) {
+    split_hilo(x, r.xh, r.xl);
+    split_hilo(y, r.yh, r.yl);
+    split_hilo(z, r.zh, r.zl);
+  } else {
+    r.x = x;
+    r.y = y;
+    r.z = z;
+  }
+  return r;
+}
+
+// k_force_small with the prediction of its sources on load (the predictor's work folded
+// into the force pass for small active sets): the thread that owns source j predicts it
+// to the block time, stores its predicted planes (for the corrector and the criterion)
+// and sums with the values in registers; each workgroup predicts the targets itself
+// (active particles: their Taylor polynomial).  Same arithmetic as the predictor followed
+// by k_force_small, so the results are the same bit for bit.
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictArgs Pr) {
+  using F = typename V::F;
+  __shared__ typename V::I si[kSmallAct];
+  __shared__ int sg[kSmallAct];
+  __shared__ F red[kSmallAct][4][kWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tile = blockIdx.x;
+  const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
+  const float ms = Scale<V, NEWTON>::kMass;
+  typename V::J J;
+  if (j < Pr.n) {
+    double st[6];
+    predict_state(Pr, j, true, st);
+    const double m = Pr.m[j];
+    store_particle(Pr.o, j, st[0], st[1], st[2], st[3], st[4], st[5], m);
+    J = j_from_state<V>(st[0], st[1], st[2], m, ms);
+  } else {
+    store_pad(Pr.o, j);
+    J = j_from_state<V>(kFar, kFar, kFar, 0.0, ms);
+  }
+  if (tid < A.n_act) {
+    sg[tid] = A.idx[tid];
+    double st[6];
+    predict_state(Pr, sg[tid], false, st);
+    si[tid] = i_from_state<V>(st[0], st[1], st[2]);
+  }
+  __syncthreads();
+  for (int q = 0; q < A.n_act; ++q) {
+    F ax = F(0), ay = F(0), az = F(0), pp = F(0);
+    pair_acc<V, NEWTON, 1, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
+    ax = wave_sum_t(ax);
+    ay = wave_sum_t(ay);
+    az = wave_sum_t(az);
+    pp = wave_sum_t(pp);
+    if (lane == 0) {
+      red[q][0][w] = ax;
+      red[q][1][w] = ay;
+      red[q][2][w] = az;
+      red[q][3][w] = pp;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < 4 * A.n_act; t += kWG) {
+    const int q = t >> 2, c = t & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kWG / 64; ++ww) s += static_cast<double>(red[q][c][ww]);
+    A.part[(static_cast<int64_t>(tile) * 4 + c) * A.n_act + q] = s;
+  }
+}
+
 // Add the slices' partials in slice order and finish (scale, sign).
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_force_reduce(ForceArgs A) {
@@ -339,12 +442,16 @@ hipError_t run(ForceArgs &A, hipStream_t st) {
 }
 
 template <class V, int NEWTON>
-hipError_t run_small(ForceArgs &A, hipStream_t st) {
+hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nullptr) {
   A.plan.n_itiles = 1;
   A.plan.n_slices = A.n_jtiles;
   A.plan.tiles_per_slice = 1;
   A.plan.nblk = A.n_jtiles;
-  hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
+  if (pred)
+    hipLaunchKernelGGL((k_force_small_pred<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A,
+                       *pred);
+  else
+    hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
   if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
@@ -429,6 +536,40 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (sep64) return newton ? pick_ipl<MixSep64, 1>(A, st) : pick_ipl<MixSep64, 0>(A, st);
   return newton ? pick_ipl<MixHiLo, 1>(A, st) : pick_ipl<MixHiLo, 0>(A, st);
+}
+
+int small_act_limit(const tsbts_ctx *c) {
+  return c->precision == TSBTS_FP64 ? kSmallActFp64 : kSmallAct;
+}
+
+hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                                  int use_history, double *acc, double *pot, hipStream_t st,
+                                  const CorrectArgs *corr) {
+  ForceArgs A;
+  A.correct = corr ? 1 : 0;
+  if (corr) A.corr = *corr;
+  A.p32 = c->p32;
+  A.p64 = c->p64;
+  A.npad = c->npad;
+  A.idx = idx;
+  A.n_act = n_act;
+  A.n_jtiles = static_cast<int>(c->npad / kTJ);
+  A.eps2f = static_cast<float>(c->eps * c->eps);
+  A.eps2 = c->eps * c->eps;
+  A.part = c->part;
+  A.acc = acc;
+  A.pot = pot;
+  A.blocks = c->tune_blocks;
+  A.ipl = 1;
+  A.scalar_j = 0;
+  A.chunk = kTJ;
+  const PredictArgs P = predict_args(c, t_block, use_history);
+  if (c->precision == TSBTS_FP64) return run_small<Fp64, 0>(A, st, &P);
+  const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
+  const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
+  if (sep64)
+    return newton ? run_small<MixSep64, 1>(A, st, &P) : run_small<MixSep64, 0>(A, st, &P);
+  return newton ? run_small<MixHiLo, 1>(A, st, &P) : run_small<MixHiLo, 0>(A, st, &P);
 }
 
 }  // namespace tsbts

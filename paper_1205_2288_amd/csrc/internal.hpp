@@ -220,6 +220,8 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
                             double eta, double *acc, double *dtc, hipStream_t stream);
 // Force on the active set and its corrector in the same launches (checked like the two
 // entry points; returns a status code).
+int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                            int use_history, double *acc, hipStream_t stream);
 int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
                   double *acc, hipStream_t stream);
 // With corr, every target's corrector (correct_one) runs where its force is final.
@@ -246,6 +248,13 @@ hipError_t launch_fill(double *x, int64_t len, double v, hipStream_t st);
 hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int n_act,
                                 double t_block, double *rbar, double *vbar, double *abar,
                                 double *pbar, double *seeds, hipStream_t st);
+// Largest active set of the j-parallel small-set kernels.
+int small_act_limit(const tsbts_ctx *c);
+// Predictor and force (with the corrector, if corr) in the small-set kernels, the sources
+// predicted as they are loaded (n_act <= small_act_limit).
+hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
+                                  int use_history, double *acc, double *pot, hipStream_t st,
+                                  const CorrectArgs *corr);
 // Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.
 struct SymPlan;
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,

@@ -144,6 +144,7 @@ struct Scheduler {
   std::vector<double> s0_dtc;
   int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
   int crit_before = 0;  // criterion with the predicted velocities, fused with the force
+  int pred_on_load = 0;  // small active sets: prediction folded into the force kernel
 
   void rebuild_levels() {
     for (auto &m : mem) m.clear();
@@ -233,11 +234,16 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     }
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
     SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
-    SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
-    if (S.crit_before) {
+    if (S.pred_on_load && !S.crit_before && k <= tsbts::small_act_limit(c)) {
+      SCHED_CALL(tsbts::force_correct_predicted(c, S.idx_d, k, tbs, p > 0 ? 1 : 0, S.acc_d,
+                                                st));
+      SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
+    } else if (S.crit_before) {
+      SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
       SCHED_CALL(tsbts::force_criterion_correct(c, S.idx_d, k, tbs, S.eta, S.acc_d, S.dtc_hd,
                                                 st));
     } else {
+      SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
       SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st));
       SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     }
@@ -413,10 +419,14 @@ int tsbts_sched_option(tsbts_ctx *c, int option, int value) {
   if (!c) return TSBTS_EINVAL;
   Scheduler *S = static_cast<Scheduler *>(c->sched);
   if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_option: call tsbts_sched_init first");
-  if (option != TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR)
+  if (option != TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR &&
+      option != TSBTS_SCHED_PREDICT_ON_LOAD)
     return sfail(c, TSBTS_EINVAL, "tsbts_sched_option: unknown option");
   if (value != 0 && value != 1) return sfail(c, TSBTS_EINVAL, "option value must be 0 or 1");
-  S->crit_before = value;
+  if (option == TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR)
+    S->crit_before = value;
+  else
+    S->pred_on_load = value;
   return TSBTS_OK;
 }
 

@@ -286,10 +286,12 @@ class NativeTSBTS:
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
                  era=None, precision="mixed", separation="f64", newton=False,
-                 criterion="after", tune=None):
+                 criterion="after", tune=None, predict_on_load=False):
         """criterion: "after" the corrector (the paper's order) or "before" it, with the
         predicted velocities, in the same pass over the pairs as the force.  tune: keyword
-        arguments of Context.tune, applied before the first force evaluation."""
+        arguments of Context.tune, applied before the first force evaluation.
+        predict_on_load: small active sets predict their sources inside the force kernel
+        (one launch less per block step, same results)."""
         from . import _lib as L
         if criterion not in ("after", "before"):
             raise ValueError("criterion must be 'after' or 'before'")
@@ -304,6 +306,8 @@ class NativeTSBTS:
                            0.0 if era is None else era)
         if criterion == "before":
             L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR, 1)
+        if predict_on_load:
+            L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_PREDICT_ON_LOAD, 1)
         self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
         self._host()
         self.wall_s = 0.0

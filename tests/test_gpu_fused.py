@@ -114,3 +114,31 @@ def test_native_run_criterion_before_corrector(prec, name):
     assert d <= 2.0 * g["max_rel_energy_error"]
     assert 0.9 <= steps / g["stats"]["block_steps"] <= 1.1
     sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["plummer256", "plummer4096_t1"])
+def test_native_run_predict_on_load(prec, name):
+    # small active sets predicting their sources inside the force kernel: the same run,
+    # bit for bit, with one launch less per small block step
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    with open(os.path.join(GOLDEN, f"tsbts_{name}.json")) as f:
+        g = json.load(f)
+    cfg = config(g["workload"])
+    r, v, m = cfg.ic()
+    out = {}
+    for pol in (False, True):
+        sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=g["passes"], era=cfg.era,
+                          dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=prec,
+                          predict_on_load=pol)
+        series = sim.run(g["t_end"])
+        out[pol] = (sim.stats["block_steps"], sim.stats["wall_s"], series,
+                    sim.ctx.r.cpu().numpy().copy(), sim.ctx.v.cpu().numpy().copy())
+        sim.close()
+    print(f"{name} {prec}: {out[False][0]} block steps; separate predictor "
+          f"{out[False][1] / out[False][0] * 1e6:.1f} us/step, predicted on load "
+          f"{out[True][1] / out[True][0] * 1e6:.1f} us/step")
+    assert out[True][0] == out[False][0]
+    assert out[True][2] == out[False][2]
+    assert np.array_equal(out[True][3], out[False][3])
+    assert np.array_equal(out[True][4], out[False][4])
