@@ -176,7 +176,8 @@ def test_tune_rejects_bad_values():
     from paper_1205_2288_amd._lib import TsbtsError, TSBTS_EINVAL
     ctx = make_ctx(100, 0.01, "mixed")
     for kw in ({"blocks": 63}, {"blocks": 65537}, {"ipl": 3}, {"ipl": -1}, {"ipl": 8},
-               {"chunk": 32}, {"chunk": 128}, {"chunk": -64}):
+               {"chunk": 32}, {"chunk": 128}, {"chunk": -64}, {"symmetric": 3},
+               {"symmetric": -1}):
         with pytest.raises(TsbtsError) as e:
             ctx.tune(**kw)
         assert e.value.status == TSBTS_EINVAL
