@@ -13,7 +13,12 @@
 namespace tsbts {
 namespace {
 
-constexpr int kFBlock = 8;  // columns per LDS transposition (4 values each)
+// columns per LDS transposition and values per column: with the potential 8 columns of
+// (x, y, z, potential), without it 16 columns of (x, y, z) (same LDS footprint per wave)
+template <int POT> struct FCols {
+  static constexpr int kBlock = POT ? 8 : 16;
+  static constexpr int kNV = POT ? 4 : 3;
+};
 
 struct ForceSymArgs {
   int64_t n, npad;
@@ -63,8 +68,9 @@ __device__ __forceinline__ void force_block(const ForceSymArgs &A,
                                             const float (&mr)[kSymRows],
                                             const int (&k)[kSymRows], int64_t jb,
                                             float (&a)[kSymRows][4], float *L, int lane) {
+  constexpr int NV = FCols<POT>::kNV;
 #pragma unroll 8
-  for (int c = 0; c < kFBlock; ++c) {
+  for (int c = 0; c < FCols<POT>::kBlock; ++c) {
     const int64_t j = jb + c;
     const typename V::J Jr = V::load_j(A.p32, A.p64, A.npad, j, 1.0f);
     float cx = 0.0f, cy = 0.0f, cz = 0.0f, cp = 0.0f;
@@ -74,11 +80,11 @@ __device__ __forceinline__ void force_block(const ForceSymArgs &A,
       pair_acc_sym<V, POT>(rows[r], mr[r], Jr, A.eps2, skip, a[r][0], a[r][1], a[r][2],
                            a[r][3], cx, cy, cz, cp);
     }
-    float *e = L + (c * kSymLdsStride + lane) * 4;
+    float *e = L + (c * kSymLdsStride + lane) * NV;
     e[0] = cx;
     e[1] = cy;
     e[2] = cz;
-    e[3] = cp;
+    if (POT) e[NV - 1] = cp;
   }
 }
 
@@ -88,7 +94,8 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
                                                    const double *__restrict__ p64,
                                                    float *__restrict__ col_part,
                                                    double *__restrict__ row_part) {
-  __shared__ float lds[kWG / 64][kFBlock * kSymLdsStride * 4];
+  constexpr int BLK = FCols<POT>::kBlock, NV = FCols<POT>::kNV;
+  __shared__ float lds[kWG / 64][BLK * kSymLdsStride * NV];
   ForceSymArgs A = A0;
   A.p32 = p32;
   A.p64 = p64;
@@ -120,17 +127,18 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
     for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
       for (int v = 0; v < 4; ++v) a[r][v] = 0.0f;
-    for (int64_t jb = jt; jb < jt + 64; jb += kFBlock) {
-      if (rows_pad || jb < row0 + kSymWaveRows || jb + kFBlock > A.n)
+    for (int64_t jb = jt; jb < jt + 64; jb += BLK) {
+      if (rows_pad || jb < row0 + kSymWaveRows || jb + BLK > A.n)
         force_block<V, POT, 1>(A, rows, mr, k, jb, a, L, lane);
       else
         force_block<V, POT, 0>(A, rows, mr, k, jb, a, L, lane);
       wave_lds_sync();
-      float cs[4];
-      sym_col_sums<kFBlock, 4>(L, lane, cs);
-      if (lane < kFBlock) {
+      float cs[NV];
+      sym_col_sums<BLK, NV>(L, lane, cs);
+      if (lane < BLK) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) cpart[v * A.npad + jb + lane] = cs[v];
+        for (int v = 0; v < 3; ++v) cpart[v * A.npad + jb + lane] = cs[v];
+        cpart[3 * A.npad + jb + lane] = POT ? cs[NV - 1] : 0.0f;
       }
       wave_lds_sync();
     }
