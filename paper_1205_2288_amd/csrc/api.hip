@@ -78,7 +78,7 @@ int check_bound(tsbts_ctx *c) {
 // Work list and partials of the symmetric all-targets force, when it serves the call.
 int prepare_force_sym(tsbts_ctx *c, int32_t n_act) {
   if (!force_sym_applies(c, n_act)) return TSBTS_OK;
-  if (int s = sym_prepare(c, 4, 8, 4))
+  if (int s = sym_prepare(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4))
     return fail(c, s, "symmetric force: work list or partials not allocated");
   return TSBTS_OK;
 }
@@ -406,7 +406,7 @@ int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, 
   if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
   if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
-  if (sym_enabled(c, n_act)) {
+  if (criterion_sym_applies(c, n_act)) {
     const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
     if (int s = sym_prepare(c, 2, vb, vb))
       return fail(c, s, "symmetric criterion: work list or partials not allocated");

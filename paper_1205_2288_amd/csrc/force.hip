@@ -510,7 +510,7 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
                         double *pot, hipStream_t st, const CorrectArgs *corr) {
   if (force_sym_applies(c, n_act)) {
     SymPlan plan;
-    if (sym_plan(c, 4, 8, 4, &plan))
+    if (sym_plan(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
       return launch_force_sym(c, plan, idx, n_act, acc, pot, st, corr);
   }
   ForceArgs A;

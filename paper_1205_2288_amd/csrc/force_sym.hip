@@ -25,6 +25,7 @@ struct ForceSymArgs {
   const float *p32;
   const double *p64;
   float eps2;
+  double eps2_64;
   SymPlan plan;
   const int32_t *idx;
   int n_act;
@@ -62,25 +63,59 @@ __device__ __forceinline__ void pair_acc_sym(const typename V::I &i, float mi,
   }
 }
 
+template <class V, int POT>
+__device__ __forceinline__ void pair_acc_sym(const typename V::I &i, double mi,
+                                             const typename V::J &j, double eps2, bool skip,
+                                             double &ax, double &ay, double &az, double &pp,
+                                             double &cx, double &cy, double &cz,
+                                             double &cp) {
+  double dx, dy, dz;
+  V::sep(i, j, dx, dy, dz);
+  const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  double y = rsqrt_f64<2>(s);
+  if (skip) y = 0.0;
+  const double y3 = y * (y * y);
+  const double mj = V::mass(j);
+  const double mj3 = mj * y3;
+  const double mi3 = mi * y3;
+  ax = fma(mj3, dx, ax);
+  ay = fma(mj3, dy, ay);
+  az = fma(mj3, dz, az);
+  cx = fma(-mi3, dx, cx);
+  cy = fma(-mi3, dy, cy);
+  cz = fma(-mi3, dz, cz);
+  if (POT) {
+    pp = fma(mj, y, pp);
+    cp = fma(mi, y, cp);
+  }
+}
+
 template <class V, int POT, int MASK>
 __device__ __forceinline__ void force_block(const ForceSymArgs &A,
                                             const typename V::I (&rows)[kSymRows],
-                                            const float (&mr)[kSymRows],
+                                            const typename V::F (&mr)[kSymRows],
                                             const int (&k)[kSymRows], int64_t jb,
-                                            float (&a)[kSymRows][4], float *L, int lane) {
+                                            typename V::F (&a)[kSymRows][4],
+                                            typename V::F *L, int lane) {
+  using F = typename V::F;
   constexpr int NV = FCols<POT>::kNV;
-#pragma unroll 8
-  for (int c = 0; c < FCols<POT>::kBlock; ++c) {
+  // columns per transposition (float64: half, same LDS bytes); the float64 column records
+  // of an 8-column batch would not fit the scalar registers, so those batch by 4
+  constexpr int BLK = sizeof(F) == 4 ? FCols<POT>::kBlock : FCols<POT>::kBlock / 2;
+  constexpr int UNR = sizeof(F) == 4 ? 8 : 4;
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2) : static_cast<F>(A.eps2_64);
+#pragma unroll UNR
+  for (int c = 0; c < BLK; ++c) {
     const int64_t j = jb + c;
     const typename V::J Jr = V::load_j(A.p32, A.p64, A.npad, j, 1.0f);
-    float cx = 0.0f, cy = 0.0f, cz = 0.0f, cp = 0.0f;
+    F cx = F(0), cy = F(0), cz = F(0), cp = F(0);
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
       const bool skip = MASK && (j <= k[r] || j >= A.n || k[r] >= A.n);
-      pair_acc_sym<V, POT>(rows[r], mr[r], Jr, A.eps2, skip, a[r][0], a[r][1], a[r][2],
+      pair_acc_sym<V, POT>(rows[r], mr[r], Jr, eps2, skip, a[r][0], a[r][1], a[r][2],
                            a[r][3], cx, cy, cz, cp);
     }
-    float *e = L + (c * kSymLdsStride + lane) * NV;
+    F *e = L + (c * kSymLdsStride + lane) * NV;
     e[0] = cx;
     e[1] = cy;
     e[2] = cz;
@@ -92,10 +127,13 @@ template <class V, int POT>
 __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
                                                    const float *__restrict__ p32,
                                                    const double *__restrict__ p64,
-                                                   float *__restrict__ col_part,
+                                                   typename V::F *__restrict__ col_part,
                                                    double *__restrict__ row_part) {
-  constexpr int BLK = FCols<POT>::kBlock, NV = FCols<POT>::kNV;
-  __shared__ float lds[kWG / 64][BLK * kSymLdsStride * NV];
+  using F = typename V::F;
+  // float64: half the columns per transposition (same LDS bytes)
+  constexpr int BLK = sizeof(F) == 4 ? FCols<POT>::kBlock : FCols<POT>::kBlock / 2;
+  constexpr int NV = FCols<POT>::kNV;
+  __shared__ F lds[kWG / 64][BLK * kSymLdsStride * NV];
   ForceSymArgs A = A0;
   A.p32 = p32;
   A.p64 = p64;
@@ -106,7 +144,7 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
   const int4 it = A.plan.items[item];
   const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
   typename V::I rows[kSymRows];
-  float mr[kSymRows];
+  F mr[kSymRows];
   int k[kSymRows];
   double tot[kSymRows][4];
 #pragma unroll
@@ -114,31 +152,34 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
     k[r] = static_cast<int>(row0) + r * 64 + lane;
     const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
     rows[r] = V::load_i(A.p32, A.p64, A.npad, kk);
-    mr[r] = A.p32[P32_M * A.npad + kk];
+    if constexpr (sizeof(F) == 4)
+      mr[r] = A.p32[P32_M * A.npad + kk];
+    else
+      mr[r] = A.p64[P64_M * A.npad + kk];
 #pragma unroll
     for (int v = 0; v < 4; ++v) tot[r][v] = 0.0;
   }
-  float *L = lds[wv];
-  float *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
+  F *L = lds[wv];
+  F *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
   const bool rows_pad = row0 + kSymWaveRows > A.n;
   for (int64_t jt = it.y; jt < it.z; jt += 64) {
-    float a[kSymRows][4];
+    F a[kSymRows][4];
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a[r][v] = 0.0f;
+      for (int v = 0; v < 4; ++v) a[r][v] = F(0);
     for (int64_t jb = jt; jb < jt + 64; jb += BLK) {
       if (rows_pad || jb < row0 + kSymWaveRows || jb + BLK > A.n)
         force_block<V, POT, 1>(A, rows, mr, k, jb, a, L, lane);
       else
         force_block<V, POT, 0>(A, rows, mr, k, jb, a, L, lane);
       wave_lds_sync();
-      float cs[NV];
+      F cs[NV];
       sym_col_sums<BLK, NV>(L, lane, cs);
       if (lane < BLK) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) cpart[v * A.npad + jb + lane] = cs[v];
-        cpart[3 * A.npad + jb + lane] = POT ? cs[NV - 1] : 0.0f;
+        cpart[3 * A.npad + jb + lane] = POT ? cs[NV - 1] : F(0);
       }
       wave_lds_sync();
     }
@@ -156,6 +197,7 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
 
 // Particle p (target q = inv[p]): the row partials of its row tile in slot order, then
 // the column partials of the row tiles 0 .. its own; then acc, pot and the corrector.
+template <class F>
 __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
@@ -168,7 +210,7 @@ __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
   for (int s = 0; s < slots; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
-  const float *cp = static_cast<const float *>(A.plan.col_part);
+  const F *cp = static_cast<const F *>(A.plan.col_part);
   for (int u = 0; u <= R; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
@@ -182,8 +224,9 @@ __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
 
 template <class V>
 hipError_t run(ForceSymArgs &A, hipStream_t st) {
+  using F = typename V::F;
   const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
-  float *cp = static_cast<float *>(A.plan.col_part);
+  F *cp = static_cast<F *>(A.plan.col_part);
   double *rp = static_cast<double *>(A.plan.row_part);
   if (A.pot)
     hipLaunchKernelGGL((k_force_sym<V, 1>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, cp,
@@ -192,16 +235,15 @@ hipError_t run(ForceSymArgs &A, hipStream_t st) {
     hipLaunchKernelGGL((k_force_sym<V, 0>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, cp,
                        rp);
   launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
-  hipLaunchKernelGGL(k_force_sym_reduce, dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
-                     dim3(kWG), 0, st, A);
+  hipLaunchKernelGGL(k_force_sym_reduce<F>,
+                     dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)), dim3(kWG), 0, st, A);
   return hipGetLastError();
 }
 
 }  // namespace
 
 bool force_sym_applies(const tsbts_ctx *c, int64_t n_act) {
-  return sym_enabled(c, n_act) && c->precision != TSBTS_FP64 &&
-         (c->flags & TSBTS_FLAG_NEWTON) == 0;
+  return sym_enabled(c, n_act) && (c->flags & TSBTS_FLAG_NEWTON) == 0;
 }
 
 hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
@@ -213,6 +255,7 @@ hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *id
   A.p32 = c->p32;
   A.p64 = c->p64;
   A.eps2 = static_cast<float>(c->eps * c->eps);
+  A.eps2_64 = c->eps * c->eps;
   A.plan = plan;
   A.idx = idx;
   A.n_act = n_act;
@@ -220,6 +263,7 @@ hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *id
   A.pot = pot;
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;
+  if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);
 }

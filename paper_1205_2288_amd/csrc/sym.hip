@@ -42,9 +42,12 @@ bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
   if (n_act != c->n) return false;
   if (c->tune_sym == 0) return false;
   if (c->tune_sym == 1) return true;
-  // automatic: mixed precision only (the float64 records do not fit the scalar registers
-  // of a column batch, and the symmetric float64 criterion measured slower)
-  return c->n >= kSymMinN && c->precision != TSBTS_FP64;
+  return c->n >= kSymMinN;
+}
+
+bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act) {
+  if (!sym_enabled(c, n_act)) return false;
+  return c->tune_sym == 1 || c->precision != TSBTS_FP64;
 }
 
 int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {

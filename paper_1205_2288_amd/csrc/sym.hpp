@@ -62,15 +62,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Column sums of one transposition block: L holds, for each of the BLK columns c, the
 // NV values of every lane at (c * kSymLdsStride + lane) * NV.  Lane l adds the BLK
 // entries of column l % BLK in part l / BLK, then the parts are added across lanes; lanes
-// l < BLK return column l's sums (float, in this fixed order).
-template <int BLK, int NV>
-__device__ __forceinline__ void sym_col_sums(const float *L, int lane, float out[NV]) {
+// l < BLK return column l's sums (in this fixed order).
+template <int BLK, int NV, class T>
+__device__ __forceinline__ void sym_col_sums(const T *L, int lane, T out[NV]) {
   const int c = lane % BLK, part = lane / BLK;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v] = 0.0f;
+  for (int v = 0; v < NV; ++v) out[v] = T(0);
 #pragma unroll
   for (int i = 0; i < BLK; ++i) {
-    const float *e = L + (c * kSymLdsStride + part * BLK + i) * NV;
+    const T *e = L + (c * kSymLdsStride + part * BLK + i) * NV;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] += e[v];
   }
@@ -81,6 +81,10 @@ __device__ __forceinline__ void sym_col_sums(const float *L, int lane, float out
   }
 }
 
+// Whether the symmetric criterion serves the call: as sym_enabled, but automatically in
+// mixed precision only (the float64 column records of a batch do not fit the scalar
+// registers, and the symmetric float64 criterion measured slower).
+bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act);
 // Whether the symmetric kernels serve a call with n_act targets (all particles).
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act);
 // Items and partial buffers for NV values per particle, row partials of row_bytes and

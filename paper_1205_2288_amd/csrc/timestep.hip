@@ -286,7 +286,7 @@ hipError_t run(StepArgs &A, hipStream_t st) {
 
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st) {
-  if (sym_enabled(c, n_act)) {
+  if (criterion_sym_applies(c, n_act)) {
     SymPlan plan;
     const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
     if (sym_plan(c, 2, vb, vb, &plan))

@@ -123,12 +123,12 @@ def test_plummer131k_symmetric_criterion(prec):
 from gpu_util import rel_err_vec  # noqa: E402
 
 
-@pytest.mark.parametrize("sep", ["f64", "hilo"])
+@pytest.mark.parametrize("prec,sep", CASES)
 @pytest.mark.parametrize("n", [3, 300, 700, 1100, 5000])
-def test_symmetric_force_matches_gather_and_oracle(sep, n):
+def test_symmetric_force_matches_gather_and_oracle(prec, sep, n):
     eps = 1 / 256
     r, v, m = _state(n, 3400 + n)
-    ctx = make_ctx(n, eps, "mixed", sep)
+    ctx = make_ctx(n, eps, prec, sep)
     ctx.bind(r, v, m)
     ctx.predict(0.0)
     idx = _perm(n, n + 1)
@@ -140,10 +140,15 @@ def test_symmetric_force_matches_gather_and_oracle(sep, n):
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)   # fixed order
     ra, rp = oracle.force(r, m, eps, idx)
     e = rel_err_vec(a1, ra)
-    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
-    assert rel_err(p1, rp).max() <= 1e-5
-    # same sums as the gather kernel up to float32 rounding of the partial sums
-    assert np.median(rel_err_vec(a1, a0)) <= 1e-6
+    if prec == "fp64":
+        assert e.max() <= 1e-12, summary(e)
+        assert rel_err(p1, rp).max() <= 1e-12
+        assert rel_err_vec(a1, a0).max() <= 1e-12
+    else:
+        assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
+        assert rel_err(p1, rp).max() <= 1e-5
+        # same sums as the gather kernel up to float32 rounding of the partial sums
+        assert np.median(rel_err_vec(a1, a0)) <= 1e-6
     ctx.close()
 
 
@@ -172,11 +177,12 @@ def test_symmetric_kernels_in_native_runs():
     assert np.abs(runs[0][2] - runs[1][2]).max() <= 1e-5
 
 
-def test_plummer131k_symmetric_force():
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_plummer131k_symmetric_force(prec):
     cfg = config("plummer131k")
     n, eps = cfg.n, cfg.eps
     r, v, m = cfg.ic()
-    ctx = make_ctx(n, eps, "mixed")
+    ctx = make_ctx(n, eps, prec)
     ctx.bind(r, v, m)
     ctx.predict(0.0)
     idx = _perm(n, 9)
@@ -192,14 +198,17 @@ def test_plummer131k_symmetric_force():
         torch.cuda.synchronize()
         ms[sym] = (time.perf_counter() - t0) / 3 * 1e3
         out[sym] = acc.cpu().numpy().copy()
-    print(f"plummer131k mixed force, all targets: gather {ms[0]:.2f} ms, "
+    print(f"plummer131k {prec} force, all targets: gather {ms[0]:.2f} ms, "
           f"symmetric {ms[1]:.2f} ms")
     order = np.argsort(idx)
     sample = np.arange(0, n, n // 256)
     ra, _ = oracle.force(r, m, eps, sample.astype(np.int32))
     e = rel_err_vec(out[1][:, order][:, sample], ra)
-    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
-    assert np.median(rel_err_vec(out[1], out[0])) <= 1e-6
+    if prec == "fp64":
+        assert e.max() <= 1e-12, summary(e)
+    else:
+        assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
+        assert np.median(rel_err_vec(out[1], out[0])) <= 1e-6
     ctx.close()
 
 
