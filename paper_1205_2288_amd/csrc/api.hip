@@ -371,7 +371,7 @@ int tsbts_force_backward(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, backward_partials_needed(c, n_act))) return s;
   if (bwd_sym_applies(c, n_act)) {
-    if (int s = sym_prepare(c, 4, 8, 4))
+    if (int s = sym_prepare(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4))
       return fail(c, s, "symmetric adjoint: work list or partials not allocated");
   }
   hipError_t e = launch_backward(c, idx, n_act, ga, gp, gr, gm, stream);

@@ -541,7 +541,8 @@ hipError_t run(BwdArgs &A, hipStream_t st, tsbts_ctx *c) {
                        dim3(kWG), 0, st, A);
     if (bwd_sym_applies(c, A.n_act)) {
       SymPlan plan;
-      if (sym_plan(c, 4, 8, 4, &plan)) return launch_bwd_sym(c, plan, A.gr, A.gm, st);
+      if (sym_plan(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
+        return launch_bwd_sym(c, plan, A.gr, A.gm, st);
     }
     A.plan = plan_all(A);
     A.n_ctiles = static_cast<int>(A.npad / kTJ);

@@ -6,17 +6,16 @@
 //   dL/dr_k += t,   dL/dr_j -= t,
 //   t = y^3 (m_k g_j - m_j g_k) - y^3 [3 y^2 (m_k u_j - m_j u_k) + m_k gp_j + m_j gp_k] e,
 //   dL/dm_k += -y (y^2 u_j + gp_j),   dL/dm_j += y (y^2 u_k - gp_k)
-// (the position part is antisymmetric in the pair).  Mixed precision without the Newton
-// step: float32 pair arithmetic on the float64 (or hi/lo) separation, float32 sums over a
-// column tile of 64 (rows) or over a work item's rows (columns), float64 across them,
-// combined in a fixed order and added to grad_r, grad_m.
+// (the position part is antisymmetric in the pair).  Mixed precision (without the Newton
+// step): float32 pair arithmetic on the float64 (or hi/lo) separation, float32 sums over a
+// column tile of 64 (rows) or over a work item's rows (columns), float64 across them;
+// float64 mode: everything in float64.  Combined in a fixed order and added to grad_r,
+// grad_m.
 #include "sym.hpp"
 #include "pair.hpp"
 
 namespace tsbts {
 namespace {
-
-constexpr int kBBlock = 8;  // columns per LDS transposition (4 values each)
 
 struct BwdSymArgs {
   int64_t n, npad;
@@ -24,6 +23,7 @@ struct BwdSymArgs {
   const double *p64;
   const double *gord;  // [4][npad] seeds in particle order (zero for padding)
   float eps2;
+  double eps2_64;
   SymPlan plan;
   double *gr, *gm;
 };
@@ -35,55 +35,69 @@ __global__ __launch_bounds__(kWG) void k_bwd_seeds32(int64_t len, const double *
 }
 
 template <class V>
-__device__ __forceinline__ void pair_bwd_sym(const typename V::I &i, float mi,
-                                             const float (&gi)[4], const typename V::J &j,
-                                             const float (&gj)[4], float eps2, bool skip,
-                                             float (&acc)[4], float (&cacc)[4]) {
-  float ex, ey, ez;
+__device__ __forceinline__ void pair_bwd_sym(const typename V::I &i, typename V::F mi,
+                                             const typename V::F (&gi)[4],
+                                             const typename V::J &j,
+                                             const typename V::F (&gj)[4],
+                                             typename V::F eps2, bool skip,
+                                             typename V::F (&acc)[4],
+                                             typename V::F (&cacc)[4]) {
+  using F = typename V::F;
+  F ex, ey, ez;
   V::sep(i, j, ex, ey, ez);
-  const float s = fmaf(ex, ex, fmaf(ey, ey, fmaf(ez, ez, eps2)));
-  float y = rsq_f32(s);
-  if (skip) y = 0.0f;
-  const float y2 = y * y;
-  const float y3 = y2 * y;
-  const float mj = V::mass(j);
-  const float uj = fmaf(ex, gj[0], fmaf(ey, gj[1], ez * gj[2]));
-  const float ui = fmaf(ex, gi[0], fmaf(ey, gi[1], ez * gi[2]));
-  const float a = fmaf(mi, uj, -(mj * ui));
-  const float gs = fmaf(mi, gj[3], mj * gi[3]);
-  const float c = y3 * fmaf(-3.0f * y2, a, -gs);
-  const float tx = fmaf(y3, fmaf(mi, gj[0], -(mj * gi[0])), c * ex);
-  const float ty = fmaf(y3, fmaf(mi, gj[1], -(mj * gi[1])), c * ey);
-  const float tz = fmaf(y3, fmaf(mi, gj[2], -(mj * gi[2])), c * ez);
+  const F s = fma(ex, ex, fma(ey, ey, fma(ez, ez, eps2)));
+  F y;
+  if constexpr (sizeof(F) == 4)
+    y = rsq_f32(s);
+  else
+    y = rsqrt_f64<2>(s);
+  if (skip) y = F(0);
+  const F y2 = y * y;
+  const F y3 = y2 * y;
+  const F mj = V::mass(j);
+  const F uj = fma(ex, gj[0], fma(ey, gj[1], ez * gj[2]));
+  const F ui = fma(ex, gi[0], fma(ey, gi[1], ez * gi[2]));
+  const F a = fma(mi, uj, -(mj * ui));
+  const F gs = fma(mi, gj[3], mj * gi[3]);
+  const F c = y3 * fma(F(-3) * y2, a, -gs);
+  const F tx = fma(y3, fma(mi, gj[0], -(mj * gi[0])), c * ex);
+  const F ty = fma(y3, fma(mi, gj[1], -(mj * gi[1])), c * ey);
+  const F tz = fma(y3, fma(mi, gj[2], -(mj * gi[2])), c * ez);
   acc[0] += tx;
   acc[1] += ty;
   acc[2] += tz;
   cacc[0] -= tx;
   cacc[1] -= ty;
   cacc[2] -= tz;
-  acc[3] = fmaf(-y, fmaf(y2, uj, gj[3]), acc[3]);
-  cacc[3] = fmaf(y, fmaf(y2, ui, -gi[3]), cacc[3]);
+  acc[3] = fma(-y, fma(y2, uj, gj[3]), acc[3]);
+  cacc[3] = fma(y, fma(y2, ui, -gi[3]), cacc[3]);
 }
 
+// columns per LDS transposition: 8 of float32, 4 of float64 (same LDS bytes)
+template <class F> struct BCols { static constexpr int kBlock = sizeof(F) == 4 ? 8 : 4; };
+
 template <class V, int MASK>
-__device__ __forceinline__ void bwd_block(const BwdSymArgs &A, const float *g32,
+__device__ __forceinline__ void bwd_block(const BwdSymArgs &A, const typename V::F *g,
                                           const typename V::I (&rows)[kSymRows],
-                                          const float (&mr)[kSymRows],
-                                          const float (&gr)[kSymRows][4],
+                                          const typename V::F (&mr)[kSymRows],
+                                          const typename V::F (&gr)[kSymRows][4],
                                           const int (&k)[kSymRows], int64_t jb,
-                                          float (&a)[kSymRows][4], float *L, int lane) {
+                                          typename V::F (&a)[kSymRows][4], typename V::F *L,
+                                          int lane) {
+  using F = typename V::F;
+  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2) : static_cast<F>(A.eps2_64);
 #pragma unroll 4
-  for (int c = 0; c < kBBlock; ++c) {
+  for (int c = 0; c < BCols<F>::kBlock; ++c) {
     const int64_t j = jb + c;
     const typename V::J Jr = V::load_j(A.p32, A.p64, A.npad, j, 1.0f);
-    const float gj[4] = {g32[j], g32[A.npad + j], g32[2 * A.npad + j], g32[3 * A.npad + j]};
-    float ca[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const F gj[4] = {g[j], g[A.npad + j], g[2 * A.npad + j], g[3 * A.npad + j]};
+    F ca[4] = {F(0), F(0), F(0), F(0)};
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
       const bool skip = MASK && (j <= k[r] || j >= A.n || k[r] >= A.n);
-      pair_bwd_sym<V>(rows[r], mr[r], gr[r], Jr, gj, A.eps2, skip, a[r], ca);
+      pair_bwd_sym<V>(rows[r], mr[r], gr[r], Jr, gj, eps2, skip, a[r], ca);
     }
-    float *e = L + (c * kSymLdsStride + lane) * 4;
+    F *e = L + (c * kSymLdsStride + lane) * 4;
     e[0] = ca[0];
     e[1] = ca[1];
     e[2] = ca[2];
@@ -94,10 +108,12 @@ __device__ __forceinline__ void bwd_block(const BwdSymArgs &A, const float *g32,
 template <class V>
 __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__restrict__ p32,
                                                  const double *__restrict__ p64,
-                                                 const float *__restrict__ g32,
-                                                 float *__restrict__ col_part,
+                                                 const typename V::F *__restrict__ g32,
+                                                 typename V::F *__restrict__ col_part,
                                                  double *__restrict__ row_part) {
-  __shared__ float lds[kWG / 64][kBBlock * kSymLdsStride * 4];
+  using F = typename V::F;
+  constexpr int BLK = BCols<F>::kBlock;
+  __shared__ F lds[kWG / 64][BLK * kSymLdsStride * 4];
   BwdSymArgs A = A0;
   A.p32 = p32;
   A.p64 = p64;
@@ -108,7 +124,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
   const int4 it = A.plan.items[item];
   const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
   typename V::I rows[kSymRows];
-  float mr[kSymRows], gr[kSymRows][4];
+  F mr[kSymRows], gr[kSymRows][4];
   int k[kSymRows];
   double tot[kSymRows][4];
 #pragma unroll
@@ -116,31 +132,34 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
     k[r] = static_cast<int>(row0) + r * 64 + lane;
     const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
     rows[r] = V::load_i(A.p32, A.p64, A.npad, kk);
-    mr[r] = A.p32[P32_M * A.npad + kk];
+    if constexpr (sizeof(F) == 4)
+      mr[r] = A.p32[P32_M * A.npad + kk];
+    else
+      mr[r] = A.p64[P64_M * A.npad + kk];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       gr[r][v] = g32[v * A.npad + kk];
       tot[r][v] = 0.0;
     }
   }
-  float *L = lds[wv];
-  float *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
+  F *L = lds[wv];
+  F *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
   const bool rows_pad = row0 + kSymWaveRows > A.n;
   for (int64_t jt = it.y; jt < it.z; jt += 64) {
-    float a[kSymRows][4];
+    F a[kSymRows][4];
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a[r][v] = 0.0f;
-    for (int64_t jb = jt; jb < jt + 64; jb += kBBlock) {
-      if (rows_pad || jb < row0 + kSymWaveRows || jb + kBBlock > A.n)
+      for (int v = 0; v < 4; ++v) a[r][v] = F(0);
+    for (int64_t jb = jt; jb < jt + 64; jb += BLK) {
+      if (rows_pad || jb < row0 + kSymWaveRows || jb + BLK > A.n)
         bwd_block<V, 1>(A, g32, rows, mr, gr, k, jb, a, L, lane);
       else
         bwd_block<V, 0>(A, g32, rows, mr, gr, k, jb, a, L, lane);
       wave_lds_sync();
-      float cs[4];
-      sym_col_sums<kBBlock, 4>(L, lane, cs);
-      if (lane < kBBlock) {
+      F cs[4];
+      sym_col_sums<BLK, 4>(L, lane, cs);
+      if (lane < BLK) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) cpart[v * A.npad + jb + lane] = cs[v];
       }
@@ -160,6 +179,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
 
 // Particle p: its row tile's row partials in slot order, then the column partials of the
 // row tiles 0 .. its own, added to grad_r and grad_m.
+template <class F>
 __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
@@ -170,7 +190,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
   for (int s = 0; s < slots; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
-  const float *cp = static_cast<const float *>(A.plan.col_part);
+  const F *cp = static_cast<const F *>(A.plan.col_part);
   for (int u = 0; u <= R; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
@@ -181,24 +201,34 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
 
 template <class V>
 hipError_t run(BwdSymArgs &A, hipStream_t st) {
-  const int64_t len = 4 * A.npad;
-  hipLaunchKernelGGL(k_bwd_seeds32, dim3(static_cast<unsigned>((len + kWG - 1) / kWG)),
-                     dim3(kWG), 0, st, len, A.gord, A.plan.aux);
+  using F = typename V::F;
+  const F *g;
+  if constexpr (sizeof(F) == 4) {
+    // float32 seeds for the scalar loads of the column records
+    const int64_t len = 4 * A.npad;
+    hipLaunchKernelGGL(k_bwd_seeds32, dim3(static_cast<unsigned>((len + kWG - 1) / kWG)),
+                       dim3(kWG), 0, st, len, A.gord, A.plan.aux);
+    g = A.plan.aux;
+  } else {
+    g = A.gord;
+  }
   const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
-  hipLaunchKernelGGL((k_bwd_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64,
-                     static_cast<const float *>(A.plan.aux),
-                     static_cast<float *>(A.plan.col_part),
+  hipLaunchKernelGGL((k_bwd_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, g,
+                     static_cast<F *>(A.plan.col_part),
                      static_cast<double *>(A.plan.row_part));
-  hipLaunchKernelGGL(k_bwd_sym_reduce, dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
+  hipLaunchKernelGGL(k_bwd_sym_reduce<F>, dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
                      dim3(kWG), 0, st, A);
   return hipGetLastError();
 }
 
 }  // namespace
 
+// Automatic in mixed precision only: the float64 form needs every vector register of a
+// wave (four rows of float64 state and sums per lane) and measured slower than the gather
+// kernel (26.3 against 23.6 ms at N = 131072); forced with tsbts_tune it is exact too.
 bool bwd_sym_applies(const tsbts_ctx *c, int64_t n_act) {
-  return sym_enabled(c, n_act) && c->precision != TSBTS_FP64 &&
-         (c->flags & TSBTS_FLAG_NEWTON) == 0;
+  if (!sym_enabled(c, n_act) || (c->flags & TSBTS_FLAG_NEWTON) != 0) return false;
+  return c->tune_sym == 1 || c->precision != TSBTS_FP64;
 }
 
 // After k_bwd_order has put the seeds in particle order (gord).
@@ -211,9 +241,11 @@ hipError_t launch_bwd_sym(tsbts_ctx *c, const SymPlan &plan, double *gr, double 
   A.p64 = c->p64;
   A.gord = c->gord;
   A.eps2 = static_cast<float>(c->eps * c->eps);
+  A.eps2_64 = c->eps * c->eps;
   A.plan = plan;
   A.gr = gr;
   A.gm = gm;
+  if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);
 }

@@ -213,13 +213,13 @@ def test_plummer131k_symmetric_force(prec):
 
 
 # ---------------------------------------------------------------- force adjoint
-@pytest.mark.parametrize("sep", ["f64", "hilo"])
+@pytest.mark.parametrize("prec,sep", CASES)
 @pytest.mark.parametrize("n", [3, 300, 700, 5000])
 @pytest.mark.parametrize("with_gp", [False, True])
-def test_symmetric_adjoint_matches_gather_and_oracle(sep, n, with_gp):
+def test_symmetric_adjoint_matches_gather_and_oracle(prec, sep, n, with_gp):
     eps = 1 / 256
     r, v, m = _state(n, 3600 + n)
-    ctx = make_ctx(n, eps, "mixed", sep)
+    ctx = make_ctx(n, eps, prec, sep)
     ctx.bind(r, v, m)
     ctx.predict(0.0)
     idx = _perm(n, n + 2)
@@ -236,18 +236,20 @@ def test_symmetric_adjoint_matches_gather_and_oracle(sep, n, with_gp):
             assert all(np.array_equal(a, b) for a, b in zip(res, out[sym]))   # fixed order
         out[sym] = res
     rr, rm = oracle.force_backward(r, m, eps, idx, g, gp)
+    tol = 1e-11 if prec == "fp64" else 2e-5
     for got, ref in ((out[1][0], rr), (out[1][1], rm)):
-        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     for got, ref in zip(out[1], out[0]):
-        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     ctx.close()
 
 
-def test_plummer131k_symmetric_adjoint():
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_plummer131k_symmetric_adjoint(prec):
     cfg = config("plummer131k")
     n, eps = cfg.n, cfg.eps
     r, v, m = cfg.ic()
-    ctx = make_ctx(n, eps, "mixed")
+    ctx = make_ctx(n, eps, prec)
     ctx.bind(r, v, m)
     ctx.predict(0.0)
     idx = _perm(n, 13)
@@ -265,13 +267,14 @@ def test_plummer131k_symmetric_adjoint():
         torch.cuda.synchronize()
         ms[sym] = (time.perf_counter() - t0) / 2 * 1e3
         out[sym] = (gr.cpu().numpy() / 3, gm.cpu().numpy() / 3)
-    print(f"plummer131k mixed adjoint, all targets: gather {ms[0]:.2f} ms, "
+    print(f"plummer131k {prec} adjoint, all targets: gather {ms[0]:.2f} ms, "
           f"symmetric {ms[1]:.2f} ms")
+    tol = 1e-11 if prec == "fp64" else 2e-5
     for got, ref in zip(out[1], out[0]):
-        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     # sampled rows against the oracle
     rows = np.arange(0, n, n // 128).astype(np.int32)
     rr, rm = oracle.force_backward_rows(r, m, eps, idx, g.cpu().numpy(), rows)
     for got, ref in ((out[1][0][:, rows], rr), (out[1][1][rows], rm)):
-        assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     ctx.close()
