@@ -324,7 +324,9 @@ def rooflines(ms, n, precision="mixed", symmetric=True):
 
 
 def force_variants(cfg, r, v, m, reps=5):
-    """Full-active force time and accuracy (vs the float64 kernel) of each mixed variant."""
+    """Full-active force time and accuracy (vs the float64 kernel) of each mixed variant,
+    all on the gather kernels (symmetric kernels off) so that the pair-arithmetic variants
+    compare on one kernel form."""
     from paper_1205_2288_amd import Context
     n = cfg.n
     res = {}
@@ -333,6 +335,7 @@ def force_variants(cfg, r, v, m, reps=5):
                               ("mixed", "f64", True), ("mixed", "hilo", False),
                               ("mixed", "hilo", True)):
         with Context(n, cfg.eps, precision=prec, separation=sep, newton=newton) as c:
+            c.tune(symmetric=0)
             c.bind(r, v, m)
             c.predict(0.0)
             idx = c.idx(np.arange(n, dtype=np.int32))
