@@ -60,24 +60,24 @@ FLOPS_ADJOINT_SYM = 64.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (411308.8, 131072.0,
+    "k_timestep_scalar": (411271.9, 131072.0,
         ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
-        "73b1678449491c76"),
-    "k_force_scalar": (50979.5, 65536.0,
-        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp"),
-        "959ae23cabae0ed8"),
-    "k_timestep_sym": (424665.3, 332259.5,
+        "306aab454531058b"),
+    "k_force_scalar": (52489.8, 65536.0,
+        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp", "predict.hpp", "hermite.hpp"),
+        "41be8caafd628fdf"),
+    "k_timestep_sym": (424654.3, 332272.3,
         ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
-        "fa1d61a5d662c90f"),
-    "k_force_sym": (311024.0, 790087.9,
+        "af3d4b4cb4648210"),
+    "k_force_sym": (301812.6, 790295.1,
         ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
-        "4489612d30c1f9d3"),
-    "k_bwd_sym": (609883.8, 792229.5,
+        "1233bc3db98338ee"),
+    "k_bwd_sym": (609813.6, 792185.3,
         ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
-        "6e36e9d052bf6676"),
-    "k_energy_pairs": (23349.4, 4104.0,
+        "88b9aef735368a4c"),
+    "k_energy_pairs": (23325.9, 4104.0,
         ("energy.hip", "internal.hpp"),
-        "fdf7af56d3adecd9"),
+        "d29a035bddc34946"),
 }
 
 
