@@ -35,8 +35,8 @@ class TsbtsError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                      "or python paper_1205_2288_amd/build.py")
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "python paper_1205_2288_amd/build.py")
 
 lib = ctypes.CDLL(LIB_PATH)
 
