@@ -38,11 +38,24 @@ hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act
   return hipGetLastError();
 }
 
+// Partial-buffer bytes for nv values per particle (float64 rows, col_bytes columns).
+int64_t sym_bytes(int64_t npad, int nv, int col_bytes) {
+  const int chunk = sym_chunk(npad);
+  const int64_t n_rtiles = (npad + kSymWaveRows - 1) / kSymWaveRows;
+  const int64_t npad_rows = n_rtiles * kSymWaveRows;
+  const int64_t max_slots = sym_slots(npad, 0, chunk);
+  return (max_slots * npad_rows * 8 + n_rtiles * npad * col_bytes) * nv +
+         npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
+}
+
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
   if (n_act != c->n) return false;
   if (c->tune_sym == 0) return false;
   if (c->tune_sym == 1) return true;
-  return c->n >= kSymMinN;
+  // automatic: from kSymMinN particles while the partials (which grow as N^2 / 256 column
+  // sums) stay within kSymMaxBytes
+  const int cb = c->precision == TSBTS_FP64 ? 8 : 4;
+  return c->n >= kSymMinN && sym_bytes(c->npad, 4, cb) <= kSymMaxBytes;
 }
 
 bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act) {
