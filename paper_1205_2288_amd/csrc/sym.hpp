@@ -25,7 +25,7 @@ constexpr int kSymBlock = 16;                      // columns per LDS transposit
 constexpr int kSymLdsStride = 65;                  // LDS entries per column (one pad)
 constexpr int kSymMinN = 32768;                    // automatic use from this many particles
 constexpr int kSymTargetItems = 32768;             // work items aimed at by the column chunk
-constexpr int64_t kSymMaxBytes = int64_t(8) << 30; // automatic use while partials fit this
+constexpr int64_t kSymMaxBytes = int64_t(32) << 30; // automatic use while partials fit this
 
 struct SymPlan {
   const int4 *items;  // (row tile, first column, end column, slot of the row tile)
