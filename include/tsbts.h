@@ -87,9 +87,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *   TSBTS_TUNE_SYMMETRIC: when every particle is a target (n_active = n), evaluate each
  *                      unordered pair once for both of its particles (0 = never, 1 =
  *                      always, 2 = automatic: from 32768 particles while the partial
- *                      sums (about N^2/16 bytes) fit 32 GiB, the force in both
- *                      precisions, the criterion and the adjoint in mixed precision;
- *                      default 2).  The criterion (maxima and minima) is then
+ *                      sums (about N^2/64 bytes) fit 32 GiB; default 2).  The criterion (maxima and minima) is then
  *                      bit-identical; sums are combined in another fixed order.  The
  *                      first such call on a context allocates its work list and partial
  *                      buffers.

@@ -86,7 +86,7 @@ __device__ __forceinline__ void bwd_block(const BwdSymArgs &A, const typename V:
                                           int lane) {
   using F = typename V::F;
   const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2) : static_cast<F>(A.eps2_64);
-#pragma unroll 4
+#pragma unroll 2
   for (int c = 0; c < BCols<F>::kBlock; ++c) {
     const int64_t j = jb + c;
     const typename V::J Jr = V::load_j(A.p32, A.p64, A.npad, j, 1.0f);
@@ -117,12 +117,11 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
   BwdSymArgs A = A0;
   A.p32 = p32;
   A.p64 = p64;
+  __shared__ F xs[2][kSymWaves][4][BLK];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int item = blockIdx.x * (kWG / 64) + wv;
-  if (item >= A.plan.n_items) return;  // whole wave; the kernel has no workgroup barrier
-  const int4 it = A.plan.items[item];
-  const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
+  const int4 it = A.plan.items[blockIdx.x];  // one work item per workgroup
+  const int64_t row0 = (static_cast<int64_t>(it.x) * kSymWaves + wv) * kSymWaveRows;
   typename V::I rows[kSymRows];
   F mr[kSymRows], gr[kSymRows][4];
   int k[kSymRows];
@@ -145,6 +144,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
   F *L = lds[wv];
   F *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
   const bool rows_pad = row0 + kSymWaveRows > A.n;
+  int buf = 0;
   for (int64_t jt = it.y; jt < it.z; jt += 64) {
     F a[kSymRows][4];
 #pragma unroll
@@ -159,10 +159,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
       wave_lds_sync();
       F cs[4];
       sym_col_sums<BLK, 4>(L, lane, cs);
-      if (lane < BLK) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cpart[v * A.npad + jb + lane] = cs[v];
-      }
+      sym_group_store<BLK, 4>(xs, buf, wv, lane, cs, cpart + jb, A.npad,
+                              [](F x, F y) { return x + y; });
       wave_lds_sync();
     }
 #pragma unroll
@@ -177,13 +175,13 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
     for (int v = 0; v < 4; ++v) rp[v * A.plan.npad_rows + k[r]] = tot[r][v];
 }
 
-// Particle p: its row tile's row partials in slot order, then the column partials of the
-// row tiles 0 .. its own, added to grad_r and grad_m.
+// Particle p: its row group's row partials in slot order, then the column partials of the
+// row groups 0 .. its own, added to grad_r and grad_m.
 template <class F>
 __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
-  const int R = static_cast<int>(p / kSymWaveRows);
+  const int R = static_cast<int>(p / kSymGroupRows);  // the particle's row group
   const int slots = sym_slots(A.npad, R, A.plan.chunk);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   const double *rp = static_cast<const double *>(A.plan.row_part);
@@ -212,7 +210,7 @@ hipError_t run(BwdSymArgs &A, hipStream_t st) {
   } else {
     g = A.gord;
   }
-  const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
+  const int nb = A.plan.n_items;  // one work item per workgroup
   hipLaunchKernelGGL((k_bwd_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, g,
                      static_cast<F *>(A.plan.col_part),
                      static_cast<double *>(A.plan.row_part));
@@ -223,12 +221,8 @@ hipError_t run(BwdSymArgs &A, hipStream_t st) {
 
 }  // namespace
 
-// Automatic in mixed precision only: the float64 form needs every vector register of a
-// wave (four rows of float64 state and sums per lane) and measured slower than the gather
-// kernel (26.3 against 23.6 ms at N = 131072); forced with tsbts_tune it is exact too.
 bool bwd_sym_applies(const tsbts_ctx *c, int64_t n_act) {
-  if (!sym_enabled(c, n_act) || (c->flags & TSBTS_FLAG_NEWTON) != 0) return false;
-  return c->tune_sym == 1 || c->precision != TSBTS_FP64;
+  return sym_enabled(c, n_act) && (c->flags & TSBTS_FLAG_NEWTON) == 0;
 }
 
 // After k_bwd_order has put the seeds in particle order (gord).

@@ -137,12 +137,11 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
   ForceSymArgs A = A0;
   A.p32 = p32;
   A.p64 = p64;
+  __shared__ F xs[2][kSymWaves][NV][BLK];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int item = blockIdx.x * (kWG / 64) + wv;
-  if (item >= A.plan.n_items) return;  // whole wave; the kernel has no workgroup barrier
-  const int4 it = A.plan.items[item];
-  const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
+  const int4 it = A.plan.items[blockIdx.x];  // one work item per workgroup
+  const int64_t row0 = (static_cast<int64_t>(it.x) * kSymWaves + wv) * kSymWaveRows;
   typename V::I rows[kSymRows];
   F mr[kSymRows];
   int k[kSymRows];
@@ -162,6 +161,7 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
   F *L = lds[wv];
   F *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
   const bool rows_pad = row0 + kSymWaveRows > A.n;
+  int buf = 0;
   for (int64_t jt = it.y; jt < it.z; jt += 64) {
     F a[kSymRows][4];
 #pragma unroll
@@ -176,11 +176,8 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
       wave_lds_sync();
       F cs[NV];
       sym_col_sums<BLK, NV>(L, lane, cs);
-      if (lane < BLK) {
-#pragma unroll
-        for (int v = 0; v < 3; ++v) cpart[v * A.npad + jb + lane] = cs[v];
-        cpart[3 * A.npad + jb + lane] = POT ? cs[NV - 1] : F(0);
-      }
+      sym_group_store<BLK, NV>(xs, buf, wv, lane, cs, cpart + jb, A.npad,
+                               [](F x, F y) { return x + y; });
       wave_lds_sync();
     }
 #pragma unroll
@@ -195,15 +192,15 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
     for (int v = 0; v < 4; ++v) rp[v * A.plan.npad_rows + k[r]] = tot[r][v];
 }
 
-// Particle p (target q = inv[p]): the row partials of its row tile in slot order, then
-// the column partials of the row tiles 0 .. its own; then acc, pot and the corrector.
+// Particle p (target q = inv[p]): the row partials of its row group in slot order, then
+// the column partials of the row groups 0 .. its own; then acc, pot and the corrector.
 template <class F>
 __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
   const int q = A.plan.inv[p];
   if (q < 0 || q >= A.n_act) return;  // not in the list
-  const int R = static_cast<int>(p / kSymWaveRows);
+  const int R = static_cast<int>(p / kSymGroupRows);  // the particle's row group
   const int slots = sym_slots(A.npad, R, A.plan.chunk);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   const double *rp = static_cast<const double *>(A.plan.row_part);
@@ -211,9 +208,9 @@ __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
   const F *cp = static_cast<const F *>(A.plan.col_part);
+  const int nv = A.pot ? 4 : 3;  // without the potential its column plane is not written
   for (int u = 0; u <= R; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
+    for (int v = 0; v < nv; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
   const double an[3] = {t[0], t[1], t[2]};
   A.acc[q] = an[0];
   A.acc[A.n_act + q] = an[1];
@@ -225,7 +222,7 @@ __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
 template <class V>
 hipError_t run(ForceSymArgs &A, hipStream_t st) {
   using F = typename V::F;
-  const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
+  const int nb = A.plan.n_items;  // one work item per workgroup
   F *cp = static_cast<F *>(A.plan.col_part);
   double *rp = static_cast<double *>(A.plan.row_part);
   if (A.pot)

@@ -8,9 +8,11 @@ namespace tsbts {
 namespace {
 
 int sym_chunk(int64_t npad) {
-  const int64_t n_rtiles = (npad + kSymWaveRows - 1) / kSymWaveRows;
-  // about kSymTargetItems items over the upper triangle, whole column tiles of 64
-  const int64_t cols = (npad * n_rtiles / 2 + kSymTargetItems - 1) / kSymTargetItems;
+  const int64_t n_groups = (npad + kSymGroupRows - 1) / kSymGroupRows;
+  // about kSymTargetItems waves' worth of items over the upper triangle, whole column tiles
+  // of 64
+  const int64_t waves = kSymTargetItems / kSymWaves;
+  const int64_t cols = (npad * n_groups / 2 + waves - 1) / waves;
   int64_t chunk = std::max<int64_t>(64, (cols + 63) / 64 * 64);
   chunk = std::min<int64_t>(chunk, (npad + 63) / 64 * 64);
   return static_cast<int>(chunk);
@@ -41,10 +43,10 @@ hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act
 // Partial-buffer bytes for nv values per particle (float64 rows, col_bytes columns).
 int64_t sym_bytes(int64_t npad, int nv, int col_bytes) {
   const int chunk = sym_chunk(npad);
-  const int64_t n_rtiles = (npad + kSymWaveRows - 1) / kSymWaveRows;
-  const int64_t npad_rows = n_rtiles * kSymWaveRows;
+  const int64_t n_groups = (npad + kSymGroupRows - 1) / kSymGroupRows;
+  const int64_t npad_rows = n_groups * kSymGroupRows;
   const int64_t max_slots = sym_slots(npad, 0, chunk);
-  return (max_slots * npad_rows * 8 + n_rtiles * npad * col_bytes) * nv +
+  return (max_slots * npad_rows * 8 + n_groups * npad * col_bytes) * nv +
          npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
 }
 
@@ -59,20 +61,19 @@ bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
 }
 
 bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act) {
-  if (!sym_enabled(c, n_act)) return false;
-  return c->tune_sym == 1 || c->precision != TSBTS_FP64;
+  return sym_enabled(c, n_act);
 }
 
 int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
   const int64_t npad = c->npad;
   const int chunk = sym_chunk(npad);
-  const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
+  const int n_groups = static_cast<int>((npad + kSymGroupRows - 1) / kSymGroupRows);
   if (c->sym_items_npad != npad || c->sym_chunk != chunk) {
     std::vector<int4> items;
-    for (int R = 0; R < n_rtiles; ++R) {
+    for (int g = 0; g < n_groups; ++g) {
       int s = 0;
-      for (int64_t j0 = static_cast<int64_t>(R) * kSymWaveRows; j0 < npad; j0 += chunk, ++s)
-        items.push_back(make_int4(R, static_cast<int>(j0),
+      for (int64_t j0 = static_cast<int64_t>(g) * kSymGroupRows; j0 < npad; j0 += chunk, ++s)
+        items.push_back(make_int4(g, static_cast<int>(j0),
                                   static_cast<int>(std::min<int64_t>(j0 + chunk, npad)), s));
     }
     if (c->sym_items) (void)hipFree(c->sym_items);
@@ -91,10 +92,10 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
     c->sym_items_npad = npad;
     c->sym_chunk = chunk;
   }
-  const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
+  const int64_t npad_rows = static_cast<int64_t>(n_groups) * kSymGroupRows;
   const int max_slots = sym_slots(npad, 0, chunk);
   const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows * row_bytes +
-                         static_cast<int64_t>(n_rtiles) * npad * col_bytes) * nv +
+                         static_cast<int64_t>(n_groups) * npad * col_bytes) * nv +
                         npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
   if (bytes > c->sym_part_bytes) {
     (void)hipDeviceSynchronize();
@@ -113,17 +114,17 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
 bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *p) {
   const int64_t npad = c->npad;
   if (!c->sym_items || c->sym_items_npad != npad) return false;
-  const int n_rtiles = static_cast<int>((npad + kSymWaveRows - 1) / kSymWaveRows);
-  const int64_t npad_rows = static_cast<int64_t>(n_rtiles) * kSymWaveRows;
+  const int n_groups = static_cast<int>((npad + kSymGroupRows - 1) / kSymGroupRows);
+  const int64_t npad_rows = static_cast<int64_t>(n_groups) * kSymGroupRows;
   const int max_slots = sym_slots(npad, 0, c->sym_chunk);
   const int64_t rows = static_cast<int64_t>(max_slots) * npad_rows * nv * row_bytes;
-  const int64_t cols = static_cast<int64_t>(n_rtiles) * npad * nv * col_bytes;
+  const int64_t cols = static_cast<int64_t>(n_groups) * npad * nv * col_bytes;
   const int64_t bytes = rows + cols + npad * static_cast<int64_t>(4 * sizeof(float) +
                                                                  sizeof(int32_t));
   if (bytes > c->sym_part_bytes) return false;
   p->items = static_cast<const int4 *>(c->sym_items);
   p->n_items = c->sym_items_n;
-  p->n_rtiles = n_rtiles;
+  p->n_groups = n_groups;
   p->chunk = c->sym_chunk;
   p->max_slots = max_slots;
   p->npad_rows = npad_rows;

@@ -3,16 +3,17 @@
 // When every particle is a target, each unordered pair {k, j} enters two rows: k's sum
 // over j and j's sum over k, with the same separation, distance and reciprocal powers.
 // The symmetric kernels evaluate each pair once.  The upper triangle of the pair matrix is
-// cut into wave work items: a row tile of kSymWaveRows particles (kSymRows per lane)
-// against a contiguous range of columns at or right of the tile's first particle.  A
-// lane accumulates the row side of its particles in registers.  The column side of each
-// column j is first combined over the lane's rows in registers, then over the 64 lanes
-// through a wave-private LDS transposition of kSymBlock columns at a time, and written
-// once per (row tile, column) to a partial.  A reduction kernel combines, for each
-// particle, the row partials of its own row tile's items and the column partials of all
-// row tiles at or above it, in a fixed order.  Pairs with j <= k inside the diagonal
-// block, padding rows and padding columns are masked (wave-uniform choice of the masked
-// loop, as in the gather kernels).
+// cut into workgroup work items: a row group of kSymGroupRows particles (four waves, each
+// a row tile of kSymWaveRows, kSymRows per lane) against a contiguous range of columns at
+// or right of the group's first particle.  A lane accumulates the row side of its
+// particles in registers.  The column side of each column j is combined over the lane's
+// rows in registers, over the 64 lanes through a wave-private LDS transposition of a few
+// columns at a time, over the four waves through LDS in wave order, and written once per
+// (row group, column) to a partial.  A reduction kernel combines, for each particle, the
+// row partials of its own row group's items and the column partials of all row groups at
+// or above it, in a fixed order.  Pairs with j <= k (the diagonal block and, for the
+// group's later waves, the columns left of their rows), padding rows and padding columns
+// are masked (wave-uniform choice of the masked loop, as in the gather kernels).
 #pragma once
 
 #include "internal.hpp"
@@ -20,7 +21,9 @@
 namespace tsbts {
 
 constexpr int kSymRows = 4;                        // rows per lane
-constexpr int kSymWaveRows = 64 * kSymRows;        // rows of one work item
+constexpr int kSymWaveRows = 64 * kSymRows;        // rows of one wave
+constexpr int kSymWaves = kWG / 64;                // waves of a work item
+constexpr int kSymGroupRows = kSymWaves * kSymWaveRows;  // rows of one work item
 constexpr int kSymBlock = 16;                      // columns per LDS transposition
 constexpr int kSymLdsStride = 65;                  // LDS entries per column (one pad)
 constexpr int kSymMinN = 32768;                    // automatic use from this many particles
@@ -28,14 +31,14 @@ constexpr int kSymTargetItems = 32768;             // work items aimed at by the
 constexpr int64_t kSymMaxBytes = int64_t(32) << 30; // automatic use while partials fit this
 
 struct SymPlan {
-  const int4 *items;  // (row tile, first column, end column, slot of the row tile)
+  const int4 *items;  // (row group, first column, end column, slot of the row group)
   int n_items;
-  int n_rtiles;       // row tiles of kSymWaveRows
+  int n_groups;       // row groups of kSymGroupRows
   int chunk;          // columns per work item (multiple of 64)
-  int max_slots;      // items of row tile 0 (the most of any row tile)
-  int64_t npad_rows;  // n_rtiles * kSymWaveRows
+  int max_slots;      // items of row group 0 (the most of any row group)
+  int64_t npad_rows;  // n_groups * kSymGroupRows
   void *row_part;     // [max_slots][NV][npad_rows]
-  void *col_part;     // [n_rtiles][NV][npad]
+  void *col_part;     // [n_groups][NV][npad]
   float *aux;         // [4][npad]: per-particle float32 values a kernel stages (seeds)
   int32_t *inv;       // [npad]: position of each particle in the active list
 };
@@ -46,10 +49,35 @@ struct SymPlan {
 hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act, int64_t n,
                               hipStream_t st);
 
-// Work items of a row tile: those covering columns [R * kSymWaveRows, npad) in chunks.
-__host__ __device__ inline int sym_slots(int64_t npad, int R, int chunk) {
-  const int64_t cols = npad - static_cast<int64_t>(R) * kSymWaveRows;
+// Work items of a row group: those covering columns [g * kSymGroupRows, npad) in chunks.
+__host__ __device__ inline int sym_slots(int64_t npad, int g, int chunk) {
+  const int64_t cols = npad - static_cast<int64_t>(g) * kSymGroupRows;
   return static_cast<int>((cols + chunk - 1) / chunk);
+}
+
+// The four waves' column values of one transposition block (lanes < BLK of each wave hold
+// those of column jb + lane) are combined through LDS in wave order by the first wave and
+// stored to dst[v * stride + lane].  xs is double-buffered: one workgroup barrier per block
+// keeps a wave from overwriting a buffer the first wave still reads.
+template <int BLK, int NV, class T, class Op>
+__device__ __forceinline__ void sym_group_store(T (&xs)[2][kSymWaves][NV][BLK], int &buf,
+                                                int wv, int lane, const T (&cs)[NV],
+                                                T *dst, int64_t stride, Op op) {
+  if (lane < BLK) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xs[buf][wv][v][lane] = cs[v];
+  }
+  __syncthreads();
+  if (wv == 0 && lane < BLK) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T t = xs[buf][0][v][lane];
+#pragma unroll
+      for (int w = 1; w < kSymWaves; ++w) t = op(t, xs[buf][w][v][lane]);
+      dst[v * stride + lane] = t;
+    }
+  }
+  buf ^= 1;
 }
 
 // Make the LDS writes of this wave visible to its other lanes and keep the compiler from
@@ -82,9 +110,7 @@ __device__ __forceinline__ void sym_col_sums(const T *L, int lane, T out[NV]) {
   }
 }
 
-// Whether the symmetric criterion serves the call: as sym_enabled, but automatically in
-// mixed precision only (the float64 column records of a batch do not fit the scalar
-// registers, and the symmetric float64 criterion measured slower).
+// Whether the symmetric criterion serves the call (as sym_enabled).
 bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act);
 // Whether the symmetric kernels serve a call with n_act targets (all particles).
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act);

@@ -2,8 +2,9 @@
 // unordered pair is evaluated once for both of its particles (symmetric all-targets
 // scheme of sym.hpp).  The per-pair terms are the gather kernels' (pair_step_sym), and
 // maxima and minima do not depend on the order in which they are taken, so the result
-// equals the gather kernels' bit for bit.  Partials: [slot][2][rows] and [row tile][2][n]
-// of max v^2/r^2 and min s m^(-2/3), in the kernel's float type.
+// equals the gather kernels' bit for bit.  Partials: [slot][2][rows] and [row group][2][n]
+// of max v^2/r^2 and min s m^(-2/3) (the column minima stored negated), in the kernel's
+// float type.
 #include "criterion.hpp"
 #include "sym.hpp"
 
@@ -55,7 +56,9 @@ __device__ __forceinline__ void sym_block(const StepSymArgs &A,
                                           int lane) {
   using F = typename V::F;
   // unrolled so that the column records of consecutive columns merge into wide scalar loads
-#pragma unroll 8
+  // (float64 records by two: eight would not fit the scalar registers)
+  constexpr int UNR = sizeof(F) == 4 ? 4 : 2;
+#pragma unroll UNR
   for (int c = 0; c < kSymBlock; ++c) {
     const int64_t j = jb + c;
     const typename StepRec<V>::J Jr = load_jv<V>(A, j);
@@ -89,14 +92,13 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
   A.p64 = p64;
   A.v64 = v64;
   __shared__ F lds[kWG / 64][kSymBlock * kSymLdsStride * 2];
-  // the wave index is uniform over the wave: say so, so that the work item and the column
+  __shared__ F xs[2][kSymWaves][2][kSymBlock];
+  // the wave index is uniform over the wave: say so, so that the row tile and the column
   // index are scalar and the column records arrive through scalar loads
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int item = blockIdx.x * (kWG / 64) + wv;
-  if (item >= A.plan.n_items) return;  // whole wave; the kernel has no workgroup barrier
-  const int4 it = A.plan.items[item];
-  const int64_t row0 = static_cast<int64_t>(it.x) * kSymWaveRows;
+  const int4 it = A.plan.items[blockIdx.x];  // one work item per workgroup
+  const int64_t row0 = (static_cast<int64_t>(it.x) * kSymWaves + wv) * kSymWaveRows;
   typename StepRec<V>::I rows[kSymRows];
   F wr[kSymRows], er[kSymRows], qmax[kSymRows], swmin[kSymRows];
   int k[kSymRows];  // row particles (fewer than 2^31)
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
   const F eps2 = static_cast<F>(A.eps2);
   F *L = lds[wv];
   F *colq = col_part + static_cast<int64_t>(it.x) * 2 * A.npad;
-  F *cols = colq + A.npad;
   const bool rows_pad = row0 + kSymWaveRows > A.n;
+  int buf = 0;
   for (int64_t jb = it.y; jb < it.z; jb += kSymBlock) {
     if (rows_pad || jb < row0 + kSymWaveRows || jb + kSymBlock > A.n)
       sym_block<V, 1>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
@@ -134,10 +136,10 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
     cs = fmin(cs, __shfl_xor(cs, 16, 64));
     cq = fmax(cq, __shfl_xor(cq, 32, 64));
     cs = fmin(cs, __shfl_xor(cs, 32, 64));
-    if (lane < 16) {
-      colq[jb + c] = cq;
-      cols[jb + c] = cs;
-    }
+    // over the four waves: maxima of the first value, minima of the second
+    const F both[2] = {cq, -cs};
+    sym_group_store<kSymBlock, 2>(xs, buf, wv, lane, both, colq + jb, A.npad,
+                                  [](F x, F y) { return fmax(x, y); });
     wave_lds_sync();
   }
   F *rq = row_part + static_cast<int64_t>(it.w) * 2 * A.plan.npad_rows;
@@ -149,8 +151,9 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
   }
 }
 
-// Particle p (target q = inv[p]): its row tile's row partials in slot order, then the
-// column partials of the row tiles 0 .. its own.
+// Particle p (target q = inv[p]): its row group's row partials in slot order, then the
+// column partials of the row groups 0 .. its own (the minima stored negated, so that the
+// four waves of a group combine both values by maxima).
 template <class V>
 __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   using F = typename V::F;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   if (p >= A.n) return;
   const int q = A.plan.inv[p];
   if (q < 0 || q >= A.n_act) return;  // not in the list
-  const int R = static_cast<int>(p / kSymWaveRows);
+  const int R = static_cast<int>(p / kSymGroupRows);  // the particle's row group
   const int slots = sym_slots(A.npad, R, A.plan.chunk);
   double qm = 0.0, sm = __builtin_inf();
   const F *rp = static_cast<const F *>(A.plan.row_part);
@@ -169,14 +172,14 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   const F *cp = static_cast<const F *>(A.plan.col_part);
   for (int t = 0; t <= R; ++t) {
     qm = fmax(qm, static_cast<double>(cp[(2 * t) * A.npad + p]));
-    sm = fmin(sm, static_cast<double>(cp[(2 * t + 1) * A.npad + p]));
+    sm = fmin(sm, -static_cast<double>(cp[(2 * t + 1) * A.npad + p]));  // stored negated
   }
   A.dtc[q] = finish_dt(A.eta, qm, sm);
 }
 
 template <class V>
 hipError_t run(StepSymArgs &A, hipStream_t st) {
-  const int nb = (A.plan.n_items + kWG / 64 - 1) / (kWG / 64);
+  const int nb = A.plan.n_items;  // one work item per workgroup
   using F = typename V::F;
   hipLaunchKernelGGL((k_timestep_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, A.v64,
                      static_cast<F *>(A.plan.col_part), static_cast<F *>(A.plan.row_part));
