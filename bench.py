@@ -60,22 +60,22 @@ FLOPS_ADJOINT_SYM = 64.0
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (411271.9, 131072.0,
+    "k_timestep_scalar": (411281.2, 131072.0,
         ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
-        "306aab454531058b"),
-    "k_force_scalar": (52489.8, 65536.0,
+        "bc73d1bd397ae114"),
+    "k_force_scalar": (51225.2, 65536.0,
         ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp", "predict.hpp", "hermite.hpp"),
-        "41be8caafd628fdf"),
-    "k_timestep_sym": (424654.3, 332272.3,
+        "eb865f1044a6de5f"),
+    "k_timestep_sym": (200530.6, 132103.4,
         ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
-        "af3d4b4cb4648210"),
-    "k_force_sym": (301812.6, 790295.1,
+        "20b3bf2f9670c39c"),
+    "k_force_sym": (134504.3, 363362.5,
         ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
-        "1233bc3db98338ee"),
-    "k_bwd_sym": (609813.6, 792185.3,
+        "366ef5186ea8be57"),
+    "k_bwd_sym": (236463.6, 396387.7,
         ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
-        "88b9aef735368a4c"),
-    "k_energy_pairs": (23325.9, 4104.0,
+        "0694cf107411d877"),
+    "k_energy_pairs": (23350.4, 4104.0,
         ("energy.hip", "internal.hpp"),
         "d29a035bddc34946"),
 }
