@@ -356,9 +356,12 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
  * value. */
 int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);
 
-/* Integrate one era with all its passes; *era_end (host, may be NULL) receives its end
- * time.  The bound state then holds the final pass's state; particles are synchronised at
- * era ends that are multiples of dt_max. */
+/* Integrate one era with all its passes (Algorithm 2); *era_end (host, may be NULL)
+ * receives its end time.  Every pass restarts from the era-start state; from the second
+ * pass on, the step of each particle at the era start is chosen again by Algorithm 1
+ * (from the step that brought it there) with the previous pass's criterion values, and
+ * later steps likewise.  The bound state then holds the final pass's state; particles are
+ * synchronised at era ends that are multiples of dt_max. */
 int tsbts_sched_era(tsbts_ctx *ctx, double *era_end, hipStream_t stream);
 
 /* Host copies of the scheduler state (each pointer may be NULL): t_ticks, dt_ticks [n]

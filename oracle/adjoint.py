@@ -153,9 +153,10 @@ def block_gradient(r0, v0, m, eps, dt, t_end, r_target, v_target):
 # ----------------------------------------------------------------------------------------
 # Block schedules with eras and passes (Section 2's time-symmetric scheme on a given
 # schedule).  A schedule lists the initial steps and, per era and pass, the block steps
-# (t_b, active set, the active particles' steps after the step).  Each era is integrated
-# once per listed pass from its start state (positions, velocities, accelerations, times
-# and steps).  A pass records, per particle, its era-start state and the state after each
+# (t_b, active set, the active particles' steps after the step), and optionally the
+# steps of all particles when each pass starts (a later pass may choose the first step
+# of the era again).  Each era is integrated once per listed pass from its start state
+# (positions, velocities, accelerations, times and steps).  A pass records, per particle, its era-start state and the state after each
 # of its steps (t, r, v, a).  In the first pass every particle is Taylor-predicted to the
 # block time; from the second pass on the active particles are still Taylor-predicted from
 # their own state (their leapfrog position) and every other particle is taken from the
@@ -255,8 +256,12 @@ def schedule_forward(r0, v0, m, eps, schedule):
         start = (r.copy(), v.copy(), a.copy(), t_last.copy(), dt.copy())
         prev = None
         passes_log = []
-        for steps in era["passes"]:
+        for p, steps in enumerate(era["passes"]):
             r, v, a, t_last, dt = (x.copy() for x in start)
+            if "dt_start" in era:
+                # steps of the particles when the pass starts (later passes choose the
+                # first step of the era again)
+                dt = np.array(era["dt_start"][p], dtype=np.float64)
             recs, log = _pass((r, v, a, t_last, dt), m, eps, steps, prev)
             passes_log.append((recs, log))
             prev = recs

@@ -23,6 +23,11 @@ with the reasons, in the design notes of the repository):
   interpolated (cubic Hermite) from the previous pass's stored points when those bracket
   the block time, otherwise Taylor-predicted.
 * A particle whose next time lies beyond the era end is not advanced in that era.
+* The step that leaves the era start is a new step of the era: a particle at the era
+  start keeps the step chosen when it arrived there in the first pass, and from the
+  second pass on that step is chosen again by Algorithm 1 (from the step that brought
+  the particle to the era start) with the end values of the previous pass, so that the
+  first step of every era is symmetrized like the others.
 * Dynamic era (Algorithm 3): size = last - first next block time, clamped to
   [dt_max / 8, dt_max] and rounded down to a power of two; the era then ends at the next
   multiple of that size.
@@ -104,8 +109,9 @@ class OracleTSBTS:
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
                  era=None, criterion=None, record_schedule=False):
         """record_schedule: keep the block steps taken (``self.schedule``: initial steps
-        and, per era and pass, (t_b, active set, new steps of the active set), in time
-        units) so that the same schedule can be replayed."""
+        and, per era, the steps of all particles when each pass starts and, per pass,
+        (t_b, active set, new steps of the active set), in time units) so that the same
+        schedule can be replayed."""
         self.n = int(np.asarray(m).size)
         self.m = np.array(m, dtype=np.float64)
         self.eps = float(eps)
@@ -123,6 +129,8 @@ class OracleTSBTS:
         self.t = np.zeros(self.n, dtype=np.int64)
         self.dt = np.array([level_from_criterion(c, c, self.dt_min, self.dt_max)
                             for c in self.dtc], dtype=np.int64)
+        # the step that brought each particle to its current time (0: none yet)
+        self.dtp = np.zeros(self.n, dtype=np.int64)
         self.time = 0
         self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0}
         self.schedule = ({"dt0": self.dt * TICK, "eras": []} if record_schedule else None)
@@ -220,6 +228,7 @@ class OracleTSBTS:
             self.r[:, idx] = rp[:, idx]
             self.v[:, idx] = self.v[:, idx] + 0.5 * (self.a[:, idx] + a_new) * h
             self.a[:, idx] = a_new
+            self.dtp[idx] = tb - self.t[idx]
             self.t[idx] = tb
             # criterion: corrected active particles, predicted others
             vc = vp.copy()
@@ -237,23 +246,33 @@ class OracleTSBTS:
         return hist.freeze(self.n)
 
     # ------------------------------------------------------------------ one era
+    def _first_steps(self, T0: int, prev: History):
+        """Later passes: the step of every particle at the era start chosen again by
+        Algorithm 1, from the step that brought it there, with the previous pass's end
+        values (particles that have not taken a step yet keep their initial step)."""
+        for i in np.nonzero((self.t == T0) & (self.dtp > 0))[0]:
+            self.dt[i] = self.dtp[i]
+            self.dt[i] = self._new_step(int(i), T0, float(self.dtc[i]), prev)
+
     def era_step(self):
         T0 = self.time
         T1 = self._era_end(T0)
-        saved = [x.copy() for x in (self.r, self.v, self.a, self.t, self.dt, self.dtc)]
+        names = ("r", "v", "a", "t", "dt", "dtc", "dtp")
+        saved = [getattr(self, x).copy() for x in names]
         prev = None
         era_rec = None
         if self.schedule is not None:
-            era_rec = {"passes": []}
+            era_rec = {"passes": [], "dt_start": []}
             self.schedule["eras"].append(era_rec)
         for p in range(self.passes):
             if p > 0:
-                for dst, src in zip((self.r, self.v, self.a, self.t, self.dt, self.dtc),
-                                    saved):
-                    dst[...] = src
+                for name, src in zip(names, saved):
+                    getattr(self, name)[...] = src
+                self._first_steps(T0, prev)
             if era_rec is not None:
                 self._log = []
                 era_rec["passes"].append(self._log)
+                era_rec["dt_start"].append(self.dt * TICK)
             prev = self._pass(T1, prev)
         self._log = None
         self.last_history = prev
@@ -281,9 +300,9 @@ class OracleTSBTS:
     def state(self):
         return {"r": self.r.copy(), "v": self.v.copy(), "a": self.a.copy(),
                 "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
-                "time": self.time}
+                "dtp": self.dtp.copy(), "time": self.time}
 
     def load_state(self, s):
-        for name in ("r", "v", "a", "t", "dt", "dtc"):
+        for name in ("r", "v", "a", "t", "dt", "dtc", "dtp"):
             getattr(self, name)[...] = s[name]
         self.time = int(s["time"])

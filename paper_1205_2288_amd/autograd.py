@@ -299,7 +299,8 @@ def fixed_schedule(dt, t_end: float, era: float, passes: int):
 
 
 class _DeviceSchedule:
-    """A schedule ({"dt0": steps, "eras": [{"passes": [[(t_b, active, new steps), ...]]}]},
+    """A schedule ({"dt0": steps, "eras": [{"passes": [[(t_b, active, new steps), ...]],
+    "dt_start": [steps of all particles when each pass starts] (optional)}]},
     as recorded by driver.TSBTS(record_schedule=True)) with its index and step arrays on the
     device."""
 
@@ -310,7 +311,13 @@ class _DeviceSchedule:
             raise ValueError("the schedule's initial steps must cover every particle")
         cache = {}
         self.eras = []
+        self.pass_dt = []  # per era and pass: the steps when the pass starts, or None
         for era in schedule["eras"]:
+            starts = era.get("dt_start")
+            self.pass_dt.append([
+                None if starts is None else
+                torch.tensor(np.asarray(starts[p], dtype=np.float64), device=dev)
+                for p in range(len(era["passes"]))])
             passes = []
             for steps in era["passes"]:
                 dev_steps = []
@@ -327,9 +334,13 @@ class _DeviceSchedule:
             self.eras.append(passes)
 
 
-def _sched_pass(ctx: Context, steps, buf, use_history: bool, record: bool, pre=None):
+def _sched_pass(ctx: Context, steps, buf, use_history: bool, record: bool, pre=None,
+                dt_start=None):
     """One pass over the listed block steps; record = keep its states as the next pass's
-    interpolation source; pre = list receiving each step's pre-step state."""
+    interpolation source; pre = list receiving each step's pre-step state; dt_start =
+    the steps of all particles when the pass starts (None: those of the state)."""
+    if dt_start is not None:
+        ctx.dt.copy_(dt_start)
     if record:
         ctx.history_begin()
     for (tb, idx, dtn) in steps:
@@ -377,7 +388,8 @@ class TsbtsScheduleLeapfrog(torch.autograd.Function):
             for p, steps in enumerate(passes):
                 if p:
                     _restore(ctx, start)
-                _sched_pass(ctx, steps, buf, p > 0, p < len(passes) - 1)
+                _sched_pass(ctx, steps, buf, p > 0, p < len(passes) - 1,
+                            dt_start=sched.pass_dt[len(starts) - 1][p])
         ctx.history_clear()
         fctx.tsbts = ctx
         fctx.sched = sched
@@ -417,13 +429,15 @@ class TsbtsScheduleLeapfrog(torch.autograd.Function):
                 ctx.history_clear()
                 for q in range(p):
                     _restore(ctx, start)
-                    _sched_pass(ctx, passes[q], buf, q > 0, True)
+                    _sched_pass(ctx, passes[q], buf, q > 0, True,
+                                dt_start=sched.pass_dt[e][q])
                 if p:
                     layout = ctx.history_layout()
                     hbar = torch.zeros((6, layout[0]), dtype=torch.float64, device=dev)
                 _restore(ctx, start)
                 pre = []
-                _sched_pass(ctx, passes[p], buf, p > 0, False, pre)
+                _sched_pass(ctx, passes[p], buf, p > 0, False, pre,
+                            dt_start=sched.pass_dt[e][p])
                 rb, vb, ab = (rbar, vbar, abar) if p == P - 1 else (z(), z(), z())
                 for s in range(len(passes[p]) - 1, -1, -1):
                     _restore(ctx, pre[s])

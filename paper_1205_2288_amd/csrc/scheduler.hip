@@ -17,7 +17,10 @@
 //     values come from the previous pass's criterion values of the particle, linear in
 //     time between stored values, the start value past the last one;
 //   dynamic era: size = (last - first next block time) clamped to [dt_max/8, dt_max],
-//     rounded down to a power of two; the era ends at the next multiple of the size.
+//     rounded down to a power of two; the era ends at the next multiple of the size;
+//   era start: from the second pass on, the step of every particle at the era start is
+//     chosen again by the later-pass rule (from the step that brought it there) with the
+//     previous pass's end values, so the first step of an era is symmetrized too.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -123,6 +126,7 @@ struct Scheduler {
   int passes = 3;
   int64_t dt_min = 1, dt_max = 1 << 14, era = 0;
   std::vector<int64_t> t, dt;
+  std::vector<int64_t> dtp;  // the step that brought each particle to t (0: none yet)
   std::vector<double> dtc;
   int64_t time = 0;
   // level member lists
@@ -140,7 +144,7 @@ struct Scheduler {
   int32_t *idx_d = nullptr;
   double *acc_d = nullptr;
   double *s0 = nullptr;  // era-start device copy: r, v, a (3n each), t_last, dt
-  std::vector<int64_t> s0_t, s0_dt;
+  std::vector<int64_t> s0_t, s0_dt, s0_dtp;
   std::vector<double> s0_dtc;
   int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
   int crit_before = 0;  // criterion with the predicted velocities, fused with the force
@@ -252,6 +256,7 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       const int32_t i = S.idx_h[q];
       const double b = S.dtc_h[q];
       S.dtc[i] = b;
+      S.dtp[i] = tb - S.t[i];
       S.t[i] = tb;
       S.cur.add(i, tb, b);
       const int64_t d = S.dt[i];
@@ -277,6 +282,29 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
   S.cur.close(n);
   std::swap(S.prev, S.cur);
   S.have_prev = true;
+  return TSBTS_OK;
+}
+
+// Later passes: the steps of the particles at the era start T0 chosen again from the
+// steps that brought them there, with the previous pass's end values; the device copy
+// of the steps follows.
+int first_steps(tsbts_ctx *c, Scheduler &S, int64_t T0, hipStream_t st) {
+  const int64_t n = S.n;
+  // the last step update of the previous pass may still be reading dtn_h
+  SCHED_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    if (S.t[i] == T0 && S.dtp[i] > 0) {
+      const int64_t d = S.dtp[i];
+      const double b = S.dtc[i];
+      const double e1 = S.prev.value_at(static_cast<int32_t>(i), T0 + d, b);
+      const double e2 = S.prev.value_at(static_cast<int32_t>(i), T0 + 2 * d, b);
+      S.dt[i] = tsbts::step_rule(0, d, T0, b, e1, e2, S.dt_min, S.dt_max);
+    }
+    S.dtn_h[i] = static_cast<double>(S.dt[i]) * tsbts::kTick;
+  }
+  SCHED_HIP(hipMemcpyAsync(c->dt, S.dtn_h, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  // dtn_h is rewritten by the next block step on the host: wait for the copy
+  SCHED_HIP(hipStreamSynchronize(st));
   return TSBTS_OK;
 }
 
@@ -344,6 +372,7 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   S->era = era > 0.0 ? static_cast<int64_t>(k_era) : 0;
   S->t.assign(n, 0);
   S->dt.assign(n, 0);
+  S->dtp.assign(n, 0);
   S->dtc.assign(n, 0.0);
   S->lvl.assign(n, 0);
   S->pos.assign(n, 0);
@@ -393,6 +422,7 @@ int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
   SCHED_HIP(hipMemcpyAsync(s0 + 10 * n, c->dt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   S->s0_t = S->t;
   S->s0_dt = S->dt;
+  S->s0_dtp = S->dtp;
   S->s0_dtc = S->dtc;
   S->have_prev = false;
   for (int p = 0; p < S->passes; ++p) {
@@ -404,7 +434,9 @@ int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
       SCHED_HIP(hipMemcpyAsync(c->dt, s0 + 10 * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
       S->t = S->s0_t;
       S->dt = S->s0_dt;
+      S->dtp = S->s0_dtp;
       S->dtc = S->s0_dtc;
+      SCHED_CALL(first_steps(c, *S, T0, st));
     }
     S->rebuild_levels();
     SCHED_CALL(run_pass(c, *S, p, T1, st));

@@ -100,8 +100,9 @@ class TSBTS:
                  era=None, precision="mixed", separation="f64", newton=False, context=None,
                  record_schedule=False):
         """record_schedule: keep the block steps taken in ``self.schedule`` (initial steps
-        and, per era and pass, (t_b, active set, new steps of the active set), in time
-        units), the input of autograd.tsbts_schedule_leapfrog."""
+        and, per era, the steps of all particles when each pass starts and, per pass,
+        (t_b, active set, new steps of the active set), in time units), the input of
+        autograd.tsbts_schedule_leapfrog."""
         self.n = n = int(np.asarray(m).size)
         self.schedule = {"dt0": None, "eras": []} if record_schedule else None
         self._log = None
@@ -127,6 +128,7 @@ class TSBTS:
         # host mirrors (ticks) and last criterion values
         self.t = np.zeros(n, dtype=np.int64)
         self.dt = np.zeros(n, dtype=np.int64)
+        self.dtp = np.zeros(n, dtype=np.int64)  # step that brought each particle to t
         self.dtc = np.zeros(n)
         self.time = 0
         self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0,
@@ -205,6 +207,7 @@ class TSBTS:
             c.synchronize()
             begin = self._dtc_h[:k].numpy().copy()
             self.dtc[idx] = begin
+            self.dtp[idx] = tb - self.t[idx]
             self.t[idx] = tb
             hist.add(idx, tb, begin)
             new = self._new_steps(idx, tb, begin, prev)
@@ -221,26 +224,40 @@ class TSBTS:
         c.history_end()
         return hist.close(self.n)
 
+    def _first_steps(self, T0: int, prev: CriterionHistory):
+        """Later passes: the step of every particle at the era start chosen again by
+        Algorithm 1 (from the step that brought it there) with the previous pass's end
+        values, so that the first step of an era is symmetrized like the others;
+        particles that have not taken a step yet keep their initial step."""
+        idx = np.flatnonzero((self.t == T0) & (self.dtp > 0)).astype(np.int32)
+        if idx.size == 0:
+            return
+        self.dt[idx] = self.dtp[idx]
+        self.dt[idx] = self._new_steps(idx, T0, self.dtc[idx], prev)
+        self.ctx.dt.copy_(torch.from_numpy(self.dt * TICK))
+
     def era_step(self) -> int:
         c = self.ctx
         T0 = self.time
         T1 = self._era_end(T0)
         saved_dev = [x.clone() for x in (c.r, c.v, c.a, c.t_last, c.dt)]
-        saved_host = [x.copy() for x in (self.t, self.dt, self.dtc)]
+        saved_host = [x.copy() for x in (self.t, self.dt, self.dtc, self.dtp)]
         prev = None
         era_rec = None
         if self.schedule is not None:
-            era_rec = {"passes": []}
+            era_rec = {"passes": [], "dt_start": []}
             self.schedule["eras"].append(era_rec)
         for p in range(self.passes):
             if p > 0:
                 for dst, src in zip((c.r, c.v, c.a, c.t_last, c.dt), saved_dev):
                     dst.copy_(src)
-                for dst, src in zip((self.t, self.dt, self.dtc), saved_host):
+                for dst, src in zip((self.t, self.dt, self.dtc, self.dtp), saved_host):
                     dst[...] = src
+                self._first_steps(T0, prev)
             if era_rec is not None:
                 self._log = []
                 era_rec["passes"].append(self._log)
+                era_rec["dt_start"].append(self.dt * TICK)
             prev = self._pass(p, T1, prev)
         self._log = None
         self.time = T1
@@ -273,7 +290,7 @@ class TSBTS:
         c.synchronize()
         return {"r": c.r.cpu().numpy(), "v": c.v.cpu().numpy(), "a": c.a.cpu().numpy(),
                 "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
-                "time": self.time}
+                "dtp": self.dtp.copy(), "time": self.time}
 
     def close(self):
         self.ctx.close()

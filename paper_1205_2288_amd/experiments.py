@@ -15,8 +15,12 @@ eras keep the error in a random walk; dynamic eras perform like the best fixed e
 
     python -m paper_1205_2288_amd.experiments era --n 100 --t-end 100 --seeds 3
     python -m paper_1205_2288_amd.experiments dynamic --n 100 --t-end 100 --seeds 10
+    python -m paper_1205_2288_amd.experiments era --n 500 --eta 0.5 --workers 12 ...
 
 Each finished run prints one JSON line (progress and result); the last line is a summary.
+With --workers K > 1 the runs go to K child processes at a time (each its own GPU context;
+a run at N of a few hundred is bound by launch latency, not by the GPU's throughput, so
+concurrent runs share one GPU almost for free).  The parent process never touches the GPU.
 """
 from __future__ import annotations
 
@@ -24,8 +28,10 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -73,17 +79,41 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
             "series_t": t.tolist(), "series_err": err.tolist()}
 
 
+def _run_child(spec: dict) -> dict:
+    """One energy_error_run in a child process (its own GPU context); returns its result."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cmd = [sys.executable, "-m", "paper_1205_2288_amd.experiments", "run",
+           "--spec", json.dumps(spec)]
+    # progress lines of the child go to this process's stderr as they come
+    proc = subprocess.run(cmd, cwd=root, stdout=subprocess.PIPE, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"run {spec} failed with exit status {proc.returncode}")
+    return json.loads(proc.stdout.strip().splitlines()[-1])
+
+
+def run_many(specs: list, workers: int = 1, out=sys.stdout) -> list:
+    """energy_error_run over a list of keyword dicts, in this process (workers <= 1) or in
+    up to `workers` child processes at a time; results in the order of `specs`, each one
+    emitted (without its series) as it finishes."""
+    def emit(res):
+        _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
+        return res
+
+    if workers <= 1:
+        return [emit(energy_error_run(**s)) for s in specs]
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        futs = [pool.submit(_run_child, s) for s in specs]
+        return [emit(f.result()) for f in futs]
+
+
 def era_study(n=100, seeds=3, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
               eras=(1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4), passes=(3, 5), every=1.0,
-              seed0=1205, out=sys.stdout):
+              seed0=1205, out=sys.stdout, workers=1):
     """Fixed era sizes x pass counts x initial conditions (Section 3, fixed-era tests)."""
-    rows = []
-    for k in range(seeds):
-        for p in passes:
-            for era in eras:
-                res = energy_error_run(n, seed0 + k, eps, eta, p, era, dt_max, t_end, every)
-                rows.append(res)
-                _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
+    specs = [dict(n=n, seed=seed0 + k, eps=eps, eta=eta, passes=p, era=era, dt_max=dt_max,
+                  t_end=t_end, every=every)
+             for k in range(seeds) for p in passes for era in eras]
+    rows = run_many(specs, workers, out)
     summary = {}
     for p in passes:
         for era in eras:
@@ -97,16 +127,13 @@ def era_study(n=100, seeds=3, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
 
 
 def dynamic_era_study(n=100, seeds=10, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
-                      passes=3, every=1.0, seed0=2205, out=sys.stdout):
+                      passes=3, every=1.0, seed0=2205, out=sys.stdout, workers=1):
     """Fixed era (= dt_max) against the dynamic era (Section 4), same initial conditions."""
-    rows = []
-    for k in range(seeds):
-        pair = {}
-        for era in (dt_max, None):
-            res = energy_error_run(n, seed0 + k, eps, eta, passes, era, dt_max, t_end, every)
-            pair["fixed" if era else "dynamic"] = res
-            _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
-        rows.append(pair)
+    specs = [dict(n=n, seed=seed0 + k, eps=eps, eta=eta, passes=passes, era=era,
+                  dt_max=dt_max, t_end=t_end, every=every)
+             for k in range(seeds) for era in (dt_max, None)]
+    res = run_many(specs, workers, out)
+    rows = [{"fixed": res[2 * k], "dynamic": res[2 * k + 1]} for k in range(seeds)]
     better = sum(1 for p in rows if p["dynamic"]["final_err"] < p["fixed"]["final_err"])
     summary = {
         "dynamic_smaller_final_err_fraction": better / len(rows),
@@ -126,7 +153,10 @@ def _emit(out, obj):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("study", choices=["era", "dynamic"])
+    ap.add_argument("study", choices=["era", "dynamic", "run"])
+    ap.add_argument("--spec", default=None, help="run: energy_error_run keywords as JSON")
+    ap.add_argument("--workers", type=int, default=1,
+                    help="child processes running at a time (each its own GPU context)")
     ap.add_argument("--n", type=int, default=100)
     ap.add_argument("--seeds", type=int, default=3)
     ap.add_argument("--t-end", type=float, default=100.0)
@@ -138,17 +168,23 @@ def main(argv=None):
     ap.add_argument("--seed0", type=int, default=None, help="first sphere's seed")
     ap.add_argument("--every", type=float, default=1.0, help="energy sampling interval")
     args = ap.parse_args(argv)
+    if args.study == "run":
+        _emit(sys.stdout, energy_error_run(**json.loads(args.spec)))
+        return
+    if not 1 <= args.workers <= 15:
+        ap.error("--workers must be between 1 and 15")
     if args.study == "era":
         kw = {} if args.eras is None else {"eras": tuple(args.eras)}
         if args.seed0 is not None:
             kw["seed0"] = args.seed0
         era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta, eps=args.eps,
-                  passes=tuple(args.passes or (3, 5)), every=args.every, **kw)
+                  passes=tuple(args.passes or (3, 5)), every=args.every,
+                  workers=args.workers, **kw)
     else:
         kw = {} if args.seed0 is None else {"seed0": args.seed0}
         dynamic_era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta,
                           eps=args.eps, passes=(args.passes or [3])[0], every=args.every,
-                          **kw)
+                          workers=args.workers, **kw)
 
 
 if __name__ == "__main__":

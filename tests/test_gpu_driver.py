@@ -92,6 +92,36 @@ def test_native_scheduler_matches_python_scheduler(prec, name, eras):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_era_of_one_max_step_first_steps(prec):
+    # era = dt_max: every particle is at the era start each era and its first step is
+    # chosen again in every later pass; the native scheduler, the Python one and (float64)
+    # the oracle make the same choices
+    from paper_1205_2288_amd.driver import TSBTS, NativeTSBTS
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=0.5, passes=3, era=cfg.dt_max, dt_max=cfg.dt_max, dt_min=cfg.dt_min)
+    py = TSBTS(r, v, m, cfg.eps, precision=prec, record_schedule=True, **kw)
+    nat = NativeTSBTS(r, v, m, cfg.eps, precision=prec, **kw)
+    ref = OracleTSBTS(r, v, m, cfg.eps, **kw) if prec == "fp64" else None
+    for _ in range(16):
+        py.era_step()
+        nat.era_step()
+        a, b = py.state(), nat.state()
+        for key in ("t", "dt", "dtc", "r", "v", "a"):
+            assert np.array_equal(a[key], b[key]), key
+        if ref is not None:
+            ref.era_step()
+            assert np.array_equal(b["dt"], ref.dt), "schedules diverged"
+            assert np.abs(b["r"] - ref.r).max() <= 1e-9
+    # some particles took a first step other than the one chosen when they arrived
+    changed = sum(int(np.count_nonzero(e["dt_start"][-1] != e["dt_start"][0]))
+                  for e in py.schedule["eras"])
+    assert changed > 0
+    py.close()
+    nat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["plummer256", "plummer256_1pass", "plummer4096_t1"])
 def test_energy_drift_within_twice_oracle(prec, name):
     from paper_1205_2288_amd.driver import NativeTSBTS
@@ -151,3 +181,13 @@ def test_experiments_module_small():
         assert 2.5 <= by[(3, era)] / by[(1, era)] <= 3.5
     rows, summary = ex.dynamic_era_study(n=32, seeds=2, t_end=0.5, every=0.25, out=buf)
     assert 0.0 <= summary["dynamic_smaller_final_err_fraction"] <= 1.0
+    # the same runs in two child processes: identical results (the runs are deterministic)
+    rows2, summary2 = ex.dynamic_era_study(n=32, seeds=2, t_end=0.5, every=0.25, out=buf,
+                                           workers=2)
+    for key in ("dynamic_smaller_final_err_fraction", "median_final_err_fixed",
+                "median_final_err_dynamic"):
+        assert summary2[key] == summary[key]
+    for a, b in zip(rows, rows2):
+        for kind in ("fixed", "dynamic"):
+            assert a[kind]["series_err"] == b[kind]["series_err"]
+            assert a[kind]["block_steps"] == b[kind]["block_steps"]
