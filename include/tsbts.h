@@ -313,9 +313,12 @@ int tsbts_adjoint_accumulate(tsbts_ctx *ctx, const double *rbar, const double *v
  *   - every pass restarts from the era-start state; passes after the first interpolate
  *     the non-active particles from the previous pass (tsbts_predict with history);
  *   - fixed era: a multiple of dt_max; dynamic era (Algorithm 3): size = last minus first
- *     next block time, clamped to [dt_max/8, dt_max] and rounded down to a power of two,
- *     the era ending at the next multiple of it; particles whose next time is past the era
- *     end are not advanced in that era.
+ *     next block time, clamped to [dt_max/8, dt_max] and rounded up to a power of two,
+ *     dt_max when that is below the largest step in use (Section 4), the era ending at
+ *     the next multiple of it; particles whose next time is past the era end are not
+ *     advanced in that era;
+ *   - from the second pass on, the step of each particle at the era start is chosen
+ *     again by Algorithm 1 with the previous pass's end values.
  * --------------------------------------------------------------------------------------- */
 
 /* Admissible step (ticks) for criterion values begin and end at the start and end of a

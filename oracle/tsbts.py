@@ -29,8 +29,10 @@ with the reasons, in the design notes of the repository):
   the particle to the era start) with the end values of the previous pass, so that the
   first step of every era is symmetrized like the others.
 * Dynamic era (Algorithm 3): size = last - first next block time, clamped to
-  [dt_max / 8, dt_max] and rounded down to a power of two; the era then ends at the next
-  multiple of that size.
+  [dt_max / 8, dt_max] and rounded up to a power of two; when that is still smaller than
+  the largest step in use the era takes dt_max (Section 4's remedy: an era shorter than
+  a step leaves that particle out, with no past information to symmetrize it); the era
+  then ends at the next multiple of that size.
 * Iterations = passes: one pass is the classical block-step scheme (no symmetrization).
 """
 from __future__ import annotations
@@ -150,7 +152,9 @@ class OracleTSBTS:
         nxt = self.t + self.dt
         size = int(nxt.max() - nxt.min())
         size = max(self.dt_max // 8, min(self.dt_max, size))
-        size = 1 << (size.bit_length() - 1)
+        size = 1 << (size - 1).bit_length()  # smallest power of two >= size
+        if size < int(self.dt.max()):
+            size = self.dt_max
         return (t0 // size + 1) * size
 
     # ------------------------------------------------------------------ prediction

@@ -17,7 +17,9 @@
 //     values come from the previous pass's criterion values of the particle, linear in
 //     time between stored values, the start value past the last one;
 //   dynamic era: size = (last - first next block time) clamped to [dt_max/8, dt_max],
-//     rounded down to a power of two; the era ends at the next multiple of the size;
+//     rounded up to a power of two, dt_max when that is below the largest step in use
+//     (an era shorter than a step leaves the particle unsymmetrized); the era ends at
+//     the next multiple of the size;
 //   era start: from the second pass on, the step of every particle at the era start is
 //     chosen again by the later-pass rule (from the step that brought it there) with the
 //     previous pass's end values, so the first step of an era is symmetrized too.
@@ -180,16 +182,18 @@ struct Scheduler {
   }
   int64_t era_end(int64_t t0) const {
     if (era > 0) return t0 + era;
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    int64_t lo = INT64_MAX, hi = INT64_MIN, largest = 0;
     for (int l = 0; l <= kMaxLevel; ++l) {
       if (mem[l].empty()) continue;
       const int64_t nx = t[mem[l][0]] + (int64_t(1) << l);
       lo = std::min(lo, nx);
       hi = std::max(hi, nx);
+      largest = int64_t(1) << l;
     }
-    int64_t size = std::min(dt_max, std::max(dt_max / 8, hi - lo));
+    const int64_t size = std::min(dt_max, std::max(dt_max / 8, hi - lo));
     int64_t p2 = 1;
-    while (p2 * 2 <= size) p2 *= 2;
+    while (p2 < size) p2 *= 2;  // smallest power of two >= size
+    if (p2 < largest) p2 = dt_max;
     return (t0 / p2 + 1) * p2;
   }
 };

@@ -18,8 +18,11 @@ and applies the step-size rules, vectorised over the active set:
 * Algorithm 2: every pass of an era restarts from the era-start state; passes after the
   first interpolate the non-active particles from the previous pass's stored states;
 * Algorithm 3 (dynamic era): era size = last minus first next block time, clamped to
-  [dt_max / 8, dt_max], rounded down to a power of two; the era ends at the next multiple.
-  A particle whose next time is past the era end is not advanced in that era.
+  [dt_max / 8, dt_max], rounded up to a power of two, and dt_max when that is below the
+  largest step in use (Section 4); the era ends at the next multiple.  A particle whose
+  next time is past the era end is not advanced in that era.
+* From the second pass on, the step of each particle at the era start is chosen again by
+  Algorithm 1 with the previous pass's end values.
 """
 from __future__ import annotations
 
@@ -181,7 +184,9 @@ class TSBTS:
             return t0 + self.era
         nxt = self.t + self.dt
         size = int(np.clip(nxt.max() - nxt.min(), self.dt_max // 8, self.dt_max))
-        size = 1 << (size.bit_length() - 1)
+        size = 1 << (size - 1).bit_length()  # smallest power of two >= size
+        if size < int(self.dt.max()):
+            size = self.dt_max  # an era shorter than a step would leave it unsymmetrized
         return (t0 // size + 1) * size
 
     def _pass(self, p: int, T1: int, prev: CriterionHistory | None) -> CriterionHistory:

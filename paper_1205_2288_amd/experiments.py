@@ -101,6 +101,8 @@ def run_many(specs: list, workers: int = 1, out=sys.stdout) -> list:
 
     if workers <= 1:
         return [emit(energy_error_run(**s)) for s in specs]
+    if workers > 15:
+        raise ValueError("at most 15 child processes (each holds a GPU context)")
     with ThreadPoolExecutor(max_workers=workers) as pool:
         futs = [pool.submit(_run_child, s) for s in specs]
         return [emit(f.result()) for f in futs]

@@ -101,23 +101,31 @@ def test_algorithm1_odd_time_branches():
 
 
 def test_dynamic_era_size():
+    # Algorithm 3 with the clamps of Section 4; the size is rounded up to a power of two
+    # and replaced by dt_max when it is below the largest step in use
     s = OracleTSBTS.__new__(OracleTSBTS)
     s.era = None
     s.dt_max = DTMAX
     s.t = np.array([0, 0, 0], dtype=np.int64)
     s.dt = np.array([DTMAX, DTMAX, DTMAX], dtype=np.int64)
-    assert s._era_end(0) == DTMAX // 8            # all equal: lower clamp dt_max/8
+    assert s._era_end(0) == DTMAX                 # all on the top level: spread 0 < dt_max
+    s.dt = np.array([1 << 10, 1 << 10, 1 << 10], dtype=np.int64)
+    assert s._era_end(0) == DTMAX // 8            # all equal, low level: lower clamp
     s.dt = np.array([1, 1 << 12, DTMAX], dtype=np.int64)
-    assert s._era_end(0) == DTMAX // 2            # spread dt_max - 1 rounds down
+    assert s._era_end(0) == DTMAX                 # spread dt_max - 1 rounds up
     s.t = np.array([0, 0, 2 * DTMAX], dtype=np.int64)
     assert s._era_end(0) == DTMAX                 # spread above dt_max: upper clamp
     s.t = np.array([0, 0, 0], dtype=np.int64)
     s.dt = np.array([1 << 10, 1 << 12, 1 << 12], dtype=np.int64)
-    assert s._era_end(0) == 1 << 11               # 3*2^10 rounds down to 2^11
+    assert s._era_end(0) == 1 << 12               # 3*2^10 rounds up to 2^12
+    # a particle mid-step from an earlier era: spread 2^11 < its step 2^13 -> dt_max
+    s.t = np.array([1 << 12, 0], dtype=np.int64)
+    s.dt = np.array([1 << 11, 1 << 13], dtype=np.int64)
+    assert s._era_end(1 << 12) == DTMAX
     # era end aligned to a multiple of the size
     s.t = np.array([3 << 11, 3 << 11, 3 << 11], dtype=np.int64)
     s.dt = np.array([1 << 10, 1 << 13, 1 << 13], dtype=np.int64)
-    assert s._era_end(3 << 11) == 1 << 13         # size 2^12 ... next multiple of 2^12
+    assert s._era_end(3 << 11) == 1 << 13         # size 2^13: next multiple after 3*2^11
 
 
 def _big_criterion(r, v, idx):
