@@ -61,6 +61,30 @@ def test_scheduler_matches_oracle_bitwise(name, eras):
     assert prod.stats["block_steps"] == ref.stats["block_steps"]
 
 
+def test_era_start_steps_and_schedule_match_oracle():
+    # era = dt_max with a large eta: every particle is at each era start and its first
+    # step is chosen again in the later passes; same choices and recorded schedule
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=0.5, passes=3, era=cfg.dt_max, dt_max=cfg.dt_max, dt_min=cfg.dt_min)
+    prod = TSBTS(r, v, m, cfg.eps, context=FakeContext(cfg.n, cfg.eps),
+                 record_schedule=True, **kw)
+    ref = OracleTSBTS(r, v, m, cfg.eps, record_schedule=True, **kw)
+    for _ in range(12):
+        assert prod.era_step() == ref.era_step()
+        st = prod.state()
+        for key in ("t", "dt", "dtp", "r", "v"):
+            assert np.array_equal(st[key], getattr(ref, key)), key
+    changed = 0
+    for ea, eb in zip(prod.schedule["eras"], ref.schedule["eras"]):
+        for p in range(3):
+            assert np.array_equal(ea["dt_start"][p], eb["dt_start"][p])
+            for (ta, ia, da), (tb, ib, db) in zip(ea["passes"][p], eb["passes"][p]):
+                assert ta == tb and np.array_equal(ia, ib) and np.array_equal(da, db)
+        changed += int(np.count_nonzero(ea["dt_start"][2] != ea["dt_start"][0]))
+    assert changed > 0
+
+
 def test_one_pass_and_energy_series_match_oracle():
     r, v, m = plummer(64, 8)
     kw = dict(eta=0.2, passes=1, era=1 / 32, dt_max=1 / 64, dt_min=2.0 ** -20)
