@@ -31,7 +31,7 @@ import os
 import subprocess
 import sys
 import time
-from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import ThreadPoolExecutor, as_completed
 
 import numpy as np
 
@@ -93,8 +93,8 @@ def _run_child(spec: dict) -> dict:
 
 def run_many(specs: list, workers: int = 1, out=sys.stdout) -> list:
     """energy_error_run over a list of keyword dicts, in this process (workers <= 1) or in
-    up to `workers` child processes at a time; results in the order of `specs`, each one
-    emitted (without its series) as it finishes."""
+    up to `workers` child processes at a time; results returned in the order of `specs`,
+    each one emitted (without its series) as soon as it finishes."""
     def emit(res):
         _emit(out, {key: val for key, val in res.items() if not key.startswith("series")})
         return res
@@ -105,7 +105,9 @@ def run_many(specs: list, workers: int = 1, out=sys.stdout) -> list:
         raise ValueError("at most 15 child processes (each holds a GPU context)")
     with ThreadPoolExecutor(max_workers=workers) as pool:
         futs = [pool.submit(_run_child, s) for s in specs]
-        return [emit(f.result()) for f in futs]
+        for f in as_completed(futs):  # each result is emitted as soon as it is known
+            emit(f.result())
+        return [f.result() for f in futs]
 
 
 def era_study(n=100, seeds=3, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
