@@ -198,9 +198,14 @@ def time_steps(b: EraBench, steps: int, warmup: int):
 
 
 def sweep(cfg, r, v, m, precision, reps=5):
-    """Single force calls at active fractions 2^-k (k = 0..17), median of reps."""
+    """Single force calls at active fractions 2^-k (k = 0..17), median of reps.  Each entry
+    also gives the call's algorithmic HBM bytes (every source record read once: float64
+    x, y, z and a float32 mass in mixed precision, 28 B; x, y, z, m in float64, 32 B; plus
+    each target's record and its acceleration and potential, 32 B) over its time: the
+    bandwidth view that matters at small active sets, where the pair work is tiny."""
     from paper_1205_2288_amd import Context
     n = cfg.n
+    jb = 28 if precision == "mixed" else 32
     out = []
     with Context(n, cfg.eps, precision=precision) as c:
         c.bind(r, v, m)
@@ -216,8 +221,11 @@ def sweep(cfg, r, v, m, precision, reps=5):
             for _ in range(reps):
                 T("force", c.force, idx, 0.0, acc=acc, pot=pot)
             ms = float(np.median(T.ms()["force"]))
+            nbytes = n * jb + n_act * (jb + 32)
             out.append({"n_active": n_act, "us": round(ms * 1e3, 2),
-                        "interactions_per_s": n_act * n / (ms * 1e-3)})
+                        "interactions_per_s": n_act * n / (ms * 1e-3),
+                        "algorithmic_bytes": nbytes,
+                        "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)})
     return out
 
 
