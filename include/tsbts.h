@@ -373,6 +373,25 @@ int tsbts_sched_era(tsbts_ctx *ctx, double *era_end, hipStream_t stream);
 int tsbts_sched_state(const tsbts_ctx *ctx, int64_t *t_ticks, int64_t *dt_ticks, double *dtc,
                       int64_t *stats, double *time);
 
+/* Host copy of each particle's previous step (the step that brought it to its current
+ * time; 0 before its first step), dtp_ticks [n] int64: with tsbts_sched_state and the
+ * bound r, v, a it makes an era-end checkpoint.  TSBTS_EINVAL without a scheduler. */
+int tsbts_sched_prev_steps(const tsbts_ctx *ctx, int64_t *dtp_ticks);
+
+/* Resume from an era-end checkpoint (Section 2: every era end is a point where the
+ * integration can stop and start again).  The caller first writes the checkpoint's r, v
+ * and a into the bound arrays; this call sets the scheduler's times t_ticks, steps
+ * dt_ticks, previous steps dtp_ticks, criterion values dtc ([n] host arrays, copied),
+ * statistics stats ([4] host, may be NULL: kept) and current time `time` (a multiple of
+ * 2^-20), and writes the bound t_last and dt from them.  The scheduler must have been
+ * started with the same eta, passes, step bounds and era (tsbts_sched_init).  Returns
+ * TSBTS_EINVAL, changing nothing, unless every particle is in an era-end state: steps
+ * powers of two within the bounds, t aligned to the step, t <= time < t + dt, dtp zero or
+ * a power of two not above t, dtc finite and positive.  Synchronises the stream. */
+int tsbts_sched_restore(tsbts_ctx *ctx, const int64_t *t_ticks, const int64_t *dt_ticks,
+                        const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
+                        double time, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,8 @@ _SIGS = {
     "tsbts_sched_init": ([_p, _d, _int, _d, _d, _d, _p], _int),
     "tsbts_sched_era": ([_p, ctypes.POINTER(_d), _p], _int),
     "tsbts_sched_state": ([_p, _p, _p, _p, _p, ctypes.POINTER(_d)], _int),
+    "tsbts_sched_prev_steps": ([_p, _p], _int),
+    "tsbts_sched_restore": ([_p, _p, _p, _p, _p, _p, _d, _p], _int),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -351,3 +353,28 @@ def tsbts_sched_state(ctx, n):
                                       ctypes.c_void_p(dtc.ctypes.data),
                                       ctypes.c_void_p(stats.ctypes.data), ctypes.byref(time)))
     return t, dt, dtc, stats, time.value
+
+
+def tsbts_sched_prev_steps(ctx, n):
+    """Host copy of each particle's previous step (ticks, int64[n])."""
+    import numpy as np
+    dtp = np.empty(n, dtype=np.int64)
+    _check(ctx, lib.tsbts_sched_prev_steps(ctx, ctypes.c_void_p(dtp.ctypes.data)))
+    return dtp
+
+
+def tsbts_sched_restore(ctx, n, t, dt, dtp, dtc, stats, time, stream=None):
+    """Resume the scheduler from an era-end checkpoint (host arrays of n particles, ticks;
+    time in time units); the bound r, v, a must already hold the checkpoint's values."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(x, dtype=dt_) for x, dt_ in
+            ((t, np.int64), (dt, np.int64), (dtp, np.int64), (dtc, np.float64))]
+    if any(a.shape != (n,) for a in arrs):
+        raise ValueError(f"checkpoint arrays must have shape ({n},)")
+    st = None if stats is None else np.ascontiguousarray(stats, dtype=np.int64)
+    if st is not None and st.size != 4:
+        raise ValueError("stats must have 4 entries")
+    _check(ctx, lib.tsbts_sched_restore(
+        ctx, *(ctypes.c_void_p(a.ctypes.data) for a in arrs),
+        None if st is None else ctypes.c_void_p(st.ctypes.data), float(time),
+        _stream(stream)))

@@ -231,7 +231,9 @@ hipError_t run(ForceSymArgs &A, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_force_sym<V, 0>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, cp,
                        rp);
-  launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  // its error check clears the launch error state: keep what it found
+  const hipError_t e = launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_force_sym_reduce<F>,
                      dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)), dim3(kWG), 0, st, A);
   return hipGetLastError();

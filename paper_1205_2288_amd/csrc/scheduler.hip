@@ -466,6 +466,61 @@ int tsbts_sched_option(tsbts_ctx *c, int option, int value) {
   return TSBTS_OK;
 }
 
+int tsbts_sched_prev_steps(const tsbts_ctx *c, int64_t *dtp_ticks) {
+  if (!c || !c->sched || !dtp_ticks) return TSBTS_EINVAL;
+  const Scheduler *S = static_cast<const Scheduler *>(c->sched);
+  std::copy(S->dtp.begin(), S->dtp.end(), dtp_ticks);
+  return TSBTS_OK;
+}
+
+int tsbts_sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_ticks,
+                        const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
+                        double time, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  Scheduler *S = static_cast<Scheduler *>(c->sched);
+  if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_restore: call tsbts_sched_init first");
+  if (!t_ticks || !dt_ticks || !dtp_ticks || !dtc)
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_restore: null state array");
+  const double k_time = time / tsbts::kTick;
+  if (!(k_time >= 0.0) || k_time != std::floor(k_time) || k_time > 9.0e15)
+    return sfail(c, TSBTS_EINVAL, "tsbts_sched_restore: time is not a multiple of 2^-20");
+  const int64_t T = static_cast<int64_t>(k_time);
+  const int64_t n = S->n;
+  auto pow2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t ti = t_ticks[i], di = dt_ticks[i], pi = dtp_ticks[i];
+    // an era end: every particle aligned to its step, at or before T, next time after T
+    const bool ok = pow2(di) && di >= S->dt_min && di <= S->dt_max && ti >= 0 && ti <= T &&
+                    ti % di == 0 && ti + di > T && (pi == 0 || (pow2(pi) && pi <= ti)) &&
+                    std::isfinite(dtc[i]) && dtc[i] > 0.0;
+    if (!ok) {
+      snprintf(c->err, sizeof(c->err),
+               "tsbts_sched_restore: particle %lld is not in an era-end state",
+               static_cast<long long>(i));
+      return TSBTS_EINVAL;
+    }
+  }
+  S->t.assign(t_ticks, t_ticks + n);
+  S->dt.assign(dt_ticks, dt_ticks + n);
+  S->dtp.assign(dtp_ticks, dtp_ticks + n);
+  S->dtc.assign(dtc, dtc + n);
+  S->time = T;
+  if (stats) std::copy(stats, stats + 4, S->stats);
+  S->have_prev = false;
+  // device copies of the times and steps (the bound t_last and dt), staged through the
+  // pinned buffers; no step update of an earlier block step can still be reading them
+  SCHED_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    S->dtn_h[i] = static_cast<double>(S->dt[i]) * tsbts::kTick;
+    S->dtc_h[i] = static_cast<double>(S->t[i]) * tsbts::kTick;
+  }
+  SCHED_HIP(hipMemcpyAsync(c->dt, S->dtn_h, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  SCHED_HIP(hipMemcpyAsync(c->t_last, S->dtc_h, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  SCHED_HIP(hipStreamSynchronize(st));
+  S->rebuild_levels();
+  return TSBTS_OK;
+}
+
 int tsbts_sched_state(const tsbts_ctx *c, int64_t *t_ticks, int64_t *dt_ticks, double *dtc,
                       int64_t *stats, double *time) {
   if (!c || !c->sched) return TSBTS_EINVAL;

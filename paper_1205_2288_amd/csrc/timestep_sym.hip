@@ -183,7 +183,9 @@ hipError_t run(StepSymArgs &A, hipStream_t st) {
   using F = typename V::F;
   hipLaunchKernelGGL((k_timestep_sym<V>), dim3(nb), dim3(kWG), 0, st, A, A.p32, A.p64, A.v64,
                      static_cast<F *>(A.plan.col_part), static_cast<F *>(A.plan.row_part));
-  launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  // its error check clears the launch error state: keep what it found
+  const hipError_t e = launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_timestep_sym_reduce<V>), dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)),
                      dim3(kWG), 0, st, A);
   return hipGetLastError();

@@ -377,5 +377,26 @@ class NativeTSBTS:
                 "t": self.t.copy(), "dt": self.dt.copy(), "dtc": self.dtc.copy(),
                 "time": self.time}
 
+    def checkpoint(self) -> dict:
+        """Era-end checkpoint (host arrays; times and steps in ticks): continuing it with
+        restore() in a scheduler built with the same parameters gives the same run, bit
+        for bit.  The dict can be saved with numpy.savez."""
+        ck = self.state()
+        ck["dtp"] = self._L.tsbts_sched_prev_steps(self.ctx.ctx, self.n)
+        ck["stats"] = np.array(self._stats, dtype=np.int64)
+        return ck
+
+    def restore(self, ck) -> None:
+        """Continue from a checkpoint() of a run with the same parameters."""
+        c = self.ctx
+        for name in ("r", "v", "a"):
+            x = np.asarray(ck[name], dtype=np.float64)
+            if x.shape != (3, self.n):
+                raise ValueError(f"checkpoint {name} must have shape (3, {self.n})")
+            getattr(c, name).copy_(torch.from_numpy(x))
+        self._L.tsbts_sched_restore(c.ctx, self.n, ck["t"], ck["dt"], ck["dtp"], ck["dtc"],
+                                    ck.get("stats"), int(ck["time"]) * TICK)
+        self._host()
+
     def close(self):
         self.ctx.close()

@@ -191,3 +191,40 @@ def test_experiments_module_small():
         for kind in ("fixed", "dynamic"):
             assert a[kind]["series_err"] == b[kind]["series_err"]
             assert a[kind]["block_steps"] == b[kind]["block_steps"]
+
+
+@pytest.mark.parametrize("prec,era", [("fp64", 1.0 / 8), ("mixed", None)])
+def test_native_checkpoint_resume_bitwise(prec, era):
+    # an era-end checkpoint, saved through numpy's npz format and restored into a fresh
+    # scheduler, continues the run bit for bit (fixed and dynamic eras)
+    import io
+    from paper_1205_2288_amd._lib import TsbtsError
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=cfg.eta, passes=3, era=era, dt_max=cfg.dt_max, dt_min=cfg.dt_min,
+              precision=prec)
+    full = NativeTSBTS(r, v, m, cfg.eps, **kw)
+    e_full = full.run(0.5, energy_every=1.0 / 8)
+    first = NativeTSBTS(r, v, m, cfg.eps, **kw)
+    first.run(0.25, energy_every=1.0 / 8)
+    ck = first.checkpoint()
+    first.close()
+    buf = io.BytesIO()
+    np.savez(buf, **ck)
+    buf.seek(0)
+    with np.load(buf) as z:
+        ck = {k: z[k] for k in z.files}
+    second = NativeTSBTS(r, v, m, cfg.eps, **kw)
+    bad = dict(ck, t=ck["t"] + 1)  # no longer aligned to the steps: refused
+    with pytest.raises(TsbtsError):
+        second.restore(bad)
+    second.restore(ck)
+    e_second = second.run(0.5, energy_every=1.0 / 8)
+    a, b = full.checkpoint(), second.checkpoint()
+    for key in ("r", "v", "a", "t", "dt", "dtp", "dtc", "stats"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["time"] == b["time"]
+    assert e_second == [x for x in e_full if x[0] >= 0.25]
+    full.close()
+    second.close()
