@@ -74,6 +74,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
 #define TSBTS_TUNE_IPL 2
 #define TSBTS_TUNE_CHUNK 3
 #define TSBTS_TUNE_SYMMETRIC 4
+#define TSBTS_TUNE_CHECK_INDICES 5
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
  *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
@@ -91,6 +92,12 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      bit-identical; sums are combined in another fixed order.  The
  *                      first such call on a context allocates its work list and partial
  *                      buffers.
+ *   TSBTS_TUNE_CHECK_INDICES: 1 = every call that takes active_idx first checks on the
+ *                      device that each index lies in [0, n), synchronises the stream and
+ *                      returns TSBTS_EINVAL, with nothing else launched, if one does not
+ *                      (a debugging aid: one extra launch and one synchronisation per
+ *                      call); 0 = indices trusted (default; an index outside [0, n) is
+ *                      then undefined behaviour).
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);
@@ -136,7 +143,8 @@ int tsbts_load_positions(tsbts_ctx *ctx, const double *r, const double *m, doubl
  *   acc_i =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2)
  *   pot_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps^2)^(1/2)
  *   active_idx [n_active] int32   particle indices in [0, n) (any order, no duplicates
- *                                 required by the physics, not checked)
+ *                                 required by the physics, not checked; the range is
+ *                                 checked with TSBTS_TUNE_CHECK_INDICES)
  *   acc        [3][n_active]      float64 output, row k for particle active_idx[k]
  *   pot        [n_active]         float64 output, or NULL to skip
  * 1 <= n_active <= n.  The sum over j is split over workgroups when the active set is small

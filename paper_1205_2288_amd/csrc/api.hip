@@ -61,11 +61,33 @@ void dev_free(T *&p) {
 
 int check_ctx(const tsbts_ctx *c) { return c ? TSBTS_OK : TSBTS_EINVAL; }
 
-int check_active(tsbts_ctx *c, const int32_t *idx, int32_t n_act) {
+// Flags an active index outside [0, n) (reads the index list only).
+__global__ __launch_bounds__(kWG) void k_check_idx(const int32_t *idx, int32_t n_act, int64_t n,
+                                                   int *flag) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (k < n_act) {
+    const int32_t v = idx[k];
+    if (v < 0 || v >= n) *flag = 1;
+  }
+}
+
+int check_active(tsbts_ctx *c, const int32_t *idx, int32_t n_act, hipStream_t stream) {
   if (!idx) return fail(c, TSBTS_EINVAL, "active_idx is NULL");
   if (n_act < 1 || n_act > c->n)
     return fail(c, TSBTS_EINVAL, "n_active=%d outside [1, %lld]", n_act,
                 static_cast<long long>(c->n));
+  if (c->check_idx) {
+    // every earlier use of the flag ended with a synchronisation, so it is free here
+    *c->idx_flag_h = 0;
+    hipLaunchKernelGGL(k_check_idx, dim3((n_act + kWG - 1) / kWG), dim3(kWG), 0, stream, idx,
+                       n_act, c->n, c->idx_flag_d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "active index check");
+    if (*c->idx_flag_h)
+      return fail(c, TSBTS_EINVAL, "active_idx holds an index outside [0, %lld)",
+                  static_cast<long long>(c->n));
+  }
   return TSBTS_OK;
 }
 
@@ -246,6 +268,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   dev_free(c->gord);
   if (c->sym_items) (void)hipFree(c->sym_items);
   if (c->sym_part) (void)hipFree(c->sym_part);
+  if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
   dev_free(c->h.pid);
   dev_free(c->h.rank);
   dev_free(c->h.t);
@@ -280,6 +303,22 @@ int tsbts_tune(tsbts_ctx *c, int param, int value) {
     case TSBTS_TUNE_SYMMETRIC:
       if (value < 0 || value > 2) return fail(c, TSBTS_EINVAL, "symmetric must be 0, 1 or 2");
       c->tune_sym = value;
+      return TSBTS_OK;
+    case TSBTS_TUNE_CHECK_INDICES:
+      if (value != 0 && value != 1) return fail(c, TSBTS_EINVAL, "check must be 0 or 1");
+      if (value && !c->idx_flag_h) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->idx_flag_h), sizeof(int));
+        if (e == hipSuccess)
+          e = hipHostGetDevicePointer(reinterpret_cast<void **>(&c->idx_flag_d), c->idx_flag_h,
+                                      0);
+        if (e != hipSuccess) {
+          if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
+          c->idx_flag_h = nullptr;
+          c->idx_flag_d = nullptr;
+          return hip_fail(c, e, "index check flag");
+        }
+      }
+      c->check_idx = value;
       return TSBTS_OK;
     default:
       return fail(c, TSBTS_EINVAL, "unknown tuning parameter %d", param);
@@ -329,7 +368,7 @@ int tsbts_load_positions(tsbts_ctx *c, const double *r, const double *m, double 
 int tsbts_force(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block, double *acc,
                 double *pot, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
@@ -343,7 +382,7 @@ int tsbts_force_criterion(tsbts_ctx *c, const int32_t *idx, int32_t n_act, doubl
                           double eta, double *acc, double *pot, double *dtc,
                           hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
   if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
   if (int s = check_pred(c, t_block)) return s;
@@ -366,7 +405,7 @@ int tsbts_force_backward(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double
                          const double *ga, const double *gp, double *gr, double *gm,
                          hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!ga || !gr || !gm) return fail(c, TSBTS_EINVAL, "tsbts_force_backward: NULL array");
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, backward_partials_needed(c, n_act))) return s;
@@ -383,7 +422,7 @@ int tsbts_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
                   const double *acc_new, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc_new) return fail(c, TSBTS_EINVAL, "acc_new is NULL");
   if (int s = check_pred(c, t_block)) return s;
   if (c->h.recording) {
@@ -401,7 +440,7 @@ int tsbts_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
 int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, double *dtc,
                    hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!dtc) return fail(c, TSBTS_EINVAL, "dtc is NULL");
   if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TSBTS_EINVAL, "eta must be > 0");
   if (!c->have_pred) return fail(c, TSBTS_ESTATE, "no predicted particle arrays");
@@ -420,7 +459,7 @@ int tsbts_set_dt(tsbts_ctx *c, const int32_t *idx, int32_t n_act, const double *
                  hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!dt_new) return fail(c, TSBTS_EINVAL, "dt_new is NULL");
   hipError_t e = launch_set_dt(c, idx, n_act, dt_new, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_set_dt launch");
@@ -510,7 +549,7 @@ int tsbts_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int32_t n_a
   if (!rbar || !vbar || !abar || !pbar)
     return fail(c, TSBTS_EINVAL, "tsbts_block_adjoint: NULL array");
   if (phase == 0) {
-    if (int s = check_active(c, idx, n_act)) return s;
+    if (int s = check_active(c, idx, n_act, stream)) return s;
     if (!seeds) return fail(c, TSBTS_EINVAL, "seeds is NULL");
   }
   hipError_t e = launch_block_adjoint(c, phase, idx, n_act, t_block, rbar, vbar, abar, pbar,
@@ -553,7 +592,7 @@ int tsbts_record_adjoint(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double
                          const int32_t *off, const double *t, int64_t n_records,
                          const double *hbar, double *rbar, double *vbar, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!off || !hbar || !rbar || !vbar || (n_records > 0 && !t))
     return fail(c, TSBTS_EINVAL, "tsbts_record_adjoint: NULL array");
   if (n_records < 0) return fail(c, TSBTS_EINVAL, "n_records < 0");
@@ -588,7 +627,7 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
                   double *acc, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, partial_elems_needed(c, n_act))) return s;
@@ -613,7 +652,7 @@ int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
                             int use_history, double *acc, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
   if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
   if (n_act > small_act_limit(c))
@@ -644,7 +683,7 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
                             double eta, double *acc, double *dtc, hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act)) return s;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
   if (!acc || !dtc) return fail(c, TSBTS_EINVAL, "acc or dtc is NULL");
   if (int s = check_pred(c, t_block)) return s;
   if (int s = ensure_part(c, std::max(fused_partials_needed(c, n_act),

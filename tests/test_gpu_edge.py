@@ -118,3 +118,34 @@ def test_criterion_bulk_motion(prec, n, n_act):
     assert np.array_equal(ref, oracle.timestep(r, vz, m, eps, eta, idx))  # velocity-free
     assert np.allclose(dtc, ref, rtol=1e-12 if prec == "fp64" else 2e-6)
     ctx.close()
+
+
+def test_index_check_mode():
+    # TSBTS_TUNE_CHECK_INDICES: a device active set with an index outside [0, n) is refused
+    # before any kernel uses it; valid sets give the same results as without the check.
+    # The bad index is n itself, which lies in the arrays' padding, so nothing could be
+    # touched outside them even without the check.
+    from paper_1205_2288_amd._lib import TsbtsError
+    n = 1000
+    r, v, m = plummer(n, 3)
+    ctx = make_ctx(n, 0.01, "mixed")
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    good = ctx.idx(np.arange(0, n, 3, dtype=np.int32))
+    acc_ref, _ = ctx.force(good, 0.0)
+    dtc_ref = ctx.timestep(good, 0.1)
+    ctx.tune(check_indices=1)
+    acc, _ = ctx.force(good, 0.0)
+    assert torch.equal(acc, acc_ref)
+    assert torch.equal(ctx.timestep(good, 0.1), dtc_ref)
+    bad = torch.tensor([0, 5, n], dtype=torch.int32, device=ctx.device)
+    with pytest.raises(TsbtsError, match="outside"):
+        ctx.force(bad, 0.0)
+    with pytest.raises(TsbtsError, match="outside"):
+        ctx.timestep(bad, 0.1)
+    acc, _ = ctx.force(good, 0.0)  # still usable after a refusal
+    assert torch.equal(acc, acc_ref)
+    with pytest.raises(TsbtsError):
+        ctx.tune(check_indices=2)
+    ctx.tune(check_indices=0)
+    ctx.close()
