@@ -26,6 +26,7 @@ and applies the step-size rules, vectorised over the active set:
 """
 from __future__ import annotations
 
+import json
 import time
 
 import numpy as np
@@ -91,6 +92,54 @@ class CriterionHistory:
         w = np.where(has_next, (t - tk) / np.where(has_next, t1 - tk, 1), 0.0)
         lin = (1.0 - w) * self.c[k] + w * self.c[k1]
         return np.where(tk == t, self.c[k], np.where(has_next, lin, fallback))
+
+
+def _run_loop(sim, t_end: float, energy_every, log):
+    """Run loop of both schedulers: eras up to t_end, the float64 energy at every era end
+    that is a multiple of energy_every (default dt_max), where all particles are
+    synchronised.  A non-finite energy stops the run with the time and era.  With a log
+    stream, each energy sample also writes one JSON line: t, E, the energy error relative
+    to the first energy this scheduler measured, block steps, force calls, interactions,
+    eras, particle-eras left out of their era since the previous sample, the number of
+    particles per step size 2^-k and the wall time of this call."""
+    stop = to_ticks(t_end)
+    every = sim.dt_max if energy_every is None else to_ticks(energy_every)
+    t0 = time.perf_counter()
+    excluded = 0
+
+    def sample(T, E):
+        if not np.isfinite(E):
+            raise FloatingPointError(f"energy is not finite at t = {T * TICK} "
+                                     f"(after era {sim.stats['eras']})")
+        if not hasattr(sim, "_e_first"):
+            sim._e_first = E
+        if log is not None:
+            st = sim.stats
+            ks, counts = np.unique(TICK_BITS - np.log2(sim.dt).astype(np.int64),
+                                   return_counts=True)
+            rec = {"t": T * TICK, "E": E,
+                   "rel_dE": (E - sim._e_first) / abs(sim._e_first),
+                   "block_steps": st["block_steps"], "force_calls": st["force_calls"],
+                   "interactions": st["interactions"], "eras": st["eras"],
+                   "excluded": excluded,
+                   "levels": {str(int(k)): int(c) for k, c in zip(ks, counts)},
+                   "wall_s": time.perf_counter() - t0}
+            log.write(json.dumps(rec) + "\n")
+            log.flush()
+        return (T * TICK, E)
+
+    out = [sample(sim.time, sim.energy())]
+    while sim.time < stop:
+        T1 = sim.era_step()
+        if log is not None:
+            excluded += int(np.count_nonzero(sim.t != T1))
+        if T1 % every == 0:
+            if not np.all(sim.t == T1):
+                raise RuntimeError("particles not synchronised at a dt_max multiple")
+            out.append(sample(T1, sim.energy()))
+            excluded = 0
+    sim.ctx.synchronize()
+    return out
 
 
 class TSBTS:
@@ -273,20 +322,12 @@ class TSBTS:
         kw = self.ctx.energy(out=self._ek_d).cpu().numpy()
         return float(kw[0] + kw[1])
 
-    def run(self, t_end: float, energy_every: float | None = None):
+    def run(self, t_end: float, energy_every: float | None = None, log=None):
         """Integrate to t_end; return [(t, E)] at era ends that are multiples of
-        energy_every (default dt_max), where every particle is synchronised."""
-        stop = to_ticks(t_end)
-        every = self.dt_max if energy_every is None else to_ticks(energy_every)
-        out = [(self.time * TICK, self.energy())]
+        energy_every (default dt_max), where every particle is synchronised.  log: a
+        text stream receiving one JSON line of run metrics per energy sample."""
         t0 = time.perf_counter()
-        while self.time < stop:
-            T1 = self.era_step()
-            if T1 % every == 0:
-                if not np.all(self.t == T1):
-                    raise RuntimeError("particles not synchronised at a dt_max multiple")
-                out.append((T1 * TICK, self.energy()))
-        self.ctx.synchronize()
+        out = _run_loop(self, t_end, energy_every, log)
         self.stats["wall_s"] += time.perf_counter() - t0
         return out
 
@@ -355,18 +396,10 @@ class NativeTSBTS:
         kw = self.ctx.energy(out=self._ek).cpu().numpy()
         return float(kw[0] + kw[1])
 
-    def run(self, t_end: float, energy_every: float | None = None):
-        stop = to_ticks(t_end)
-        every = self.dt_max if energy_every is None else to_ticks(energy_every)
-        out = [(self.time * TICK, self.energy())]
+    def run(self, t_end: float, energy_every: float | None = None, log=None):
+        """As TSBTS.run."""
         t0 = time.perf_counter()
-        while self.time < stop:
-            T1 = self.era_step()
-            if T1 % every == 0:
-                if not np.all(self.t == T1):
-                    raise RuntimeError("particles not synchronised at a dt_max multiple")
-                out.append((T1 * TICK, self.energy()))
-        self.ctx.synchronize()
+        out = _run_loop(self, t_end, energy_every, log)
         self.wall_s += time.perf_counter() - t0
         return out
 

@@ -129,3 +129,28 @@ def test_native_rule_matches_oracle_rules():
         ref = s._new_step(0, tb, begin, None if first else h)
         got = L.tsbts_sched_rule(first, dt, tb, begin, ends[dt], ends[2 * dt], 1, DTMAX)
         assert got == ref, (trial, dt, tb, begin, ends)
+
+
+def test_run_log_and_nonfinite_energy():
+    # the run loop's JSON metrics (one line per energy sample) and its stop on a
+    # non-finite energy
+    import io
+    import json
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=cfg.eta, passes=2, era=cfg.era, dt_max=cfg.dt_max, dt_min=cfg.dt_min)
+    prod = TSBTS(r, v, m, cfg.eps, context=FakeContext(cfg.n, cfg.eps), **kw)
+    buf = io.StringIO()
+    series = prod.run(0.25, energy_every=0.125, log=buf)
+    recs = [json.loads(x) for x in buf.getvalue().splitlines()]
+    assert [x["t"] for x in recs] == [t for t, _ in series] == [0.0, 0.125, 0.25]
+    assert [x["E"] for x in recs] == [e for _, e in series]
+    assert recs[0]["rel_dE"] == 0.0 and recs[0]["block_steps"] == 0
+    assert recs[-1]["block_steps"] == prod.stats["block_steps"]
+    assert recs[-1]["eras"] == prod.stats["eras"] == 2
+    for x in recs:
+        assert sum(x["levels"].values()) == cfg.n and x["excluded"] == 0
+        assert all(6 <= int(k) <= 20 for k in x["levels"])
+    prod.energy = lambda: float("nan")
+    with pytest.raises(FloatingPointError, match="not finite"):
+        prod.run(0.5, energy_every=0.125)
