@@ -55,14 +55,16 @@ __device__ __forceinline__ void pair_bwd_sym(const typename V::I &i, typename V:
   const F y2 = y * y;
   const F y3 = y2 * y;
   const F mj = V::mass(j);
+  // the masses enter only through y^3 m_k and y^3 m_j
+  const F P = y3 * mi, Q = y3 * mj;
   const F uj = fma(ex, gj[0], fma(ey, gj[1], ez * gj[2]));
   const F ui = fma(ex, gi[0], fma(ey, gi[1], ez * gi[2]));
-  const F a = fma(mi, uj, -(mj * ui));
-  const F gs = fma(mi, gj[3], mj * gi[3]);
-  const F c = y3 * fma(F(-3) * y2, a, -gs);
-  const F tx = fma(y3, fma(mi, gj[0], -(mj * gi[0])), c * ex);
-  const F ty = fma(y3, fma(mi, gj[1], -(mj * gi[1])), c * ey);
-  const F tz = fma(y3, fma(mi, gj[2], -(mj * gi[2])), c * ez);
+  const F a3 = fma(P, uj, -(Q * ui));        // y^3 (m_k u_j - m_j u_k)
+  const F gs3 = fma(P, gj[3], Q * gi[3]);    // y^3 (m_k gp_j + m_j gp_k)
+  const F c = fma(F(-3) * y2, a3, -gs3);
+  const F tx = fma(P, gj[0], fma(-Q, gi[0], c * ex));
+  const F ty = fma(P, gj[1], fma(-Q, gi[1], c * ey));
+  const F tz = fma(P, gj[2], fma(-Q, gi[2], c * ez));
   acc[0] += tx;
   acc[1] += ty;
   acc[2] += tz;
