@@ -420,15 +420,19 @@ class NativeTSBTS:
         return ck
 
     def restore(self, ck) -> None:
-        """Continue from a checkpoint() of a run with the same parameters."""
+        """Continue from a checkpoint() of a run with the same parameters.  A checkpoint
+        that is not an era-end state is refused before anything changes."""
         c = self.ctx
+        xs = {}
         for name in ("r", "v", "a"):
-            x = np.asarray(ck[name], dtype=np.float64)
-            if x.shape != (3, self.n):
+            xs[name] = np.ascontiguousarray(ck[name], dtype=np.float64)
+            if xs[name].shape != (3, self.n):
                 raise ValueError(f"checkpoint {name} must have shape (3, {self.n})")
-            getattr(c, name).copy_(torch.from_numpy(x))
+        # validates the times and steps, then sets them (and the bound t_last, dt)
         self._L.tsbts_sched_restore(c.ctx, self.n, ck["t"], ck["dt"], ck["dtp"], ck["dtc"],
                                     ck.get("stats"), int(ck["time"]) * TICK)
+        for name, x in xs.items():
+            getattr(c, name).copy_(torch.from_numpy(x))
         self._host()
 
     def close(self):

@@ -216,9 +216,18 @@ def test_native_checkpoint_resume_bitwise(prec, era):
     with np.load(buf) as z:
         ck = {k: z[k] for k in z.files}
     second = NativeTSBTS(r, v, m, cfg.eps, **kw)
+    before = second.checkpoint()
     bad = dict(ck, t=ck["t"] + 1)  # no longer aligned to the steps: refused
     with pytest.raises(TsbtsError):
         second.restore(bad)
+    bad = dict(ck, dt=np.where(np.arange(cfg.n) == 7, 3, ck["dt"]))  # not a power of two
+    with pytest.raises(TsbtsError, match="particle 7"):
+        second.restore(bad)
+    with pytest.raises(ValueError):
+        second.restore(dict(ck, r=ck["r"][:, :-1]))
+    after = second.checkpoint()  # the refusals changed nothing
+    for key in ("r", "v", "a", "t", "dt", "dtp", "dtc", "stats"):
+        assert np.array_equal(before[key], after[key]), key
     second.restore(ck)
     e_second = second.run(0.5, energy_every=1.0 / 8)
     a, b = full.checkpoint(), second.checkpoint()
