@@ -395,7 +395,8 @@ int tsbts_sched_prev_steps(const tsbts_ctx *ctx, int64_t *dtp_ticks);
  * started with the same eta, passes, step bounds and era (tsbts_sched_init).  Returns
  * TSBTS_EINVAL, changing nothing, unless every particle is in an era-end state: steps
  * powers of two within the bounds, t aligned to the step, t <= time < t + dt, dtp zero or
- * a power of two not above t, dtc finite and positive.  Synchronises the stream. */
+ * a power of two that divides t and is not above it, dtc finite and positive.
+ * Synchronises the stream. */
 int tsbts_sched_restore(tsbts_ctx *ctx, const int64_t *t_ticks, const int64_t *dt_ticks,
                         const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
                         double time, hipStream_t stream);

@@ -491,7 +491,7 @@ int tsbts_sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_
     const int64_t ti = t_ticks[i], di = dt_ticks[i], pi = dtp_ticks[i];
     // an era end: every particle aligned to its step, at or before T, next time after T
     const bool ok = pow2(di) && di >= S->dt_min && di <= S->dt_max && ti >= 0 && ti <= T &&
-                    ti % di == 0 && ti + di > T && (pi == 0 || (pow2(pi) && pi <= ti)) &&
+                    ti % di == 0 && ti + di > T && (pi == 0 || (pow2(pi) && pi <= ti && ti % pi == 0)) &&
                     std::isfinite(dtc[i]) && dtc[i] > 0.0;
     if (!ok) {
       snprintf(c->err, sizeof(c->err),
