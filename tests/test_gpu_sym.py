@@ -278,3 +278,41 @@ def test_plummer131k_symmetric_adjoint(prec):
     for got, ref in ((out[1][0][:, rows], rr), (out[1][1][rows], rm)):
         assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_large_ragged_n_symmetric_paths(prec):
+    # twice the benchmark size and not a multiple of the padding (262147 particles):
+    # criterion bitwise and force / adjoint close to the gather kernels, sampled rows
+    # against the oracle
+    n, eps, eta = 262147, 1 / 4096, 0.1
+    r, v, m = _state(n, 4242)
+    ctx = make_ctx(n, eps, prec)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _perm(n, 17)
+    order = np.argsort(idx)
+    g = torch.tensor(gaussian((3, n), 18), dtype=torch.float64, device="cuda")
+    out = {}
+    for sym in (0, 1):
+        ctx.tune(symmetric=sym)
+        dtc = ctx.timestep(idx, eta).cpu().numpy()
+        acc, _ = ctx.force(idx, 0.0, with_pot=False)
+        gr = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        gm = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.force_backward(idx, 0.0, g, None, gr, gm)
+        out[sym] = (dtc, acc.cpu().numpy(), gr.cpu().numpy(), gm.cpu().numpy())
+    assert np.array_equal(out[0][0], out[1][0])
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    for got, ref in zip(out[1][1:], out[0][1:]):
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    sample = idx[:: n // 64]
+    e = rel_err(out[1][0][order][sample], oracle.timestep(r, v, m, eps, eta, sample))
+    assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), summary(e)
+    ra, _ = oracle.force(r, m, eps, sample.astype(np.int32))
+    e = rel_err_vec(out[1][1][:, order][:, sample], ra)
+    if prec == "fp64":
+        assert e.max() <= 1e-12, summary(e)
+    else:
+        assert np.median(e) <= 1e-6 and e.max() <= 1e-4, summary(e)
+    ctx.close()
