@@ -1,11 +1,15 @@
 // Total energy E = K + W for the energy-error diagnostic (Section 3), in float64:
 //   K =  1/2 sum_i m_i |v_i|^2,   W = -sum_{i<j} m_i m_j (|r_i - r_j|^2 + eps^2)^(-1/2).
-// The upper triangle of 256x256 particle tiles (I <= J) is enumerated one tile pair per
-// workgroup: target i = 256 I + lane in registers, the 256 sources of tile J in LDS, and on
-// diagonal tiles only j > i counts.  Each workgroup reduces its sums in a fixed order into
-// one partial; a single workgroup then adds the partials in a fixed order, so the result
-// is bit-reproducible.  1/sqrt uses the hardware float64 estimate refined by kNewton
-// Newton steps.
+// The upper triangle of 256x256 particle tiles (I <= J) is enumerated in row order and cut
+// into at most kMaxEB contiguous ranges of tile pairs, one per workgroup: for each pair,
+// target i = 256 I + lane in registers, the 256 sources of tile J in LDS, and on diagonal
+// tiles only j > i counts.  Each lane sums its pairs in range order, the workgroup
+// reduces its lanes in a fixed order into one partial, and a single workgroup then adds
+// the partials in a fixed order, so the result is bit-reproducible and the partials take
+// at most 2 kMaxEB float64 values whatever N.  1/sqrt uses the hardware float64 estimate
+// refined by kNewton Newton steps.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace tsbts {
@@ -13,6 +17,7 @@ namespace {
 
 constexpr int kTE = 256;
 constexpr int kNewton = 1;
+constexpr int64_t kMaxEB = 8192;  // workgroups (and partials) of the pair kernel
 
 struct EnergyArgs {
   int64_t n;
@@ -20,7 +25,8 @@ struct EnergyArgs {
   double eps2;
   int64_t T;       // tile rows
   int64_t ntp;     // tile pairs T (T + 1) / 2
-  double *part;    // [ntp][2]
+  int64_t nb;      // workgroups: min(ntp, kMaxEB)
+  double *part;    // [nb][2]
   double *out;
 };
 
@@ -41,59 +47,65 @@ __global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
   __shared__ SRec sj[kTE];
   __shared__ double red[2][kWG / 64];
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  int64_t I, J;
-  tile_pair(b, A.T, I, J);
   const int64_t n = A.n;
-  const int64_t i = I * kTE + tid;
-  const int64_t j = J * kTE + tid;
-  SRec rec;
-  if (j < n) {
-    rec.x = A.r[j];
-    rec.y = A.r[n + j];
-    rec.z = A.r[2 * n + j];
-    rec.m = A.m[j];
-  } else {
-    rec.x = rec.y = rec.z = kFar;
-    rec.m = 0.0;
-  }
-  sj[tid] = rec;
-  double xi = kFar, yi = kFar, zi = kFar, mi = 0.0, ki = 0.0;
-  if (i < n) {
-    xi = A.r[i];
-    yi = A.r[n + i];
-    zi = A.r[2 * n + i];
-    mi = A.m[i];
-    if (I == J) {
-      const double vx = A.v[i], vy = A.v[n + i], vz = A.v[2 * n + i];
-      ki = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+  // this workgroup's contiguous range of tile pairs
+  const int64_t b0 = blockIdx.x * A.ntp / A.nb, b1 = (blockIdx.x + 1) * A.ntp / A.nb;
+  double pw = 0.0, pk = 0.0;
+  for (int64_t b = b0; b < b1; ++b) {
+    int64_t I, J;
+    tile_pair(b, A.T, I, J);
+    const int64_t i = I * kTE + tid;
+    const int64_t j = J * kTE + tid;
+    SRec rec;
+    if (j < n) {
+      rec.x = A.r[j];
+      rec.y = A.r[n + j];
+      rec.z = A.r[2 * n + j];
+      rec.m = A.m[j];
+    } else {
+      rec.x = rec.y = rec.z = kFar;
+      rec.m = 0.0;
     }
-  }
-  __syncthreads();
-  double w = 0.0;
-  if (i >= n) {
-    // padding target: contributes nothing (and must not meet padding sources at d = 0)
-  } else if (I != J) {
+    __syncthreads();  // the previous pair's sources are no longer read
+    sj[tid] = rec;
+    double xi = kFar, yi = kFar, zi = kFar, mi = 0.0;
+    if (i < n) {
+      xi = A.r[i];
+      yi = A.r[n + i];
+      zi = A.r[2 * n + i];
+      mi = A.m[i];
+      if (I == J) {
+        const double vx = A.v[i], vy = A.v[n + i], vz = A.v[2 * n + i];
+        pk += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+      }
+    }
+    __syncthreads();
+    double w = 0.0;
+    if (i >= n) {
+      // padding target: contributes nothing (and must not meet padding sources at d = 0)
+    } else if (I != J) {
 #pragma unroll 4
-    for (int jj = 0; jj < kTE; ++jj) {
-      const SRec s = sj[jj];
-      const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-      const double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
-      w = fma(s.m, rsqrt_f64<kNewton>(q), w);
+      for (int jj = 0; jj < kTE; ++jj) {
+        const SRec s = sj[jj];
+        const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        const double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
+        w = fma(s.m, rsqrt_f64<kNewton>(q), w);
+      }
+    } else {
+      for (int jj = 0; jj < kTE; ++jj) {
+        const SRec s = sj[jj];
+        const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
+        const bool upper = jj > tid;
+        q = upper ? q : 1.0;
+        const double mj = upper ? s.m : 0.0;
+        w = fma(mj, rsqrt_f64<kNewton>(q), w);
+      }
     }
-  } else {
-    for (int jj = 0; jj < kTE; ++jj) {
-      const SRec s = sj[jj];
-      const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-      double q = fma(dx, dx, fma(dy, dy, fma(dz, dz, A.eps2)));
-      const bool upper = jj > tid;
-      q = upper ? q : 1.0;
-      const double mj = upper ? s.m : 0.0;
-      w = fma(mj, rsqrt_f64<kNewton>(q), w);
-    }
+    pw = fma(mi, w, pw);
   }
-  double pw = wave_sum(mi * w);
-  double pk = wave_sum(ki);
+  pw = wave_sum(pw);
+  pk = wave_sum(pk);
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = pw;
     red[1][tid >> 6] = pk;
@@ -105,8 +117,8 @@ __global__ __launch_bounds__(kWG) void k_energy_pairs(EnergyArgs A) {
       sw += red[0][k];
       sk += red[1][k];
     }
-    A.part[2 * b] = sw;
-    A.part[2 * b + 1] = sk;
+    A.part[2 * blockIdx.x] = sw;
+    A.part[2 * blockIdx.x + 1] = sk;
   }
 }
 
@@ -115,7 +127,7 @@ __global__ __launch_bounds__(kRedWG) void k_energy_reduce(EnergyArgs A) {
   __shared__ double sw[kRedWG], sk[kRedWG];
   const int t = threadIdx.x;
   double w = 0.0, k = 0.0;
-  for (int64_t b = t; b < A.ntp; b += kRedWG) {
+  for (int64_t b = t; b < A.nb; b += kRedWG) {
     w += A.part[2 * b];
     k += A.part[2 * b + 1];
   }
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(kRedWG) void k_energy_reduce(EnergyArgs A) {
 
 int64_t energy_partials_needed(const tsbts_ctx *c) {
   const int64_t T = (c->n + kTE - 1) / kTE;
-  return T * (T + 1);  // two doubles per tile pair
+  return 2 * std::min<int64_t>(T * (T + 1) / 2, kMaxEB);  // two doubles per workgroup
 }
 
 hipError_t launch_energy(tsbts_ctx *c, const double *r, const double *v, const double *m,
@@ -152,9 +164,10 @@ hipError_t launch_energy(tsbts_ctx *c, const double *r, const double *v, const d
   A.eps2 = c->eps * c->eps;
   A.T = (c->n + kTE - 1) / kTE;
   A.ntp = A.T * (A.T + 1) / 2;
+  A.nb = std::min<int64_t>(A.ntp, kMaxEB);
   A.part = c->epart;
   A.out = out;
-  hipLaunchKernelGGL(k_energy_pairs, dim3(static_cast<unsigned>(A.ntp)), dim3(kWG), 0, st, A);
+  hipLaunchKernelGGL(k_energy_pairs, dim3(static_cast<unsigned>(A.nb)), dim3(kWG), 0, st, A);
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(kRedWG), 0, st, A);
   return hipGetLastError();
 }
