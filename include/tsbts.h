@@ -153,6 +153,33 @@ int tsbts_load_positions(tsbts_ctx *ctx, const double *r, const double *m, doubl
 int tsbts_force(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active, double t_block,
                 double *acc, double *pot, hipStream_t stream);
 
+/* Float64 values in the fixed device array of tsbts_force_noalloc (64 MiB per GPU). */
+#define TSBTS_NOALLOC_PARTIALS (1 << 23)
+
+/* For callers that cannot allocate device memory (work under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tsbts_force with the split-j partial
+ * sums in a fixed device array of TSBTS_NOALLOC_PARTIALS float64 values instead of the
+ * context's buffer.  The call allocates and frees nothing (no hipMalloc, hipFree or
+ * allocating library routine); the array is part of the library's code object, held by
+ * every GPU the library runs on until the process ends, and its address is looked up
+ * once per device by the first tsbts_create there.
+ * Arguments, checks and outputs are those of tsbts_force.  Differences:
+ *   - the all-targets symmetric kernels are never used (their partials are about N^2/64
+ *     bytes); the gather kernels serve every call;
+ *   - the split of the j-sum is tsbts_force's when its partials fit the array, otherwise
+ *     it aims for fewer workgroups (halving until they fit); results are then equal to
+ *     tsbts_force's within rounding (another fixed order of float64 tile sums), and bit
+ *     for bit whenever tsbts_force also takes the gather kernels with the same split;
+ *   - a call that cannot fit at all (n_active <= 32, or <= 16 in TSBTS_FP64, needs
+ *     4 * n_active partials per 256 particles: beyond 2^24 particles) returns
+ *     TSBTS_EINVAL with nothing enqueued.
+ * Every call on one GPU shares that GPU's array and leaves its partials there (each value
+ * a call reads is written earlier in the same call, so nothing needs clearing): calls
+ * that overlap on one GPU (other streams, contexts or host threads) race and give
+ * undefined results; serialise them. */
+int tsbts_force_noalloc(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active,
+                        double t_block, double *acc, double *pot, hipStream_t stream);
+
 /* Vector-Jacobian product of tsbts_force at the same arrays and time (the adjoint used for
  * gradients; not in the paper).  Given grad_acc = dL/dacc [3][n_active] and optionally
  * grad_pot = dL/dpot [n_active] (NULL = zero), ADDS dL/dr into grad_r [3][n] and dL/dm into

@@ -57,6 +57,7 @@ _SIGS = {
     "tsbts_predict": ([_p, _d, _int, _p], _int),
     "tsbts_load_positions": ([_p, _p, _p, _d, _p], _int),
     "tsbts_force": ([_p, _p, _i32, _d, _p, _p, _p], _int),
+    "tsbts_force_noalloc": ([_p, _p, _i32, _d, _p, _p, _p], _int),
     "tsbts_force_criterion": ([_p, _p, _i32, _d, _d, _p, _p, _p, _p], _int),
     "tsbts_sched_option": ([_p, _int, _int], _int),
     "tsbts_force_backward": ([_p, _p, _i32, _d, _p, _p, _p, _p, _p], _int),
@@ -202,6 +203,16 @@ def tsbts_force(ctx, active_idx, t_block, acc, pot=None, stream=None):
     _check(ctx, lib.tsbts_force(ctx, _i32p(active_idx), k, float(t_block),
                                 _f64(acc, (3, k), "acc"), _f64(pot, (k,), "pot"),
                                 _stream(stream)))
+
+
+TSBTS_NOALLOC_PARTIALS = 1 << 23
+
+
+def tsbts_force_noalloc(ctx, active_idx, t_block, acc, pot=None, stream=None):
+    k = active_idx.numel()
+    _check(ctx, lib.tsbts_force_noalloc(ctx, _i32p(active_idx), k, float(t_block),
+                                        _f64(acc, (3, k), "acc"), _f64(pot, (k,), "pot"),
+                                        _stream(stream)))
 
 
 def tsbts_force_backward(ctx, n, active_idx, t_block, grad_acc, grad_pot, grad_r, grad_m,

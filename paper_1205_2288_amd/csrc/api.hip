@@ -229,6 +229,12 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
     delete c;
     return TSBTS_EHIP;
   }
+  // the fixed partial-sum array of tsbts_force_noalloc on this device (once per device)
+  if (noalloc_setup(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return TSBTS_EHIP;
+  }
   int st = TSBTS_OK;
   if (!st) st = dev_alloc(c, &c->p64, P64_PLANES * c->npad);
   if (!st) st = dev_alloc(c, &c->v64, 3 * c->npad);
@@ -375,6 +381,34 @@ int tsbts_force(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
   if (int s = prepare_force_sym(c, n_act)) return s;
   hipError_t e = launch_force(c, idx, n_act, acc, pot, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_force launch");
+  return TSBTS_OK;
+}
+
+int tsbts_force_noalloc(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
+                        double *acc, double *pot, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_active(c, idx, n_act, stream)) return s;
+  if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
+  if (int s = check_pred(c, t_block)) return s;
+  double *part = noalloc_partials(c->device);
+  if (!part)
+    return fail(c, TSBTS_ESTATE, "tsbts_force_noalloc: no fixed partial array on device %d",
+                c->device);
+  // tsbts_force's split when its partials fit the array, else fewer workgroups
+  int blocks = c->tune_blocks;
+  int64_t need = force_partial_elems(c, n_act, blocks);
+  while (need > TSBTS_NOALLOC_PARTIALS && blocks > 64) {
+    blocks = std::max(64, blocks / 2);
+    need = force_partial_elems(c, n_act, blocks);
+  }
+  if (need > TSBTS_NOALLOC_PARTIALS)
+    return fail(c, TSBTS_EINVAL,
+                "tsbts_force_noalloc: the call needs %lld partial sums, more than the fixed "
+                "array's %lld (n_active <= %d needs 4 * n_active per 256 particles)",
+                static_cast<long long>(need), static_cast<long long>(TSBTS_NOALLOC_PARTIALS),
+                small_act_limit(c));
+  hipError_t e = launch_force_gather(c, idx, n_act, acc, pot, part, blocks, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tsbts_force_noalloc launch");
   return TSBTS_OK;
 }
 

@@ -488,31 +488,32 @@ SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_bl
   return p;
 }
 
-int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
-  const int64_t n_jtiles = c->npad / kTJ;
-  // small sets: one partial per j-tile; the criterion uses the same plans with 2 values
-  // per target instead of 4
-  if (n_act <= kSmallAct) return n_jtiles * 4 * n_act;
+int64_t force_partial_elems(const tsbts_ctx *c, int n_act, int blocks) {
+  // small sets: one partial per j-tile and target
+  if (n_act <= small_act_limit(c)) return c->npad / kTJ * 4 * n_act;
   const SplitPlan pf =
       force_scalar_j(c)
-          ? plan_split(n_act, 1, c->npad / scalar_chunk(c, n_act, 1), c->tune_blocks)
-          : plan_split(n_act, force_targets_per_lane(c, n_act), n_jtiles, c->tune_blocks);
+          ? plan_split(n_act, 1, c->npad / scalar_chunk(c, n_act, 1), blocks)
+          : plan_split(n_act, force_targets_per_lane(c, n_act), c->npad / kTJ, blocks);
+  return pf.n_slices > 1 ? static_cast<int64_t>(pf.n_slices) * 4 * n_act : 0;
+}
+
+int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
+  const int64_t n_jtiles = c->npad / kTJ;
+  const int64_t need_f = force_partial_elems(c, n_act, c->tune_blocks);
+  // the criterion: small sets one partial per j-tile with 2 values per target
+  if (n_act <= kSmallAct) return std::max(need_f, n_jtiles * 2 * n_act);
   const int ipl_c = criterion_targets_per_lane(c, n_act);
   const int64_t units_c =
       criterion_scalar_j(c, n_act) ? c->npad / scalar_chunk(c, n_act, ipl_c) : n_jtiles;
   const SplitPlan pc = plan_split(n_act, ipl_c, units_c, criterion_blocks(c, n_act));
-  const int64_t need_f = pf.n_slices > 1 ? static_cast<int64_t>(pf.n_slices) * 4 * n_act : 0;
   const int64_t need_c = pc.n_slices > 1 ? static_cast<int64_t>(pc.n_slices) * 2 * n_act : 0;
   return std::max(need_f, need_c);
 }
 
-hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
-                        double *pot, hipStream_t st, const CorrectArgs *corr) {
-  if (force_sym_applies(c, n_act)) {
-    SymPlan plan;
-    if (sym_plan(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
-      return launch_force_sym(c, plan, idx, n_act, acc, pot, st, corr);
-  }
+hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                               double *pot, double *part, int blocks, hipStream_t st,
+                               const CorrectArgs *corr) {
   ForceArgs A;
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;
@@ -524,10 +525,10 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   A.n_jtiles = static_cast<int>(c->npad / kTJ);
   A.eps2f = static_cast<float>(c->eps * c->eps);
   A.eps2 = c->eps * c->eps;
-  A.part = c->part;
+  A.part = part;
   A.acc = acc;
   A.pot = pot;
-  A.blocks = c->tune_blocks;
+  A.blocks = blocks;
   A.ipl = force_targets_per_lane(c, n_act);
   A.scalar_j = force_scalar_j(c) ? 1 : 0;
   A.chunk = scalar_chunk(c, n_act, 1);
@@ -536,6 +537,16 @@ hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (sep64) return newton ? pick_ipl<MixSep64, 1>(A, st) : pick_ipl<MixSep64, 0>(A, st);
   return newton ? pick_ipl<MixHiLo, 1>(A, st) : pick_ipl<MixHiLo, 0>(A, st);
+}
+
+hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                        double *pot, hipStream_t st, const CorrectArgs *corr) {
+  if (force_sym_applies(c, n_act)) {
+    SymPlan plan;
+    if (sym_plan(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4, &plan))
+      return launch_force_sym(c, plan, idx, n_act, acc, pot, st, corr);
+  }
+  return launch_force_gather(c, idx, n_act, acc, pot, c->part, c->tune_blocks, st, corr);
 }
 
 int small_act_limit(const tsbts_ctx *c) {

@@ -229,6 +229,18 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
 // With corr, every target's corrector (correct_one) runs where its force is final.
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr = nullptr);
+// The gather force kernels (never the symmetric ones) with split-j partials in `part`
+// and a split aiming for `blocks` workgroups.
+hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                               double *pot, double *part, int blocks, hipStream_t st,
+                               const CorrectArgs *corr = nullptr);
+// float64 partials of that launch (0 when the j-range is not split).
+int64_t force_partial_elems(const tsbts_ctx *c, int n_act, int blocks);
+// Fixed partial-sum array of tsbts_force_noalloc: find its address on `device` (once per
+// device); returns the HIP status of the lookup.
+hipError_t noalloc_setup(int device);
+// Its looked-up address on `device` (NULL before noalloc_setup succeeded there).
+double *noalloc_partials(int device);
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st);
 hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const double *ga,

@@ -1,0 +1,117 @@
+"""GPU test of tsbts_force_noalloc (the force for callers that cannot allocate): through the
+C ABI, its outputs against tsbts_force's on the same predicted state, two calls in a row
+(the second smaller, so the shared fixed array holds the first call's partials), both
+precisions, the split-j and j-parallel paths, a split shrunk to fit the array, the full
+set (symmetric kernels in tsbts_force), and the refusal of a call that cannot fit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1205_2288_amd import _lib as L
+from gpu_util import make_ctx, rel_err_vec
+from workloads import active_subset, plummer
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(n, seed):
+    r, v, m = plummer(n, seed, masses="loguniform")
+    rng = np.random.default_rng(seed + 1)
+    a = rng.standard_normal((3, n)) * 0.1
+    # three block levels at t_block = 2^-8 (a quarter of them due there)
+    lev = rng.integers(0, 3, n)
+    dt = 2.0 ** -(8 + lev)
+    t_last = 2.0 ** -8 - dt
+    return r, v, m, a, t_last, dt
+
+
+def _both(ctx, idx, tb):
+    k = idx.numel()
+    dev = ctx.device
+    acc1 = torch.full((3, k), np.nan, dtype=torch.float64, device=dev)
+    pot1 = torch.full((k,), np.nan, dtype=torch.float64, device=dev)
+    acc2 = torch.full((3, k), np.nan, dtype=torch.float64, device=dev)
+    pot2 = torch.full((k,), np.nan, dtype=torch.float64, device=dev)
+    L.tsbts_force(ctx.ctx, idx, tb, acc1, pot1)
+    L.tsbts_force_noalloc(ctx.ctx, idx, tb, acc2, pot2)
+    torch.cuda.synchronize()
+    return acc1.cpu().numpy(), pot1.cpu().numpy(), acc2.cpu().numpy(), pot2.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_noalloc_force_equals_force_two_calls(precision):
+    tb = 2.0 ** -8
+    # (n, eps, active-set sizes in call order): split-j scalar-load kernel, then a smaller
+    # call on the same context (j-parallel kernel), then a smaller context
+    cases = [(20011, 1.0 / 256, [9001, 20]), (3001, 1.0 / 64, [700, 5])]
+    for n, eps, sizes in cases:
+        r, v, m, a, t_last, dt = _state(n, 12052300 + n)
+        with make_ctx(n, eps, precision) as ctx:
+            ctx.bind(r, v, m, a=a, t_last=t_last, dt=dt)
+            ctx.predict(tb)
+            for k in sizes:
+                print(f"noalloc {precision} n={n} n_active={k}", flush=True)
+                idx = ctx.idx(active_subset(n, k, 7 * k + n))
+                a1, p1, a2, p2 = _both(ctx, idx, tb)
+                assert np.isfinite(a2).all() and np.isfinite(p2).all()
+                # same kernels, same split: bit for bit
+                assert np.array_equal(a1, a2), (n, k)
+                assert np.array_equal(p1, p2), (n, k)
+
+
+def test_noalloc_shrunk_split_and_full_set():
+    """N = 131072 with 130816 targets: tsbts_force's split needs more partials than the
+    fixed array holds, so the variant aims for fewer workgroups (another fixed order of
+    float64 tile sums); the full set is served by the symmetric kernels in tsbts_force and
+    by the gather kernels here."""
+    n, eps, tb = 131072, 1.0 / 4096, 2.0 ** -8
+    r, v, m, a, t_last, dt = _state(n, 12052293)
+    with make_ctx(n, eps, "mixed") as ctx:
+        ctx.bind(r, v, m, a=a, t_last=t_last, dt=dt)
+        ctx.predict(tb)
+        k = 130816
+        print(f"noalloc mixed n={n} n_active={k}", flush=True)
+        idx = ctx.idx(active_subset(n, k, 99 + k))
+        a1, p1, a2, p2 = _both(ctx, idx, tb)
+        e = rel_err_vec(a2, a1)
+        # float64 sums of the same float32 tile sums, grouped into fewer slices
+        assert np.median(e) < 1e-14 and e.max() < 1e-11, (np.median(e), e.max())
+        ep = np.abs(p2 - p1) / np.abs(p1)
+        assert ep.max() < 1e-12, ep.max()
+        print(f"noalloc mixed n={n} n_active={n}", flush=True)
+        idx = ctx.idx(np.arange(n, dtype=np.int32))
+        a1, p1, a2, p2 = _both(ctx, idx, tb)
+        # another float32 pair evaluation order (each pair once there): the mixed bar
+        e = rel_err_vec(a2, a1)
+        assert np.median(e) < 1e-6 and e.max() < 1e-5, (np.median(e), e.max())
+        ep = np.abs(p2 - p1) / np.abs(p1)
+        assert np.median(ep) < 1e-6 and ep.max() < 1e-5, (np.median(ep), ep.max())
+
+
+def test_noalloc_refuses_a_call_that_cannot_fit():
+    """32 targets among 2^24 + 1 particles need 4 * 32 partials per 256 particles, more
+    than the fixed array holds: refused with nothing enqueued."""
+    n, tb = (1 << 24) + 1, 0.0
+    with make_ctx(n, 1.0 / 4096, "mixed") as ctx:
+        rng = np.random.default_rng(5)
+        r = torch.randn((3, n), dtype=torch.float64, device="cuda")
+        v = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        m = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        ctx.bind(r, v, m)
+        ctx.predict(tb)
+        idx = ctx.idx(rng.choice(n, 32, replace=False).astype(np.int32))
+        acc = torch.full((3, 32), 7.0, dtype=torch.float64, device="cuda")
+        with pytest.raises(L.TsbtsError) as ei:
+            L.tsbts_force_noalloc(ctx.ctx, idx, tb, acc)
+        assert ei.value.status == L.TSBTS_EINVAL
+        assert "fixed array" in str(ei.value)
+        torch.cuda.synchronize()
+        assert (acc == 7.0).all()
+        # 33 targets take the split-j kernel, whose partials fit: same split, bit for bit
+        idx = ctx.idx(rng.choice(n, 33, replace=False).astype(np.int32))
+        acc = torch.empty((3, 33), dtype=torch.float64, device="cuda")
+        L.tsbts_force_noalloc(ctx.ctx, idx, tb, acc)
+        acc1 = torch.empty((3, 33), dtype=torch.float64, device="cuda")
+        L.tsbts_force(ctx.ctx, idx, tb, acc1)
+        torch.cuda.synchronize()
+        assert torch.equal(acc, acc1)
