@@ -368,6 +368,16 @@ int tsbts_sched_admissible(double begin, double end, int64_t dt_min, int64_t dt_
 int tsbts_sched_rule(int first_pass, int64_t dt, int64_t t_block, double begin, double end_dt,
                      double end_2dt, int64_t dt_min, int64_t dt_max, int64_t *out);
 
+/* End (ticks) of the era that starts at t0 (ticks) for particles at times t_ticks [n] with
+ * steps dt_ticks [n] (host arrays, ticks): t0 + era for a fixed era (era > 0, a multiple
+ * of dt_max), else Algorithm 3 as read above - size = last minus first next block time
+ * t_i + dt_i, clamped to [dt_max/8, dt_max] and rounded up to a power of two, dt_max when
+ * that is below the largest step, the era ending at the next multiple of the size after
+ * t0.  Every particle must be in an era-start state (steps powers of two up to dt_max, t
+ * aligned to the step, t <= t0 < t + dt), else TSBTS_EINVAL.  Host only. */
+int tsbts_sched_era_end(int64_t t0, const int64_t *t_ticks, const int64_t *dt_ticks, int64_t n,
+                        int64_t dt_max, int64_t era, int64_t *out);
+
 /* Start a scheduled integration of the bound state at time 0 (Algorithm 2, step 1):
  * sets t_last = 0, computes the accelerations of all particles (into the bound a), their
  * criterion values and block steps (into the bound dt).  eta: accuracy parameter of

@@ -134,7 +134,9 @@ class OracleTSBTS:
         # the step that brought each particle to its current time (0: none yet)
         self.dtp = np.zeros(self.n, dtype=np.int64)
         self.time = 0
-        self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0}
+        # era_sizes: number of eras of each size (time units, as text)
+        self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0,
+                      "era_sizes": {}}
         self.schedule = ({"dt0": self.dt * TICK, "eras": []} if record_schedule else None)
         self._log = None
 
@@ -282,6 +284,8 @@ class OracleTSBTS:
         self.last_history = prev
         self.time = T1
         self.stats["eras"] += 1
+        key = repr((T1 - T0) * TICK)
+        self.stats["era_sizes"][key] = self.stats["era_sizes"].get(key, 0) + 1
         return T1
 
     def run(self, t_end: float, energy_every: float | None = None):

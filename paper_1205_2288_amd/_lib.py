@@ -78,6 +78,7 @@ _SIGS = {
     "tsbts_sched_admissible": ([_d, _d, _i64, _i64, ctypes.POINTER(_i64)], _int),
     "tsbts_sched_rule": ([_int, _i64, _i64, _d, _d, _d, _i64, _i64, ctypes.POINTER(_i64)],
                          _int),
+    "tsbts_sched_era_end": ([_i64, _p, _p, _i64, _i64, _i64, ctypes.POINTER(_i64)], _int),
     "tsbts_sched_init": ([_p, _d, _int, _d, _d, _d, _p], _int),
     "tsbts_sched_era": ([_p, ctypes.POINTER(_d), _p], _int),
     "tsbts_sched_state": ([_p, _p, _p, _p, _p, ctypes.POINTER(_d)], _int),
@@ -333,6 +334,20 @@ def tsbts_sched_rule(first_pass: bool, dt: int, t_block: int, begin: float, end_
     _check(None, lib.tsbts_sched_rule(int(bool(first_pass)), int(dt), int(t_block),
                                       float(begin), float(end_dt), float(end_2dt),
                                       int(dt_min), int(dt_max), ctypes.byref(out)))
+    return out.value
+
+
+def tsbts_sched_era_end(t0: int, t, dt, dt_max: int, era: int = 0) -> int:
+    """End of the era starting at t0 (all in ticks; t, dt host int64 arrays)."""
+    import numpy as np
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    dt = np.ascontiguousarray(dt, dtype=np.int64)
+    if t.shape != dt.shape or t.ndim != 1:
+        raise ValueError("t and dt must be 1-d arrays of one length")
+    out = ctypes.c_int64()
+    _check(None, lib.tsbts_sched_era_end(int(t0), ctypes.c_void_p(t.ctypes.data),
+                                         ctypes.c_void_p(dt.ctypes.data), t.size, int(dt_max),
+                                         int(era), ctypes.byref(out)))
     return out.value
 
 

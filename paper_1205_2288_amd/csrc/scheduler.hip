@@ -49,6 +49,17 @@ int64_t admissible_ticks(double begin, double end, int64_t dt_min, int64_t dt_ma
   return std::min(dt_max, std::max(dt_min, p2));
 }
 
+int64_t era_end_rule(int64_t t0, int64_t first, int64_t last, int64_t largest,
+                     int64_t dt_max, int64_t era) {
+  if (era > 0) return t0 + era;
+  // Algorithm 3: last minus first next block time, clamped to [dt_max/8, dt_max]
+  const int64_t size = std::min(dt_max, std::max(dt_max / 8, last - first));
+  int64_t p2 = 1;
+  while (p2 < size) p2 *= 2;  // smallest power of two >= size
+  if (p2 < largest) p2 = dt_max;  // shorter than a step in use: no past to symmetrize it
+  return (t0 / p2 + 1) * p2;
+}
+
 int64_t step_rule(int first_pass, int64_t dt, int64_t tb, double begin, double end_dt,
                   double end_2dt, int64_t dt_min, int64_t dt_max) {
   if (first_pass) {
@@ -190,11 +201,7 @@ struct Scheduler {
       hi = std::max(hi, nx);
       largest = int64_t(1) << l;
     }
-    const int64_t size = std::min(dt_max, std::max(dt_max / 8, hi - lo));
-    int64_t p2 = 1;
-    while (p2 < size) p2 *= 2;  // smallest power of two >= size
-    if (p2 < largest) p2 = dt_max;
-    return (t0 / p2 + 1) * p2;
+    return era_end_rule(t0, lo, hi, largest, dt_max, era);
   }
 };
 
@@ -345,6 +352,26 @@ int tsbts_sched_rule(int first_pass, int64_t dt, int64_t t_block, double begin, 
                      double end_2dt, int64_t dt_min, int64_t dt_max, int64_t *out) {
   if (!out || dt < 1 || dt_min < 1 || dt_max < dt_min || t_block % dt != 0) return TSBTS_EINVAL;
   *out = tsbts::step_rule(first_pass, dt, t_block, begin, end_dt, end_2dt, dt_min, dt_max);
+  return TSBTS_OK;
+}
+
+int tsbts_sched_era_end(int64_t t0, const int64_t *t_ticks, const int64_t *dt_ticks, int64_t n,
+                        int64_t dt_max, int64_t era, int64_t *out) {
+  if (!t_ticks || !dt_ticks || !out || n < 1 || t0 < 0 || era < 0 || dt_max < 1 ||
+      (dt_max & (dt_max - 1)) || dt_max > (int64_t(1) << tsbts::kMaxLevel))
+    return TSBTS_EINVAL;
+  if (era > 0 && era % dt_max != 0) return TSBTS_EINVAL;
+  int64_t lo = INT64_MAX, hi = INT64_MIN, largest = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t d = dt_ticks[i], ti = t_ticks[i];
+    if (d < 1 || (d & (d - 1)) || d > dt_max || ti < 0 || ti > t0 || ti % d != 0 ||
+        ti + d <= t0)
+      return TSBTS_EINVAL;  // not an era-start state
+    lo = std::min(lo, ti + d);
+    hi = std::max(hi, ti + d);
+    largest = std::max(largest, d);
+  }
+  *out = tsbts::era_end_rule(t0, lo, hi, largest, dt_max, era);
   return TSBTS_OK;
 }
 

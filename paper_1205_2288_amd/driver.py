@@ -142,6 +142,11 @@ def _run_loop(sim, t_end: float, energy_every, log):
     return out
 
 
+def _count_era(sizes: dict, ticks: int):
+    key = repr(ticks * TICK)
+    sizes[key] = sizes.get(key, 0) + 1
+
+
 class TSBTS:
     """Dynamic- or fixed-era TSBTS integration on the GPU.
 
@@ -183,8 +188,9 @@ class TSBTS:
         self.dtp = np.zeros(n, dtype=np.int64)  # step that brought each particle to t
         self.dtc = np.zeros(n)
         self.time = 0
+        # era_sizes: number of eras of each size (time units, as text)
         self.stats = {"block_steps": 0, "force_calls": 0, "interactions": 0, "eras": 0,
-                      "wall_s": 0.0}
+                      "era_sizes": {}, "wall_s": 0.0}
         self._initialise()
 
     # ------------------------------------------------------------------ device plumbing
@@ -316,6 +322,7 @@ class TSBTS:
         self._log = None
         self.time = T1
         self.stats["eras"] += 1
+        _count_era(self.stats["era_sizes"], T1 - T0)
         return T1
 
     def energy(self) -> float:
@@ -374,6 +381,7 @@ class NativeTSBTS:
         self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
         self._host()
         self.wall_s = 0.0
+        self.era_sizes = {}  # eras of each size run by this object (time units, as text)
 
     def _host(self):
         t, dt, dtc, st, time_ = self._L.tsbts_sched_state(self.ctx.ctx, self.n)
@@ -385,12 +393,16 @@ class NativeTSBTS:
     def stats(self):
         st = self._stats
         return {"block_steps": int(st[0]), "force_calls": int(st[1]),
-                "interactions": int(st[2]), "eras": int(st[3]), "wall_s": self.wall_s}
+                "interactions": int(st[2]), "eras": int(st[3]),
+                "era_sizes": dict(self.era_sizes), "wall_s": self.wall_s}
 
     def era_step(self) -> int:
+        T0 = self.time
         end = self._L.tsbts_sched_era(self.ctx.ctx)
         self._host()
-        return to_ticks(end)
+        T1 = to_ticks(end)
+        _count_era(self.era_sizes, T1 - T0)
+        return T1
 
     def energy(self) -> float:
         kw = self.ctx.energy(out=self._ek).cpu().numpy()

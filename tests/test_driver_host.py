@@ -131,6 +131,99 @@ def test_native_rule_matches_oracle_rules():
         assert got == ref, (trial, dt, tb, begin, ends)
 
 
+def _oracle_era_end(t, dt, t0, dt_max, era=None):
+    s = OracleTSBTS.__new__(OracleTSBTS)
+    s.t = np.asarray(t, dtype=np.int64)
+    s.dt = np.asarray(dt, dtype=np.int64)
+    s.dt_max, s.era = dt_max, era
+    return s._era_end(t0)
+
+
+def _era_start_table(rng, n, t0, dt_max, top):
+    """Particles in an era-start state at t0: power-of-two steps up to `top`, each at the
+    last multiple of its step at or before t0."""
+    lv = rng.integers(0, 9, n)
+    dt = np.maximum(top >> lv, 1).astype(np.int64)
+    t = (t0 // dt) * dt
+    return t, dt
+
+
+def test_native_era_end_matches_oracle():
+    from paper_1205_2288_amd import _lib as L
+    DTMAX = 1 << 14
+    rng = np.random.default_rng(3)
+    seen = set()
+    for trial in range(600):
+        top = DTMAX >> int(rng.integers(0, 6))  # largest step in use, up to dt_max/32
+        n = int(rng.integers(1, 40))
+        t0 = int(rng.integers(0, 64)) * (DTMAX >> 5)
+        t, dt = _era_start_table(rng, n, t0, DTMAX, top)
+        got = L.tsbts_sched_era_end(t0, t, dt, DTMAX)
+        ref = _oracle_era_end(t, dt, t0, DTMAX)
+        assert got == ref, (trial, t0, t, dt)
+        seen.add(ref - t0 if ref % (ref - t0) == 0 else None)
+        # fixed era: t0 + era
+        assert L.tsbts_sched_era_end(t0, t, dt, DTMAX, 2 * DTMAX) == \
+            _oracle_era_end(t, dt, t0, DTMAX, 2 * DTMAX) == t0 + 2 * DTMAX
+    # the random tables reach every era size from dt_max/8 to dt_max
+    assert {DTMAX >> k for k in range(4)} <= seen
+
+
+def test_era_end_rule_cases_from_algorithm_3():
+    """Algorithm 3 read literally: the era is the last minus the first block time, kept
+    between the lower limit (dt_max/8, Section 4's 2^-3 multiples) and dt_max."""
+    from paper_1205_2288_amd import _lib as L
+    D = 1 << 14
+    cases = [
+        # every particle on one level far below dt_max: the difference is zero -> the
+        # lower limit dt_max/8 (an era longer than every step)
+        (0, [0, 0, 0], [D // 64] * 3, D // 8),
+        # first block at t0 + D/64, last at t0 + D/4: difference 15D/64 -> 2^k above it
+        # (D/4), the largest step D/4 fits
+        (0, [0, 0], [D // 64, D // 4], D // 4),
+        # a particle on the top level: last - first = D - D/64 -> dt_max
+        (D, [D, D], [D // 64, D], 2 * D),
+        # first block at t0 + D/32, last (a D/2 particle) at D: the difference 3D/16
+        # rounds up to D/4, below the largest step D/2 -> dt_max (Section 4: the D/2
+        # particles would have no past to be symmetrized with); the era ends at the next
+        # multiple of dt_max
+        (3 * D // 4 + D // 32, [D // 2, 3 * D // 4 + D // 32], [D // 2, D // 32], D),
+        # era ends keep alignment: the next multiple of the size after t0
+        (D // 16 + D // 64, [D // 16 + D // 64], [D // 64], D // 8),
+    ]
+    for t0, t, dt, end in cases:
+        assert _oracle_era_end(t, dt, t0, D) == end, (t0, t, dt)
+        assert L.tsbts_sched_era_end(t0, t, dt, D) == end, (t0, t, dt)
+
+
+def test_native_era_end_refuses_a_state_that_is_not_an_era_start():
+    from paper_1205_2288_amd import _lib as L
+    D = 1 << 14
+    for t0, t, dt in [(D, [D - D // 4], [D // 8]),   # due before t0
+                      (D, [D // 3], [D]),            # not aligned to its step
+                      (D, [D], [3])]:                # not a power of two
+        with pytest.raises(L.TsbtsError):
+            L.tsbts_sched_era_end(t0, t, dt, D)
+    with pytest.raises(L.TsbtsError):
+        L.tsbts_sched_era_end(0, [0], [D // 2], D, D // 2)  # era not a multiple of dt_max
+
+
+def test_scheduler_dynamic_era_follows_oracle_bitwise():
+    # eta = 0.05, dt_max = 1/8 on the 256-body sphere: Algorithm 3 sets the era to 1/8
+    # while a particle is on the top level and to 1/16 afterwards
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=0.05, passes=3, era=None, dt_max=1 / 8, dt_min=cfg.dt_min)
+    prod = TSBTS(r, v, m, cfg.eps, context=FakeContext(cfg.n, cfg.eps), **kw)
+    ref = OracleTSBTS(r, v, m, cfg.eps, **kw)
+    for _ in range(4):
+        assert prod.era_step() == ref.era_step()
+        st = prod.state()
+        for key in ("t", "dt", "dtp", "r", "v"):
+            assert np.array_equal(st[key], getattr(ref, key)), key
+    assert prod.stats["era_sizes"] == ref.stats["era_sizes"] == {"0.125": 2, "0.0625": 2}
+
+
 def test_run_log_and_nonfinite_energy():
     # the run loop's JSON metrics (one line per energy sample) and its stop on a
     # non-finite energy

@@ -122,24 +122,57 @@ def test_era_of_one_max_step_first_steps(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["plummer256", "plummer256_1pass", "plummer4096_t1"])
+@pytest.mark.parametrize("name", ["plummer256", "plummer256_1pass", "plummer4096_t1",
+                                  "plummer256_dyn"])
 def test_energy_drift_within_twice_oracle(prec, name):
     from paper_1205_2288_amd.driver import NativeTSBTS
     g = _golden(name)
     cfg = config(g["workload"])
     r, v, m = cfg.ic()
-    sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=g["passes"], era=cfg.era,
-                      dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=prec)
+    sim = NativeTSBTS(r, v, m, cfg.eps, eta=g["eta"], passes=g["passes"], era=g["era"],
+                      dt_max=g["dt_max"], dt_min=g["dt_min"], precision=prec)
     series = sim.run(g["t_end"])
     d = _drift(series)
     print(f"{name} {prec}: GPU drift {d:.3e}, oracle {g['max_rel_energy_error']:.3e}, "
           f"steps {sim.stats['block_steps']} vs {g['stats']['block_steps']}, "
+          f"eras {sim.stats['era_sizes']} vs {g['stats'].get('era_sizes')}, "
           f"{sim.stats['wall_s']:.1f} s")
     assert len(series) == len(g["times"])
     assert d <= 2.0 * g["max_rel_energy_error"]
     # the schedule work is comparable (chaotic divergence allowed)
     assert 0.5 <= sim.stats["block_steps"] / g["stats"]["block_steps"] <= 2.0
+    if prec == "fp64" and "era_sizes" in g["stats"]:
+        # t <= 1 is short enough for float64 runs to keep the oracle's schedule
+        assert sim.stats["era_sizes"] == g["stats"]["era_sizes"]
     sim.close()
+
+
+@pytest.mark.parametrize("native", [False, True])
+def test_plummer256_dynamic_era_follows_oracle(native):
+    """eta = 0.05, dt_max = 1/8, dynamic era: Algorithm 3 sets eras of 1/8 and then 1/16.
+    In float64 both schedulers take the oracle's era ends, times and steps era by era."""
+    from paper_1205_2288_amd.driver import TSBTS, NativeTSBTS
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    kw = dict(eta=0.05, passes=3, era=None, dt_max=1 / 8, dt_min=cfg.dt_min)
+    gpu = (NativeTSBTS if native else TSBTS)(r, v, m, cfg.eps, precision="fp64", **kw)
+    ref = OracleTSBTS(r, v, m, cfg.eps, **kw)
+    assert np.array_equal(gpu.dt, ref.dt)
+    ends = []
+    while ref.time * 2.0 ** -20 < 0.5:
+        T1 = ref.era_step()
+        assert gpu.era_step() == T1, "era ends differ"
+        ends.append(T1)
+        st = gpu.state()
+        assert np.array_equal(st["t"], ref.t)
+        assert np.array_equal(st["dt"], ref.dt), "schedules diverged"
+        assert np.abs(st["r"] - ref.r).max() <= 1e-9
+        assert np.abs(st["v"] - ref.v).max() <= 1e-8
+    sizes = np.diff([0] + ends)
+    dt_max = 1 << 17
+    assert (sizes == dt_max).any() and (sizes < dt_max).any(), sizes
+    assert gpu.stats["era_sizes"] == ref.stats["era_sizes"]
+    gpu.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
