@@ -6,9 +6,9 @@ never calls it, and it imports nothing from the product package.
 
 Contents
 --------
-* ``force``, ``energy``, ``timestep``, ``force_backward``, ``force_backward_rows``:
-  ctypes wrappers around the plain C double loops in ``oracle.c`` (definitions cited
-  there).
+* ``force``, ``energy``, ``timestep``, ``force_backward``, ``force_backward_rows``,
+  ``force_backward_scale``: ctypes wrappers around the plain C double loops in
+  ``oracle.c`` (definitions cited there).
 * ``taylor``: the predictor of Section 2 (second-order positions, first-order
   velocities).
 * ``hermite``: the cubic Hermite interpolant used as the time-symmetric interpolation of
@@ -65,6 +65,8 @@ def _load():
                                               _d, _d, _d, _d, _d, _d, _d, _d]
         lib.oracle_force_backward_rows.argtypes = [i64, _d, _d, _d, _d, dbl, _i, i64,
                                                    _d, _d, _d, _d, _i, i64, _d, _d]
+        lib.oracle_force_backward_scale.argtypes = [i64, _d, _d, _d, _d, dbl, _i, i64,
+                                                    _d, _d, _d, _d, _i, i64, _d, _d, _d, _d]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -198,6 +200,39 @@ def force_backward(r, m, eps, idx, g_acc, g_pot=None):
                               _p(gp) if gp is not None else ctypes.cast(None, _d),
                               _p(gr[0]), _p(gr[1]), _p(gr[2]), _p(gm))
     return gr, gm
+
+
+def force_backward_scale(r, m, eps, idx, g_acc, g_pot=None, rows=None):
+    """Rounding scale of ``force_backward``: (S_r [3, K], S_m [K]) for all N particles
+    (K = N) or the listed rows, the same sums with every term replaced by its magnitude
+    (definition in oracle.c).  |dL/dr| <= S_r and |dL/dm| <= S_m component by component
+    (triangle inequality), with equality when one term of one sign enters; an element
+    whose terms are each evaluated with relative error u is off by at most about u S.
+
+    Pinned by those two properties (tests/test_oracle_adjoint.py)."""
+    lib = _load()
+    r = _soa(r, "r")
+    n = r.shape[1]
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    idx = _idx(idx, n)
+    g_acc = _soa(g_acc, "g_acc")
+    if g_acc.shape[1] != idx.size:
+        raise ValueError("g_acc must have shape (3, n_act)")
+    gp = None
+    if g_pot is not None:
+        gp = np.ascontiguousarray(g_pot, dtype=np.float64)
+    if rows is not None:
+        rows = _idx(rows, n)
+    k = n if rows is None else rows.size
+    sr = np.zeros((3, k))
+    sm = np.zeros(k)
+    lib.oracle_force_backward_scale(n, _p(r[0]), _p(r[1]), _p(r[2]), _p(m), float(eps),
+                                    _pi(idx), idx.size, _p(g_acc[0]), _p(g_acc[1]),
+                                    _p(g_acc[2]),
+                                    _p(gp) if gp is not None else ctypes.cast(None, _d),
+                                    _pi(rows) if rows is not None else ctypes.cast(None, _i),
+                                    k, _p(sr[0]), _p(sr[1]), _p(sr[2]), _p(sm))
+    return sr, sm
 
 
 def taylor(r, v, a, h):

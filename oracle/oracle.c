@@ -251,6 +251,105 @@ void oracle_force_backward_rows(int64_t n, const double *x, const double *y, con
     }
 }
 
+/* Rounding scale of the vector-Jacobian product above: the same sums with every product
+ * replaced by its magnitude and every sum of products by the sum of their magnitudes,
+ *   source (k != c):  S_r[k] += |m_k| [ s^(-3/2) |g_c| + 3 s^(-5/2) e_c |d| + |gp_c| s^(-3/2) |d| ]
+ *                     S_m[k] += e_c s^(-3/2) + |gp_c| s^(-1/2)
+ *   target (k = c, over all j != k):
+ *                     S_r[k] += sum_j |m_j| [ s^(-3/2) |g_k| + 3 s^(-5/2) e_k |d| ]
+ *                               + |gp_k| sum_j |m_j| s^(-3/2) |d|
+ * with |.| taken per component and e_c = |d_x g_cx| + |d_y g_cy| + |d_z g_cz|.  By the
+ * triangle inequality |dL/dr_k| <= S_r[k] and |dL/dm_k| <= S_m[k] component by component,
+ * with equality when a single term of one sign enters; an implementation that evaluates
+ * each term with relative error u and sums them has an error of at most about u S.
+ * Written (not accumulated) into sr_x, sr_y, sr_z, sm [n], or for the listed rows only
+ * when rows is not NULL ([nrows] outputs indexed by position in rows). */
+static void scale_source_row(int64_t k, const double *x, const double *y, const double *z,
+                             const double *m, double eps2, const int32_t *idx, int64_t nact,
+                             const double *gax, const double *gay, const double *gaz,
+                             const double *gp, double out[4])
+{
+    double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+    for (int64_t q = 0; q < nact; ++q) {
+        const int64_t c = idx[q];
+        if (c == k) continue;
+        const double dx = x[k] - x[c];
+        const double dy = y[k] - y[c];
+        const double dz = z[k] - z[c];
+        const double s = dx * dx + dy * dy + dz * dz + eps2;
+        const double rinv = 1.0 / sqrt(s);
+        const double r3 = rinv * rinv * rinv;
+        const double r5 = r3 * rinv * rinv;
+        const double e = fabs(dx * gax[q]) + fabs(dy * gay[q]) + fabs(dz * gaz[q]);
+        const double g2 = gp ? fabs(gp[q]) : 0.0;
+        sx += r3 * fabs(gax[q]) + 3.0 * r5 * e * fabs(dx) + g2 * r3 * fabs(dx);
+        sy += r3 * fabs(gay[q]) + 3.0 * r5 * e * fabs(dy) + g2 * r3 * fabs(dy);
+        sz += r3 * fabs(gaz[q]) + 3.0 * r5 * e * fabs(dz) + g2 * r3 * fabs(dz);
+        sm += e * r3 + g2 * rinv;
+    }
+    out[0] = fabs(m[k]) * sx;
+    out[1] = fabs(m[k]) * sy;
+    out[2] = fabs(m[k]) * sz;
+    out[3] = sm;
+}
+
+static void scale_target_row(int64_t q, int64_t n, const double *x, const double *y,
+                             const double *z, const double *m, double eps2,
+                             const int32_t *idx, const double *gax, const double *gay,
+                             const double *gaz, const double *gp, double out[3])
+{
+    const int64_t k = idx[q];
+    const double g2 = gp ? fabs(gp[q]) : 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == k) continue;
+        const double dx = x[k] - x[j];
+        const double dy = y[k] - y[j];
+        const double dz = z[k] - z[j];
+        const double s = dx * dx + dy * dy + dz * dz + eps2;
+        const double rinv = 1.0 / sqrt(s);
+        const double r3 = rinv * rinv * rinv;
+        const double r5 = r3 * rinv * rinv;
+        const double e = fabs(dx * gax[q]) + fabs(dy * gay[q]) + fabs(dz * gaz[q]);
+        const double mj = fabs(m[j]);
+        sx += mj * (r3 * fabs(gax[q]) + 3.0 * r5 * e * fabs(dx)) + g2 * mj * r3 * fabs(dx);
+        sy += mj * (r3 * fabs(gay[q]) + 3.0 * r5 * e * fabs(dy)) + g2 * mj * r3 * fabs(dy);
+        sz += mj * (r3 * fabs(gaz[q]) + 3.0 * r5 * e * fabs(dz)) + g2 * mj * r3 * fabs(dz);
+    }
+    out[0] = sx;
+    out[1] = sy;
+    out[2] = sz;
+}
+
+void oracle_force_backward_scale(int64_t n, const double *x, const double *y,
+                                 const double *z, const double *m, double eps,
+                                 const int32_t *idx, int64_t nact, const double *gax,
+                                 const double *gay, const double *gaz, const double *gp,
+                                 const int32_t *rows, int64_t nrows, double *sr_x,
+                                 double *sr_y, double *sr_z, double *sm)
+{
+    const double eps2 = eps * eps;
+    const int64_t nout = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nout; ++t) {
+        const int64_t k = rows ? rows[t] : t;
+        double o[4];
+        scale_source_row(k, x, y, z, m, eps2, idx, nact, gax, gay, gaz, gp, o);
+        for (int64_t q = 0; q < nact; ++q) {
+            if (idx[q] != k) continue;
+            double tg[3];
+            scale_target_row(q, n, x, y, z, m, eps2, idx, gax, gay, gaz, gp, tg);
+            o[0] += tg[0];
+            o[1] += tg[1];
+            o[2] += tg[2];
+        }
+        sr_x[t] = o[0];
+        sr_y[t] = o[1];
+        sr_z[t] = o[2];
+        sm[t] = o[3];
+    }
+}
+
 /* Number of threads the OpenMP runtime will use (1 without OpenMP). */
 int oracle_threads(void)
 {

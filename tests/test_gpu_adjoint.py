@@ -17,6 +17,7 @@ import torch
 import oracle
 from oracle import adjoint as oadj
 from workloads import plummer, active_subset, gaussian, config
+from gpu_util import check_adjoint, check_run_gradient, check_fd
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +40,9 @@ def test_force_function_backward_matches_oracle(prec):
     acc, pot = tsbts_force(rt, mt, ctx.idx(idx_np), ctx)
     ((acc * _t(ga)).sum() + (pot * _t(gp)).sum()).backward()
     rr, rm = oracle.force_backward(r, m, eps, idx_np, ga, gp)
-    tol = 1e-11 if prec == "fp64" else 2e-5
-    assert np.linalg.norm(rt.grad.cpu().numpy() - rr) <= tol * np.linalg.norm(rr)
-    assert np.linalg.norm(mt.grad.cpu().numpy() - rm) <= tol * np.linalg.norm(rm)
+    sr, sm = oracle.force_backward_scale(r, m, eps, idx_np, ga, gp)
+    check_adjoint(rt.grad.cpu().numpy(), mt.grad.cpu().numpy(), rr, rm, sr, sm, prec,
+                  "autograd force function")
     ctx.close()
 
 
@@ -66,10 +67,9 @@ def test_leapfrog_gradient_matches_oracle(prec, era):
     target = oadj.forward(r0, v0, m, eps, h, steps)[0] + 0.01 * gaussian((3, n), 7)
     L, gr, gv, gm = _leapfrog_grads(prec, r0, v0, m, eps, h, steps, era, target)
     Lr, rr, rv, rm = oadj.gradient(r0, v0, m, eps, h, steps, target)
-    tol = 1e-10 if prec == "fp64" else 1e-5
     assert L == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
-    for got, ref in ((gr, rr), (gv, rv), (gm, rm)):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    for name, got, ref in (("r", gr, rr), ("v", gv, rv), ("m", gm, rm)):
+        check_run_gradient(got, ref, prec, f"dL/d{name}")
 
 
 def _loss_fp64(ctx, r0, v0, m, h, steps, target):
@@ -93,8 +93,8 @@ def test_adjoint8192_gradients_vs_finite_differences(prec):
     target = r_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 7)
     L, gr, gv, gm = _leapfrog_grads(prec, r0, v0, m, eps, h, steps, era, target)
     step = 1e-6
-    worst = 0.0
-    for trial in range(3):
+    rows = []
+    for trial in range(8):
         for which, g in (("r", gr), ("v", gv), ("m", gm)):
             d = gaussian((3, n) if which != "m" else n, 900 + 10 * trial + len(which))
             if which == "m":
@@ -105,10 +105,9 @@ def test_adjoint8192_gradients_vs_finite_differences(prec):
                 mm = m + sgn * step * d if which == "m" else m
                 return _loss_fp64(ref_ctx, rr, vv, mm, h, steps, target)
             fd = (f(1) - f(-1)) / (2 * step)
-            rel = abs((g * d).sum() - fd) / abs(fd)
-            worst = max(worst, rel)
-            print(f"{prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} rel {rel:.2e}")
-    assert worst <= 1e-5
+            rows.append((which, (g * d).sum(), fd))
+            print(f"{prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e}")
+    check_fd(rows, prec, "adjoint8192 shared steps")
     ref_ctx.close()
 
 
@@ -145,10 +144,9 @@ def test_block_leapfrog_gradient_matches_oracle(prec, era):
     vt = vt + 0.01 * gaussian((3, n), 22)
     Lr, rr, rv, rm = oadj.block_gradient(r0, v0, m, eps, dt, t_end, rt, vt)
     L, gr, gv, gm = _block_grads(prec, r0, v0, m, eps, dt, t_end, era, rt, vt)
-    tol = 1e-10 if prec == "fp64" else 1e-5
     assert L == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
-    for got, ref in ((gr, rr), (gv, rv), (gm, rm)):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    for name, got, ref in (("r", gr, rr), ("v", gv, rv), ("m", gm, rm)):
+        check_run_gradient(got, ref, prec, f"dL/d{name}")
 
 
 def test_block_adjoint_phases_elementwise():
@@ -237,8 +235,8 @@ def test_adjoint8192_block_schedule_vs_finite_differences(prec):
 
     L, gr, gv, gm = _block_grads(prec, r0, v0, m, eps, dt, t_end, era, rt, vt)
     step = 1e-6
-    worst = 0.0
-    for trial in range(2):
+    rows = []
+    for trial in range(8):
         for which, g in (("r", gr), ("v", gv), ("m", gm)):
             d = gaussian((3, n) if which != "m" else n, 950 + 10 * trial + len(which))
             if which == "m":
@@ -248,10 +246,9 @@ def test_adjoint8192_block_schedule_vs_finite_differences(prec):
                             v0 + sgn * step * d if which == "v" else v0,
                             m + sgn * step * d if which == "m" else m)
             fd = (f(1) - f(-1)) / (2 * step)
-            rel = abs((g * d).sum() - fd) / abs(fd)
-            worst = max(worst, rel)
-            print(f"block {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} rel {rel:.2e}")
-    assert worst <= 1e-5
+            rows.append((which, (g * d).sum(), fd))
+            print(f"block {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e}")
+    check_fd(rows, prec, "adjoint8192 block")
     ref.close()
 
 
@@ -287,10 +284,9 @@ def test_era_leapfrog_gradient_matches_oracle(prec, passes):
     fwd_tol = 1e-12 if prec == "fp64" else 1e-6
     assert np.abs(r_end - r_ref).max() <= fwd_tol * np.abs(r_ref).max()
     assert np.abs(v_end - v_ref).max() <= fwd_tol * np.abs(v_ref).max() * 10
-    tol = 1e-10 if prec == "fp64" else 1e-5
     assert L == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
-    for got, ref in ((gr, rr), (gv, rv), (gm, rm)):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    for name, got, ref in (("r", gr, rr), ("v", gv, rv), ("m", gm, rm)):
+        check_run_gradient(got, ref, prec, f"dL/d{name}")
 
 
 def _history_pass(ctx, dt, h, steps):
@@ -443,8 +439,8 @@ def test_adjoint8192_era_passes_vs_finite_differences(prec):
 
     L, gr, gv, gm, _, _ = _era_grads(prec, r0, v0, m, eps, dt, t_end, era, passes, rt, vt)
     step = 1e-6
-    worst = 0.0
-    for trial in range(2):
+    rows = []
+    for trial in range(8):
         for which, g in (("r", gr), ("v", gv), ("m", gm)):
             d = gaussian((3, n) if which != "m" else n, 960 + 10 * trial + len(which))
             if which == "m":
@@ -454,11 +450,9 @@ def test_adjoint8192_era_passes_vs_finite_differences(prec):
                             v0 + sgn * step * d if which == "v" else v0,
                             m + sgn * step * d if which == "m" else m)
             fd = (f(1) - f(-1)) / (2 * step)
-            rel = abs((g * d).sum() - fd) / abs(fd)
-            worst = max(worst, rel)
-            print(f"era passes {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e} "
-                  f"rel {rel:.2e}")
-    assert worst <= 1e-5
+            rows.append((which, (g * d).sum(), fd))
+            print(f"era passes {prec} {which}: adjoint {(g * d).sum():.10e} fd {fd:.10e}")
+    check_fd(rows, prec, "adjoint8192 era passes")
     ref.close()
 
 
@@ -485,11 +479,9 @@ def test_recorded_schedule_gradient_matches_oracle(prec):
     assert np.abs(r_end.detach().cpu().numpy() - sim.r).max() <= fwd_tol
     loss = ((r_end - _t(rt)) ** 2).sum() + ((v_end - _t(vt)) ** 2).sum()
     loss.backward()
-    tol = 1e-10 if prec == "fp64" else 1e-5
     assert float(loss.detach()) == pytest.approx(Lr, rel=1e-9 if prec == "fp64" else 1e-5)
-    for got, ref in ((r.grad, rr), (v.grad, rv), (mm.grad, rm)):
-        got = got.cpu().numpy()
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    for name, got, ref in (("r", r.grad, rr), ("v", v.grad, rv), ("m", mm.grad, rm)):
+        check_run_gradient(got.cpu().numpy(), ref, prec, f"recorded schedule dL/d{name}")
     ctx.close()
 
 
@@ -530,9 +522,9 @@ def test_driver_schedule_replay_and_finite_differences():
     ((a - _t(rt)) ** 2).sum().add(((b - _t(vt)) ** 2).sum()).backward()
     grads = {"r": r.grad.cpu().numpy(), "v": v.grad.cpu().numpy(), "m": mm.grad.cpu().numpy()}
     step = 1e-6
-    worst = 0.0
-    for which in ("r", "v", "m"):
-        d = gaussian((3, n) if which != "m" else n, 990 + len(which))
+    rows = []
+    for trial, which in [(k, w) for k in range(3) for w in ("r", "v", "m")]:
+        d = gaussian((3, n) if which != "m" else n, 990 + 10 * trial + len(which))
         if which == "m":
             d = d * m
         fd = (loss(r0 + step * d if which == "r" else r0, v0 + step * d if which == "v" else v0,
@@ -541,9 +533,8 @@ def test_driver_schedule_replay_and_finite_differences():
                      v0 - step * d if which == "v" else v0,
                      m - step * d if which == "m" else m)) / (2 * step)
         g = (grads[which] * d).sum()
-        rel = abs(g - fd) / abs(fd)
-        worst = max(worst, rel)
+        rows.append((which, g, fd))
         print(f"driver schedule ({steps} block steps, {len(sched['eras'])} eras) {which}: "
-              f"adjoint {g:.10e} fd {fd:.10e} rel {rel:.2e}")
-    assert worst <= 1e-5
+              f"adjoint {g:.10e} fd {fd:.10e}")
+    check_fd(rows, "fp64", "driver schedule replay")
     ctx.close()

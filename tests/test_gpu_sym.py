@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from workloads import plummer, gaussian, config
-from gpu_util import rel_err, summary, make_ctx
+from gpu_util import rel_err, summary, make_ctx, check_adjoint
 
 pytestmark = pytest.mark.gpu
 
@@ -228,19 +228,18 @@ def test_symmetric_adjoint_matches_gather_and_oracle(prec, sep, n, with_gp):
     out = {}
     for sym in (0, 1, 1):
         ctx.tune(symmetric=sym)
-        gr = torch.full((3, n), 0.5, dtype=torch.float64, device="cuda")   # accumulates
-        gm = torch.full((n,), 0.25, dtype=torch.float64, device="cuda")
+        gr = torch.zeros((3, n), dtype=torch.float64, device="cuda")   # accumulates
+        gm = torch.zeros((n,), dtype=torch.float64, device="cuda")
         ctx.force_backward(idx, 0.0, g, gp, gr, gm)
-        res = (gr.cpu().numpy() - 0.5, gm.cpu().numpy() - 0.25)
+        res = (gr.cpu().numpy(), gm.cpu().numpy())
         if sym in out:
             assert all(np.array_equal(a, b) for a, b in zip(res, out[sym]))   # fixed order
         out[sym] = res
     rr, rm = oracle.force_backward(r, m, eps, idx, g, gp)
-    tol = 1e-11 if prec == "fp64" else 2e-5
-    for got, ref in ((out[1][0], rr), (out[1][1], rm)):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
-    for got, ref in zip(out[1], out[0]):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    sr, sm = oracle.force_backward_scale(r, m, eps, idx, g, gp)
+    for sym in (1, 0):
+        check_adjoint(out[sym][0], out[sym][1], rr, rm, sr, sm, prec,
+                      f"n={n} symmetric={sym} gp={with_gp}")
     ctx.close()
 
 
@@ -269,14 +268,14 @@ def test_plummer131k_symmetric_adjoint(prec):
         out[sym] = (gr.cpu().numpy() / 3, gm.cpu().numpy() / 3)
     print(f"plummer131k {prec} adjoint, all targets: gather {ms[0]:.2f} ms, "
           f"symmetric {ms[1]:.2f} ms")
-    tol = 1e-11 if prec == "fp64" else 2e-5
-    for got, ref in zip(out[1], out[0]):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
-    # sampled rows against the oracle
+    # sampled rows against the oracle, both kernels
     rows = np.arange(0, n, n // 128).astype(np.int32)
-    rr, rm = oracle.force_backward_rows(r, m, eps, idx, g.cpu().numpy(), rows)
-    for got, ref in ((out[1][0][:, rows], rr), (out[1][1][rows], rm)):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    gh = g.cpu().numpy()
+    rr, rm = oracle.force_backward_rows(r, m, eps, idx, gh, rows)
+    sr, sm = oracle.force_backward_scale(r, m, eps, idx, gh, rows=rows)
+    for sym in (1, 0):
+        check_adjoint(out[sym][0][:, rows], out[sym][1][rows], rr, rm, sr, sm, prec,
+                      f"plummer131k symmetric={sym} sampled rows")
     ctx.close()
 
 
@@ -303,10 +302,19 @@ def test_large_ragged_n_symmetric_paths(prec):
         ctx.force_backward(idx, 0.0, g, None, gr, gm)
         out[sym] = (dtc, acc.cpu().numpy(), gr.cpu().numpy(), gm.cpu().numpy())
     assert np.array_equal(out[0][0], out[1][0])
-    tol = 1e-11 if prec == "fp64" else 2e-5
-    for got, ref in zip(out[1][1:], out[0][1:]):
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
     sample = idx[:: n // 64]
+    # adjoint: sampled rows of both kernels against the oracle
+    gh = g.cpu().numpy()
+    rows = np.sort(sample).astype(np.int32)
+    rr, rm = oracle.force_backward_rows(r, m, eps, idx, gh, rows)
+    sr, sm = oracle.force_backward_scale(r, m, eps, idx, gh, rows=rows)
+    for sym in (1, 0):
+        check_adjoint(out[sym][2][:, rows], out[sym][3][rows], rr, rm, sr, sm, prec,
+                      f"n=262147 symmetric={sym} sampled rows")
+    # force: symmetric against gather, every particle, at the force bars
+    e = rel_err_vec(out[1][1], out[0][1])
+    assert np.median(e) <= (1e-13 if prec == "fp64" else 1e-6) and \
+        e.max() <= (1e-11 if prec == "fp64" else 1e-5), summary(e)
     e = rel_err(out[1][0][order][sample], oracle.timestep(r, v, m, eps, eta, sample))
     assert e.max() <= (1e-12 if prec == "fp64" else 2e-6), summary(e)
     ra, _ = oracle.force(r, m, eps, sample.astype(np.int32))

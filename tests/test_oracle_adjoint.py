@@ -161,6 +161,44 @@ def test_force_backward_rows_equal_full(oracle, n_act):
     assert np.array_equal(rr, gr[:, rows]) and np.array_equal(rm, gm[rows])
 
 
+@pytest.mark.parametrize("n_act", [1, 40, 97])
+def test_force_backward_scale_bounds_and_equality(oracle, n_act):
+    # the rounding scale bounds the gradient component by component (triangle
+    # inequality) and its row form is the full form's rows
+    n, eps = 97, 1.0 / 32
+    r, _, m = plummer(n, 34, masses="loguniform")
+    m[3] = 0.0  # a massless particle: its position gradient and scale vanish
+    idx = active_subset(n, n_act, 7)
+    ga, gp = gaussian((3, n_act), 8), gaussian(n_act, 9)
+    gr, gm = oracle.force_backward(r, m, eps, idx, ga, gp)
+    sr, sm = oracle.force_backward_scale(r, m, eps, idx, ga, gp)
+    assert (np.abs(gr) <= sr * (1 + 1e-12)).all() and (np.abs(gm) <= sm * (1 + 1e-12)).all()
+    # every particle with a target other than itself has a nonzero mass-gradient scale
+    others = np.setdiff1d(np.arange(n), idx) if n_act == 1 else np.arange(n)
+    assert (sr > 0).sum() >= 3 * (n - 2) and sm[others].min() > 0
+    if 3 not in idx:
+        assert (sr[:, 3] == 0).all() and (gr[:, 3] == 0).all()
+    rows = np.array([0, 3, 17, 96, 40], dtype=np.int32)
+    srr, smr = oracle.force_backward_scale(r, m, eps, idx, ga, gp, rows=rows)
+    assert np.array_equal(srr, sr[:, rows]) and np.array_equal(smr, sm[rows])
+
+
+def test_force_backward_scale_single_term_equality(oracle):
+    # two particles, one target: with the seed along x and the separation along y (no
+    # d.g term), or a potential seed alone, every component of the source row is one
+    # term, so the scale equals the gradient's magnitude exactly
+    eps = 0.1
+    r = np.array([[0.0, 0.0], [0.0, 0.7], [0.0, 0.0]])
+    m = np.array([0.3, 0.9])
+    idx = np.array([0], dtype=np.int32)
+    for ga, gp in ((np.array([[2.0], [0.0], [0.0]]), np.zeros(1)),
+                   (np.zeros((3, 1)), np.array([-1.5]))):
+        gr, gm = oracle.force_backward(r, m, eps, idx, ga, gp)
+        sr, sm = oracle.force_backward_scale(r, m, eps, idx, ga, gp)
+        assert np.array_equal(sr[:, 1], np.abs(gr[:, 1]))
+        assert sm[1] == abs(gm[1])
+
+
 # ---------------------------------------------------------------- eras and passes
 def test_era_forward_matches_the_era_driver(oracle):
     # the fixed-schedule multi-pass run is the era driver's run when the criterion hands
