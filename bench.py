@@ -39,18 +39,27 @@ METRIC = "force interactions/s (mixed vs FP64, same accuracy) + adjoint interact
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# algorithmic flops per interaction (FMA = 2 flops)
+# Algorithmic work per unit of the method (FMA = 2 flops), independent of how a kernel
+# issues it: force 20 flop per interaction (n_act x N interactions per call, the masked
+# self pair counted), force adjoint 52 per interaction when every particle is active (34
+# when the particle is not a target), time-step criterion 15 per pair, energy 12 per
+# unordered pair.
 FLOPS_FORCE = 20.0
-FLOPS_ADJOINT = 73.0
+FLOPS_ADJOINT_ALL = 52.0
+FLOPS_CRITERION = 15.0
 FLOPS_ENERGY_PAIR = 12.0
-FLOPS_CRITERION = 20.0
-# symmetric all-targets kernels, per unordered pair (FMA = 2): criterion 26 (separation 3,
-# r^2 5, velocity difference 3, v^2 5, v^2/r^2 2, two free-fall terms 4, two maxima and two
-# minima 4); force 26 (separation 3, s 6, 1/sqrt(s) 1, y^3 2, two mass factors 2, row and
-# column sums 12); adjoint 64 (see DESIGN)
+# The same kernels counted by what they evaluate: the gather criterion 20 flop per pair
+# (separation 3, r^2 3 FMA, velocity difference 3 and v^2 3 FMA, v^2/r^2 2, free-fall
+# term 2, max and min 2); the symmetric all-targets kernels per unordered pair, each
+# evaluated once for both particles: criterion 26 (separation 3, r^2 5, velocity
+# difference 3, v^2 5, v^2/r^2 2, two free-fall terms 4, two maxima and two minima 4),
+# force 26 (separation 3, s 6, 1/sqrt(s) 1, y^3 2, two mass factors 2, row and column
+# sums 12), adjoint 64 (both rows' tidal-tensor products and mass terms from one pair).
+FLOPS_CRITERION_GATHER = 20.0
 FLOPS_CRITERION_SYM = 26.0
 FLOPS_FORCE_SYM = 26.0
 FLOPS_ADJOINT_SYM = 64.0
+FLOPS_ADJOINT_GATHER = 73.0  # fused all-active gather kernel: source 38 + target 35
 
 # HBM bytes per launch in the default (mixed) era step, from two rocprofv3 --pmc passes
 # over this workload: FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch, averaged over the
@@ -229,6 +238,113 @@ def sweep(cfg, r, v, m, precision, reps=5):
     return out
 
 
+def sweep_c3(reps=20):
+    """Force sweep at N = 32768 (eps = 1/1024, equal masses): the state at t_block = 1/64
+    with t_last = t_block - 2^-(6+l), l drawn uniformly from 0..8 per particle, and the
+    accelerations of the float64 force at the initial positions; active sets of 1, 8, 64,
+    512, 4096 and 32768 random particles.  Each timed call is one prediction of all
+    particles to t_block and one force call (median and minimum over `reps` calls after
+    5 untimed ones), mixed precision against float64."""
+    from paper_1205_2288_amd import Context
+    cfg = config("sweep32768")
+    n = cfg.n
+    r, v, m = cfg.ic()
+    tb = 1.0 / 64
+    lev = np.random.default_rng(cfg.seed + 5).integers(0, 9, n)
+    dt = 2.0 ** -(6 + lev)
+    t_last = tb - dt
+    with Context(n, cfg.eps, precision="fp64") as c:
+        c.bind(r, v, m)
+        c.predict(0.0)
+        a0, _ = c.force(np.arange(n, dtype=np.int32), 0.0, with_pot=False)
+        a0 = a0.cpu().numpy()
+    res = {}
+    for prec in ("mixed", "fp64"):
+        rows = []
+        with Context(n, cfg.eps, precision=prec) as c:
+            c.bind(r, v, m, a=a0, t_last=t_last, dt=dt)
+            for n_act in (1, 8, 64, 512, 4096, 32768):
+                idx = c.idx(active_subset(n, n_act, cfg.seed + 1000 * int(np.log2(n_act))))
+                acc = torch.empty((3, n_act), dtype=torch.float64, device=c.device)
+                pot = torch.empty(n_act, dtype=torch.float64, device=c.device)
+
+                def call():
+                    c.predict(tb)
+                    c.force(idx, tb, acc=acc, pot=pot)
+
+                for _ in range(5):
+                    call()
+                T = Timer()
+                for _ in range(reps):
+                    T("call", call)
+                t = np.array(T.ms()["call"])
+                rows.append({"n_active": n_act, "median_us": round(float(np.median(t)) * 1e3, 2),
+                             "min_us": round(float(t.min()) * 1e3, 2),
+                             "interactions_per_s": n_act * n / (float(np.median(t)) * 1e-3)})
+        res[prec] = rows
+    for a, b in zip(res["mixed"], res["fp64"]):
+        a["fp64_over_mixed"] = b["median_us"] / a["median_us"]
+    return {"workload": "sweep32768: Plummer N=32768, eps=1/1024, equal masses; "
+                        "one predict + one force per call",
+            "mixed": res["mixed"], "fp64": res["fp64"]}
+
+
+def adjoint_c4(reps=3):
+    """The N = 8192 gradient workload: 64 shared leapfrog steps of 1/256 with era-start
+    checkpoints every 16 steps, L = sum |r_final - r_target|^2 (r_target = the float64 run's
+    end positions plus 0.01 N(0, 1)).  Times the forward run alone (no graph), the forward
+    run that keeps the checkpoints, and the backward pass (per-era recompute of the
+    forward plus the reverse sweep with the force adjoint at every step); adjoint
+    interactions/s = 64 N^2 over the backward time."""
+    from paper_1205_2288_amd import Context
+    from paper_1205_2288_amd.autograd import tsbts_leapfrog
+    cfg = config("adjoint8192")
+    n, h, steps, era = cfg.n, 1.0 / 256, 64, 16
+    r0, v0, m = cfg.ic()
+    dev = torch.device("cuda")
+
+    def t_(x, grad=False):
+        return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev,
+                            requires_grad=grad)
+
+    with Context(n, cfg.eps, precision="fp64") as c:
+        with torch.no_grad():
+            r_fin, _ = tsbts_leapfrog(t_(r0), t_(v0), t_(m), c, h, steps, era)
+    target = t_(r_fin.cpu().numpy() + 0.01 * gaussian((3, n), cfg.seed + 7))
+    out = {}
+    for prec in ("mixed", "fp64"):
+        with Context(n, cfg.eps, precision=prec) as c:
+            tf, tg, tb = [], [], []
+            for k in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                with torch.no_grad():
+                    tsbts_leapfrog(t_(r0), t_(v0), t_(m), c, h, steps, era)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rt, vt, mt = t_(r0, True), t_(v0, True), t_(m, True)
+                r_end, _ = tsbts_leapfrog(rt, vt, mt, c, h, steps, era)
+                loss = ((r_end - target) ** 2).sum()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                loss.backward()
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                if k > 0:  # the first run is a warm-up
+                    tf.append(t1 - t0)
+                    tg.append(t2 - t1)
+                    tb.append(t3 - t2)
+            b = float(np.median(tb))
+            out[prec] = {"forward_s": float(np.median(tf)),
+                         "forward_with_checkpoints_s": float(np.median(tg)),
+                         "backward_s": b,
+                         "adjoint_interactions_per_s": steps * float(n) * n / b,
+                         "force_interactions_per_s_forward":
+                             steps * float(n) * n / float(np.median(tf))}
+    return {"workload": "adjoint8192: Plummer N=8192, eps=1/256, 64 shared steps of 1/256, "
+                        "checkpoints every 16 steps", **out}
+
+
 def cpu_baseline(cfg, r, v, m, gpu_force_rows, target_s=12.0):
     """The oracle (plain FP64 C loops, OpenMP) on a bounded sample of the same step's
     work: force plus adjoint for a sample of targets against all N particles."""
@@ -283,51 +399,67 @@ def gpu_force_rows(cfg, r, v, m):
 def rooflines(ms, n, precision="mixed", symmetric=True):
     """Roofline entries per kernel from HIP-event times of their calls in the timed steps.
 
-    Each entry: algorithmic TFLOP/s = (flops per unit x units per call) / mean call time.
-    Gather kernels (active subsets): force n_act*N interactions, criterion n_act*N pairs.
-    Symmetric all-targets kernels (every particle active, mixed precision from N = 32768):
-    N(N-1)/2 unordered pairs, each evaluated once for both particles.  Energy N(N-1)/2
-    pairs.  The events enclose each call's reduction kernels too."""
+    `achieved` = algorithmic TFLOP/s: the per-unit work of the method (force 20 flop per
+    interaction, all-active adjoint 52 per interaction, criterion 15 per pair, energy 12
+    per unordered pair) x the units one call processes (n_act x N interactions or pairs;
+    N(N-1)/2 for the energy), over the mean call time.  `as_evaluated` gives the same
+    time counted by what the kernel evaluates: the symmetric all-targets kernels take
+    each unordered pair once for both particles (N(N-1)/2 pairs at 26, 26 and 64 flop),
+    the gather criterion 20 flop per pair.  The events enclose each call's reduction
+    kernels too."""
     peak32 = PEAK_FP32_TFLOPS if precision == "mixed" else PEAK_FP64_TFLOPS
     out = {}
     pairs = n * (n - 1) / 2
 
-    def entry(kernel, flops, ms_list, peak):
+    def entry(kernel, flop_per_unit, units_per_call, unit, ms_list, peak, evaluated=None):
         t = float(np.sum(ms_list)) * 1e-3
-        achieved = flops / t / 1e12
+        calls = len(ms_list)
+        achieved = flop_per_unit * units_per_call * calls / t / 1e12
         traffic = traffic_bytes(kernel) if precision == "mixed" else None
-        return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "avg_launch_us": t / len(ms_list) * 1e6, "calls": len(ms_list),
-                "total_ms": t * 1e3}
+        e = {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak,
+             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+             "flop_per_unit": flop_per_unit, "work_unit": unit,
+             "units_per_launch": units_per_call,
+             "avg_launch_us": t / calls * 1e6, "calls": calls, "total_ms": t * 1e3}
+        if evaluated is not None:
+            f, u, name = evaluated
+            a = f * u * calls / t / 1e12
+            e["as_evaluated"] = {"flop_per_unit": f, "work_unit": name,
+                                 "units_per_launch": u, "achieved": a, "frac": a / peak}
+        return e
 
-    nf, nh = len(ms["force_full"]), len(ms["force_half"])
-    tf, th = len(ms["timestep_full"]), len(ms["timestep_half"])
-    nb = len(ms["backward"])
-    out["k_force_scalar"] = entry("k_force_scalar", FLOPS_FORCE * n * (n // 2) * nh,
+    nn, nh = float(n) * n, float(n) * (n // 2)
+    out["k_force_scalar"] = entry("k_force_scalar", FLOPS_FORCE, nh, "interaction",
                                   ms["force_half"], peak32)
-    out["k_timestep_scalar"] = entry("k_timestep_scalar",
-                                     FLOPS_CRITERION * n * (n // 2) * th,
-                                     ms["timestep_half"], peak32)
+    out["k_timestep_scalar"] = entry("k_timestep_scalar", FLOPS_CRITERION, nh, "pair",
+                                     ms["timestep_half"], peak32,
+                                     (FLOPS_CRITERION_GATHER, nh, "pair"))
     if symmetric:
-        out["k_force_sym"] = entry("k_force_sym", FLOPS_FORCE_SYM * pairs * nf,
-                                   ms["force_full"], peak32)
-        out["k_timestep_sym"] = entry("k_timestep_sym", FLOPS_CRITERION_SYM * pairs * tf,
-                                      ms["timestep_full"], peak32)
-        out["k_bwd_sym"] = entry("k_bwd_sym", FLOPS_ADJOINT_SYM * pairs * nb,
-                                 ms["backward"], peak32)
+        out["k_force_sym"] = entry("k_force_sym", FLOPS_FORCE, nn, "interaction",
+                                   ms["force_full"], peak32,
+                                   (FLOPS_FORCE_SYM, pairs, "unordered pair"))
+        out["k_timestep_sym"] = entry("k_timestep_sym", FLOPS_CRITERION, nn, "pair",
+                                      ms["timestep_full"], peak32,
+                                      (FLOPS_CRITERION_SYM, pairs, "unordered pair"))
+        out["k_bwd_sym"] = entry("k_bwd_sym", FLOPS_ADJOINT_ALL, nn, "interaction",
+                                 ms["backward"], peak32,
+                                 (FLOPS_ADJOINT_SYM, pairs, "unordered pair"))
     else:
-        out["k_force_scalar"] = entry("k_force_scalar",
-                                      FLOPS_FORCE * n * (nf * n + nh * (n // 2)),
-                                      ms["force_full"] + ms["force_half"], peak32)
-        out["k_timestep_scalar"] = entry("k_timestep_scalar",
-                                         FLOPS_CRITERION * n * (tf * n + th * (n // 2)),
-                                         ms["timestep_full"] + ms["timestep_half"], peak32)
-        out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT * n * n * nb, ms["backward"],
-                                 peak32)
-    out["k_energy_pairs"] = entry("k_energy_pairs",
-                                  FLOPS_ENERGY_PAIR * pairs * len(ms["energy"]),
-                                  ms["energy"], PEAK_FP64_TFLOPS)
+        out["k_force_scalar"] = entry(
+            "k_force_scalar", FLOPS_FORCE, (nn * len(ms["force_full"]) +
+                                            nh * len(ms["force_half"])) /
+            (len(ms["force_full"]) + len(ms["force_half"])), "interaction",
+            ms["force_full"] + ms["force_half"], peak32)
+        u_c = (nn * len(ms["timestep_full"]) + nh * len(ms["timestep_half"])) / \
+            (len(ms["timestep_full"]) + len(ms["timestep_half"]))
+        out["k_timestep_scalar"] = entry("k_timestep_scalar", FLOPS_CRITERION, u_c, "pair",
+                                         ms["timestep_full"] + ms["timestep_half"], peak32,
+                                         (FLOPS_CRITERION_GATHER, u_c, "pair"))
+        out["k_bwd_all"] = entry("k_bwd_all", FLOPS_ADJOINT_ALL, nn, "interaction",
+                                 ms["backward"], peak32,
+                                 (FLOPS_ADJOINT_GATHER, nn, "interaction"))
+    out["k_energy_pairs"] = entry("k_energy_pairs", FLOPS_ENERGY_PAIR, pairs,
+                                  "unordered pair", ms["energy"], PEAK_FP64_TFLOPS)
     return out
 
 
@@ -450,11 +582,14 @@ def main():
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 sums", "data": "synthetic",
+        "dtype": "f32 pair arithmetic (separation formed in f64, rounded once to f32), "
+                 "f64 sums", "data": "synthetic",
         "config": {"workload": "plummer131k: Plummer N=131072, eps=1/4096, log-uniform "
                                "masses; one two-level two-pass era per step",
                    "n": n, "eps": cfg.eps, "seed": cfg.seed, "precision": "mixed",
-                   "interactions_per_step": b.interactions},
+                   "interactions_per_step": b.interactions,
+                   "potential": "not computed in the timed block steps (the integrator "
+                                "does not use it); the sweeps time force + potential"},
         "roofline": roof,
         "rooflines": roofs,
         "force_interactions_per_s": n * n / (np.mean(ms["force_full"]) * 1e-3),
@@ -469,6 +604,9 @@ def main():
         out["sweep_fp64"] = sweep(cfg, r, v, m, "fp64")
     if not args.no_pass_cost:
         out["pass_cost"] = pass_cost()
+    if not args.no_sweep:
+        out["sweep32768"] = sweep_c3()
+        out["adjoint8192"] = adjoint_c4()
     if not args.no_sweep:
         bf = EraBench(cfg, r, v, m, "mixed", fused=True)
         stepsf = max(2, args.steps // 2)
