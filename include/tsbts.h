@@ -93,11 +93,13 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      first such call on a context allocates its work list and partial
  *                      buffers.
  *   TSBTS_TUNE_CHECK_INDICES: 1 = every call that takes active_idx first checks on the
- *                      device that each index lies in [0, n), synchronises the stream and
- *                      returns TSBTS_EINVAL, with nothing else launched, if one does not
- *                      (a debugging aid: one extra launch and one synchronisation per
- *                      call); 0 = indices trusted (default; an index outside [0, n) is
- *                      then undefined behaviour).
+ *                      device that each index lies in [0, n) and occurs once, synchronises
+ *                      the stream and returns TSBTS_EINVAL, with nothing else launched, if
+ *                      not (a debugging aid: two extra launches and one synchronisation
+ *                      per call; enabling it allocates n counters); 0 = indices trusted
+ *                      (default; an index outside [0, n) is then undefined behaviour, and
+ *                      a repeated index leaves undefined output rows when every particle
+ *                      is a target and the symmetric kernels serve the call).
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);
@@ -142,9 +144,8 @@ int tsbts_load_positions(tsbts_ctx *ctx, const double *r, const double *m, doubl
  * TSBTS_ESTATE):
  *   acc_i =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2)
  *   pot_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps^2)^(1/2)
- *   active_idx [n_active] int32   particle indices in [0, n) (any order, no duplicates
- *                                 required by the physics, not checked; the range is
- *                                 checked with TSBTS_TUNE_CHECK_INDICES)
+ *   active_idx [n_active] int32   particle indices in [0, n), any order, each at most
+ *                                 once (both checked with TSBTS_TUNE_CHECK_INDICES)
  *   acc        [3][n_active]      float64 output, row k for particle active_idx[k]
  *   pot        [n_active]         float64 output, or NULL to skip
  * 1 <= n_active <= n.  The sum over j is split over workgroups when the active set is small

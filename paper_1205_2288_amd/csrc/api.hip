@@ -61,13 +61,22 @@ void dev_free(T *&p) {
 
 int check_ctx(const tsbts_ctx *c) { return c ? TSBTS_OK : TSBTS_EINVAL; }
 
-// Flags an active index outside [0, n) (reads the index list only).
+__global__ __launch_bounds__(kWG) void k_zero_i32(int32_t *x, int64_t len) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (k < len) x[k] = 0;
+}
+
+// Flags an active index outside [0, n) in flag[0] and an index that occurs more than once
+// in flag[1] (seen: n counters, zero on entry).
 __global__ __launch_bounds__(kWG) void k_check_idx(const int32_t *idx, int32_t n_act, int64_t n,
-                                                   int *flag) {
+                                                   int32_t *seen, int *flag) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (k < n_act) {
     const int32_t v = idx[k];
-    if (v < 0 || v >= n) *flag = 1;
+    if (v < 0 || v >= n)
+      flag[0] = 1;
+    else if (atomicAdd(&seen[v], 1) != 0)
+      flag[1] = 1;
   }
 }
 
@@ -77,16 +86,19 @@ int check_active(tsbts_ctx *c, const int32_t *idx, int32_t n_act, hipStream_t st
     return fail(c, TSBTS_EINVAL, "n_active=%d outside [1, %lld]", n_act,
                 static_cast<long long>(c->n));
   if (c->check_idx) {
-    // every earlier use of the flag ended with a synchronisation, so it is free here
-    *c->idx_flag_h = 0;
+    // every earlier use of the flags ended with a synchronisation, so they are free here
+    c->idx_flag_h[0] = c->idx_flag_h[1] = 0;
+    hipLaunchKernelGGL(k_zero_i32, dim3((c->n + kWG - 1) / kWG), dim3(kWG), 0, stream,
+                       c->idx_seen, c->n);
     hipLaunchKernelGGL(k_check_idx, dim3((n_act + kWG - 1) / kWG), dim3(kWG), 0, stream, idx,
-                       n_act, c->n, c->idx_flag_d);
+                       n_act, c->n, c->idx_seen, c->idx_flag_d);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "active index check");
-    if (*c->idx_flag_h)
+    if (c->idx_flag_h[0])
       return fail(c, TSBTS_EINVAL, "active_idx holds an index outside [0, %lld)",
                   static_cast<long long>(c->n));
+    if (c->idx_flag_h[1]) return fail(c, TSBTS_EINVAL, "active_idx repeats an index");
   }
   return TSBTS_OK;
 }
@@ -126,66 +138,55 @@ int ensure_part(tsbts_ctx *c, int64_t need) {
   return TSBTS_OK;
 }
 
-// Grow a [planes][cap] float64 buffer, preserving the first `used` entries of each plane.
-int grow_planes(tsbts_ctx *c, double *&buf, int64_t &cap, int planes, int64_t used,
-                int64_t need, hipStream_t st, double **t_buf = nullptr) {
-  if (need <= cap) return TSBTS_OK;
-  const int64_t ncap = std::max<int64_t>(need, cap + cap / 2 + 1024);
-  double *nb = nullptr;
-  int s = dev_alloc(c, &nb, ncap * planes);
-  if (s) return s;
-  double *nt = nullptr;
-  if (t_buf) {
-    s = dev_alloc(c, &nt, ncap);
-    if (s) {
-      dev_free(nb);
-      return s;
-    }
-  }
-  if (used > 0) {
-    for (int p = 0; p < planes; ++p)
-      TSBTS_CHECK_HIP(c, hipMemcpyAsync(nb + p * ncap, buf + p * cap, used * sizeof(double),
-                                        hipMemcpyDeviceToDevice, st));
-    if (t_buf)
-      TSBTS_CHECK_HIP(c, hipMemcpyAsync(nt, *t_buf, used * sizeof(double),
-                                        hipMemcpyDeviceToDevice, st));
-  }
-  // earlier kernels may still read the old buffer: wait before freeing it
-  TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
-  dev_free(buf);
-  buf = nb;
-  if (t_buf) {
-    dev_free(*t_buf);
-    *t_buf = nt;
-  }
-  cap = ncap;
-  return TSBTS_OK;
-}
-
+// Grow the era log to at least `need` records, preserving the `count` records appended
+// so far.  Every new buffer is allocated before anything changes: on a failed allocation
+// the log keeps its old buffers, capacity and contents.
 int grow_log(tsbts_ctx *c, int64_t need, hipStream_t st) {
   History &h = c->h;
   if (need <= h.cap) return TSBTS_OK;
-  const int64_t old_cap = h.cap;
-  int64_t cap = h.cap;
-  int s = grow_planes(c, h.s, cap, kHistPlanes, h.count, need, st, &h.t);
-  if (s) return s;
-  // index arrays
+  const int64_t cap = std::max<int64_t>(need, h.cap + h.cap / 2 + 1024);
+  double *ns = nullptr, *nt = nullptr;
   int32_t *np = nullptr, *nr = nullptr;
-  if ((s = dev_alloc(c, &np, cap))) return s;
-  if ((s = dev_alloc(c, &nr, cap))) {
+  int s = dev_alloc(c, &ns, cap * kHistPlanes);
+  if (!s) s = dev_alloc(c, &nt, cap);
+  if (!s) s = dev_alloc(c, &np, cap);
+  if (!s) s = dev_alloc(c, &nr, cap);
+  if (s) {
+    dev_free(ns);
+    dev_free(nt);
     dev_free(np);
+    dev_free(nr);
     return s;
   }
+  hipError_t e = hipSuccess;
   if (h.count > 0) {
-    TSBTS_CHECK_HIP(c, hipMemcpyAsync(np, h.pid, h.count * sizeof(int32_t),
-                                      hipMemcpyDeviceToDevice, st));
-    TSBTS_CHECK_HIP(c, hipMemcpyAsync(nr, h.rank, h.count * sizeof(int32_t),
-                                      hipMemcpyDeviceToDevice, st));
+    const size_t used = static_cast<size_t>(h.count);
+    for (int p = 0; p < kHistPlanes && e == hipSuccess; ++p)
+      e = hipMemcpyAsync(ns + p * cap, h.s + p * h.cap, used * sizeof(double),
+                         hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(nt, h.t, used * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(np, h.pid, used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(nr, h.rank, used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   }
-  TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
-  (void)old_cap;
+  // earlier kernels may still read the old buffers, and the copies must land: wait
+  // before freeing them
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    dev_free(ns);
+    dev_free(nt);
+    dev_free(np);
+    dev_free(nr);
+    return hip_fail(c, e, "era log growth");
+  }
+  dev_free(h.s);
+  dev_free(h.t);
   dev_free(h.pid);
   dev_free(h.rank);
+  h.s = ns;
+  h.t = nt;
   h.pid = np;
   h.rank = nr;
   h.cap = cap;
@@ -275,6 +276,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   if (c->sym_items) (void)hipFree(c->sym_items);
   if (c->sym_part) (void)hipFree(c->sym_part);
   if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
+  dev_free(c->idx_seen);
   dev_free(c->h.pid);
   dev_free(c->h.rank);
   dev_free(c->h.t);
@@ -313,15 +315,20 @@ int tsbts_tune(tsbts_ctx *c, int param, int value) {
     case TSBTS_TUNE_CHECK_INDICES:
       if (value != 0 && value != 1) return fail(c, TSBTS_EINVAL, "check must be 0 or 1");
       if (value && !c->idx_flag_h) {
-        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->idx_flag_h), sizeof(int));
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->idx_flag_h), 2 * sizeof(int));
         if (e == hipSuccess)
           e = hipHostGetDevicePointer(reinterpret_cast<void **>(&c->idx_flag_d), c->idx_flag_h,
                                       0);
+        if (e == hipSuccess)
+          e = hipMalloc(reinterpret_cast<void **>(&c->idx_seen), sizeof(int32_t) * c->n);
         if (e != hipSuccess) {
+          (void)hipGetLastError();
           if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
+  dev_free(c->idx_seen);
           c->idx_flag_h = nullptr;
           c->idx_flag_d = nullptr;
-          return hip_fail(c, e, "index check flag");
+          c->idx_seen = nullptr;
+          return hip_fail(c, e, "index check buffers");
         }
       }
       c->check_idx = value;
@@ -517,14 +524,27 @@ int tsbts_history_end(tsbts_ctx *c, hipStream_t stream) {
   if (!c->h.recording) return fail(c, TSBTS_ESTATE, "no history is being recorded");
   History &h = c->h;
   if (h.count > h.hcap) {
-    // the finished buffers are replaced wholesale, nothing to preserve
-    TSBTS_CHECK_HIP(c, hipDeviceSynchronize());
+    // the finished buffers are replaced wholesale, nothing to preserve; the new ones are
+    // allocated first, so a failed allocation leaves the previous history usable
+    const int64_t cap = std::max<int64_t>(h.count, h.cap);
+    double *hs = nullptr, *ht = nullptr;
+    int s = dev_alloc(c, &hs, cap * kHistPlanes);
+    if (!s) s = dev_alloc(c, &ht, cap);
+    if (s) {
+      dev_free(hs);
+      return s;
+    }
+    // earlier kernels (predictions from the previous history) may still read the old ones
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      dev_free(hs);
+      dev_free(ht);
+      return hip_fail(c, e, "tsbts_history_end");
+    }
     dev_free(h.ht);
     dev_free(h.hs);
-    h.hcap = 0;
-    const int64_t cap = std::max<int64_t>(h.count, h.cap);
-    if (int s = dev_alloc(c, &h.hs, cap * kHistPlanes)) return s;
-    if (int s = dev_alloc(c, &h.ht, cap)) return s;
+    h.hs = hs;
+    h.ht = ht;
     h.hcap = cap;
   }
   hipError_t e = launch_history_end(c, stream);

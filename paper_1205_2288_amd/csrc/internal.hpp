@@ -73,7 +73,10 @@ struct tsbts_ctx {
   int tune_chunk = 0;  // j-particles per split unit of the scalar-load kernels (0: automatic)
   int tune_sym = 2;    // symmetric all-targets kernels: 0 off, 1 on, 2 automatic
   int check_idx = 0;   // device range check of every active set (TSBTS_TUNE_CHECK_INDICES)
-  int *idx_flag_h = nullptr, *idx_flag_d = nullptr;  // its result (mapped pinned memory)
+  int *idx_flag_h = nullptr, *idx_flag_d = nullptr;  // its results: [0] an index out of
+                                                      // range, [1] a repeated index
+                                                      // (mapped pinned memory)
+  int32_t *idx_seen = nullptr;  // [n] occurrence counters of the check
   // symmetric all-targets kernels: work items (int4) and partials
   void *sym_items = nullptr;
   int sym_items_n = 0;

@@ -145,7 +145,39 @@ def test_index_check_mode():
         ctx.timestep(bad, 0.1)
     acc, _ = ctx.force(good, 0.0)  # still usable after a refusal
     assert torch.equal(acc, acc_ref)
+    rep = torch.tensor([0, 5, 9, 5], dtype=torch.int32, device=ctx.device)
+    with pytest.raises(TsbtsError, match="repeats"):
+        ctx.force(rep, 0.0)
+    with pytest.raises(TsbtsError, match="repeats"):
+        ctx.force_backward(rep, 0.0, np.ones((3, 4)))
+    acc, _ = ctx.force(good, 0.0)
+    assert torch.equal(acc, acc_ref)
     with pytest.raises(TsbtsError):
         ctx.tune(check_indices=2)
     ctx.tune(check_indices=0)
+    ctx.close()
+
+
+def test_index_check_mode_full_set_permutation():
+    # every particle a target at N = 32768 (the symmetric kernels, which write their rows
+    # through the inverse of the active list): a list with a repeated index is refused in
+    # check mode; a permutation gives the same results as without the check
+    from paper_1205_2288_amd._lib import TsbtsError
+    n = 32768
+    r, v, m = plummer(n, 4)
+    ctx = make_ctx(n, 1 / 1024, "mixed")
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    perm = np.random.default_rng(2).permutation(n).astype(np.int32)
+    good = ctx.idx(perm)
+    acc_ref, _ = ctx.force(good, 0.0)
+    ctx.tune(check_indices=1)
+    acc, _ = ctx.force(good, 0.0)
+    assert torch.equal(acc, acc_ref)
+    dup = perm.copy()
+    dup[100] = dup[2000]
+    with pytest.raises(TsbtsError, match="repeats"):
+        ctx.force(ctx.idx(dup), 0.0)
+    with pytest.raises(TsbtsError, match="repeats"):
+        ctx.timestep(ctx.idx(dup), 0.1)
     ctx.close()
