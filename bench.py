@@ -524,6 +524,53 @@ def pass_cost(t_end=1.0):
     return out
 
 
+def force_calls(sizes, precision, reps=5):
+    """predict + force at each active-set size on the N = 131072 workload (the sweep's
+    subsets), mean call time over `reps` calls after 2 untimed ones."""
+    from paper_1205_2288_amd import Context
+    cfg = config("plummer131k")
+    n = cfg.n
+    r, v, m = cfg.ic()
+    out = []
+    with Context(n, cfg.eps, precision=precision) as c:
+        c.bind(r, v, m)
+        for n_act in sizes:
+            k = int(np.log2(n // n_act)) if n_act < n else 0
+            idx = c.idx(active_subset(n, n_act, cfg.seed + 1000 * k))
+            acc = torch.empty((3, n_act), dtype=torch.float64, device=c.device)
+            pot = torch.empty(n_act, dtype=torch.float64, device=c.device)
+            for _ in range(2):
+                c.predict(0.0)
+                c.force(idx, 0.0, acc=acc, pot=pot)
+            T = Timer()
+            for _ in range(reps):
+                c.predict(0.0)
+                T("force", c.force, idx, 0.0, acc=acc, pot=pot)
+            out.append({"n_active": n_act, "force_us": float(np.mean(T.ms()["force"])) * 1e3})
+    return {"workload": "plummer131k", "precision": precision, "calls": out}
+
+
+def native_run(name, t_end, precision):
+    """One whole integration of a workload with the native scheduler (its own era, step
+    bounds and eta): wall time, block steps and the mean wall time per block step."""
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    cfg = config(name)
+    r, v, m = cfg.ic()
+    sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=cfg.era,
+                      dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=precision)
+    series = sim.run(t_end)
+    st = sim.stats
+    e0 = series[0][1]
+    out = {"workload": name, "precision": precision, "t_end": t_end,
+           "wall_s": st["wall_s"], "block_steps": st["block_steps"],
+           "us_per_block_step": st["wall_s"] / st["block_steps"] * 1e6,
+           "interactions": st["interactions"], "eras": st["eras"],
+           "era_sizes": st["era_sizes"],
+           "drift": max(abs(e - e0) / abs(e0) for _, e in series)}
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,6 +580,15 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-pass-cost", action="store_true")
+    ap.add_argument("--native-run", default=None, metavar="WORKLOAD",
+                    help="only integrate WORKLOAD (plummer256, plummer4096) with the native "
+                         "scheduler to --t-end and print its block-step statistics (for "
+                         "kernel traces of whole runs)")
+    ap.add_argument("--t-end", type=float, default=1.0)
+    ap.add_argument("--force-calls", default=None, metavar="N_ACT[,N_ACT...]",
+                    help="only time predict + force calls on the N=131072 workload at these "
+                         "active-set sizes (5 each after 2 untimed; for counter runs)")
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -544,6 +600,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.native_run:
+        print(json.dumps(native_run(args.native_run, args.t_end, args.precision)))
+        return
+    if args.force_calls:
+        sizes = [int(x) for x in args.force_calls.split(",")]
+        print(json.dumps(force_calls(sizes, args.precision)))
+        return
     cfg = config("plummer131k")
     n = cfg.n
     r, v, m = cfg.ic()

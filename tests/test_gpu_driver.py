@@ -226,6 +226,32 @@ def test_experiments_module_small():
             assert a[kind]["block_steps"] == b[kind]["block_steps"]
 
 
+def test_era_study_matches_oracle():
+    # the era-size / iteration study driver (64 bodies, two spheres, eras 1/64 and 1/8,
+    # 1 and 3 passes, float64, t = 0..2) against the oracle's integrations of the same
+    # spheres with the same parameters, run by run: the same number of block steps and
+    # the same energy-error series up to rounding, hence the same drift
+    import io
+    from paper_1205_2288_amd import experiments as ex
+    rows, summary = ex.era_study(n=64, seeds=2, t_end=2.0, eras=(1 / 64, 1 / 8),
+                                 passes=(1, 3), every=1.0, seed0=1205, out=io.StringIO())
+    assert len(rows) == 8 and len(summary) == 4
+    for row in rows:
+        r, v, m = plummer(64, row["seed"])
+        ref = OracleTSBTS(r, v, m, row["eps"], eta=row["eta"], passes=row["passes"],
+                          era=row["era"], dt_max=row["dt_max"])
+        series = ref.run(row["t_end"], energy_every=1.0)
+        e0 = series[0][1]
+        err = np.array([abs(e - e0) / abs(e0) for _, e in series])
+        print(f"seed {row['seed']} passes {row['passes']} era {row['era']}: block steps "
+              f"{row['block_steps']} (oracle {ref.stats['block_steps']}), max error "
+              f"{row['max_err']:.4e} (oracle {err.max():.4e})")
+        assert row["series_t"] == [t for t, _ in series]
+        assert row["block_steps"] == ref.stats["block_steps"]
+        assert np.abs(np.array(row["series_err"]) - err).max() <= 1e-10 * max(1.0, err.max())
+        assert row["max_err"] <= 2.0 * err.max() + 1e-14
+
+
 @pytest.mark.parametrize("prec,era", [("fp64", 1.0 / 8), ("mixed", None)])
 def test_native_checkpoint_resume_bitwise(prec, era):
     # an era-end checkpoint, saved through numpy's npz format and restored into a fresh
