@@ -525,8 +525,9 @@ def pass_cost(t_end=1.0):
 
 
 def force_calls(sizes, precision, reps=5):
-    """predict + force at each active-set size on the N = 131072 workload (the sweep's
-    subsets), mean call time over `reps` calls after 2 untimed ones."""
+    """predict + force + criterion (on the predicted state) at each active-set size on the
+    N = 131072 workload (the sweep's subsets), mean call times over `reps` calls after 2
+    untimed ones."""
     from paper_1205_2288_amd import Context
     cfg = config("plummer131k")
     n = cfg.n
@@ -542,11 +543,17 @@ def force_calls(sizes, precision, reps=5):
             for _ in range(2):
                 c.predict(0.0)
                 c.force(idx, 0.0, acc=acc, pot=pot)
+            dtc = torch.empty(n_act, dtype=torch.float64, device=c.device)
+            for _ in range(2):
+                c.timestep(idx, cfg.eta, dtc=dtc)
             T = Timer()
             for _ in range(reps):
                 c.predict(0.0)
                 T("force", c.force, idx, 0.0, acc=acc, pot=pot)
-            out.append({"n_active": n_act, "force_us": float(np.mean(T.ms()["force"])) * 1e3})
+                T("criterion", c.timestep, idx, cfg.eta, dtc=dtc)
+            ms = T.ms()
+            out.append({"n_active": n_act, "force_us": float(np.mean(ms["force"])) * 1e3,
+                        "criterion_us": float(np.mean(ms["criterion"])) * 1e3})
     return {"workload": "plummer131k", "precision": precision, "calls": out}
 
 
@@ -586,8 +593,9 @@ def main():
                          "kernel traces of whole runs)")
     ap.add_argument("--t-end", type=float, default=1.0)
     ap.add_argument("--force-calls", default=None, metavar="N_ACT[,N_ACT...]",
-                    help="only time predict + force calls on the N=131072 workload at these "
-                         "active-set sizes (5 each after 2 untimed; for counter runs)")
+                    help="only time predict + force + criterion calls on the N=131072 "
+                         "workload at these active-set sizes (5 each after 2 untimed; for "
+                         "counter runs)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "

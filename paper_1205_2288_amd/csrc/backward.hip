@@ -169,9 +169,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_src(BwdArgs A) {
   __shared__ Col<V> sc[kTJ];
   __shared__ int srange[2][kWG / 64];
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int rtile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int rtile, slice;
+  split_tile(blockIdx.x, A.plan, rtile, slice);
   if (slice >= A.plan.n_slices) return;
   const int ct0 = slice * A.plan.tiles_per_slice;
   const int ct1 = min(ct0 + A.plan.tiles_per_slice, A.n_ctiles);
@@ -290,9 +289,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_tgt(BwdArgs A) {
   using F = typename V::F;
   __shared__ typename V::J sj[kTJ];
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);
@@ -406,9 +404,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_all(BwdArgs A) {
   using F = typename V::F;
   __shared__ ColAll<V> sc[kTJ];
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int rtile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int rtile, slice;
+  split_tile(blockIdx.x, A.plan, rtile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);
@@ -476,9 +473,8 @@ template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_bwd_all_scalar(BwdArgs A) {
   using F = typename V::F;
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int rtile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int rtile, slice;
+  split_tile(blockIdx.x, A.plan, rtile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_ctiles);

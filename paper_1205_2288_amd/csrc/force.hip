@@ -81,9 +81,8 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   using F = typename V::F;
   __shared__ typename V::J sj[kTJ];
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
@@ -164,9 +163,8 @@ __device__ __forceinline__ void scalar_tile(const ForceArgs &A, const typename V
 template <class V, int NEWTON, int POT, int CH>
 __global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
   using F = typename V::F;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);

@@ -73,9 +73,8 @@ __device__ __forceinline__ void fused_unit(const FusedArgs &A, const typename V:
 template <class V, int NEWTON, int POT, int CH>
 __global__ __launch_bounds__(kWG) void k_fused(FusedArgs A) {
   using F = typename V::F;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_units);

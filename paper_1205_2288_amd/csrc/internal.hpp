@@ -170,6 +170,23 @@ struct SplitPlan {
 
 SplitPlan plan_split(int64_t n_targets, int ipl, int64_t n_jtiles, int target_blocks);
 
+// Block -> (target tile, j-slice) of a split launch.  Each XCD takes a contiguous range of
+// logical ids (xcd_linear).  When the slice count is a multiple of 8, each XCD's range is
+// one group of n_slices/8 consecutive slices in which the slice varies fastest: the
+// workgroups an XCD runs back to back share a target tile, whose gathered records then
+// come from that XCD's L2, and sweep the group's slices, whose sources stay in the same
+// L2.  Otherwise the target tile varies fastest over all slices.  Either way every
+// (tile, slice) pair is computed by exactly one workgroup, as before the remapping.
+__device__ __forceinline__ void split_tile(int bid, const SplitPlan &p, int &itile,
+                                           int &slice) {
+  const int L = xcd_linear(bid, p.nblk);
+  const int g = (p.n_slices & 7) == 0 ? (p.n_slices >> 3) : 1;
+  const int per = g * p.n_itiles;
+  const int r = L % per;
+  itile = r / g;
+  slice = (L / per) * g + r % g;
+}
+
 // Targets per lane of the force and criterion kernels for an active set of n_act.
 inline int targets_per_lane(const tsbts_ctx *c, int n_act) {
   if (c->tune_ipl) return c->tune_ipl;

@@ -54,9 +54,8 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
   using J = typename StepRec<V>::J;
   __shared__ J sj[kTJ];
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
@@ -121,9 +120,8 @@ template <class V, int IPL, int CH>
 __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
   using F = typename V::F;
   const int tid = threadIdx.x;
-  const int L = xcd_linear(blockIdx.x, A.plan.nblk);
-  const int itile = L % A.plan.n_itiles;
-  const int slice = L / A.plan.n_itiles;
+  int itile, slice;
+  split_tile(blockIdx.x, A.plan, itile, slice);
   if (slice >= A.plan.n_slices) return;
   const int jt0 = slice * A.plan.tiles_per_slice;
   const int jt1 = min(jt0 + A.plan.tiles_per_slice, A.n_jtiles);
