@@ -88,10 +88,11 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *   TSBTS_TUNE_SYMMETRIC: when every particle is a target (n_active = n), evaluate each
  *                      unordered pair once for both of its particles (0 = never, 1 =
  *                      always, 2 = automatic: from 32768 particles while the partial
- *                      sums (about N^2/64 bytes) fit 32 GiB; default 2).  The criterion (maxima and minima) is then
- *                      bit-identical; sums are combined in another fixed order.  The
- *                      first such call on a context allocates its work list and partial
- *                      buffers.
+ *                      sums, which grow linearly (about 6 KB per particle), fit 32 GiB:
+ *                      N up to about 5.6 million; default 2).  The criterion (maxima and
+ *                      minima) is then bit-identical; sums are combined in another fixed
+ *                      order.  The first such call on a context allocates its work list
+ *                      and partial buffers.
  *   TSBTS_TUNE_CHECK_INDICES: 1 = every call that takes active_idx first checks on the
  *                      device that each index lies in [0, n) and occurs once, synchronises
  *                      the stream and returns TSBTS_EINVAL, with nothing else launched, if
@@ -165,8 +166,8 @@ int tsbts_force(tsbts_ctx *ctx, const int32_t *active_idx, int32_t n_active, dou
  * every GPU the library runs on until the process ends, and its address is looked up
  * once per device by the first tsbts_create there.
  * Arguments, checks and outputs are those of tsbts_force.  Differences:
- *   - the all-targets symmetric kernels are never used (their partials are about N^2/64
- *     bytes); the gather kernels serve every call;
+ *   - the all-targets symmetric kernels are never used (their partials take about 6 KB
+ *     per particle); the gather kernels serve every call;
  *   - the split of the j-sum is tsbts_force's when its partials fit the array, otherwise
  *     it aims for fewer workgroups (halving until they fit); results are then equal to
  *     tsbts_force's within rounding (another fixed order of float64 tile sums), and bit

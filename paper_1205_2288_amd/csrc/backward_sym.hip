@@ -123,75 +123,79 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym(BwdSymArgs A0, const float *__r
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int4 it = A.plan.items[blockIdx.x];  // one work item per workgroup
-  const int64_t row0 = (static_cast<int64_t>(it.x) * kSymWaves + wv) * kSymWaveRows;
-  typename V::I rows[kSymRows];
-  F mr[kSymRows], gr[kSymRows][4];
-  int k[kSymRows];
-  double tot[kSymRows][4];
-#pragma unroll
-  for (int r = 0; r < kSymRows; ++r) {
-    k[r] = static_cast<int>(row0) + r * 64 + lane;
-    const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
-    rows[r] = V::load_i(A.p32, A.p64, A.npad, kk);
-    if constexpr (sizeof(F) == 4)
-      mr[r] = A.p32[P32_M * A.npad + kk];
-    else
-      mr[r] = A.p64[P64_M * A.npad + kk];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      gr[r][v] = g32[v * A.npad + kk];
-      tot[r][v] = 0.0;
-    }
-  }
   F *L = lds[wv];
   F *cpart = col_part + static_cast<int64_t>(it.x) * 4 * A.npad;
-  const bool rows_pad = row0 + kSymWaveRows > A.n;
+  double *rp = row_part + static_cast<int64_t>(it.w) * 4 * A.plan.npad_rows;
   int buf = 0;
-  for (int64_t jt = it.y; jt < it.z; jt += 64) {
-    F a[kSymRows][4];
+  SymSub sg;
+  for (int sub = 0; sym_sub(A.plan, it, sub, sg); ++sub) {
+    const int64_t row0 = sg.grow0 + static_cast<int64_t>(wv) * kSymWaveRows;
+    typename V::I rows[kSymRows];
+    F mr[kSymRows], gr[kSymRows][4];
+    int k[kSymRows];
+    double tot[kSymRows][4];
 #pragma unroll
-    for (int r = 0; r < kSymRows; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a[r][v] = F(0);
-    for (int64_t jb = jt; jb < jt + 64; jb += BLK) {
-      if (rows_pad || jb < row0 + kSymWaveRows || jb + BLK > A.n)
-        bwd_block<V, 1>(A, g32, rows, mr, gr, k, jb, a, L, lane);
+    for (int r = 0; r < kSymRows; ++r) {
+      k[r] = static_cast<int>(row0) + r * 64 + lane;
+      const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
+      rows[r] = V::load_i(A.p32, A.p64, A.npad, kk);
+      if constexpr (sizeof(F) == 4)
+        mr[r] = A.p32[P32_M * A.npad + kk];
       else
-        bwd_block<V, 0>(A, g32, rows, mr, gr, k, jb, a, L, lane);
-      wave_lds_sync();
-      F cs[4];
-      sym_col_sums<BLK, 4>(L, lane, cs);
-      sym_group_store<BLK, 4>(xs, buf, wv, lane, cs, cpart + jb, A.npad,
-                              [](F x, F y) { return x + y; });
-      wave_lds_sync();
+        mr[r] = A.p64[P64_M * A.npad + kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        gr[r][v] = g32[v * A.npad + kk];
+        tot[r][v] = 0.0;
+      }
+    }
+    const bool rows_pad = row0 + kSymWaveRows > A.n;
+    for (int64_t jt = sg.j0; jt < it.z; jt += 64) {
+      F a[kSymRows][4];
+#pragma unroll
+      for (int r = 0; r < kSymRows; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[r][v] = F(0);
+      for (int64_t jb = jt; jb < jt + 64; jb += BLK) {
+        if (rows_pad || jb < row0 + kSymWaveRows || jb + BLK > A.n)
+          bwd_block<V, 1>(A, g32, rows, mr, gr, k, jb, a, L, lane);
+        else
+          bwd_block<V, 0>(A, g32, rows, mr, gr, k, jb, a, L, lane);
+        wave_lds_sync();
+        F cs[4];
+        sym_col_sums<BLK, 4>(L, lane, cs);
+        sym_group_store<BLK, 4>(xs, buf, wv, lane, cs, cpart + jb, A.npad,
+                                [](F x, F y) { return x + y; }, sub > 0);
+        wave_lds_sync();
+      }
+#pragma unroll
+      for (int r = 0; r < kSymRows; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tot[r][v] += static_cast<double>(a[r][v]);
     }
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tot[r][v] += static_cast<double>(a[r][v]);
+      for (int v = 0; v < 4; ++v) rp[v * A.plan.npad_rows + k[r]] = tot[r][v];
   }
-  double *rp = row_part + static_cast<int64_t>(it.w) * 4 * A.plan.npad_rows;
-#pragma unroll
-  for (int r = 0; r < kSymRows; ++r)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) rp[v * A.plan.npad_rows + k[r]] = tot[r][v];
 }
 
-// Particle p: its row group's row partials in slot order, then the column partials of the
-// row groups 0 .. its own, added to grad_r and grad_m.
+// Particle p: the row partials of the items of its band that reach its row group, in
+// slot order, then the column partials of the bands 0 .. its own, added to grad_r and
+// grad_m.
 template <class F>
 __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
-  const int R = static_cast<int>(p / kSymGroupRows);  // the particle's row group
-  const int slots = sym_slots(A.npad, R, A.plan.chunk);
+  int band, s0, s1;
+  sym_row_slots(A.plan, A.npad, p, band, s0, s1);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   const double *rp = static_cast<const double *>(A.plan.row_part);
-  for (int s = 0; s < slots; ++s)
+  for (int s = s0; s < s1; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
   const F *cp = static_cast<const F *>(A.plan.col_part);
-  for (int u = 0; u <= R; ++u)
+  for (int u = 0; u <= band; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
 #pragma unroll

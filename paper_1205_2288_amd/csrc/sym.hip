@@ -7,15 +7,38 @@
 namespace tsbts {
 namespace {
 
-int sym_chunk(int64_t npad) {
-  const int64_t n_groups = (npad + kSymGroupRows - 1) / kSymGroupRows;
-  // about kSymTargetItems waves' worth of items over the upper triangle, whole column tiles
-  // of 64
-  const int64_t waves = kSymTargetItems / kSymWaves;
-  const int64_t cols = (npad * n_groups / 2 + waves - 1) / waves;
-  int64_t chunk = std::max<int64_t>(64, (cols + 63) / 64 * 64);
+// Layout of the work items for npad particles: row groups per band, bands, column chunk.
+struct SymShape {
+  int n_groups, band_groups, n_bands, chunk, max_slots;
+};
+
+SymShape sym_shape(int64_t npad) {
+  SymShape s;
+  s.n_groups = static_cast<int>((npad + kSymGroupRows - 1) / kSymGroupRows);
+  s.band_groups = (s.n_groups + kSymMaxBands - 1) / kSymMaxBands;
+  s.n_bands = (s.n_groups + s.band_groups - 1) / s.band_groups;
+  // about kSymTargetItems waves' worth of items over the upper triangle (a band has about
+  // npad / (2 chunk) items on average), whole column tiles of 64, and at most
+  // kSymMaxSlots chunks per band
+  const int64_t items = kSymTargetItems / kSymWaves;
+  const int64_t by_items = (s.n_bands * npad / 2 + items - 1) / items;
+  const int64_t by_slots = (npad + kSymMaxSlots - 1) / kSymMaxSlots;
+  int64_t chunk = std::max<int64_t>({64, by_items, by_slots});
+  chunk = (chunk + 63) / 64 * 64;
   chunk = std::min<int64_t>(chunk, (npad + 63) / 64 * 64);
-  return static_cast<int>(chunk);
+  s.chunk = static_cast<int>(chunk);
+  s.max_slots = sym_slots(npad, 0, s.chunk);
+  return s;
+}
+
+// Partial-buffer bytes for nv values per particle: row partials of row_bytes, column
+// partials of col_bytes, then the staged float32 values and the inverse permutation.
+int64_t sym_buffer_bytes(const SymShape &sh, int64_t npad, int nv, int row_bytes,
+                         int col_bytes) {
+  const int64_t npad_rows = static_cast<int64_t>(sh.n_groups) * kSymGroupRows;
+  return (static_cast<int64_t>(sh.max_slots) * npad_rows * row_bytes +
+          static_cast<int64_t>(sh.n_bands) * npad * col_bytes) * nv +
+         npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
 }
 
 }  // namespace
@@ -42,20 +65,16 @@ hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act
 
 // Partial-buffer bytes for nv values per particle (float64 rows, col_bytes columns).
 int64_t sym_bytes(int64_t npad, int nv, int col_bytes) {
-  const int chunk = sym_chunk(npad);
-  const int64_t n_groups = (npad + kSymGroupRows - 1) / kSymGroupRows;
-  const int64_t npad_rows = n_groups * kSymGroupRows;
-  const int64_t max_slots = sym_slots(npad, 0, chunk);
-  return (max_slots * npad_rows * 8 + n_groups * npad * col_bytes) * nv +
-         npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
+  return sym_buffer_bytes(sym_shape(npad), npad, nv, 8, col_bytes);
 }
 
 bool sym_enabled(const tsbts_ctx *c, int64_t n_act) {
   if (n_act != c->n) return false;
   if (c->tune_sym == 0) return false;
   if (c->tune_sym == 1) return true;
-  // automatic: from kSymMinN particles while the partials (which grow as N^2 / 256 column
-  // sums) stay within kSymMaxBytes
+  // automatic: from kSymMinN particles while the partials (at most kSymMaxSlots row and
+  // kSymMaxBands column values per particle and value: about 6 KB per particle with four
+  // values, 768 MB at N = 131072) stay within kSymMaxBytes (N up to about 5.6 million)
   const int cb = c->precision == TSBTS_FP64 ? 8 : 4;
   return c->n >= kSymMinN && sym_bytes(c->npad, 4, cb) <= kSymMaxBytes;
 }
@@ -66,15 +85,15 @@ bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act) {
 
 int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
   const int64_t npad = c->npad;
-  const int chunk = sym_chunk(npad);
-  const int n_groups = static_cast<int>((npad + kSymGroupRows - 1) / kSymGroupRows);
-  if (c->sym_items_npad != npad || c->sym_chunk != chunk) {
+  const SymShape sh = sym_shape(npad);
+  if (c->sym_items_npad != npad || c->sym_chunk != sh.chunk) {
     std::vector<int4> items;
-    for (int g = 0; g < n_groups; ++g) {
+    for (int b = 0; b < sh.n_bands; ++b) {
+      const int64_t first = static_cast<int64_t>(b) * sh.band_groups * kSymGroupRows;
       int s = 0;
-      for (int64_t j0 = static_cast<int64_t>(g) * kSymGroupRows; j0 < npad; j0 += chunk, ++s)
-        items.push_back(make_int4(g, static_cast<int>(j0),
-                                  static_cast<int>(std::min<int64_t>(j0 + chunk, npad)), s));
+      for (int64_t j0 = first; j0 < npad; j0 += sh.chunk, ++s)
+        items.push_back(make_int4(b, static_cast<int>(j0),
+                                  static_cast<int>(std::min<int64_t>(j0 + sh.chunk, npad)), s));
     }
     if (c->sym_items) (void)hipFree(c->sym_items);
     c->sym_items = nullptr;
@@ -82,6 +101,7 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
     c->sym_items_npad = 0;
     if (hipMalloc(reinterpret_cast<void **>(&c->sym_items), items.size() * sizeof(int4)) !=
         hipSuccess) {
+      (void)hipGetLastError();
       c->sym_items = nullptr;
       return TSBTS_ENOMEM;
     }
@@ -90,19 +110,16 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
       return TSBTS_EHIP;
     c->sym_items_n = static_cast<int>(items.size());
     c->sym_items_npad = npad;
-    c->sym_chunk = chunk;
+    c->sym_chunk = sh.chunk;
   }
-  const int64_t npad_rows = static_cast<int64_t>(n_groups) * kSymGroupRows;
-  const int max_slots = sym_slots(npad, 0, chunk);
-  const int64_t bytes = (static_cast<int64_t>(max_slots) * npad_rows * row_bytes +
-                         static_cast<int64_t>(n_groups) * npad * col_bytes) * nv +
-                        npad * static_cast<int64_t>(4 * sizeof(float) + sizeof(int32_t));
+  const int64_t bytes = sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes);
   if (bytes > c->sym_part_bytes) {
     (void)hipDeviceSynchronize();
     if (c->sym_part) (void)hipFree(c->sym_part);
     c->sym_part = nullptr;
     c->sym_part_bytes = 0;
     if (hipMalloc(&c->sym_part, bytes) != hipSuccess) {
+      (void)hipGetLastError();
       c->sym_part = nullptr;
       return TSBTS_ENOMEM;
     }
@@ -114,19 +131,18 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
 bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *p) {
   const int64_t npad = c->npad;
   if (!c->sym_items || c->sym_items_npad != npad) return false;
-  const int n_groups = static_cast<int>((npad + kSymGroupRows - 1) / kSymGroupRows);
-  const int64_t npad_rows = static_cast<int64_t>(n_groups) * kSymGroupRows;
-  const int max_slots = sym_slots(npad, 0, c->sym_chunk);
-  const int64_t rows = static_cast<int64_t>(max_slots) * npad_rows * nv * row_bytes;
-  const int64_t cols = static_cast<int64_t>(n_groups) * npad * nv * col_bytes;
-  const int64_t bytes = rows + cols + npad * static_cast<int64_t>(4 * sizeof(float) +
-                                                                 sizeof(int32_t));
-  if (bytes > c->sym_part_bytes) return false;
+  const SymShape sh = sym_shape(npad);
+  if (sh.chunk != c->sym_chunk) return false;
+  const int64_t npad_rows = static_cast<int64_t>(sh.n_groups) * kSymGroupRows;
+  const int64_t rows = static_cast<int64_t>(sh.max_slots) * npad_rows * nv * row_bytes;
+  if (sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes) > c->sym_part_bytes) return false;
   p->items = static_cast<const int4 *>(c->sym_items);
   p->n_items = c->sym_items_n;
-  p->n_groups = n_groups;
-  p->chunk = c->sym_chunk;
-  p->max_slots = max_slots;
+  p->n_groups = sh.n_groups;
+  p->band_groups = sh.band_groups;
+  p->n_bands = sh.n_bands;
+  p->chunk = sh.chunk;
+  p->max_slots = sh.max_slots;
   p->npad_rows = npad_rows;
   p->row_part = c->sym_part;
   p->col_part = static_cast<char *>(c->sym_part) + rows;

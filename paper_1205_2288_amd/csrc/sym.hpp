@@ -2,18 +2,24 @@
 //
 // When every particle is a target, each unordered pair {k, j} enters two rows: k's sum
 // over j and j's sum over k, with the same separation, distance and reciprocal powers.
-// The symmetric kernels evaluate each pair once.  The upper triangle of the pair matrix is
-// cut into workgroup work items: a row group of kSymGroupRows particles (four waves, each
-// a row tile of kSymWaveRows, kSymRows per lane) against a contiguous range of columns at
-// or right of the group's first particle.  A lane accumulates the row side of its
-// particles in registers.  The column side of each column j is combined over the lane's
-// rows in registers, over the 64 lanes through a wave-private LDS transposition of a few
-// columns at a time, over the four waves through LDS in wave order, and written once per
-// (row group, column) to a partial.  A reduction kernel combines, for each particle, the
-// row partials of its own row group's items and the column partials of all row groups at
-// or above it, in a fixed order.  Pairs with j <= k (the diagonal block and, for the
-// group's later waves, the columns left of their rows), padding rows and padding columns
-// are masked (wave-uniform choice of the masked loop, as in the gather kernels).
+// The symmetric kernels evaluate each pair once.  The rows are cut into row groups of
+// kSymGroupRows particles (four waves, each a row tile of kSymWaveRows, kSymRows per
+// lane) and the row groups into at most kSymMaxBands bands of consecutive groups.  A
+// workgroup work item is a band against a contiguous chunk of columns at or right of the
+// band's first particle: it takes the band's row groups in order, each against the part
+// of the chunk at or right of that group's first particle.  A lane accumulates the row
+// side of its particles in registers and writes one row partial per (row, item).  The
+// column side of each column j is combined over the lane's rows in registers, over the 64
+// lanes through a wave-private LDS transposition of a few columns at a time, over the four
+// waves through LDS in wave order, and over the band's row groups in order into one
+// column partial per (band, column): the first row group writes it, the later ones add
+// to it.  A reduction kernel combines, for each particle, the row partials of the items
+// of its band that reach its row group, in slot order, and the column partials of the
+// bands at or above it, in band order.  With at most kSymMaxBands bands and at most
+// kSymMaxSlots chunks per band the partials take O(N) memory.  Pairs with j <= k (the
+// diagonal block and, for a group's later waves, the columns left of their rows), padding
+// rows and padding columns are masked (wave-uniform choice of the masked loop, as in the
+// gather kernels).
 #pragma once
 
 #include "internal.hpp"
@@ -27,18 +33,22 @@ constexpr int kSymGroupRows = kSymWaves * kSymWaveRows;  // rows of one work ite
 constexpr int kSymBlock = 16;                      // columns per LDS transposition
 constexpr int kSymLdsStride = 65;                  // LDS entries per column (one pad)
 constexpr int kSymMinN = 32768;                    // automatic use from this many particles
-constexpr int kSymTargetItems = 32768;             // work items aimed at by the column chunk
+constexpr int kSymTargetItems = 32768;             // waves aimed at by the column chunk
+constexpr int kSymMaxBands = 128;                  // bands of row groups, at most
+constexpr int kSymMaxSlots = 128;                  // column chunks of a band, at most
 constexpr int64_t kSymMaxBytes = int64_t(32) << 30; // automatic use while partials fit this
 
 struct SymPlan {
-  const int4 *items;  // (row group, first column, end column, slot of the row group)
+  const int4 *items;  // (band, first column, end column, slot of the band)
   int n_items;
   int n_groups;       // row groups of kSymGroupRows
+  int band_groups;    // row groups per band
+  int n_bands;
   int chunk;          // columns per work item (multiple of 64)
-  int max_slots;      // items of row group 0 (the most of any row group)
+  int max_slots;      // items of band 0 (the most of any band)
   int64_t npad_rows;  // n_groups * kSymGroupRows
   void *row_part;     // [max_slots][NV][npad_rows]
-  void *col_part;     // [n_groups][NV][npad]
+  void *col_part;     // [n_bands][NV][npad]
   float *aux;         // [4][npad]: per-particle float32 values a kernel stages (seeds)
   int32_t *inv;       // [npad]: position of each particle in the active list
 };
@@ -49,20 +59,49 @@ struct SymPlan {
 hipError_t launch_sym_inverse(const SymPlan &plan, const int32_t *idx, int n_act, int64_t n,
                               hipStream_t st);
 
-// Work items of a row group: those covering columns [g * kSymGroupRows, npad) in chunks.
-__host__ __device__ inline int sym_slots(int64_t npad, int g, int chunk) {
-  const int64_t cols = npad - static_cast<int64_t>(g) * kSymGroupRows;
-  return static_cast<int>((cols + chunk - 1) / chunk);
+// Work items of a band whose first row is `first`: its columns [first, npad) in chunks.
+__host__ __device__ inline int sym_slots(int64_t npad, int64_t first, int chunk) {
+  return static_cast<int>((npad - first + chunk - 1) / chunk);
+}
+
+// Row particle p of a plan: its band, and the slots [s0, s1) of the band's items that
+// reach its row group (the chunks not wholly left of the group's first particle).
+__host__ __device__ inline void sym_row_slots(const SymPlan &plan, int64_t npad, int64_t p,
+                                              int &band, int &s0, int &s1) {
+  const int64_t g = p / kSymGroupRows;
+  band = static_cast<int>(g / plan.band_groups);
+  const int64_t first = static_cast<int64_t>(band) * plan.band_groups * kSymGroupRows;
+  s0 = static_cast<int>((g * kSymGroupRows - first) / plan.chunk);
+  s1 = sym_slots(npad, first, plan.chunk);
+}
+
+// The row groups of a work item, in order: g runs over the item's band; the group takes
+// columns [max(first column, its first particle), end column) and stops the item when
+// that range is empty.
+struct SymSub {
+  int64_t grow0;  // first particle of the row group
+  int64_t j0;     // first column
+};
+__device__ __forceinline__ bool sym_sub(const SymPlan &plan, const int4 &it, int sub,
+                                        SymSub &out) {
+  const int g = it.x * plan.band_groups + sub;
+  if (sub >= plan.band_groups || g >= plan.n_groups) return false;
+  out.grow0 = static_cast<int64_t>(g) * kSymGroupRows;
+  if (out.grow0 >= it.z) return false;
+  out.j0 = out.grow0 > it.y ? out.grow0 : it.y;
+  return true;
 }
 
 // The four waves' column values of one transposition block (lanes < BLK of each wave hold
 // those of column jb + lane) are combined through LDS in wave order by the first wave and
 // stored to dst[v * stride + lane].  xs is double-buffered: one workgroup barrier per block
 // keeps a wave from overwriting a buffer the first wave still reads.
+// With acc, the result is combined (op) with the value already at dst: the column
+// partial of an earlier row group of the same band, written by this same lane.
 template <int BLK, int NV, class T, class Op>
 __device__ __forceinline__ void sym_group_store(T (&xs)[2][kSymWaves][NV][BLK], int &buf,
                                                 int wv, int lane, const T (&cs)[NV],
-                                                T *dst, int64_t stride, Op op) {
+                                                T *dst, int64_t stride, Op op, bool acc) {
   if (lane < BLK) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) xs[buf][wv][v][lane] = cs[v];
@@ -74,7 +113,7 @@ __device__ __forceinline__ void sym_group_store(T (&xs)[2][kSymWaves][NV][BLK], 
       T t = xs[buf][0][v][lane];
 #pragma unroll
       for (int w = 1; w < kSymWaves; ++w) t = op(t, xs[buf][w][v][lane]);
-      dst[v * stride + lane] = t;
+      dst[v * stride + lane] = acc ? op(dst[v * stride + lane], t) : t;
     }
   }
   buf ^= 1;

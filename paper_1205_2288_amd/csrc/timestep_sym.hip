@@ -98,62 +98,67 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym(StepSymArgs A0,
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int4 it = A.plan.items[blockIdx.x];  // one work item per workgroup
-  const int64_t row0 = (static_cast<int64_t>(it.x) * kSymWaves + wv) * kSymWaveRows;
-  typename StepRec<V>::I rows[kSymRows];
-  F wr[kSymRows], er[kSymRows], qmax[kSymRows], swmin[kSymRows];
-  int k[kSymRows];  // row particles (fewer than 2^31)
-#pragma unroll
-  for (int r = 0; r < kSymRows; ++r) {
-    k[r] = static_cast<int>(row0) + r * 64 + lane;
-    const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
-    rows[r] = load_iv<V>(A, kk);
-    col_weights<V>(A, kk, wr[r], er[r]);
-    qmax[r] = F(0);
-    swmin[r] = inf_of<F>();
-  }
   const F eps2 = static_cast<F>(A.eps2);
   F *L = lds[wv];
   F *colq = col_part + static_cast<int64_t>(it.x) * 2 * A.npad;
-  const bool rows_pad = row0 + kSymWaveRows > A.n;
-  int buf = 0;
-  for (int64_t jb = it.y; jb < it.z; jb += kSymBlock) {
-    if (rows_pad || jb < row0 + kSymWaveRows || jb + kSymBlock > A.n)
-      sym_block<V, 1>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
-    else
-      sym_block<V, 0>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
-    wave_lds_sync();
-    // column c = lane & 15 over the 16 lanes' entries of this lane's quarter, then the
-    // four quarters
-    const int c = lane & 15, quarter = lane >> 4;
-    F cq = F(0), cs = inf_of<F>();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int e = (c * kSymLdsStride + quarter * 16 + i) * 2;
-      cq = fmax(cq, L[e]);
-      cs = fmin(cs, L[e + 1]);
-    }
-    cq = fmax(cq, __shfl_xor(cq, 16, 64));
-    cs = fmin(cs, __shfl_xor(cs, 16, 64));
-    cq = fmax(cq, __shfl_xor(cq, 32, 64));
-    cs = fmin(cs, __shfl_xor(cs, 32, 64));
-    // over the four waves: maxima of the first value, minima of the second
-    const F both[2] = {cq, -cs};
-    sym_group_store<kSymBlock, 2>(xs, buf, wv, lane, both, colq + jb, A.npad,
-                                  [](F x, F y) { return fmax(x, y); });
-    wave_lds_sync();
-  }
   F *rq = row_part + static_cast<int64_t>(it.w) * 2 * A.plan.npad_rows;
   F *rs = rq + A.plan.npad_rows;
+  int buf = 0;
+  SymSub sg;
+  for (int sub = 0; sym_sub(A.plan, it, sub, sg); ++sub) {
+    const int64_t row0 = sg.grow0 + static_cast<int64_t>(wv) * kSymWaveRows;
+    typename StepRec<V>::I rows[kSymRows];
+    F wr[kSymRows], er[kSymRows], qmax[kSymRows], swmin[kSymRows];
+    int k[kSymRows];  // row particles (fewer than 2^31)
 #pragma unroll
-  for (int r = 0; r < kSymRows; ++r) {
-    rq[k[r]] = qmax[r];
-    rs[k[r]] = swmin[r];
+    for (int r = 0; r < kSymRows; ++r) {
+      k[r] = static_cast<int>(row0) + r * 64 + lane;
+      const int64_t kk = k[r] < A.npad ? k[r] : A.npad - 1;
+      rows[r] = load_iv<V>(A, kk);
+      col_weights<V>(A, kk, wr[r], er[r]);
+      qmax[r] = F(0);
+      swmin[r] = inf_of<F>();
+    }
+    const bool rows_pad = row0 + kSymWaveRows > A.n;
+    for (int64_t jb = sg.j0; jb < it.z; jb += kSymBlock) {
+      if (rows_pad || jb < row0 + kSymWaveRows || jb + kSymBlock > A.n)
+        sym_block<V, 1>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
+      else
+        sym_block<V, 0>(A, rows, wr, er, k, jb, eps2, qmax, swmin, L, lane);
+      wave_lds_sync();
+      // column c = lane & 15 over the 16 lanes' entries of this lane's quarter, then the
+      // four quarters
+      const int c = lane & 15, quarter = lane >> 4;
+      F cq = F(0), cs = inf_of<F>();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = (c * kSymLdsStride + quarter * 16 + i) * 2;
+        cq = fmax(cq, L[e]);
+        cs = fmin(cs, L[e + 1]);
+      }
+      cq = fmax(cq, __shfl_xor(cq, 16, 64));
+      cs = fmin(cs, __shfl_xor(cs, 16, 64));
+      cq = fmax(cq, __shfl_xor(cq, 32, 64));
+      cs = fmin(cs, __shfl_xor(cs, 32, 64));
+      // over the four waves (and the band's row groups): maxima of the first value,
+      // minima of the second
+      const F both[2] = {cq, -cs};
+      sym_group_store<kSymBlock, 2>(xs, buf, wv, lane, both, colq + jb, A.npad,
+                                    [](F x, F y) { return fmax(x, y); }, sub > 0);
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r) {
+      rq[k[r]] = qmax[r];
+      rs[k[r]] = swmin[r];
+    }
   }
 }
 
-// Particle p (target q = inv[p]): its row group's row partials in slot order, then the
-// column partials of the row groups 0 .. its own (the minima stored negated, so that the
-// four waves of a group combine both values by maxima).
+// Particle p (target q = inv[p]): the row partials of the items of its band that reach
+// its row group, in slot order, then the column partials of the bands 0 .. its own (the
+// minima stored negated, so that the four waves and the band's row groups combine both
+// values by maxima).
 template <class V>
 __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   using F = typename V::F;
@@ -161,16 +166,16 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   if (p >= A.n) return;
   const int q = A.plan.inv[p];
   if (q < 0 || q >= A.n_act) return;  // not in the list
-  const int R = static_cast<int>(p / kSymGroupRows);  // the particle's row group
-  const int slots = sym_slots(A.npad, R, A.plan.chunk);
+  int band, s0, s1;
+  sym_row_slots(A.plan, A.npad, p, band, s0, s1);
   double qm = 0.0, sm = __builtin_inf();
   const F *rp = static_cast<const F *>(A.plan.row_part);
-  for (int s = 0; s < slots; ++s) {
+  for (int s = s0; s < s1; ++s) {
     qm = fmax(qm, static_cast<double>(rp[(2 * s) * A.plan.npad_rows + p]));
     sm = fmin(sm, static_cast<double>(rp[(2 * s + 1) * A.plan.npad_rows + p]));
   }
   const F *cp = static_cast<const F *>(A.plan.col_part);
-  for (int t = 0; t <= R; ++t) {
+  for (int t = 0; t <= band; ++t) {
     qm = fmax(qm, static_cast<double>(cp[(2 * t) * A.npad + p]));
     sm = fmin(sm, -static_cast<double>(cp[(2 * t + 1) * A.npad + p]));  // stored negated
   }
