@@ -557,18 +557,20 @@ def force_calls(sizes, precision, reps=5):
     return {"workload": "plummer131k", "precision": precision, "calls": out}
 
 
-def native_run(name, t_end, precision):
+def native_run(name, t_end, precision, predict_on_load=None):
     """One whole integration of a workload with the native scheduler (its own era, step
     bounds and eta): wall time, block steps and the mean wall time per block step."""
     from paper_1205_2288_amd.driver import NativeTSBTS
     cfg = config(name)
     r, v, m = cfg.ic()
+    kw = {} if predict_on_load is None else {"predict_on_load": bool(predict_on_load)}
     sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=cfg.era,
-                      dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=precision)
+                      dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=precision, **kw)
     series = sim.run(t_end)
     st = sim.stats
     e0 = series[0][1]
     out = {"workload": name, "precision": precision, "t_end": t_end,
+           "predict_on_load": predict_on_load,
            "wall_s": st["wall_s"], "block_steps": st["block_steps"],
            "us_per_block_step": st["wall_s"] / st["block_steps"] * 1e6,
            "interactions": st["interactions"], "eras": st["eras"],
@@ -597,6 +599,9 @@ def main():
                          "workload at these active-set sizes (5 each after 2 untimed; for "
                          "counter runs)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--predict-on-load", type=int, default=None, choices=(0, 1),
+                    help="native run: small active sets predicted inside the force kernel "
+                         "(default: the scheduler's choice)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -609,7 +614,8 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     if args.native_run:
-        print(json.dumps(native_run(args.native_run, args.t_end, args.precision)))
+        print(json.dumps(native_run(args.native_run, args.t_end, args.precision,
+                                    args.predict_on_load)))
         return
     if args.force_calls:
         sizes = [int(x) for x in args.force_calls.split(",")]

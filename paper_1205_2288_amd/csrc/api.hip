@@ -9,6 +9,7 @@
 #include <new>
 
 #include "correct.hpp"
+#include "predict.hpp"
 #include "sym.hpp"
 
 namespace tsbts {
@@ -366,6 +367,31 @@ int tsbts_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t str
   return TSBTS_OK;
 }
 
+}  // extern "C"
+
+namespace tsbts {
+
+int predict_pending(tsbts_ctx *c, double t_block, int use_history, const PendingSteps *pend,
+                    const InlineIdx *in, hipStream_t stream) {
+  if (check_ctx(c)) return TSBTS_EINVAL;
+  if (int s = check_bound(c)) return s;
+  if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
+  if (use_history && !c->h.valid)
+    return fail(c, TSBTS_ESTATE, "use_history requested without a finished history");
+  if (in && in->k > 0 && (in->k > kInlineIdx || !in->out))
+    return fail(c, TSBTS_EINVAL, "inline active list larger than %d or without a target",
+                kInlineIdx);
+  hipError_t e = launch_predict(c, t_block, use_history ? 1 : 0, stream, pend, in);
+  if (e != hipSuccess) return hip_fail(c, e, "predict launch");
+  c->pred_t = t_block;
+  c->have_pred = true;
+  return TSBTS_OK;
+}
+
+}  // namespace tsbts
+
+extern "C" {
+
 int tsbts_load_positions(tsbts_ctx *c, const double *r, const double *m, double t_label,
                          hipStream_t stream) {
   if (check_ctx(c)) return TSBTS_EINVAL;
@@ -678,7 +704,7 @@ namespace tsbts {
 // reduction).  Same checks and history bookkeeping as tsbts_force + tsbts_correct; used by
 // the native scheduler, whose block steps need nothing between the two.
 int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                  double *acc, hipStream_t stream) {
+                  double *acc, hipStream_t stream, const StepTags *tags) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
   if (int s = check_active(c, idx, n_act, stream)) return s;
@@ -692,7 +718,11 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
     if (int s = grow_log(c, need, stream)) return s;
   }
   if (int s = prepare_force_sym(c, n_act)) return s;
-  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  if (tags) {
+    corr.tag = tags->tag;
+    corr.step = tags->step;
+  }
   hipError_t e = launch_force(c, idx, n_act, acc, nullptr, stream, &corr);
   if (e != hipSuccess) return hip_fail(c, e, "force + corrector launch");
   if (c->h.recording) c->h.count += n_act;
@@ -703,10 +733,18 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
 // as the force kernel loads them (one launch less than tsbts_predict + force_correct, same
 // results).  Same checks and history bookkeeping as tsbts_predict + force_correct.
 int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                            int use_history, double *acc, hipStream_t stream) {
+                            int use_history, double *acc, hipStream_t stream,
+                            const StepTags *tags, const PendingSteps *pend,
+                            const InlineIdx *in) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
-  if (int s = check_active(c, idx, n_act, stream)) return s;
+  if (in && in->k > 0) {
+    // the list arrives by value and is written to idx by the kernel itself
+    if (in->k != n_act || in->out != idx || c->check_idx)
+      return fail(c, TSBTS_EINVAL, "inline active list not usable here");
+  } else if (int s = check_active(c, idx, n_act, stream)) {
+    return s;
+  }
   if (!acc) return fail(c, TSBTS_EINVAL, "acc is NULL");
   if (!std::isfinite(t_block)) return fail(c, TSBTS_EINVAL, "t_block is not finite");
   if (n_act > small_act_limit(c))
@@ -721,9 +759,13 @@ int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
       return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
     if (int s = grow_log(c, need, stream)) return s;
   }
-  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  if (tags) {
+    corr.tag = tags->tag;
+    corr.step = tags->step;
+  }
   hipError_t e = launch_force_predicted(c, idx, n_act, t_block, use_history ? 1 : 0, acc,
-                                        nullptr, stream, &corr);
+                                        nullptr, stream, &corr, pend, in);
   if (e != hipSuccess) return hip_fail(c, e, "prediction + force + corrector launch");
   c->pred_t = t_block;
   c->have_pred = true;
@@ -734,7 +776,8 @@ int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
 // The fused force + criterion with the corrector in its reduction (the native
 // scheduler's block step when the criterion is taken before the corrector).
 int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                            double eta, double *acc, double *dtc, hipStream_t stream) {
+                            double eta, double *acc, double *dtc, hipStream_t stream,
+                            const StepTags *tags) {
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
   if (int s = check_active(c, idx, n_act, stream)) return s;
@@ -749,7 +792,11 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
       return fail(c, TSBTS_EINVAL, "era history exceeds 2^31 records");
     if (int s = grow_log(c, need, stream)) return s;
   }
-  const CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  CorrectArgs corr = correct_args(c, idx, n_act, t_block, acc);
+  if (tags) {
+    corr.tag = tags->tag;
+    corr.step = tags->step;
+  }
   hipError_t e;
   if (n_act <= kSmallAct) {
     // small sets: the criterion on the predicted state first, then the force with the

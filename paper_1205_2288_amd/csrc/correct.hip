@@ -224,6 +224,8 @@ CorrectArgs base_args(tsbts_ctx *c) {
   p.cnt = c->h.cnt;
   p.rt = c->h.t;
   p.rs = c->h.s;
+  p.tag = nullptr;
+  p.step = 0;
   return p;
 }
 

@@ -22,6 +22,10 @@ struct CorrectArgs {
   int64_t cap;
   int32_t *pid, *rank, *cnt;
   double *rt, *rs;
+  // native scheduler: each target g tagged (step << 32) | q, so that the next block step's
+  // predictor finds its new step (PendingSteps); null: no tags
+  int64_t *tag;
+  int64_t step;
 };
 
 // Target q (particle g) with new acceleration an: r <- predicted position, v <- v +
@@ -47,6 +51,7 @@ __device__ __forceinline__ void correct_one(const CorrectArgs &p, int q, int64_t
     st[c + 6] = an[c];
   }
   p.t_last[g] = p.tb;
+  if (p.tag) p.tag[g] = (p.step << 32) | static_cast<int64_t>(q);
   if (p.record) {
     const int64_t slot = p.base + q;
     p.pid[slot] = static_cast<int32_t>(g);

@@ -300,7 +300,8 @@ __device__ __forceinline__ typename V::I i_from_state(double x, double y, double
 // (active particles: their Taylor polynomial).  Same arithmetic as the predictor followed
 // by k_force_small, so the results are the same bit for bit.
 template <class V, int NEWTON>
-__global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictArgs Pr) {
+__global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictArgs Pr,
+                                                          InlineIdx in) {
   using F = typename V::F;
   __shared__ typename V::I si[kSmallAct];
   __shared__ int sg[kSmallAct];
@@ -321,8 +322,9 @@ __global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictAr
     store_pad(Pr.o, j);
     J = j_from_state<V>(kFar, kFar, kFar, 0.0, ms);
   }
+  if (blockIdx.x == 0) store_inline_idx(in, tid);
   if (tid < A.n_act) {
-    sg[tid] = A.idx[tid];
+    sg[tid] = in.k ? in.v[tid] : A.idx[tid];
     double st[6];
     predict_state(Pr, sg[tid], false, st);
     si[tid] = i_from_state<V>(st[0], st[1], st[2]);
@@ -440,14 +442,19 @@ hipError_t run(ForceArgs &A, hipStream_t st) {
 }
 
 template <class V, int NEWTON>
-hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nullptr) {
+hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nullptr,
+                     const InlineIdx *in = nullptr) {
   A.plan.n_itiles = 1;
   A.plan.n_slices = A.n_jtiles;
   A.plan.tiles_per_slice = 1;
   A.plan.nblk = A.n_jtiles;
-  if (pred)
+  if (pred) {
+    InlineIdx none;
+    none.out = nullptr;
+    none.k = 0;
     hipLaunchKernelGGL((k_force_small_pred<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A,
-                       *pred);
+                       *pred, in ? *in : none);
+  }
   else
     hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
   if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
@@ -553,7 +560,8 @@ int small_act_limit(const tsbts_ctx *c) {
 
 hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
                                   int use_history, double *acc, double *pot, hipStream_t st,
-                                  const CorrectArgs *corr) {
+                                  const CorrectArgs *corr, const PendingSteps *pend,
+                                  const InlineIdx *in) {
   ForceArgs A;
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;
@@ -572,13 +580,18 @@ hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, d
   A.ipl = 1;
   A.scalar_j = 0;
   A.chunk = kTJ;
-  const PredictArgs P = predict_args(c, t_block, use_history);
-  if (c->precision == TSBTS_FP64) return run_small<Fp64, 0>(A, st, &P);
+  PredictArgs P = predict_args(c, t_block, use_history);
+  if (pend) {
+    P.pend_tag = pend->tag;
+    P.pend_dt = pend->dt;
+    P.pend_step = pend->step;
+  }
+  if (c->precision == TSBTS_FP64) return run_small<Fp64, 0>(A, st, &P, in);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
   if (sep64)
-    return newton ? run_small<MixSep64, 1>(A, st, &P) : run_small<MixSep64, 0>(A, st, &P);
-  return newton ? run_small<MixHiLo, 1>(A, st, &P) : run_small<MixHiLo, 0>(A, st, &P);
+    return newton ? run_small<MixSep64, 1>(A, st, &P, in) : run_small<MixSep64, 0>(A, st, &P, in);
+  return newton ? run_small<MixHiLo, 1>(A, st, &P, in) : run_small<MixHiLo, 0>(A, st, &P, in);
 }
 
 }  // namespace tsbts

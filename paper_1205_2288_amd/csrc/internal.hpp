@@ -225,7 +225,15 @@ inline int criterion_blocks(const tsbts_ctx *c, int n_act) {
 // ------------------------------------------------------------------ launchers
 // Each returns a hipError_t from the launch (hipSuccess on success).
 
-hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st);
+// New steps of the previous block step not yet stored (native scheduler; predict.hpp).
+struct PendingSteps {
+  const int64_t *tag;  // [n] (step << 32) | list position, written by the corrector
+  const double *dt;    // [k] new steps, by position in that step's active list
+  int64_t step;
+};
+struct InlineIdx;
+hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st,
+                          const PendingSteps *pend = nullptr, const InlineIdx *in = nullptr);
 hipError_t launch_load_positions(tsbts_ctx *c, const double *r, const double *m,
                                  hipStream_t st);
 hipError_t launch_snapshot(tsbts_ctx *c, double T, double *r_out, double *v_out,
@@ -238,14 +246,27 @@ int64_t fused_partials_needed(const tsbts_ctx *c, int n_act);
 hipError_t launch_fused(tsbts_ctx *c, const int32_t *idx, int n_act, double eta, double *acc,
                         double *pot, double *dtc, hipStream_t st,
                         const CorrectArgs *corr = nullptr);
+// Tags of the native scheduler's corrector: each target g gets tag[g] = (step << 32) | q.
+struct StepTags {
+  int64_t *tag;
+  int64_t step;
+};
 int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                            double eta, double *acc, double *dtc, hipStream_t stream);
+                            double eta, double *acc, double *dtc, hipStream_t stream,
+                            const StepTags *tags = nullptr);
 // Force on the active set and its corrector in the same launches (checked like the two
-// entry points; returns a status code).
+// entry points; returns a status code).  With `in`, the active list arrives by value
+// and the first kernel writes it to idx (which must then not be checked beforehand).
 int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                            int use_history, double *acc, hipStream_t stream);
+                            int use_history, double *acc, hipStream_t stream,
+                            const StepTags *tags = nullptr,
+                            const PendingSteps *pend = nullptr,
+                            const InlineIdx *in = nullptr);
 int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
-                  double *acc, hipStream_t stream);
+                  double *acc, hipStream_t stream, const StepTags *tags = nullptr);
+// tsbts_predict with pending new steps and an inline active list (either may be null).
+int predict_pending(tsbts_ctx *c, double t_block, int use_history, const PendingSteps *pend,
+                    const InlineIdx *in, hipStream_t stream);
 // With corr, every target's corrector (correct_one) runs where its force is final.
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr = nullptr);
@@ -288,7 +309,8 @@ int small_act_limit(const tsbts_ctx *c);
 // predicted as they are loaded (n_act <= small_act_limit).
 hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
                                   int use_history, double *acc, double *pot, hipStream_t st,
-                                  const CorrectArgs *corr);
+                                  const CorrectArgs *corr, const PendingSteps *pend = nullptr,
+                                  const InlineIdx *in = nullptr);
 // Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.
 struct SymPlan;
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,

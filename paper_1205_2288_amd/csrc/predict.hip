@@ -6,13 +6,16 @@
 // Bandwidth-bound: per particle, Taylor reads r, v, a, t_last, dt, m (88 B) and writes the
 // float64 position/mass/weight planes (40 B), float64 velocities (24 B) and, in mixed
 // precision, the float32 hi/lo, mass, weight, velocity and eps^2-weight planes (48 B).
+#include <algorithm>
+
 #include "predict.hpp"
 
 namespace tsbts {
 namespace {
 
-__global__ __launch_bounds__(kWG) void k_predict(PredictArgs p) {
+__global__ __launch_bounds__(kWG) void k_predict(PredictArgs p, InlineIdx in) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  store_inline_idx(in, j);
   if (j >= p.o.npad) return;
   if (j >= p.n) {
     store_pad(p.o, j);
@@ -120,13 +123,28 @@ PredictArgs predict_args(tsbts_ctx *c, double t_block, int use_history) {
   p.off = c->h.off;
   p.cur = c->h.cur;
   p.hcap = c->h.hcap;
+  p.pend_tag = nullptr;
+  p.pend_dt = nullptr;
+  p.pend_step = 0;
+  p.dt_w = c->dt;
   return p;
 }
 
-hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st) {
-  const PredictArgs p = predict_args(c, t_block, use_history);
-  const int nb = static_cast<int>((c->npad + kWG - 1) / kWG);
-  hipLaunchKernelGGL(k_predict, dim3(nb), dim3(kWG), 0, st, p);
+hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st,
+                          const PendingSteps *pend, const InlineIdx *in) {
+  PredictArgs p = predict_args(c, t_block, use_history);
+  if (pend) {
+    p.pend_tag = pend->tag;
+    p.pend_dt = pend->dt;
+    p.pend_step = pend->step;
+  }
+  InlineIdx none;
+  none.out = nullptr;
+  none.k = 0;
+  // the inline list is written by the first threads of the grid
+  const int64_t threads = std::max<int64_t>(c->npad, in ? in->k : 0);
+  const int nb = static_cast<int>((threads + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_predict, dim3(nb), dim3(kWG), 0, st, p, in ? *in : none);
   return hipGetLastError();
 }
 

@@ -86,7 +86,42 @@ struct PredictArgs {
   const int32_t *off;
   int32_t *cur;
   int64_t hcap;
+  // Pending new steps of the previous block step (native scheduler): the corrector of
+  // that step tagged each target g with pend_tag[g] = (step << 32) | q, q its position
+  // in that step's active list, whose new steps pend_dt[q] the host chose after it.  A
+  // particle whose tag names pend_step takes pend_dt[q] as its step; the thread that owns
+  // it also stores it in dt_w.  Null pend_tag: no pending steps.
+  const int64_t *pend_tag;
+  const double *pend_dt;
+  int64_t pend_step;
+  double *dt_w;
 };
+
+// An active list of at most kInlineIdx particles passed by value to the first kernel of
+// a block step, which writes it to `out` for the later kernels (no separate copy).
+constexpr int kInlineIdx = 256;
+struct InlineIdx {
+  int32_t *out;
+  int32_t k;  // 0: the list is already in device memory
+  int32_t v[kInlineIdx];
+};
+
+__device__ __forceinline__ void store_inline_idx(const InlineIdx &in, int64_t t) {
+  if (t < in.k) in.out[t] = in.v[t];
+}
+
+// Step of particle j at p.tb: its pending new step, else the stored one.
+__device__ __forceinline__ double step_of(const PredictArgs &p, int64_t j, bool owner) {
+  if (p.pend_tag) {
+    const int64_t e = p.pend_tag[j];
+    if ((e >> 32) == p.pend_step) {
+      const double d = p.pend_dt[static_cast<int32_t>(e & 0xffffffff)];
+      if (owner) p.dt_w[j] = d;
+      return d;
+    }
+  }
+  return p.dt[j];
+}
 
 // Predicted position and velocity of particle j < n at p.tb (Section 2 predictor;
 // Algorithm 2, step 4): an active particle (t_last + dt = t_b) and, without a usable
@@ -94,12 +129,12 @@ struct PredictArgs {
 // the cubic Hermite interpolant of the two bracketing records.  The history cursor of j
 // follows the block time in either direction (a reverse sweep predicts at decreasing
 // times) and stops at the particle's first record; only the thread that owns j may move
-// it (update_cursor).
+// it (update_cursor); that thread also stores a pending new step (step_of).
 __device__ __forceinline__ void predict_state(const PredictArgs &p, int64_t j,
                                               bool update_cursor, double s[6]) {
   const int64_t n = p.n;
   const double tl = p.t_last[j];
-  const bool active = (tl + p.dt[j] == p.tb);
+  const bool active = (tl + step_of(p, j, update_cursor) == p.tb);
   if (p.use_hist && !active) {
     const int lo = p.off[j], hi = p.off[j + 1];
     int k = p.cur[j];
@@ -123,7 +158,8 @@ __device__ __forceinline__ void predict_state(const PredictArgs &p, int64_t j,
   }
 }
 
-// Predictor arguments for the context at t_block (history source of the context).
+// Predictor arguments for the context at t_block (history source of the context), with
+// no pending steps.
 PredictArgs predict_args(tsbts_ctx *c, double t_block, int use_history);
 
 }  // namespace tsbts

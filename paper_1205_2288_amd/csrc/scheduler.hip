@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "predict.hpp"
 
 namespace tsbts {
 
@@ -162,6 +163,15 @@ struct Scheduler {
   int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
   int crit_before = 0;  // criterion with the predicted velocities, fused with the force
   int pred_on_load = 0;  // small active sets: prediction folded into the force kernel
+  // The new steps chosen after a block step are not scattered by a launch of their own:
+  // the corrector tags each target with (step id, list position), and the next block
+  // step's first kernel takes the pending steps from dtn_h through those tags.  At the
+  // end of a pass the last step's are stored by tsbts_set_dt.
+  int64_t *tag_d = nullptr;  // [n] device
+  int64_t step_id = 0;       // block steps issued so far (tags are unique per step)
+  bool pending = false;      // dtn_h holds new steps of step `pending_step` not yet stored
+  int64_t pending_step = 0;
+  int32_t pending_k = 0;     // its active-set size (its list is still in idx_d)
 
   void rebuild_levels() {
     for (auto &m : mem) m.clear();
@@ -231,6 +241,14 @@ int sfail(tsbts_ctx *c, int st, const char *msg) {
     if (_s != TSBTS_OK) return _s; \
   } while (0)
 
+// Store the new steps of the last block step, if the next block step has not (its list
+// is still in idx_d).
+int flush_steps(tsbts_ctx *c, Scheduler &S, hipStream_t st) {
+  if (!S.pending) return TSBTS_OK;
+  S.pending = false;
+  return tsbts_set_dt(c, S.idx_d, S.pending_k, S.dtn_hd, st);
+}
+
 // One pass of an era: block steps until the next block time passes T1.
 int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
   const int64_t n = S.n;
@@ -248,18 +266,33 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       k += static_cast<int32_t>(S.mem[l].size());
     }
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
-    SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+    const int64_t step = ++S.step_id;
+    // small lists travel by value in the first kernel's arguments (it writes idx_d)
+    tsbts::InlineIdx in;
+    in.out = S.idx_d;
+    in.k = 0;
+    if (k <= tsbts::kInlineIdx && !c->check_idx) {
+      in.k = k;
+      std::copy(S.idx_h, S.idx_h + k, in.v);
+    } else {
+      SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice,
+                               st));
+    }
+    const tsbts::PendingSteps pend{S.tag_d, S.dtn_hd, S.pending_step};
+    const tsbts::PendingSteps *pp = S.pending ? &pend : nullptr;
+    const tsbts::InlineIdx *ip = in.k ? &in : nullptr;
+    const tsbts::StepTags tags{S.tag_d, step};
     if (S.pred_on_load && !S.crit_before && k <= tsbts::small_act_limit(c)) {
       SCHED_CALL(tsbts::force_correct_predicted(c, S.idx_d, k, tbs, p > 0 ? 1 : 0, S.acc_d,
-                                                st));
+                                                st, &tags, pp, ip));
       SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     } else if (S.crit_before) {
-      SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
+      SCHED_CALL(tsbts::predict_pending(c, tbs, p > 0 ? 1 : 0, pp, ip, st));
       SCHED_CALL(tsbts::force_criterion_correct(c, S.idx_d, k, tbs, S.eta, S.acc_d, S.dtc_hd,
-                                                st));
+                                                st, &tags));
     } else {
-      SCHED_CALL(tsbts_predict(c, tbs, p > 0 ? 1 : 0, st));
-      SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st));
+      SCHED_CALL(tsbts::predict_pending(c, tbs, p > 0 ? 1 : 0, pp, ip, st));
+      SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st, &tags));
       SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     }
     SCHED_HIP(hipStreamSynchronize(st));
@@ -283,12 +316,16 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
         S.move(i, tsbts::level_of(nd));
       }
     }
-    // dtn_h is rewritten only after the next synchronisation, when this kernel has run
-    SCHED_CALL(tsbts_set_dt(c, S.idx_d, k, S.dtn_hd, st));
+    // the next block step's first kernel stores these steps; dtn_h is rewritten only
+    // after the next synchronisation, when that kernel has run
+    S.pending = true;
+    S.pending_step = step;
+    S.pending_k = k;
     S.stats[0] += 1;
     S.stats[1] += 1;
     S.stats[2] += static_cast<int64_t>(k) * n;
   }
+  SCHED_CALL(flush_steps(c, S, st));
   SCHED_CALL(tsbts_history_end(c, st));
   S.cur.close(n);
   std::swap(S.prev, S.cur);
@@ -327,6 +364,7 @@ void free_sched(Scheduler *S) {
   if (S->idx_d) (void)hipFree(S->idx_d);
   if (S->acc_d) (void)hipFree(S->acc_d);
   if (S->s0) (void)hipFree(S->s0);
+  if (S->tag_d) (void)hipFree(S->tag_d);
   delete S;
 }
 
@@ -415,6 +453,8 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->idx_d), sizeof(int32_t) * n));
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->acc_d), sizeof(double) * 3 * n));
   SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->s0), sizeof(double) * 11 * n));
+  SCHED_HIP(hipMalloc(reinterpret_cast<void **>(&S->tag_d), sizeof(int64_t) * n));
+  SCHED_HIP(hipMemsetAsync(S->tag_d, 0xff, sizeof(int64_t) * n, st));  // -1: no step
   // Algorithm 2, step 1: forces, criterion and block steps of all particles at t = 0
   for (int64_t i = 0; i < n; ++i) S->idx_h[i] = static_cast<int32_t>(i);
   SCHED_HIP(hipMemcpyAsync(S->idx_d, S->idx_h, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
@@ -534,6 +574,7 @@ int tsbts_sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_
   S->time = T;
   if (stats) std::copy(stats, stats + 4, S->stats);
   S->have_prev = false;
+  S->pending = false;  // every pass ends with its steps stored
   // device copies of the times and steps (the bound t_last and dt), staged through the
   // pinned buffers; no step update of an earlier block step can still be reading them
   SCHED_HIP(hipStreamSynchronize(st));
