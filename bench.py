@@ -575,7 +575,8 @@ def native_run(name, t_end, precision, predict_on_load=None):
            "us_per_block_step": st["wall_s"] / st["block_steps"] * 1e6,
            "interactions": st["interactions"], "eras": st["eras"],
            "era_sizes": st["era_sizes"],
-           "drift": max(abs(e - e0) / abs(e0) for _, e in series)}
+           "drift": max(abs(e - e0) / abs(e0) for _, e in series),
+           "phases": sim.step_timing()}
     sim.close()
     return out
 

@@ -399,9 +399,12 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
  *     corrector (default); 1 = criterion with the predicted velocities, in the same pass
  *     over the pairs as the force (tsbts_force_criterion).
  *   TSBTS_SCHED_PREDICT_ON_LOAD: 1 = for active sets of at most 32 particles (16 in
- *     float64) the predictor's work is done by the force kernel as it loads its sources
- *     (one launch less per block step, same results bit for bit); 0 = separate predictor
- *     (default).  Not combined with the option above.
+ *     float64) the predictor's work is done by the force kernel as it loads its sources,
+ *     and on few particles (active set in groups of 8 times the 256-particle tiles at
+ *     most 16, e.g. N <= 4096 and 8 targets) that kernel's last workgroup also takes the criterion of
+ *     the corrected targets: one launch per such block step instead of three, the same
+ *     results bit for bit (default); 0 = separate predictor and criterion launches.  Not
+ *     combined with the option above.
  * Returns TSBTS_ESTATE before tsbts_sched_init, TSBTS_EINVAL for an unknown option or
  * value. */
 int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);
@@ -419,6 +422,16 @@ int tsbts_sched_era(tsbts_ctx *ctx, double *era_end, hipStream_t stream);
  * calls, interactions, eras), *time (current era end). */
 int tsbts_sched_state(const tsbts_ctx *ctx, int64_t *t_ticks, int64_t *dt_ticks, double *dtc,
                       int64_t *stats, double *time);
+
+/* Wall-clock breakdown of the scheduler's block steps since tsbts_sched_init (host
+ * only): for four classes of active-set size k (k <= 32, k <= 256, k <= 1024, larger),
+ * seconds[4 * cls + ph] holds the time spent in phase ph: 0 = building the active set and
+ * issuing the step's launches (host), 1 = waiting for the step's criterion values (the
+ * GPU's work after the last launch returned), 2 = the step rule and bookkeeping of
+ * Algorithm 1 on the host, 3 = the whole step from the end of the previous one; counts
+ * [2 * cls] the block steps and [2 * cls + 1] their summed active-set sizes.  Either
+ * pointer may be NULL; TSBTS_EINVAL without a scheduler. */
+int tsbts_sched_timing(const tsbts_ctx *ctx, double *seconds, int64_t *counts);
 
 /* Host copy of each particle's previous step (the step that brought it to its current
  * time; 0 before its first step), dtp_ticks [n] int64: with tsbts_sched_state and the

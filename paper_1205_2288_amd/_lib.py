@@ -83,6 +83,7 @@ _SIGS = {
     "tsbts_sched_era": ([_p, ctypes.POINTER(_d), _p], _int),
     "tsbts_sched_state": ([_p, _p, _p, _p, _p, ctypes.POINTER(_d)], _int),
     "tsbts_sched_prev_steps": ([_p, _p], _int),
+    "tsbts_sched_timing": ([_p, _p, _p], _int),
     "tsbts_sched_restore": ([_p, _p, _p, _p, _p, _p, _d, _p], _int),
 }
 
@@ -380,6 +381,18 @@ def tsbts_sched_state(ctx, n):
                                       ctypes.c_void_p(dtc.ctypes.data),
                                       ctypes.c_void_p(stats.ctypes.data), ctypes.byref(time)))
     return t, dt, dtc, stats, time.value
+
+
+def tsbts_sched_timing(ctx):
+    """Wall-clock breakdown of the block steps: (seconds float64[4, 4] by active-set class
+    (k <= 32, <= 256, <= 1024, larger) and phase (issue, wait, rule, whole step), counts
+    int64[4, 2] (block steps, summed active-set sizes))."""
+    import numpy as np
+    sec = np.empty((4, 4), dtype=np.float64)
+    cnt = np.empty((4, 2), dtype=np.int64)
+    _check(ctx, lib.tsbts_sched_timing(ctx, ctypes.c_void_p(sec.ctypes.data),
+                                       ctypes.c_void_p(cnt.ctypes.data)))
+    return sec, cnt
 
 
 def tsbts_sched_prev_steps(ctx, n):

@@ -246,6 +246,14 @@ int tsbts_create(tsbts_ctx **out, int64_t n, double eps, int precision, int flag
   if (!st) st = dev_alloc(c, &c->h.tsum, (n + 8191) / 8192);
   if (!st) st = dev_alloc(c, &c->h.off, n + 1);
   if (!st) st = dev_alloc(c, &c->h.cur, n);
+  if (!st) st = dev_alloc(c, &c->done, 2);
+  // zero before any launch on any of the caller's streams (which may not wait for the
+  // null stream)
+  if (!st && (hipMemset(c->done, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+              hipDeviceSynchronize() != hipSuccess)) {
+    (void)hipGetLastError();
+    st = TSBTS_EHIP;
+  }
   if (!st) {
     c->epart_cap = energy_partials_needed(c);
     st = dev_alloc(c, &c->epart, c->epart_cap);
@@ -278,6 +286,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   if (c->sym_part) (void)hipFree(c->sym_part);
   if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
   dev_free(c->idx_seen);
+  dev_free(c->done);
   dev_free(c->h.pid);
   dev_free(c->h.rank);
   dev_free(c->h.t);
@@ -735,7 +744,8 @@ int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_bloc
 int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
                             int use_history, double *acc, hipStream_t stream,
                             const StepTags *tags, const PendingSteps *pend,
-                            const InlineIdx *in) {
+                            const InlineIdx *in, double eta, double *dtc, int *crit_done) {
+  if (crit_done) *crit_done = 0;
   if (check_ctx(c)) return TSBTS_EINVAL;
   if (int s = check_bound(c)) return s;
   if (in && in->k > 0) {
@@ -764,9 +774,14 @@ int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
     corr.tag = tags->tag;
     corr.step = tags->step;
   }
+  const bool crit = dtc && small_criterion_fused(c, n_act);
+  if (crit && (!(eta > 0.0) || !std::isfinite(eta)))
+    return fail(c, TSBTS_EINVAL, "eta must be > 0");
   hipError_t e = launch_force_predicted(c, idx, n_act, t_block, use_history ? 1 : 0, acc,
-                                        nullptr, stream, &corr, pend, in);
+                                        nullptr, stream, &corr, pend, in, eta,
+                                        crit ? dtc : nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "prediction + force + corrector launch");
+  if (crit_done) *crit_done = crit ? 1 : 0;
   c->pred_t = t_block;
   c->have_pred = true;
   if (c->h.recording) c->h.count += n_act;

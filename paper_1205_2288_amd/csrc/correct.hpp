@@ -28,19 +28,40 @@ struct CorrectArgs {
   int64_t step;
 };
 
-// Target q (particle g) with new acceleration an: r <- predicted position, v <- v +
-// (a + an) h / 2, a <- an, t_last <- t_block; append the record when recording.  Writes
-// only the bound state, the float64 / float32 velocity planes and the record of g, none
-// of which a force kernel reads.
-__device__ __forceinline__ void correct_one(const CorrectArgs &p, int q, int64_t g,
-                                            const double an[3]) {
+// The corrector's inputs of one target: its last time, its predicted position, the
+// velocity and acceleration of its last step, and its record count (when recording).
+struct TargetState {
+  double tl, rn[3], v[3], a[3];
+  int32_t cnt;
+};
+
+__device__ __forceinline__ TargetState load_target(const CorrectArgs &p, int64_t g) {
   const int64_t n = p.n, P = p.npad;
-  const double h = p.tb - p.t_last[g];
+  TargetState s;
+  s.tl = p.t_last[g];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s.rn[c] = p.p64[c * P + g];  // predicted position = r + v h + a h^2/2
+    s.v[c] = p.v[c * n + g];
+    s.a[c] = p.a[c * n + g];
+  }
+  s.cnt = p.record ? p.cnt[g] : 0;
+  return s;
+}
+
+// Target q (particle g, inputs s) with new acceleration an: r <- predicted position,
+// v <- v + (a + an) h / 2, a <- an, t_last <- t_block; append the record when recording.
+// Writes only the bound state, the float64 / float32 velocity planes and the record of g,
+// none of which a force kernel reads.
+__device__ __forceinline__ void correct_target(const CorrectArgs &p, int q, int64_t g,
+                                               const double an[3], const TargetState &s) {
+  const int64_t n = p.n, P = p.npad;
+  const double h = p.tb - s.tl;
   double st[9];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double rn = p.p64[c * P + g];  // predicted position = r + v h + a h^2/2
-    const double vn = p.v[c * n + g] + 0.5 * (p.a[c * n + g] + an[c]) * h;
+    const double rn = s.rn[c];
+    const double vn = s.v[c] + 0.5 * (s.a[c] + an[c]) * h;
     p.r[c * n + g] = rn;
     p.v[c * n + g] = vn;
     p.a[c * n + g] = an[c];
@@ -55,13 +76,18 @@ __device__ __forceinline__ void correct_one(const CorrectArgs &p, int q, int64_t
   if (p.record) {
     const int64_t slot = p.base + q;
     p.pid[slot] = static_cast<int32_t>(g);
-    const int32_t k = p.cnt[g];
-    p.rank[slot] = k;
-    p.cnt[g] = k + 1;
+    p.rank[slot] = s.cnt;
+    p.cnt[g] = s.cnt + 1;
     p.rt[slot] = p.tb;
 #pragma unroll
     for (int c = 0; c < 9; ++c) p.rs[c * p.cap + slot] = st[c];
   }
+}
+
+// The same with the inputs read from the context.
+__device__ __forceinline__ void correct_one(const CorrectArgs &p, int q, int64_t g,
+                                            const double an[3]) {
+  correct_target(p, q, g, an, load_target(p, g));
 }
 
 // Arguments of a corrector call on the context's bound state and era log.

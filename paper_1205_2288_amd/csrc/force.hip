@@ -19,6 +19,7 @@
 // those tiles and the unmasked one elsewhere, so the mask costs nothing on almost every
 // tile and no large self term ever enters a float32 accumulator.
 #include "correct.hpp"
+#include "criterion.hpp"
 #include "force_pair.hpp"
 #include "predict.hpp"
 #include "sym.hpp"
@@ -27,6 +28,20 @@
 
 namespace tsbts {
 namespace {
+
+// The time-step criterion of the targets after their correction, taken by the last
+// workgroup of a small predicted launch (small_criterion_last).
+struct CritArgs {
+  int on;
+  int64_t n;  // particles; j >= n are padding
+  const float *p32;
+  const double *p64;
+  const double *v64;
+  int64_t npad;
+  double eps2;
+  double eta;
+  double *dtc;
+};
 
 struct ForceArgs {
   const float *p32;
@@ -47,18 +62,24 @@ struct ForceArgs {
   int chunk;     // j-particles per split unit of k_force_scalar
   int correct;   // apply the corrector to each target as its force is finished
   CorrectArgs corr;
+  uint32_t *done;   // finished-workgroup count of the small-set kernels
+  int fuse_reduce;  // the small-set kernel's last workgroup reduces the partials
+  CritArgs crit;    // ... and then takes the criterion (k_force_small_pred)
 };
 
+// Scale and store target q's sums; with the corrector, correct it (its inputs `ts` when
+// the caller holds them, else read from the context).
 template <class V, int NEWTON>
 __device__ __forceinline__ void finish(const ForceArgs &A, int q, int64_t g, double sx,
-                                       double sy, double sz, double sp) {
+                                       double sy, double sz, double sp,
+                                       const TargetState *ts = nullptr) {
   const double k = Scale<V, NEWTON>::kAcc;
   const double an[3] = {k * sx, k * sy, k * sz};
   A.acc[q] = an[0];
   A.acc[A.n_act + q] = an[1];
   A.acc[2 * A.n_act + q] = an[2];
   if (A.pot) A.pot[q] = -sp;
-  if (A.correct) correct_one(A.corr, q, g, an);
+  if (A.correct) correct_target(A.corr, q, g, an, ts ? *ts : load_target(A.corr, g));
 }
 
 template <class V, int NEWTON, int MASK, int POT, int IPL, class F>
@@ -198,47 +219,38 @@ __global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
 }
 
 // Small active sets (n_act <= kSmallAct): one 256-particle j-tile per workgroup, one
-// source per lane, the targets broadcast from LDS; each pair is summed over the wave and
-// the 4 waves in a fixed order into one float64 partial per tile and target, which the
-// split-j reduction then combines.  Keeps every lane busy where an i-tile would leave all
-// but n_act lanes idle.
-template <class F>
-__device__ __forceinline__ F wave_sum_t(F x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
+// source per lane, the targets broadcast from LDS.  The pairs of kSmallGroup targets are
+// summed over the wave together (wave_reduce_many: one shuffle per kept value instead of a
+// butterfly per value), then over the 4 waves in a fixed order into one float64 partial
+// per tile and target.  Keeps every lane busy where an i-tile would leave all but n_act
+// lanes idle.  When the partials are few (fuse_reduce) the launch's last workgroup adds
+// them and finishes the targets (small_reduce_last) instead of a second kernel.
+constexpr int kSmallGroup = 8;
 
 template <class V, int NEWTON>
-__global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
+__device__ __forceinline__ void small_tile_sums(const ForceArgs &A, const typename V::I *si,
+                                                const int *sg, const typename V::J &J,
+                                                int64_t j, int tile) {
   using F = typename V::F;
-  __shared__ typename V::I si[kSmallAct];
-  __shared__ int sg[kSmallAct];
   __shared__ F red[kSmallAct][4][kWG / 64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int tile = blockIdx.x;
-  const int64_t P = A.npad;
-  const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
   const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
-  const typename V::J J = V::load_j(A.p32, A.p64, P, j, Scale<V, NEWTON>::kMass);
-  if (tid < A.n_act) {
-    sg[tid] = A.idx[tid];
-    si[tid] = V::load_i(A.p32, A.p64, P, sg[tid]);
-  }
-  __syncthreads();
-  for (int q = 0; q < A.n_act; ++q) {
-    F ax = F(0), ay = F(0), az = F(0), pp = F(0);
-    pair_acc<V, NEWTON, 1, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
-    ax = wave_sum_t(ax);
-    ay = wave_sum_t(ay);
-    az = wave_sum_t(az);
-    pp = wave_sum_t(pp);
-    if (lane == 0) {
-      red[q][0][w] = ax;
-      red[q][1][w] = ay;
-      red[q][2][w] = az;
-      red[q][3][w] = pp;
+  for (int q0 = 0; q0 < A.n_act; q0 += kSmallGroup) {
+    F x[4 * kSmallGroup];
+#pragma unroll
+    for (int u = 0; u < kSmallGroup; ++u) {
+      const int q = q0 + u;
+      F ax = F(0), ay = F(0), az = F(0), pp = F(0);
+      if (q < A.n_act) pair_acc<V, NEWTON, 1, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
+      x[4 * u] = ax;
+      x[4 * u + 1] = ay;
+      x[4 * u + 2] = az;
+      x[4 * u + 3] = pp;
     }
+    const F r = wave_reduce_many<4 * kSmallGroup>(x, lane, [](F a, F b) { return a + b; });
+    // lane l holds value l >> 1: target q0 + (l >> 3), component (l >> 1) & 3
+    const int q = q0 + (lane >> 3);
+    if ((lane & 1) == 0 && q < A.n_act) red[q][(lane >> 1) & 3][w] = r;
   }
   __syncthreads();
   for (int t = tid; t < 4 * A.n_act; t += kWG) {
@@ -248,6 +260,137 @@ __global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
     for (int ww = 0; ww < kWG / 64; ++ww) s += static_cast<double>(red[q][c][ww]);
     A.part[(static_cast<int64_t>(tile) * 4 + c) * A.n_act + q] = s;
   }
+}
+
+// The split-j reduction by the launch's last workgroup.  A slice's partials form a row of
+// W = 4 n_act values; thread t adds value t % W over part t / W of the slices (P = kWG / W
+// consecutive parts, coalesced rows), in slice order; the parts are then added in order
+// and each target finishes (sg: the active list in LDS; ts: the corrector's inputs of
+// target tid, held by thread tid, or null).
+template <class V, int NEWTON>
+__device__ __forceinline__ void small_reduce_last(const ForceArgs &A, const int *sg,
+                                                  const TargetState *ts = nullptr) {
+  __shared__ double sums[kWG];
+  const int tid = threadIdx.x;
+  const int W = 4 * A.n_act, P = kWG / W, S = A.plan.n_slices;
+  const int L = (S + P - 1) / P;
+  const int p = tid / W, v = tid - p * W;
+  double s = 0.0;
+  if (p < P) {
+    const int s1 = min(S, (p + 1) * L);
+#pragma unroll 8
+    for (int sl = p * L; sl < s1; ++sl) s += A.part[static_cast<int64_t>(sl) * W + v];
+  }
+  sums[tid] = s;
+  __syncthreads();
+  if (tid < A.n_act) {
+    double f[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double t = 0.0;
+      for (int pp = 0; pp < P; ++pp) t += sums[pp * W + c * A.n_act + tid];
+      f[c] = t;
+    }
+    finish<V, NEWTON>(A, tid, sg[tid], f[0], f[1], f[2], f[3], ts);
+  }
+}
+
+// The criterion of the targets after their correction, by the launch's last workgroup
+// alone (a small active set on few particles): lane l takes the particles l, l + 256, ...
+// against kCritGroup targets at a time, the records of kCritBatch tiles loaded before
+// their pairs so that one memory latency serves several tiles; the maxima and negated
+// minima are then combined over the wave (wave_reduce_many) and over the 4 waves.  Max
+// and min are exact, so dtc is what the criterion kernels give bit for bit.  The targets'
+// corrected velocities were stored by this workgroup; every other particle's predicted
+// record was stored before its workgroup counted itself in, so last_workgroup made it
+// visible.
+constexpr int kCritGroup = 8;
+constexpr int kCritBatch = 4;
+
+template <class V>
+__device__ __forceinline__ void small_criterion_last(const ForceArgs &A, const int *sg) {
+  using F = typename V::F;
+  using SR = StepRec<V>;
+  constexpr int G = kCritGroup;
+  __shared__ typename SR::I ti[kSmallAct];
+  __shared__ F red[kSmallAct][2][kWG / 64];
+  const CritArgs &C = A.crit;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __syncthreads();
+  if (tid < A.n_act) ti[tid] = load_iv<V>(C, sg[tid]);
+  __syncthreads();
+  const F eps2 = static_cast<F>(C.eps2);
+  const int n_tiles = static_cast<int>(C.npad / kTJ);
+  const F inf = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
+  for (int q0 = 0; q0 < A.n_act; q0 += G) {
+    F qm[G], sm[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      qm[u] = F(0);
+      sm[u] = inf;
+    }
+    for (int jt = 0; jt < n_tiles; jt += kCritBatch) {
+      typename SR::J J[kCritBatch];
+#pragma unroll
+      for (int b = 0; b < kCritBatch; ++b)
+        if (jt + b < n_tiles) J[b] = load_jv<V>(C, static_cast<int64_t>(jt + b) * kTJ + tid);
+#pragma unroll
+      for (int b = 0; b < kCritBatch; ++b) {
+        if (jt + b >= n_tiles) break;
+        const int64_t j = static_cast<int64_t>(jt + b) * kTJ + tid;
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int q = q0 + u;
+          if (q < A.n_act) pair_step(ti[q], J[b], eps2, j == sg[q] || j >= C.n, qm[u], sm[u]);
+        }
+      }
+    }
+    F x[2 * G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      x[u] = qm[u];
+      x[G + u] = -sm[u];
+    }
+    const F r = wave_reduce_many<2 * G>(x, lane, [](F a, F b) { return fmax(a, b); });
+    // lane l holds value v = l >> 2: the maximum of target q0 + v (v < G), else the
+    // negated minimum of target q0 + v - G
+    const int v = lane >> 2;
+    const int q = q0 + (v & (G - 1));
+    if ((lane & 3) == 0 && q < A.n_act) {
+      if (v < G)
+        red[q][0][w] = r;
+      else
+        red[q][1][w] = -r;
+    }
+  }
+  __syncthreads();
+  if (tid < A.n_act) {
+    double qmax = 0.0, swmin = __builtin_inf();
+#pragma unroll
+    for (int ww = 0; ww < kWG / 64; ++ww) {
+      qmax = fmax(qmax, static_cast<double>(red[tid][0][ww]));
+      swmin = fmin(swmin, static_cast<double>(red[tid][1][ww]));
+    }
+    C.dtc[tid] = finish_dt(C.eta, qmax, swmin);
+  }
+}
+
+template <class V, int NEWTON>
+__global__ __launch_bounds__(kWG) void k_force_small(ForceArgs A) {
+  __shared__ typename V::I si[kSmallAct];
+  __shared__ int sg[kSmallAct];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int64_t P = A.npad;
+  const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
+  const typename V::J J = V::load_j(A.p32, A.p64, P, j, Scale<V, NEWTON>::kMass);
+  if (tid < A.n_act) {
+    sg[tid] = A.idx[tid];
+    si[tid] = V::load_i(A.p32, A.p64, P, sg[tid]);
+  }
+  __syncthreads();
+  small_tile_sums<V, NEWTON>(A, si, sg, J, j, tile);
+  if (A.fuse_reduce && last_workgroup(A.done)) small_reduce_last<V, NEWTON>(A, sg);
 }
 
 // Source record of a policy built from a particle's predicted position and mass: the
@@ -302,15 +445,34 @@ __device__ __forceinline__ typename V::I i_from_state(double x, double y, double
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictArgs Pr,
                                                           InlineIdx in) {
-  using F = typename V::F;
   __shared__ typename V::I si[kSmallAct];
   __shared__ int sg[kSmallAct];
-  __shared__ F red[kSmallAct][4][kWG / 64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
-  const F eps2 = sizeof(F) == 4 ? static_cast<F>(A.eps2f) : static_cast<F>(A.eps2);
   const float ms = Scale<V, NEWTON>::kMass;
+  // Targets are active at the block time: their Taylor polynomial.  Thread q keeps target
+  // q's corrector inputs (the values the prediction used, the position it gives, the
+  // record count), so the last workgroup corrects without reading them back; the thread
+  // that owns the target as a source stores the same predicted position.
+  TargetState ts;
+  if (tid < A.n_act) {
+    const int g = in.k ? in.v[tid] : A.idx[tid];
+    sg[tid] = g;
+    const int64_t n = Pr.n;
+    ts.tl = Pr.t_last[g];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ts.v[c] = Pr.v[c * n + g];
+      ts.a[c] = Pr.a[c * n + g];
+    }
+    ts.cnt = A.correct && A.corr.record ? A.corr.cnt[g] : 0;
+    double st[6];
+    predict_taylor(Pr, g, ts.tl, st);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ts.rn[c] = st[c];
+    si[tid] = i_from_state<V>(st[0], st[1], st[2]);
+  }
   typename V::J J;
   if (j < Pr.n) {
     double st[6];
@@ -323,35 +485,11 @@ __global__ __launch_bounds__(kWG) void k_force_small_pred(ForceArgs A, PredictAr
     J = j_from_state<V>(kFar, kFar, kFar, 0.0, ms);
   }
   if (blockIdx.x == 0) store_inline_idx(in, tid);
-  if (tid < A.n_act) {
-    sg[tid] = in.k ? in.v[tid] : A.idx[tid];
-    double st[6];
-    predict_state(Pr, sg[tid], false, st);
-    si[tid] = i_from_state<V>(st[0], st[1], st[2]);
-  }
   __syncthreads();
-  for (int q = 0; q < A.n_act; ++q) {
-    F ax = F(0), ay = F(0), az = F(0), pp = F(0);
-    pair_acc<V, NEWTON, 1, 1>(si[q], J, eps2, j == sg[q], ax, ay, az, pp);
-    ax = wave_sum_t(ax);
-    ay = wave_sum_t(ay);
-    az = wave_sum_t(az);
-    pp = wave_sum_t(pp);
-    if (lane == 0) {
-      red[q][0][w] = ax;
-      red[q][1][w] = ay;
-      red[q][2][w] = az;
-      red[q][3][w] = pp;
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < 4 * A.n_act; t += kWG) {
-    const int q = t >> 2, c = t & 3;
-    double s = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < kWG / 64; ++ww) s += static_cast<double>(red[q][c][ww]);
-    A.part[(static_cast<int64_t>(tile) * 4 + c) * A.n_act + q] = s;
-  }
+  small_tile_sums<V, NEWTON>(A, si, sg, J, j, tile);
+  if (!A.fuse_reduce || !last_workgroup(A.done)) return;
+  small_reduce_last<V, NEWTON>(A, sg, &ts);
+  if (A.crit.on) small_criterion_last<V>(A, sg);
 }
 
 // Add the slices' partials in slice order and finish (scale, sign).
@@ -448,6 +586,7 @@ hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nul
   A.plan.n_slices = A.n_jtiles;
   A.plan.tiles_per_slice = 1;
   A.plan.nblk = A.n_jtiles;
+  A.fuse_reduce = fuse_small_reduce(A.plan.n_slices, 4 * A.n_act) ? 1 : 0;
   if (pred) {
     InlineIdx none;
     none.out = nullptr;
@@ -457,12 +596,14 @@ hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nul
   }
   else
     hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
-  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
-    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
-    hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
-  } else {
-    const int nb = (A.n_act + kWG - 1) / kWG;
-    hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+  if (!A.fuse_reduce) {
+    if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+      const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
+      hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+    } else {
+      const int nb = (A.n_act + kWG - 1) / kWG;
+      hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
+    }
   }
   return hipGetLastError();
 }
@@ -520,6 +661,7 @@ hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, doub
                                double *pot, double *part, int blocks, hipStream_t st,
                                const CorrectArgs *corr) {
   ForceArgs A;
+  A.crit.on = 0;
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;
   A.p32 = c->p32;
@@ -537,6 +679,8 @@ hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, doub
   A.ipl = force_targets_per_lane(c, n_act);
   A.scalar_j = force_scalar_j(c) ? 1 : 0;
   A.chunk = scalar_chunk(c, n_act, 1);
+  A.done = c->done;
+  A.fuse_reduce = 0;
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
@@ -558,11 +702,30 @@ int small_act_limit(const tsbts_ctx *c) {
   return c->precision == TSBTS_FP64 ? kSmallActFp64 : kSmallAct;
 }
 
+bool small_criterion_fused(const tsbts_ctx *c, int n_act) {
+  const int64_t tiles = c->npad / kTJ;
+  const int groups = (n_act + kCritGroup - 1) / kCritGroup;
+  return n_act <= small_act_limit(c) && fuse_small_reduce(static_cast<int>(tiles), 4 * n_act) &&
+         tiles * groups <= kCritFuseTiles;
+}
+
 hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
                                   int use_history, double *acc, double *pot, hipStream_t st,
                                   const CorrectArgs *corr, const PendingSteps *pend,
-                                  const InlineIdx *in) {
+                                  const InlineIdx *in, double eta, double *dtc) {
   ForceArgs A;
+  A.crit.on = 0;
+  if (dtc && corr && small_criterion_fused(c, n_act)) {
+    A.crit.on = 1;
+    A.crit.n = c->n;
+    A.crit.p32 = c->p32;
+    A.crit.p64 = c->p64;
+    A.crit.v64 = c->v64;
+    A.crit.npad = c->npad;
+    A.crit.eps2 = c->eps * c->eps;
+    A.crit.eta = eta;
+    A.crit.dtc = dtc;
+  }
   A.correct = corr ? 1 : 0;
   if (corr) A.corr = *corr;
   A.p32 = c->p32;
@@ -580,12 +743,10 @@ hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, d
   A.ipl = 1;
   A.scalar_j = 0;
   A.chunk = kTJ;
+  A.done = c->done;
+  A.fuse_reduce = 0;
   PredictArgs P = predict_args(c, t_block, use_history);
-  if (pend) {
-    P.pend_tag = pend->tag;
-    P.pend_dt = pend->dt;
-    P.pend_step = pend->step;
-  }
+  set_pending(P, pend);
   if (c->precision == TSBTS_FP64) return run_small<Fp64, 0>(A, st, &P, in);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;

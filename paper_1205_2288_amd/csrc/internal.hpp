@@ -77,6 +77,9 @@ struct tsbts_ctx {
                                                       // range, [1] a repeated index
                                                       // (mapped pinned memory)
   int32_t *idx_seen = nullptr;  // [n] occurrence counters of the check
+  // finished-workgroup counts of the small-set force [0] and criterion [1] launches whose
+  // last workgroup reduces the partials (last_workgroup); zero between launches
+  uint32_t *done = nullptr;
   // symmetric all-targets kernels: work items (int4) and partials
   void *sym_items = nullptr;
   int sym_items_n = 0;
@@ -140,6 +143,60 @@ __device__ __forceinline__ double wave_min(double x) {
   return x;
 }
 
+// Reduction over one wave64 of NV values per lane (NV a power of two, at most 64) by
+// recursive halving: at each of the log2(NV) stages a lane keeps half of its values and
+// combines them with its partner's copies of the same values (one shuffle per kept value,
+// 63 shuffles for 64 values where separate butterflies take 384); the remaining stages
+// combine the one value left across lanes.  Lane l returns value l >> (6 - log2 NV),
+// combined over all 64 lanes (the same in every lane of its group); x is consumed.
+template <int NV, class T, class Op>
+__device__ __forceinline__ T wave_reduce_many(T (&x)[NV], int lane, Op op) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "power of two up to 64");
+  constexpr int M = NV == 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : NV == 16 ? 4
+                  : NV == 32 ? 5 : 6;
+#pragma unroll
+  for (int s = 0; s < M; ++s) {
+    const int o = 32 >> s;
+    const int half = NV >> (s + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      // both elements read first: a select between array elements would become a select
+      // of addresses, which keeps a float64 array out of registers
+      const T a = x[i], b = x[half + i];
+      const T keep = up ? b : a;
+      const T send = up ? a : b;
+      x[i] = op(keep, __shfl_xor(send, o, 64));
+    }
+  }
+  T r = x[0];
+#pragma unroll
+  for (int o = 32 >> M; o >= 1; o >>= 1) r = op(r, __shfl_xor(r, o, 64));
+  return r;
+}
+
+// Whether this workgroup is the last of its launch (a one-dimensional grid) to get here,
+// for a launch whose last workgroup finishes a reduction over every workgroup's stores.
+// Every thread makes its stores visible device-wide (agent-scope fence: across the XCDs'
+// separate L2 caches) before one thread counts the workgroup in `done`; the last one
+// resets the count to zero for the next launch and, after an acquire fence of every
+// thread, sees all stores made before the other workgroups counted.  No workgroup waits
+// for another.  Every thread of the workgroup must call it.
+__device__ __forceinline__ bool last_workgroup(uint32_t *done) {
+  __shared__ uint32_t last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t before = atomicAdd(done, 1u);
+    last = before + 1 == gridDim.x ? 1u : 0u;
+    if (last) atomicExch(done, 0u);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  return true;
+}
+
 // Split-j partials are combined by one thread per target when there are few slices and
 // by one wave per target (lanes striding over the slices) when there are many.
 constexpr int kWaveReduceSlices = 16;
@@ -148,6 +205,15 @@ constexpr int kWaveReduceSlices = 16;
 constexpr int64_t kWaveReduceMaxTargets = 4096;
 __host__ __device__ inline bool use_wave_reduce(int n_slices, int64_t n_targets) {
   return n_slices >= kWaveReduceSlices && n_targets <= kWaveReduceMaxTargets;
+}
+
+// The small-set kernels' last workgroup reduces the partials (W values per slice) itself
+// when each of its threads then reads at most kFuseLoads of them; otherwise a reduction
+// kernel follows.
+constexpr int kFuseLoads = 32;
+__host__ __device__ inline bool fuse_small_reduce(int n_slices, int W) {
+  const int parts = W <= kWG ? kWG / W : 1;
+  return W <= kWG && (n_slices + parts - 1) / parts <= kFuseLoads;
 }
 
 // Active sets up to this size use the j-parallel pair kernels (one source per lane).
@@ -230,6 +296,10 @@ struct PendingSteps {
   const int64_t *tag;  // [n] (step << 32) | list position, written by the corrector
   const double *dt;    // [k] new steps, by position in that step's active list
   int64_t step;
+  // the same steps as powers of two, dt[q] = 2^exp[q], when k <= kInlinePend (host
+  // memory, copied into the launch arguments); null: the kernels read dt
+  const int8_t *exp;
+  int k;
 };
 struct InlineIdx;
 hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st,
@@ -257,11 +327,14 @@ int force_criterion_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, dou
 // Force on the active set and its corrector in the same launches (checked like the two
 // entry points; returns a status code).  With `in`, the active list arrives by value
 // and the first kernel writes it to idx (which must then not be checked beforehand).
+// With dtc, also the criterion (eta) of the corrected targets when small_criterion_fused
+// holds; *crit_done tells whether it did (else the caller runs tsbts_timestep).
 int force_correct_predicted(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
                             int use_history, double *acc, hipStream_t stream,
                             const StepTags *tags = nullptr,
                             const PendingSteps *pend = nullptr,
-                            const InlineIdx *in = nullptr);
+                            const InlineIdx *in = nullptr, double eta = 0.0,
+                            double *dtc = nullptr, int *crit_done = nullptr);
 int force_correct(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double t_block,
                   double *acc, hipStream_t stream, const StepTags *tags = nullptr);
 // tsbts_predict with pending new steps and an inline active list (either may be null).
@@ -307,10 +380,18 @@ hipError_t launch_block_adjoint(tsbts_ctx *c, int phase, const int32_t *idx, int
 int small_act_limit(const tsbts_ctx *c);
 // Predictor and force (with the corrector, if corr) in the small-set kernels, the sources
 // predicted as they are loaded (n_act <= small_act_limit).
+// With dtc (and corr), when small_criterion_fused holds, the launch's last workgroup also
+// takes the criterion of the corrected targets into dtc (as launch_timestep would).
 hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, double t_block,
                                   int use_history, double *acc, double *pot, hipStream_t st,
                                   const CorrectArgs *corr, const PendingSteps *pend = nullptr,
-                                  const InlineIdx *in = nullptr);
+                                  const InlineIdx *in = nullptr, double eta = 0.0,
+                                  double *dtc = nullptr);
+// Whether launch_force_predicted takes the criterion of n_act targets itself: the one
+// workgroup's passes over the particles are short (j-tiles times groups of 8 targets at
+// most kCritFuseTiles).
+constexpr int kCritFuseTiles = 8;
+bool small_criterion_fused(const tsbts_ctx *c, int n_act);
 // Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.
 struct SymPlan;
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,

@@ -127,17 +127,25 @@ PredictArgs predict_args(tsbts_ctx *c, double t_block, int use_history) {
   p.pend_dt = nullptr;
   p.pend_step = 0;
   p.dt_w = c->dt;
+  p.pend_inline = 0;
   return p;
+}
+
+void set_pending(PredictArgs &p, const PendingSteps *pend) {
+  if (!pend) return;
+  p.pend_tag = pend->tag;
+  p.pend_dt = pend->dt;
+  p.pend_step = pend->step;
+  if (pend->exp && pend->k <= kInlinePend) {
+    p.pend_inline = 1;
+    std::copy(pend->exp, pend->exp + pend->k, p.pend_exp);
+  }
 }
 
 hipError_t launch_predict(tsbts_ctx *c, double t_block, int use_history, hipStream_t st,
                           const PendingSteps *pend, const InlineIdx *in) {
   PredictArgs p = predict_args(c, t_block, use_history);
-  if (pend) {
-    p.pend_tag = pend->tag;
-    p.pend_dt = pend->dt;
-    p.pend_step = pend->step;
-  }
+  set_pending(p, pend);
   InlineIdx none;
   none.out = nullptr;
   none.k = 0;

@@ -76,6 +76,9 @@ __device__ __forceinline__ void from_records(const double *ht, const double *hs,
   }
 }
 
+// Pending new steps of at most this many targets travel by value (PredictArgs).
+constexpr int kInlinePend = 256;
+
 struct PredictArgs {
   Out o;
   int64_t n;
@@ -91,10 +94,14 @@ struct PredictArgs {
   // in that step's active list, whose new steps pend_dt[q] the host chose after it.  A
   // particle whose tag names pend_step takes pend_dt[q] as its step; the thread that owns
   // it also stores it in dt_w.  Null pend_tag: no pending steps.
+  // With pend_inline, the steps arrive by value instead: pend_dt[q] = 2^pend_exp[q] (every
+  // step of the scheduler is a power of two), so no kernel reads them from host memory.
   const int64_t *pend_tag;
   const double *pend_dt;
   int64_t pend_step;
   double *dt_w;
+  int pend_inline;
+  int8_t pend_exp[kInlinePend];
 };
 
 // An active list of at most kInlineIdx particles passed by value to the first kernel of
@@ -112,15 +119,31 @@ __device__ __forceinline__ void store_inline_idx(const InlineIdx &in, int64_t t)
 
 // Step of particle j at p.tb: its pending new step, else the stored one.
 __device__ __forceinline__ double step_of(const PredictArgs &p, int64_t j, bool owner) {
+  const double stored = p.dt[j];  // read with the tag, not after it
   if (p.pend_tag) {
     const int64_t e = p.pend_tag[j];
     if ((e >> 32) == p.pend_step) {
-      const double d = p.pend_dt[static_cast<int32_t>(e & 0xffffffff)];
+      const int32_t q = static_cast<int32_t>(e & 0xffffffff);
+      const double d = p.pend_inline ? ldexp(1.0, p.pend_exp[q]) : p.pend_dt[q];
       if (owner) p.dt_w[j] = d;
       return d;
     }
   }
-  return p.dt[j];
+  return stored;
+}
+
+// Taylor polynomial of particle j from its last time tl to p.tb (Section 2 predictor).
+__device__ __forceinline__ void predict_taylor(const PredictArgs &p, int64_t j, double tl,
+                                               double s[6]) {
+  const int64_t n = p.n;
+  const double h = p.tb - tl;
+  const double hh = 0.5 * h * h;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double rr = p.r[c * n + j], vv = p.v[c * n + j], aa = p.a[c * n + j];
+    s[c] = rr + vv * h + aa * hh;
+    s[c + 3] = vv + aa * h;
+  }
 }
 
 // Predicted position and velocity of particle j < n at p.tb (Section 2 predictor;
@@ -132,34 +155,44 @@ __device__ __forceinline__ double step_of(const PredictArgs &p, int64_t j, bool 
 // it (update_cursor); that thread also stores a pending new step (step_of).
 __device__ __forceinline__ void predict_state(const PredictArgs &p, int64_t j,
                                               bool update_cursor, double s[6]) {
-  const int64_t n = p.n;
   const double tl = p.t_last[j];
+  // the record range and cursor are read with the activity test's inputs, and the two
+  // records at the cursor together: the loads overlap instead of following one another
+  int lo = 0, hi = 0, k = 0;
+  if (p.use_hist) {
+    lo = p.off[j];
+    hi = p.off[j + 1];
+    k = p.cur[j];
+  }
   const bool active = (tl + step_of(p, j, update_cursor) == p.tb);
   if (p.use_hist && !active) {
-    const int lo = p.off[j], hi = p.off[j + 1];
-    int k = p.cur[j];
+    // every particle has a record at its era start, so lo < hi and ht[k] exists
     const int k0 = k;
-    while (k > lo && p.ht[k] > p.tb) --k;
-    while (k + 1 < hi && p.ht[k + 1] <= p.tb) ++k;
+    double tk = p.ht[k];
+    double tn = k + 1 < hi ? p.ht[k + 1] : 0.0;
+    while (k > lo && tk > p.tb) {
+      tn = tk;
+      tk = p.ht[--k];
+    }
+    while (k + 1 < hi && tn <= p.tb) {
+      tk = tn;
+      ++k;
+      tn = k + 1 < hi ? p.ht[k + 1] : 0.0;
+    }
     if (update_cursor && k != k0) p.cur[j] = k;
-    const bool exact = (p.ht[k] == p.tb);
+    const bool exact = (tk == p.tb);
     if (exact || k + 1 < hi) {
       from_records(p.ht, p.hs, p.hcap, k, p.tb, exact, s);
       return;
     }
   }
-  const double h = p.tb - tl;
-  const double hh = 0.5 * h * h;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double rr = p.r[c * n + j], vv = p.v[c * n + j], aa = p.a[c * n + j];
-    s[c] = rr + vv * h + aa * hh;
-    s[c + 3] = vv + aa * h;
-  }
+  predict_taylor(p, j, tl, s);
 }
 
 // Predictor arguments for the context at t_block (history source of the context), with
 // no pending steps.
 PredictArgs predict_args(tsbts_ctx *c, double t_block, int use_history);
+// The pending steps `pend` (may be null) in p: by value when they come as exponents.
+void set_pending(PredictArgs &p, const PendingSteps *pend);
 
 }  // namespace tsbts

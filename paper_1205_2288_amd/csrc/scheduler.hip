@@ -24,6 +24,7 @@
 //     chosen again by the later-pass rule (from the step that brought it there) with the
 //     previous pass's end values, so the first step of an era is symmetrized too.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -61,18 +62,28 @@ int64_t era_end_rule(int64_t t0, int64_t first, int64_t last, int64_t largest,
   return (t0 / p2 + 1) * p2;
 }
 
-int64_t step_rule(int first_pass, int64_t dt, int64_t tb, double begin, double end_dt,
-                  double end_2dt, int64_t dt_min, int64_t dt_max) {
+// step_rule with the previous pass's values at the ends of the two candidate steps given
+// on demand by end_dt() and end_2dt(): each is needed on some branches only.
+template <class E1, class E2>
+int64_t step_rule_lazy(int first_pass, int64_t dt, int64_t tb, double begin, E1 end_dt,
+                       E2 end_2dt, int64_t dt_min, int64_t dt_max) {
   if (first_pass) {
     const int64_t lvl = admissible_ticks(begin, begin, dt_min, dt_max);
     if (lvl >= 2 * dt && tb % (2 * dt) == 0) return 2 * dt;
     return std::min(dt, lvl);
   }
   const bool even = (tb / dt) % 2 == 0;
-  if (even && 2 * dt <= dt_max && 2 * dt <= admissible_ticks(begin, end_2dt, dt_min, dt_max))
+  if (even && 2 * dt <= dt_max && 2 * dt <= admissible_ticks(begin, end_2dt(), dt_min, dt_max))
     return 2 * dt;
-  if (dt <= admissible_ticks(begin, end_dt, dt_min, dt_max)) return dt;
+  if (dt <= admissible_ticks(begin, end_dt(), dt_min, dt_max)) return dt;
   return std::max(dt / 2, dt_min);
+}
+
+int64_t step_rule(int first_pass, int64_t dt, int64_t tb, double begin, double end_dt,
+                  double end_2dt, int64_t dt_min, int64_t dt_max) {
+  return step_rule_lazy(
+      first_pass, dt, tb, begin, [&] { return end_dt; }, [&] { return end_2dt; }, dt_min,
+      dt_max);
 }
 
 namespace {
@@ -91,6 +102,7 @@ struct CritHistory {
   std::vector<int64_t> off;  // n + 1 after close()
   std::vector<int64_t> gt;
   std::vector<double> gc;
+  std::vector<int64_t> cur;  // per particle: the record value_at found last
 
   void clear() {
     pid.clear();
@@ -114,17 +126,17 @@ struct CritHistory {
       gt[d] = t[r];
       gc[d] = c[r];
     }
+    cur.assign(off.begin(), off.end() - 1);
   }
   // value of particle i at time tt, linear between stored values, fallback past the last
-  double value_at(int32_t i, int64_t tt, double fallback) const {
+  double value_at(int32_t i, int64_t tt, double fallback) {
     const int64_t lo = off[i], hi = off[i + 1];
-    // last record with time <= tt (the first record is at or before the era start)
-    int64_t a = lo, b = hi - 1;
-    while (a < b) {
-      const int64_t mid = (a + b + 1) >> 1;
-      if (gt[mid] <= tt) a = mid; else b = mid - 1;
-    }
-    const int64_t k = a;
+    // last record with time <= tt, else the first (at or before the era start): found
+    // from the particle's cursor, which a pass's queries move by a few records at most
+    int64_t k = cur[i];
+    while (k > lo && gt[k] > tt) --k;
+    while (k + 1 < hi && gt[k + 1] <= tt) ++k;
+    cur[i] = k;
     if (gt[k] == tt) return gc[k];
     if (k + 1 >= hi) return fallback;
     const double w = static_cast<double>(tt - gt[k]) / static_cast<double>(gt[k + 1] - gt[k]);
@@ -161,8 +173,12 @@ struct Scheduler {
   std::vector<int64_t> s0_t, s0_dt, s0_dtp;
   std::vector<double> s0_dtc;
   int64_t stats[4] = {0, 0, 0, 0};  // block steps, force calls, interactions, eras
+  // wall-clock breakdown of the block steps by active-set class (tsbts_sched_timing)
+  double phase_s[4][4] = {};
+  int64_t phase_n[4][2] = {};
   int crit_before = 0;  // criterion with the predicted velocities, fused with the force
-  int pred_on_load = 0;  // small active sets: prediction folded into the force kernel
+  int pred_on_load = 1;  // small active sets: prediction (and on few particles the
+                         // criterion) folded into the force kernel
   // The new steps chosen after a block step are not scattered by a launch of their own:
   // the corrector tags each target with (step id, list position), and the next block
   // step's first kernel takes the pending steps from dtn_h through those tags.  At the
@@ -172,6 +188,8 @@ struct Scheduler {
   bool pending = false;      // dtn_h holds new steps of step `pending_step` not yet stored
   int64_t pending_step = 0;
   int32_t pending_k = 0;     // its active-set size (its list is still in idx_d)
+  // the same steps as exponents, dt = 2^exp, passed by value when at most kInlinePend
+  int8_t pend_exp[tsbts::kInlinePend];
 
   void rebuild_levels() {
     for (auto &m : mem) m.clear();
@@ -241,6 +259,41 @@ int sfail(tsbts_ctx *c, int st, const char *msg) {
     if (_s != TSBTS_OK) return _s; \
   } while (0)
 
+// Wait for the criterion values of a block step, dtc_h[0 .. k), which the step's last
+// kernel writes through the coherent mapping of dtc_h (set to kUnsetBits before the
+// launches; no arithmetic gives that NaN payload): the host spins on the values rather
+// than waiting for the stream's completion signal.  The step's other results are read
+// only by later launches on the stream, which follow it anyway.  Every 20 us of spinning
+// it asks for the stream's status, so a failed or lost launch ends the wait with an error.
+constexpr uint64_t kUnsetBits = 0x7ff4deadbeef0001ull;
+
+int wait_criterion(tsbts_ctx *c, Scheduler &S, int32_t k, hipStream_t st) {
+  using clk = std::chrono::steady_clock;
+  const auto *bits = reinterpret_cast<const uint64_t *>(S.dtc_h);
+  auto t0 = clk::now();
+  uint32_t spins = 0;
+  for (int32_t q = 0; q < k;) {
+    if (__atomic_load_n(bits + q, __ATOMIC_ACQUIRE) != kUnsetBits) {
+      ++q;
+      continue;
+    }
+    if ((++spins & 255) != 0 || clk::now() - t0 < std::chrono::microseconds(20)) continue;
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipErrorNotReady) {
+      t0 = clk::now();
+      continue;
+    }
+    SCHED_HIP(e);
+    // the stream is idle: every value of the step is in place
+    for (; q < k; ++q)
+      if (__atomic_load_n(bits + q, __ATOMIC_ACQUIRE) == kUnsetBits) {
+        snprintf(c->err, sizeof(c->err), "block step ended without criterion value %d", q);
+        return TSBTS_EHIP;
+      }
+  }
+  return TSBTS_OK;
+}
+
 // Store the new steps of the last block step, if the next block step has not (its list
 // is still in idx_d).
 int flush_steps(tsbts_ctx *c, Scheduler &S, hipStream_t st) {
@@ -255,7 +308,10 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
   S.cur.clear();
   for (int64_t i = 0; i < n; ++i) S.cur.add(static_cast<int32_t>(i), S.t[i], S.dtc[i]);
   SCHED_CALL(tsbts_history_begin(c, st));
+  using clk = std::chrono::steady_clock;
+  auto t_prev = clk::now();
   for (;;) {
+    const auto t_top = clk::now();
     const int64_t tb = S.next_time();
     if (tb > T1) break;
     // active set: all members of the levels whose next time is tb
@@ -267,6 +323,8 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     }
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
     const int64_t step = ++S.step_id;
+    std::fill(reinterpret_cast<uint64_t *>(S.dtc_h), reinterpret_cast<uint64_t *>(S.dtc_h) + k,
+              kUnsetBits);
     // small lists travel by value in the first kernel's arguments (it writes idx_d)
     tsbts::InlineIdx in;
     in.out = S.idx_d;
@@ -278,14 +336,18 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       SCHED_HIP(hipMemcpyAsync(S.idx_d, S.idx_h, sizeof(int32_t) * k, hipMemcpyHostToDevice,
                                st));
     }
-    const tsbts::PendingSteps pend{S.tag_d, S.dtn_hd, S.pending_step};
+    const tsbts::PendingSteps pend{S.tag_d, S.dtn_hd, S.pending_step,
+                                   S.pending_k <= tsbts::kInlinePend ? S.pend_exp : nullptr,
+                                   S.pending_k};
     const tsbts::PendingSteps *pp = S.pending ? &pend : nullptr;
     const tsbts::InlineIdx *ip = in.k ? &in : nullptr;
     const tsbts::StepTags tags{S.tag_d, step};
     if (S.pred_on_load && !S.crit_before && k <= tsbts::small_act_limit(c)) {
+      int crit_done = 0;
       SCHED_CALL(tsbts::force_correct_predicted(c, S.idx_d, k, tbs, p > 0 ? 1 : 0, S.acc_d,
-                                                st, &tags, pp, ip));
-      SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
+                                                st, &tags, pp, ip, S.eta, S.dtc_hd,
+                                                &crit_done));
+      if (!crit_done) SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     } else if (S.crit_before) {
       SCHED_CALL(tsbts::predict_pending(c, tbs, p > 0 ? 1 : 0, pp, ip, st));
       SCHED_CALL(tsbts::force_criterion_correct(c, S.idx_d, k, tbs, S.eta, S.acc_d, S.dtc_hd,
@@ -295,7 +357,9 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       SCHED_CALL(tsbts::force_correct(c, S.idx_d, k, tbs, S.acc_d, st, &tags));
       SCHED_CALL(tsbts_timestep(c, S.idx_d, k, S.eta, S.dtc_hd, st));
     }
-    SCHED_HIP(hipStreamSynchronize(st));
+    const auto t_issued = clk::now();
+    SCHED_CALL(wait_criterion(c, S, k, st));
+    const auto t_done = clk::now();
     for (int32_t q = 0; q < k; ++q) {
       const int32_t i = S.idx_h[q];
       const double b = S.dtc_h[q];
@@ -304,16 +368,15 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       S.t[i] = tb;
       S.cur.add(i, tb, b);
       const int64_t d = S.dt[i];
-      double e1 = b, e2 = b;
-      if (p > 0) {
-        e1 = S.prev.value_at(i, tb + d, b);
-        e2 = S.prev.value_at(i, tb + 2 * d, b);
-      }
-      const int64_t nd = tsbts::step_rule(p == 0, d, tb, b, e1, e2, S.dt_min, S.dt_max);
+      const int64_t nd = tsbts::step_rule_lazy(
+          p == 0, d, tb, b, [&] { return S.prev.value_at(i, tb + d, b); },
+          [&] { return S.prev.value_at(i, tb + 2 * d, b); }, S.dt_min, S.dt_max);
       S.dtn_h[q] = static_cast<double>(nd) * tsbts::kTick;
+      const int l = tsbts::level_of(nd);  // nd = 2^l ticks (powers of two throughout)
+      if (q < tsbts::kInlinePend) S.pend_exp[q] = static_cast<int8_t>(l - tsbts::kTickBits);
       if (nd != d) {
         S.dt[i] = nd;
-        S.move(i, tsbts::level_of(nd));
+        S.move(i, l);
       }
     }
     // the next block step's first kernel stores these steps; dtn_h is rewritten only
@@ -324,6 +387,16 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     S.stats[0] += 1;
     S.stats[1] += 1;
     S.stats[2] += static_cast<int64_t>(k) * n;
+    const auto t_end = clk::now();
+    const int cls = k <= 32 ? 0 : k <= 256 ? 1 : k <= 1024 ? 2 : 3;
+    auto sec = [](clk::duration d) { return std::chrono::duration<double>(d).count(); };
+    S.phase_s[cls][0] += sec(t_issued - t_top);
+    S.phase_s[cls][1] += sec(t_done - t_issued);
+    S.phase_s[cls][2] += sec(t_end - t_done);
+    S.phase_s[cls][3] += sec(t_end - t_prev);
+    S.phase_n[cls][0] += 1;
+    S.phase_n[cls][1] += k;
+    t_prev = t_end;
   }
   SCHED_CALL(flush_steps(c, S, st));
   SCHED_CALL(tsbts_history_end(c, st));
@@ -344,9 +417,10 @@ int first_steps(tsbts_ctx *c, Scheduler &S, int64_t T0, hipStream_t st) {
     if (S.t[i] == T0 && S.dtp[i] > 0) {
       const int64_t d = S.dtp[i];
       const double b = S.dtc[i];
-      const double e1 = S.prev.value_at(static_cast<int32_t>(i), T0 + d, b);
-      const double e2 = S.prev.value_at(static_cast<int32_t>(i), T0 + 2 * d, b);
-      S.dt[i] = tsbts::step_rule(0, d, T0, b, e1, e2, S.dt_min, S.dt_max);
+      const int32_t ii = static_cast<int32_t>(i);
+      S.dt[i] = tsbts::step_rule_lazy(
+          0, d, T0, b, [&] { return S.prev.value_at(ii, T0 + d, b); },
+          [&] { return S.prev.value_at(ii, T0 + 2 * d, b); }, S.dt_min, S.dt_max);
     }
     S.dtn_h[i] = static_cast<double>(S.dt[i]) * tsbts::kTick;
   }
@@ -446,7 +520,9 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   S->lvl.assign(n, 0);
   S->pos.assign(n, 0);
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->idx_h), sizeof(int32_t) * n));
-  SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtc_h), sizeof(double) * n));
+  // coherent: the kernels' criterion values reach host memory as they are written
+  SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtc_h), sizeof(double) * n,
+                          hipHostMallocMapped | hipHostMallocCoherent));
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtn_h), sizeof(double) * n));
   SCHED_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&S->dtc_hd), S->dtc_h, 0));
   SCHED_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&S->dtn_hd), S->dtn_h, 0));
@@ -530,6 +606,14 @@ int tsbts_sched_option(tsbts_ctx *c, int option, int value) {
     S->crit_before = value;
   else
     S->pred_on_load = value;
+  return TSBTS_OK;
+}
+
+int tsbts_sched_timing(const tsbts_ctx *c, double *seconds, int64_t *counts) {
+  if (!c || !c->sched) return TSBTS_EINVAL;
+  const Scheduler *S = static_cast<const Scheduler *>(c->sched);
+  if (seconds) std::copy(&S->phase_s[0][0], &S->phase_s[0][0] + 16, seconds);
+  if (counts) std::copy(&S->phase_n[0][0], &S->phase_n[0][0] + 8, counts);
   return TSBTS_OK;
 }
 

@@ -33,6 +33,8 @@ struct StepArgs {
   int ipl;
   int scalar_j;  // j-particles through scalar loads (k_timestep_scalar)
   int chunk;     // j-particles per split unit of k_timestep_scalar
+  uint32_t *done;   // finished-workgroup count of k_timestep_small
+  int fuse_reduce;  // its last workgroup reduces the partials
 };
 
 template <class V, int MASK, int IPL, class J, class I, class F>
@@ -160,20 +162,13 @@ __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
   }
 }
 
-// Small active sets: one j-tile per workgroup, one source per lane, targets from LDS;
-// wave-level max / min, then the 4 waves, into one partial per tile and target.
-template <class F>
-__device__ __forceinline__ F wave_max_t(F x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
-}
-template <class F>
-__device__ __forceinline__ F wave_min_t(F x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
-  return x;
-}
+// Small active sets: one j-tile per workgroup, one source per lane, targets from LDS.  The
+// maxima of kStepGroup targets and their negated minima are combined over the wave
+// together (wave_reduce_many with max), then over the 4 waves, into one partial per tile
+// and target.  When the partials are few (fuse_reduce) the launch's last workgroup
+// combines them and finishes the targets; max and min are exact, so the order of either
+// combination leaves the results unchanged.
+constexpr int kStepGroup = 16;
 
 template <class V>
 __global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
@@ -181,6 +176,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
   __shared__ typename StepRec<V>::I si[kSmallAct];
   __shared__ int sg[kSmallAct];
   __shared__ F red[kSmallAct][2][kWG / 64];
+  __shared__ double sums[kWG];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tile = blockIdx.x;
   const int64_t j = static_cast<int64_t>(tile) * kTJ + tid;
@@ -191,15 +187,27 @@ __global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
     si[tid] = load_iv<V>(A, sg[tid]);
   }
   __syncthreads();
-  for (int q = 0; q < A.n_act; ++q) {
-    F qm = F(0);
-    F sm = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
-    pair_step(si[q], J, eps2, j == sg[q] || j >= A.n, qm, sm);
-    qm = wave_max_t(qm);
-    sm = wave_min_t(sm);
-    if (lane == 0) {
-      red[q][0][w] = qm;
-      red[q][1][w] = sm;
+  for (int q0 = 0; q0 < A.n_act; q0 += kStepGroup) {
+    F x[2 * kStepGroup];
+#pragma unroll
+    for (int u = 0; u < kStepGroup; ++u) {
+      const int q = q0 + u;
+      F qm = F(0);
+      F sm = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
+      if (q < A.n_act) pair_step(si[q], J, eps2, j == sg[q] || j >= A.n, qm, sm);
+      x[u] = qm;
+      x[kStepGroup + u] = -sm;
+    }
+    const F r = wave_reduce_many<2 * kStepGroup>(x, lane, [](F a, F b) { return fmax(a, b); });
+    // lane l holds value v = l >> 1: the maximum of target q0 + v (v < kStepGroup), else
+    // the negated minimum of target q0 + v - kStepGroup
+    const int v = lane >> 1;
+    const int q = q0 + (v & (kStepGroup - 1));
+    if ((lane & 1) == 0 && q < A.n_act) {
+      if (v < kStepGroup)
+        red[q][0][w] = r;
+      else
+        red[q][1][w] = -r;
     }
   }
   __syncthreads();
@@ -211,6 +219,32 @@ __global__ __launch_bounds__(kWG) void k_timestep_small(StepArgs A) {
       s = c == 0 ? fmax(s, static_cast<double>(red[q][c][ww]))
                  : fmin(s, static_cast<double>(red[q][c][ww]));
     A.part[(static_cast<int64_t>(tile) * 2 + c) * A.n_act + q] = s;
+  }
+  if (!A.fuse_reduce || !last_workgroup(A.done)) return;
+  // the launch's last workgroup: a slice's partials form a row of W = 2 n_act values (the
+  // maxima, then the minima); thread t combines value t % W over part t / W of the slices
+  const int W = 2 * A.n_act, P = kWG / W, S = A.plan.n_slices;
+  const int L = (S + P - 1) / P;
+  const int p = tid / W, vv = tid - p * W;
+  const bool is_max = vv < A.n_act;
+  double acc = is_max ? 0.0 : __builtin_inf();
+  if (p < P) {
+    const int s1 = min(S, (p + 1) * L);
+#pragma unroll 8
+    for (int sl = p * L; sl < s1; ++sl) {
+      const double x = A.part[static_cast<int64_t>(sl) * W + vv];
+      acc = is_max ? fmax(acc, x) : fmin(acc, x);
+    }
+  }
+  sums[tid] = acc;
+  __syncthreads();
+  if (tid < A.n_act) {
+    double qm = 0.0, sm = __builtin_inf();
+    for (int pp = 0; pp < P; ++pp) {
+      qm = fmax(qm, sums[pp * W + tid]);
+      sm = fmin(sm, sums[pp * W + A.n_act + tid]);
+    }
+    A.dtc[tid] = finish_dt(A.eta, qm, sm);
   }
 }
 
@@ -248,7 +282,9 @@ hipError_t run(StepArgs &A, hipStream_t st) {
     A.plan.n_slices = A.n_jtiles;
     A.plan.tiles_per_slice = 1;
     A.plan.nblk = A.n_jtiles;
+    A.fuse_reduce = fuse_small_reduce(A.plan.n_slices, 2 * A.n_act) ? 1 : 0;
     hipLaunchKernelGGL((k_timestep_small<V>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
+    if (A.fuse_reduce) return hipGetLastError();
   } else if (A.scalar_j) {
     A.n_jtiles = static_cast<int>(A.npad / A.chunk);
     A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
@@ -307,6 +343,8 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.ipl = criterion_targets_per_lane(c, n_act);
   A.scalar_j = criterion_scalar_j(c, n_act) ? 1 : 0;
   A.chunk = scalar_chunk(c, n_act, A.ipl);
+  A.done = c->done + 1;
+  A.fuse_reduce = 0;
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);

@@ -356,12 +356,13 @@ class NativeTSBTS:
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
                  era=None, precision="mixed", separation="f64", newton=False,
-                 criterion="after", tune=None, predict_on_load=False):
+                 criterion="after", tune=None, predict_on_load=True):
         """criterion: "after" the corrector (the paper's order) or "before" it, with the
         predicted velocities, in the same pass over the pairs as the force.  tune: keyword
         arguments of Context.tune, applied before the first force evaluation.
-        predict_on_load: small active sets predict their sources inside the force kernel
-        (one launch less per block step, same results)."""
+        predict_on_load: small active sets predict their sources inside the force kernel,
+        and on few particles take the criterion in it too (fewer launches per block step,
+        same results)."""
         from . import _lib as L
         if criterion not in ("after", "before"):
             raise ValueError("criterion must be 'after' or 'before'")
@@ -376,8 +377,8 @@ class NativeTSBTS:
                            0.0 if era is None else era)
         if criterion == "before":
             L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR, 1)
-        if predict_on_load:
-            L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_PREDICT_ON_LOAD, 1)
+        L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_PREDICT_ON_LOAD,
+                             1 if predict_on_load and criterion == "after" else 0)
         self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
         self._host()
         self.wall_s = 0.0
@@ -395,6 +396,22 @@ class NativeTSBTS:
         return {"block_steps": int(st[0]), "force_calls": int(st[1]),
                 "interactions": int(st[2]), "eras": int(st[3]),
                 "era_sizes": dict(self.era_sizes), "wall_s": self.wall_s}
+
+    def step_timing(self) -> dict:
+        """Mean wall time per block step (microseconds) in each phase (issue of the
+        launches, wait for the GPU's results, host step rule, whole step), by active-set
+        class, with the class's block steps and mean active-set size."""
+        sec, cnt = self._L.tsbts_sched_timing(self.ctx.ctx)
+        out = {}
+        for c, name in enumerate(("k<=32", "k<=256", "k<=1024", "k>1024")):
+            n = int(cnt[c, 0])
+            if n == 0:
+                continue
+            us = sec[c] / n * 1e6
+            out[name] = {"block_steps": n, "mean_k": float(cnt[c, 1]) / n,
+                         "issue_us": float(us[0]), "wait_us": float(us[1]),
+                         "rule_us": float(us[2]), "step_us": float(us[3])}
+        return out
 
     def era_step(self) -> int:
         T0 = self.time

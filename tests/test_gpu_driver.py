@@ -296,3 +296,25 @@ def test_native_checkpoint_resume_bitwise(prec, era):
     assert e_second == [x for x in e_full if x[0] >= 0.25]
     full.close()
     second.close()
+
+
+def test_native_step_timing_accounts_for_every_block_step():
+    # tsbts_sched_timing: the class counts add up to the scheduler's block steps and
+    # interactions, and the phases of each class fit inside its whole-step time
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    cfg = config("plummer256")
+    r, v, m = cfg.ic()
+    sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=cfg.era, dt_max=cfg.dt_max,
+                      dt_min=cfg.dt_min)
+    for _ in range(2):
+        sim.era_step()
+    sec, cnt = sim._L.tsbts_sched_timing(sim.ctx.ctx)
+    st = sim.stats
+    assert int(cnt[:, 0].sum()) == st["block_steps"]
+    assert int(cnt[:, 1].sum()) * sim.n == st["interactions"]
+    assert (sec >= 0).all()
+    for c in range(4):
+        assert sec[c, :3].sum() <= sec[c, 3] * (1 + 1e-9) + 1e-6
+    t = sim.step_timing()
+    assert sum(x["block_steps"] for x in t.values()) == st["block_steps"]
+    sim.close()
