@@ -208,12 +208,16 @@ __host__ __device__ inline bool use_wave_reduce(int n_slices, int64_t n_targets)
 }
 
 // The small-set kernels' last workgroup reduces the partials (W values per slice) itself
-// when each of its threads then reads at most kFuseLoads of them; otherwise a reduction
-// kernel follows.
+// when the launch has at most kFuseSlices workgroups and each of its threads then reads
+// at most kFuseLoads partials; otherwise a reduction kernel follows.  Every workgroup of a
+// fused launch pays an agent-scope fence (an L2 write-back on this multi-XCD part): at 16
+// workgroups that costs less than a second launch, at 512 (N = 131072) it costs 20 us
+// more.
 constexpr int kFuseLoads = 32;
+constexpr int kFuseSlices = 64;
 __host__ __device__ inline bool fuse_small_reduce(int n_slices, int W) {
   const int parts = W <= kWG ? kWG / W : 1;
-  return W <= kWG && (n_slices + parts - 1) / parts <= kFuseLoads;
+  return W <= kWG && n_slices <= kFuseSlices && (n_slices + parts - 1) / parts <= kFuseLoads;
 }
 
 // Active sets up to this size use the j-parallel pair kernels (one source per lane).
