@@ -400,11 +400,12 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
  *     over the pairs as the force (tsbts_force_criterion).
  *   TSBTS_SCHED_PREDICT_ON_LOAD: 1 = for active sets of at most 32 particles (16 in
  *     float64) the predictor's work is done by the force kernel as it loads its sources,
- *     and on few particles (active set in groups of 8 times the 256-particle tiles at
- *     most 16, e.g. N <= 4096 and 8 targets) that kernel's last workgroup also takes the criterion of
- *     the corrected targets: one launch per such block step instead of three, the same
- *     results bit for bit (default); 0 = separate predictor and criterion launches.  Not
- *     combined with the option above.
+ *     and on few particles (groups of 8 targets times 256-particle tiles at most 8: N up
+ *     to 512 with 32 targets, 1024 with 16, 2048 with 8) that kernel's last workgroup
+ *     also takes the criterion of the corrected targets: one or two launches per such
+ *     block step instead of three or four, the same results bit for bit (default);
+ *     0 = separate predictor and criterion launches.  Not combined with the option
+ *     above.
  * Returns TSBTS_ESTATE before tsbts_sched_init, TSBTS_EINVAL for an unknown option or
  * value. */
 int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);
