@@ -17,6 +17,12 @@ eras keep the error in a random walk; dynamic eras perform like the best fixed e
     python -m paper_1205_2288_amd.experiments dynamic --n 100 --t-end 100 --seeds 10
     python -m paper_1205_2288_amd.experiments era --n 500 --eta 0.5 --workers 12 ...
 
+Long runs can span several sessions: with --state-dir DIR each run saves an era-end
+checkpoint of the scheduler (bit-exact continuation) and its energy series after every
+segment, and a later invocation with the same DIR continues each run from its checkpoint;
+with --deadline SECONDS every run stops after the first segment that ends that long after
+the study started and reports itself incomplete (a summary counts complete runs only).
+
 Each finished run prints one JSON line (progress and result); the last line is a summary.
 With --workers K > 1 the runs go to K child processes at a time (each its own GPU context;
 a run at N of a few hundred is bound by launch latency, not by the GPU's throughput, so
@@ -44,36 +50,72 @@ def _plummer(n: int, seed: int):
     return plummer(n, seed)
 
 
+def _state_path(state_dir: str, n, seed, eps, eta, passes, era, dt_max, every, precision):
+    key = (f"n{n}_seed{seed}_eps{eps:g}_eta{eta:g}_p{passes}_era"
+           f"{'dyn' if era is None else format(era, 'g')}_dtmax{dt_max:g}_every{every:g}_"
+           f"{precision}")
+    return os.path.join(state_dir, key + ".npz")
+
+
 def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
                      era: float | None, dt_max: float, t_end: float, every: float,
-                     precision: str = "fp64") -> dict:
-    """One integration; era=None selects the dynamic era (Algorithm 3)."""
+                     precision: str = "fp64", state_dir: str | None = None,
+                     deadline: float | None = None, segment: float = 25.0) -> dict:
+    """One integration; era=None selects the dynamic era (Algorithm 3).  The run goes in
+    segments of `segment` time units (at least `every`).  state_dir: keep (and continue
+    from) an era-end checkpoint and the energy series there after every segment;
+    deadline: a wall-clock time (time.time() seconds) after which the run stops at the end
+    of its current segment and reports complete = False."""
     from .driver import NativeTSBTS
     r, v, m = _plummer(n, seed)
     sim = NativeTSBTS(r, v, m, eps, eta=eta, passes=passes, era=era, dt_max=dt_max,
                       precision=precision)
+    path = None if state_dir is None else _state_path(state_dir, n, seed, eps, eta, passes,
+                                                      era, dt_max, every, precision)
+    series, wall_before, t_mark = [], 0.0, 0.0
+    if path is not None and os.path.exists(path):
+        with np.load(path) as z:  # arrays only (no pickles)
+            ck = {k: z[k] for k in z.files}
+        sim.restore(ck)
+        series = list(zip(ck["series_t"].tolist(), ck["series_e"].tolist()))
+        wall_before = float(ck["wall_s"])
+        t_mark = series[-1][0]
     t0 = time.perf_counter()
-    series = []
-    t_mark = 0.0
+    complete = True
     while t_mark < t_end:
-        # integrate in segments of at most 25 time units, reporting progress on stderr
-        t_mark = min(t_end, t_mark + max(every, 25.0))
+        # integrate segment by segment, reporting progress on stderr
+        t_mark = min(t_end, t_mark + max(every, segment))
         seg = sim.run(t_mark, energy_every=every)
         series.extend(seg if not series else seg[1:])
+        wall = wall_before + time.perf_counter() - t0
         print(f"n={n} seed={seed} passes={passes} era={era} t={t_mark:g} "
-              f"steps={sim.stats['block_steps']} wall={time.perf_counter() - t0:.1f}s",
+              f"steps={sim.stats['block_steps']} wall={wall:.1f}s",
               file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
+        if path is not None:
+            ck = sim.checkpoint()
+            ck["series_t"] = np.array([p[0] for p in series])
+            ck["series_e"] = np.array([p[1] for p in series])
+            ck["wall_s"] = np.array(wall)
+            tmp = path + ".tmp.npz"
+            np.savez(tmp, **ck)
+            os.replace(tmp, path)
+        if deadline is not None and t_mark < t_end and time.time() > deadline:
+            complete = False
+            break
+    wall = wall_before + time.perf_counter() - t0
     st = sim.stats
     sim.close()
     e0 = series[0][1]
     t = np.array([p[0] for p in series])
     err = np.array([abs(p[1] - e0) / abs(e0) for p in series])
     run_max = np.maximum.accumulate(err)
-    half = run_max[np.searchsorted(t, 0.5 * t_end)]
-    growth = float(run_max[-1] / half) if half > 0 else math.nan
+    growth = math.nan
+    if complete:
+        half = run_max[np.searchsorted(t, 0.5 * t_end)]
+        growth = float(run_max[-1] / half) if half > 0 else math.nan
     return {"n": n, "seed": seed, "passes": passes, "era": era if era else "dynamic",
             "eta": eta, "eps": eps, "dt_max": dt_max, "t_end": t_end,
+            "complete": complete, "t_reached": float(t[-1]),
             "max_err": float(err.max()), "final_err": float(err[-1]), "growth": growth,
             "block_steps": st["block_steps"], "eras": st["eras"], "wall_s": wall,
             "series_t": t.tolist(), "series_err": err.tolist()}
@@ -112,34 +154,44 @@ def run_many(specs: list, workers: int = 1, out=sys.stdout) -> list:
 
 def era_study(n=100, seeds=3, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
               eras=(1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4), passes=(3, 5), every=1.0,
-              seed0=1205, out=sys.stdout, workers=1):
+              seed0=1205, out=sys.stdout, workers=1, state_dir=None, deadline=None):
     """Fixed era sizes x pass counts x initial conditions (Section 3, fixed-era tests)."""
     specs = [dict(n=n, seed=seed0 + k, eps=eps, eta=eta, passes=p, era=era, dt_max=dt_max,
-                  t_end=t_end, every=every)
+                  t_end=t_end, every=every, state_dir=state_dir, deadline=deadline)
              for k in range(seeds) for p in passes for era in eras]
     rows = run_many(specs, workers, out)
     summary = {}
     for p in passes:
         for era in eras:
-            sel = [r for r in rows if r["passes"] == p and r["era"] == era]
+            sel = [r for r in rows if r["passes"] == p and r["era"] == era and r["complete"]]
             summary[f"passes={p} era={era:g}"] = {
-                "median_max_err": float(np.median([r["max_err"] for r in sel])),
-                "median_growth": float(np.median([r["growth"] for r in sel])),
-                "median_block_steps": float(np.median([r["block_steps"] for r in sel]))}
+                "complete_runs": len(sel),
+                "median_max_err": float(np.median([r["max_err"] for r in sel])) if sel else None,
+                "median_growth": float(np.median([r["growth"] for r in sel])) if sel else None,
+                "median_block_steps":
+                    float(np.median([r["block_steps"] for r in sel])) if sel else None}
     _emit(out, {"study": "era", "n": n, "t_end": t_end, "seeds": seeds, "summary": summary})
     return rows, summary
 
 
 def dynamic_era_study(n=100, seeds=10, t_end=100.0, eta=0.1, eps=0.01, dt_max=1.0 / 64,
-                      passes=3, every=1.0, seed0=2205, out=sys.stdout, workers=1):
+                      passes=3, every=1.0, seed0=2205, out=sys.stdout, workers=1,
+                      state_dir=None, deadline=None):
     """Fixed era (= dt_max) against the dynamic era (Section 4), same initial conditions."""
     specs = [dict(n=n, seed=seed0 + k, eps=eps, eta=eta, passes=passes, era=era,
-                  dt_max=dt_max, t_end=t_end, every=every)
+                  dt_max=dt_max, t_end=t_end, every=every, state_dir=state_dir,
+                  deadline=deadline)
              for k in range(seeds) for era in (dt_max, None)]
     res = run_many(specs, workers, out)
-    rows = [{"fixed": res[2 * k], "dynamic": res[2 * k + 1]} for k in range(seeds)]
+    rows = [{"fixed": res[2 * k], "dynamic": res[2 * k + 1]} for k in range(seeds)
+            if res[2 * k]["complete"] and res[2 * k + 1]["complete"]]
+    if not rows:
+        _emit(out, {"study": "dynamic", "n": n, "t_end": t_end, "seeds": seeds,
+                    "summary": {"complete_pairs": 0}})
+        return rows, {}
     better = sum(1 for p in rows if p["dynamic"]["final_err"] < p["fixed"]["final_err"])
     summary = {
+        "complete_pairs": len(rows),
         "dynamic_smaller_final_err_fraction": better / len(rows),
         "median_final_err_fixed": float(np.median([p["fixed"]["final_err"] for p in rows])),
         "median_final_err_dynamic": float(np.median([p["dynamic"]["final_err"] for p in rows])),
@@ -171,7 +223,18 @@ def main(argv=None):
                     help="fixed era sizes of the era study (default 1/64 ... 1/4)")
     ap.add_argument("--seed0", type=int, default=None, help="first sphere's seed")
     ap.add_argument("--every", type=float, default=1.0, help="energy sampling interval")
+    ap.add_argument("--state-dir", default=None,
+                    help="keep each run's era-end checkpoint and energy series here and "
+                         "continue runs found there")
+    ap.add_argument("--deadline", type=float, default=None,
+                    help="seconds after the start of the study at which every run stops at "
+                         "the end of its current 25-unit segment (reported as incomplete)")
     args = ap.parse_args(argv)
+    if args.state_dir is not None:
+        os.makedirs(args.state_dir, exist_ok=True)
+        args.state_dir = os.path.abspath(args.state_dir)
+    resume = {"state_dir": args.state_dir,
+              "deadline": None if args.deadline is None else time.time() + args.deadline}
     if args.study == "run":
         _emit(sys.stdout, energy_error_run(**json.loads(args.spec)))
         return
@@ -183,12 +246,12 @@ def main(argv=None):
             kw["seed0"] = args.seed0
         era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta, eps=args.eps,
                   passes=tuple(args.passes or (3, 5)), every=args.every,
-                  workers=args.workers, **kw)
+                  workers=args.workers, **kw, **resume)
     else:
         kw = {} if args.seed0 is None else {"seed0": args.seed0}
         dynamic_era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta,
                           eps=args.eps, passes=(args.passes or [3])[0], every=args.every,
-                          workers=args.workers, **kw)
+                          workers=args.workers, **kw, **resume)
 
 
 if __name__ == "__main__":

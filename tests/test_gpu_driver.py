@@ -252,6 +252,25 @@ def test_era_study_matches_oracle():
         assert row["max_err"] <= 2.0 * err.max() + 1e-14
 
 
+def test_experiment_run_resumes_across_sessions(tmp_path):
+    # a study run stopped at its deadline after its first segment and continued from its
+    # saved era-end checkpoint by a later call equals the uninterrupted run bit for bit
+    from paper_1205_2288_amd import experiments as ex
+    kw = dict(n=64, seed=1205, eps=0.01, eta=0.1, passes=3, era=1 / 16, dt_max=1 / 64,
+              t_end=2.0, every=0.25, segment=0.5)
+    full = ex.energy_error_run(**kw)
+    assert full["complete"] and full["t_reached"] == 2.0
+    part = ex.energy_error_run(**kw, state_dir=str(tmp_path), deadline=0.0)
+    assert not part["complete"] and part["t_reached"] == 0.5
+    assert part["series_err"] == full["series_err"][:len(part["series_err"])]
+    rest = ex.energy_error_run(**kw, state_dir=str(tmp_path))
+    assert rest["complete"]
+    assert rest["series_t"] == full["series_t"]
+    assert rest["series_err"] == full["series_err"]
+    assert rest["block_steps"] == full["block_steps"]
+    assert rest["growth"] == full["growth"]
+
+
 @pytest.mark.parametrize("prec,era", [("fp64", 1.0 / 8), ("mixed", None)])
 def test_native_checkpoint_resume_bitwise(prec, era):
     # an era-end checkpoint, saved through numpy's npz format and restored into a fresh
