@@ -69,25 +69,26 @@ FLOPS_ADJOINT_GATHER = 73.0  # fused all-active gather kernel: source 38 + targe
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (29648.6, 131072.0,
+    "k_timestep_scalar": (29640.1, 131072.0,
         ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
-        "d628e54bceb63451"),
-    "k_force_scalar": (19750.1, 65536.0,
+        "37dc13bbf498e9e8"),
+    "k_force_scalar": (20390.8, 65536.0,
         ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp",
          "predict.hpp", "hermite.hpp", "criterion.hpp"),
-        "cc0a904d6d5526fd"),
-    "k_timestep_sym": (200115.9, 132132.3,
+        "c3048647a9c1c95e"),
+    "k_timestep_sym": (200765.3, 132102.6,
         ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
-        "fd100a539c798f1c"),
-    "k_force_sym": (134251.6, 363352.4,
-        ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp"),
-        "14adffffae42d514"),
-    "k_bwd_sym": (237708.8, 396442.1,
+        "72b4c612ea78ece4"),
+    "k_force_sym": (134453.5, 363355.6,
+        ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp",
+         "correct.hpp"),
+        "aa0c8dec24dc7682"),
+    "k_bwd_sym": (237069.3, 396430.8,
         ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
-        "be52d90d0cd3c9f2"),
-    "k_energy_pairs": (18571.9, 256.0,
+        "bcee5d23026f181b"),
+    "k_energy_pairs": (18768.0, 256.0,
         ("energy.hip", "internal.hpp"),
-        "c5fae595e5b0e097"),
+        "9c10355a20f99983"),
 }
 
 

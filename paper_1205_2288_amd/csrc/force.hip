@@ -531,9 +531,47 @@ __global__ __launch_bounds__(kWG) void k_force_reduce_wave(ForceArgs A) {
   if (lane == 0) finish<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp);
 }
 
+// Same, a workgroup per 64 consecutive targets (one per lane) whose kRowsWaves waves each
+// add a contiguous range of the slices in order; the waves' sums are then added in wave
+// order (many targets and slices).
+template <class V, int NEWTON>
+__global__ __launch_bounds__(64 * kRowsWaves) void k_force_reduce_rows(ForceArgs A) {
+  __shared__ double sums[kRowsWaves][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = blockIdx.x * 64 + lane;
+  const int S = A.plan.n_slices;
+  const int L = (S + kRowsWaves - 1) / kRowsWaves;
+  const int s1 = min(S, (w + 1) * L);
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  if (q < A.n_act) {
+    const int64_t stride = 4 * static_cast<int64_t>(A.n_act);
+#pragma unroll 4
+    for (int s = w * L; s < s1; ++s) {
+      const double *in = A.part + s * stride;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] += in[c * A.n_act + q];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) sums[w][c][lane] = t[c];
+  __syncthreads();
+  if (w == 0 && q < A.n_act) {
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ww = 0; ww < kRowsWaves; ++ww)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) f[c] += sums[ww][c][lane];
+    finish<V, NEWTON>(A, q, A.idx[q], f[0], f[1], f[2], f[3]);
+  }
+}
+
+// The split-j reduction launch that suits the call (none when the j-range is not split).
 template <class V, int NEWTON>
 hipError_t launch_reduce(ForceArgs &A, hipStream_t st) {
-  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+  if (use_rows_reduce(A.plan.n_slices, A.n_act)) {
+    const int nb = (A.n_act + 63) / 64;
+    hipLaunchKernelGGL((k_force_reduce_rows<V, NEWTON>), dim3(nb), dim3(64 * kRowsWaves), 0, st,
+                       A);
+  } else if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {
@@ -569,14 +607,7 @@ hipError_t run(ForceArgs &A, hipStream_t st) {
     hipLaunchKernelGGL((k_force<V, NEWTON, 1, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   else
     hipLaunchKernelGGL((k_force<V, NEWTON, 0, IPL>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
-  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
-    const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
-    hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
-  } else if (A.plan.n_slices > 1) {
-    const int nb = (A.n_act + kWG - 1) / kWG;
-    hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
-  }
-  return hipGetLastError();
+  return launch_reduce<V, NEWTON>(A, st);
 }
 
 template <class V, int NEWTON>
@@ -596,15 +627,7 @@ hipError_t run_small(ForceArgs &A, hipStream_t st, const PredictArgs *pred = nul
   }
   else
     hipLaunchKernelGGL((k_force_small<V, NEWTON>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
-  if (!A.fuse_reduce) {
-    if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
-      const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
-      hipLaunchKernelGGL((k_force_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
-    } else {
-      const int nb = (A.n_act + kWG - 1) / kWG;
-      hipLaunchKernelGGL((k_force_reduce<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
-    }
-  }
+  if (!A.fuse_reduce) return launch_reduce<V, NEWTON>(A, st);
   return hipGetLastError();
 }
 

@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kWG) void k_fused(FusedArgs A) {
 }
 
 // Combine the slices in slice order (sums; max and min are exact) and finish: one thread
-// per target, or one wave per target with the lanes striding over many slices.  Always a
+// per target, one wave per target with the lanes striding over many slices, or (below)
+// rows of 64 targets, in the force reduction's order for the same call.  Always a
 // separate launch: the corrector it may apply rewrites velocity planes the pair loop reads.
 template <class V, int NEWTON>
 __global__ __launch_bounds__(kWG) void k_fused_reduce(FusedArgs A) {
@@ -154,6 +155,44 @@ __global__ __launch_bounds__(kWG) void k_fused_reduce_wave(FusedArgs A) {
   if (lane == 0) finish_all<V, NEWTON>(A, q, A.idx[q], sx, sy, sz, sp, qm, sm);
 }
 
+// Same, a workgroup per 64 consecutive targets whose kRowsWaves waves each combine a
+// contiguous range of the slices in order, then the waves in order: the association of
+// the force's k_force_reduce_rows, so the results stay those of the separate kernels.
+template <class V, int NEWTON>
+__global__ __launch_bounds__(64 * kRowsWaves) void k_fused_reduce_rows(FusedArgs A) {
+  __shared__ double sums[kRowsWaves][6][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = blockIdx.x * 64 + lane;
+  const int S = A.plan.n_slices;
+  const int L = (S + kRowsWaves - 1) / kRowsWaves;
+  const int s1 = min(S, (w + 1) * L);
+  double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, __builtin_inf()};
+  if (q < A.n_act) {
+    const int64_t stride = 6 * static_cast<int64_t>(A.n_act);
+#pragma unroll 4
+    for (int s = w * L; s < s1; ++s) {
+      const double *in = A.part + s * stride;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] += in[c * A.n_act + q];
+      t[4] = fmax(t[4], in[4 * A.n_act + q]);
+      t[5] = fmin(t[5], in[5 * A.n_act + q]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sums[w][c][lane] = t[c];
+  __syncthreads();
+  if (w == 0 && q < A.n_act) {
+    double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, __builtin_inf()};
+    for (int ww = 0; ww < kRowsWaves; ++ww) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) f[c] += sums[ww][c][lane];
+      f[4] = fmax(f[4], sums[ww][4][lane]);
+      f[5] = fmin(f[5], sums[ww][5][lane]);
+    }
+    finish_all<V, NEWTON>(A, q, A.idx[q], f[0], f[1], f[2], f[3], f[4], f[5]);
+  }
+}
+
 template <class V, int NEWTON, int CH>
 void launch_main(FusedArgs &A, hipStream_t st) {
   const dim3 grid(A.plan.nblk), block(kWG);
@@ -169,7 +208,11 @@ hipError_t run(FusedArgs &A, int chunk, hipStream_t st) {
     launch_main<V, NEWTON, kChunkSmall>(A, st);
   else
     launch_main<V, NEWTON, kTJ>(A, st);
-  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+  if (use_rows_reduce(A.plan.n_slices, A.n_act)) {
+    const int nb = (A.n_act + 63) / 64;
+    hipLaunchKernelGGL((k_fused_reduce_rows<V, NEWTON>), dim3(nb), dim3(64 * kRowsWaves), 0, st,
+                       A);
+  } else if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL((k_fused_reduce_wave<V, NEWTON>), dim3(nb), dim3(kWG), 0, st, A);
   } else {

@@ -206,6 +206,17 @@ constexpr int64_t kWaveReduceMaxTargets = 4096;
 __host__ __device__ inline bool use_wave_reduce(int n_slices, int64_t n_targets) {
   return n_slices >= kWaveReduceSlices && n_targets <= kWaveReduceMaxTargets;
 }
+// From kRowsReduceMinTargets targets on (force and criterion), many slices are combined
+// by a workgroup per 64 consecutive targets instead, its kRowsWaves waves each adding a
+// contiguous range of slices: rows of 64 consecutive partials are read coalesced (the
+// wave-per-target form touches a cache line per 8-byte partial).  Below that there are
+// too few such workgroups (at 256 targets 4, each wave walking 128 slices: 43 against
+// 34 us per call at N = 131072).
+constexpr int64_t kRowsReduceMinTargets = 2048;
+constexpr int kRowsWaves = 16;
+__host__ __device__ inline bool use_rows_reduce(int n_slices, int64_t n_targets) {
+  return n_slices >= kWaveReduceSlices && n_targets >= kRowsReduceMinTargets;
+}
 
 // The small-set kernels' last workgroup reduces the partials (W values per slice) itself
 // when the launch has at most kFuseSlices workgroups and each of its threads then reads

@@ -275,6 +275,36 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
   if (lane == 0) A.dtc[q] = finish_dt(A.eta, qm, sm);
 }
 
+// Same, a workgroup per 64 consecutive targets whose kRowsWaves waves each combine a
+// contiguous range of the slices (many targets and slices; max and min are exact).
+__global__ __launch_bounds__(64 * kRowsWaves) void k_timestep_reduce_rows(StepArgs A) {
+  __shared__ double sums[kRowsWaves][2][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = blockIdx.x * 64 + lane;
+  const int S = A.plan.n_slices;
+  const int L = (S + kRowsWaves - 1) / kRowsWaves;
+  const int s1 = min(S, (w + 1) * L);
+  double qm = 0.0, sm = __builtin_inf();
+  if (q < A.n_act) {
+#pragma unroll 4
+    for (int s = w * L; s < s1; ++s) {
+      const double *in = A.part + static_cast<int64_t>(s) * 2 * A.n_act;
+      qm = fmax(qm, in[q]);
+      sm = fmin(sm, in[A.n_act + q]);
+    }
+  }
+  sums[w][0][lane] = qm;
+  sums[w][1][lane] = sm;
+  __syncthreads();
+  if (w == 0 && q < A.n_act) {
+    for (int ww = 1; ww < kRowsWaves; ++ww) {
+      qm = fmax(qm, sums[ww][0][lane]);
+      sm = fmin(sm, sums[ww][1][lane]);
+    }
+    A.dtc[q] = finish_dt(A.eta, qm, sm);
+  }
+}
+
 template <class V>
 hipError_t run(StepArgs &A, hipStream_t st) {
   if (A.n_act <= kSmallAct) {
@@ -306,7 +336,10 @@ hipError_t run(StepArgs &A, hipStream_t st) {
     else
       hipLaunchKernelGGL((k_timestep<V, 1>), dim3(A.plan.nblk), dim3(kWG), 0, st, A);
   }
-  if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
+  if (use_rows_reduce(A.plan.n_slices, A.n_act)) {
+    const int nb = (A.n_act + 63) / 64;
+    hipLaunchKernelGGL(k_timestep_reduce_rows, dim3(nb), dim3(64 * kRowsWaves), 0, st, A);
+  } else if (use_wave_reduce(A.plan.n_slices, A.n_act)) {
     const int nb = (A.n_act + kWG / 64 - 1) / (kWG / 64);
     hipLaunchKernelGGL(k_timestep_reduce_wave, dim3(nb), dim3(kWG), 0, st, A);
   } else if (A.plan.n_slices > 1) {
