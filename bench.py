@@ -69,24 +69,24 @@ FLOPS_ADJOINT_GATHER = 73.0  # fused all-active gather kernel: source 38 + targe
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (29640.1, 131072.0,
+    "k_timestep_scalar": (29642.1, 131072.0,
         ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
-        "37dc13bbf498e9e8"),
-    "k_force_scalar": (20390.8, 65536.0,
+        "a6f59f3b43b730cd"),
+    "k_force_scalar": (20580.2, 65536.0,
         ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp",
          "predict.hpp", "hermite.hpp", "criterion.hpp"),
-        "c3048647a9c1c95e"),
-    "k_timestep_sym": (200765.3, 132102.6,
+        "ee1f2680ecdd54a2"),
+    "k_timestep_sym": (200621.8, 132102.8,
         ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
-        "72b4c612ea78ece4"),
-    "k_force_sym": (134453.5, 363355.6,
+        "ea7c2657d0d6eaf2"),
+    "k_force_sym": (134505.2, 363367.3,
         ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp",
          "correct.hpp"),
-        "aa0c8dec24dc7682"),
-    "k_bwd_sym": (237069.3, 396430.8,
+        "33f531ef07b75214"),
+    "k_bwd_sym": (237087.2, 396406.2,
         ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
-        "bcee5d23026f181b"),
-    "k_energy_pairs": (18768.0, 256.0,
+        "57d503efacb6528e"),
+    "k_energy_pairs": (18770.3, 256.0,
         ("energy.hip", "internal.hpp"),
         "9c10355a20f99983"),
 }

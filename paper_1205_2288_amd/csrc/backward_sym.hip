@@ -190,14 +190,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_sym_reduce(BwdSymArgs A) {
   int band, s0, s1;
   sym_row_slots(A.plan, A.npad, p, band, s0, s1);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
-  const double *rp = static_cast<const double *>(A.plan.row_part);
-  for (int s = s0; s < s1; ++s)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
-  const F *cp = static_cast<const F *>(A.plan.col_part);
-  for (int u = 0; u <= band; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
+  sym_sum_partials<4, 4>(static_cast<const double *>(A.plan.row_part) + p, A.plan.npad_rows,
+                         s0, s1, t);
+  sym_sum_partials<4, 4>(static_cast<const F *>(A.plan.col_part) + p, A.npad, 0, band + 1, t);
 #pragma unroll
   for (int v = 0; v < 3; ++v) A.gr[v * A.n + p] += t[v];
   A.gm[p] += t[3];

@@ -197,9 +197,12 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
 
 // Particle p (target q = inv[p]): the row partials of the items of its band that reach
 // its row group, in slot order, then the column partials of the bands 0 .. its own; then
-// acc, pot and the corrector.
-template <class F>
+// acc, pot and the corrector (sym_sum_partials: the kernel is bound by reading the
+// partials); without the potential its values are neither read nor (for the columns)
+// written.
+template <class F, int POT>
 __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
+  constexpr int NV = POT ? 4 : 3;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
   const int q = A.plan.inv[p];
@@ -207,19 +210,14 @@ __global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
   int band, s0, s1;
   sym_row_slots(A.plan, A.npad, p, band, s0, s1);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
-  const double *rp = static_cast<const double *>(A.plan.row_part);
-  for (int s = s0; s < s1; ++s)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] += rp[(4 * s + v) * A.plan.npad_rows + p];
-  const F *cp = static_cast<const F *>(A.plan.col_part);
-  const int nv = A.pot ? 4 : 3;  // without the potential its column plane is not written
-  for (int u = 0; u <= band; ++u)
-    for (int v = 0; v < nv; ++v) t[v] += static_cast<double>(cp[(4 * u + v) * A.npad + p]);
+  sym_sum_partials<4, NV>(static_cast<const double *>(A.plan.row_part) + p, A.plan.npad_rows,
+                          s0, s1, t);
+  sym_sum_partials<4, NV>(static_cast<const F *>(A.plan.col_part) + p, A.npad, 0, band + 1, t);
   const double an[3] = {t[0], t[1], t[2]};
   A.acc[q] = an[0];
   A.acc[A.n_act + q] = an[1];
   A.acc[2 * A.n_act + q] = an[2];
-  if (A.pot) A.pot[q] = -t[3];
+  if (POT) A.pot[q] = -t[3];
   if (A.correct) correct_one(A.corr, q, p, an);
 }
 
@@ -238,8 +236,11 @@ hipError_t run(ForceSymArgs &A, hipStream_t st) {
   // its error check clears the launch error state: keep what it found
   const hipError_t e = launch_sym_inverse(A.plan, A.idx, A.n_act, A.n, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_force_sym_reduce<F>,
-                     dim3(static_cast<unsigned>((A.n + kWG - 1) / kWG)), dim3(kWG), 0, st, A);
+  const dim3 grid(static_cast<unsigned>((A.n + kWG - 1) / kWG));
+  if (A.pot)
+    hipLaunchKernelGGL((k_force_sym_reduce<F, 1>), grid, dim3(kWG), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_force_sym_reduce<F, 0>), grid, dim3(kWG), 0, st, A);
   return hipGetLastError();
 }
 

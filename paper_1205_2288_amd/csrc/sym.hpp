@@ -149,6 +149,33 @@ __device__ __forceinline__ void sym_col_sums(const T *L, int lane, T out[NV]) {
   }
 }
 
+// Add, for one particle, its partials of NV values at plane stride `stride` (value v of
+// entry e at x[(NS * e + v) * stride]) for entries e in [e0, e1) into t, in entry order.
+// The loads of kSymBatch entries are issued before their additions (the reductions are
+// bound by reading the partials; one load in flight at a time would leave most of the
+// memory system idle).
+constexpr int kSymBatch = 8;
+template <int NS, int NV, class T>
+__device__ __forceinline__ void sym_sum_partials(const T *x, int64_t stride, int e0, int e1,
+                                                 double *t) {
+  const T *q = x + static_cast<int64_t>(NS) * e0 * stride;
+  int e = e0;
+  for (; e + kSymBatch <= e1; e += kSymBatch, q += NS * kSymBatch * stride) {
+    T y[kSymBatch][NV];
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) y[b][v] = q[(NS * b + v) * stride];
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v] += static_cast<double>(y[b][v]);
+  }
+  for (; e < e1; ++e, q += NS * stride)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] += static_cast<double>(q[v * stride]);
+}
+
 // Whether the symmetric criterion serves the call (as sym_enabled).
 bool criterion_sym_applies(const tsbts_ctx *c, int64_t n_act);
 // Whether the symmetric kernels serve a call with n_act targets (all particles).

@@ -169,15 +169,46 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
   int band, s0, s1;
   sym_row_slots(A.plan, A.npad, p, band, s0, s1);
   double qm = 0.0, sm = __builtin_inf();
-  const F *rp = static_cast<const F *>(A.plan.row_part);
-  for (int s = s0; s < s1; ++s) {
-    qm = fmax(qm, static_cast<double>(rp[(2 * s) * A.plan.npad_rows + p]));
-    sm = fmin(sm, static_cast<double>(rp[(2 * s + 1) * A.plan.npad_rows + p]));
+  // the loads of kSymBatch slots (bands) are issued before they are combined (the kernel
+  // is bound by reading the partials)
+  const int64_t rs = A.plan.npad_rows;
+  const F *r = static_cast<const F *>(A.plan.row_part) + 2 * s0 * rs + p;
+  int s = s0;
+  for (; s + kSymBatch <= s1; s += kSymBatch, r += 2 * kSymBatch * rs) {
+    F y[kSymBatch][2];
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b) {
+      y[b][0] = r[(2 * b) * rs];
+      y[b][1] = r[(2 * b + 1) * rs];
+    }
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b) {
+      qm = fmax(qm, static_cast<double>(y[b][0]));
+      sm = fmin(sm, static_cast<double>(y[b][1]));
+    }
   }
-  const F *cp = static_cast<const F *>(A.plan.col_part);
-  for (int t = 0; t <= band; ++t) {
-    qm = fmax(qm, static_cast<double>(cp[(2 * t) * A.npad + p]));
-    sm = fmin(sm, -static_cast<double>(cp[(2 * t + 1) * A.npad + p]));  // stored negated
+  for (; s < s1; ++s, r += 2 * rs) {
+    qm = fmax(qm, static_cast<double>(r[0]));
+    sm = fmin(sm, static_cast<double>(r[rs]));
+  }
+  const F *c = static_cast<const F *>(A.plan.col_part) + p;
+  int u = 0;
+  for (; u + kSymBatch <= band + 1; u += kSymBatch, c += 2 * kSymBatch * A.npad) {
+    F y[kSymBatch][2];
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b) {
+      y[b][0] = c[(2 * b) * A.npad];
+      y[b][1] = c[(2 * b + 1) * A.npad];
+    }
+#pragma unroll
+    for (int b = 0; b < kSymBatch; ++b) {
+      qm = fmax(qm, static_cast<double>(y[b][0]));
+      sm = fmin(sm, -static_cast<double>(y[b][1]));  // stored negated
+    }
+  }
+  for (; u <= band; ++u, c += 2 * A.npad) {
+    qm = fmax(qm, static_cast<double>(c[0]));
+    sm = fmin(sm, -static_cast<double>(c[A.npad]));
   }
   A.dtc[q] = finish_dt(A.eta, qm, sm);
 }
