@@ -199,9 +199,12 @@ __global__ __launch_bounds__(kWG) void k_force_sym(ForceSymArgs A0,
 // its row group, in slot order, then the column partials of the bands 0 .. its own; then
 // acc, pot and the corrector (sym_sum_partials: the kernel is bound by reading the
 // partials); without the potential its values are neither read nor (for the columns)
-// written.
+// written.  At most 4 waves per SIMD: a grid of one thread per particle has few waves
+// (2 per SIMD at 2^17 particles), and under a higher occupancy target the compiler gave
+// each float64 partial load the registers of its address, one load in flight at a time.
 template <class F, int POT>
-__global__ __launch_bounds__(kWG) void k_force_sym_reduce(ForceSymArgs A) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void
+k_force_sym_reduce(ForceSymArgs A) {
   constexpr int NV = POT ? 4 : 3;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (p >= A.n) return;
