@@ -75,6 +75,7 @@ int tsbts_destroy(tsbts_ctx *ctx);
 #define TSBTS_TUNE_CHUNK 3
 #define TSBTS_TUNE_SYMMETRIC 4
 #define TSBTS_TUNE_CHECK_INDICES 5
+#define TSBTS_TUNE_SPLIT 6
 
 /* Launch-shape tuning of the pair kernels (force, criterion, adjoint); host-side only.
  *   TSBTS_TUNE_BLOCKS: workgroups a split-j launch aims for (64 .. 65536; default 8192)
@@ -93,6 +94,17 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      minima) is then bit-identical; sums are combined in another fixed
  *                      order.  The first such call on a context allocates its work list
  *                      and partial buffers.
+ *   TSBTS_TUNE_SPLIT:  when a proper subset of at least 8192 particles is active
+ *                      (tsbts_force, tsbts_timestep and the native scheduler's block
+ *                      steps, without TSBTS_FLAG_NEWTON and with the automatic kernel
+ *                      form and chunk), evaluate the pairs among the targets once for both
+ *                      (the symmetric kernels on a compact copy of the targets) and their
+ *                      pairs with the other particles by the gather kernels (a compact
+ *                      copy of those as the sources); the criterion is then bit-identical,
+ *                      force sums are combined in another fixed order (0 = never, 1 = from
+ *                      8192 targets, 2 = automatic: from 16384 targets; default 2).  The
+ *                      first such call on a context allocates the copies (about 270 bytes
+ *                      per particle) and the symmetric partial buffers for its size.
  *   TSBTS_TUNE_CHECK_INDICES: 1 = every call that takes active_idx first checks on the
  *                      device that each index lies in [0, n) and occurs once, synchronises
  *                      the stream and returns TSBTS_EINVAL, with nothing else launched, if
@@ -100,7 +112,8 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      per call; enabling it allocates n counters); 0 = indices trusted
  *                      (default; an index outside [0, n) is then undefined behaviour, and
  *                      a repeated index leaves undefined output rows when every particle
- *                      is a target and the symmetric kernels serve the call).
+ *                      is a target and the symmetric kernels serve the call, or when a
+ *                      split call does).
  * Results do not depend on these except through the order of float64 tile sums.
  * Invalid values return TSBTS_EINVAL and leave the setting unchanged. */
 int tsbts_tune(tsbts_ctx *ctx, int param, int value);

@@ -169,6 +169,7 @@ TSBTS_TUNE_IPL = 2
 TSBTS_TUNE_CHUNK = 3
 TSBTS_TUNE_SYMMETRIC = 4
 TSBTS_TUNE_CHECK_INDICES = 5
+TSBTS_TUNE_SPLIT = 6
 TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR = 1
 TSBTS_SCHED_PREDICT_ON_LOAD = 2
 

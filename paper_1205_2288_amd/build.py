@@ -14,7 +14,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "predict.hip", "force.hip", "timestep.hip", "correct.hip",
            "energy.hip", "backward.hip", "scheduler.hip", "fused.hip",
            "hist_adjoint.hip", "sym.hip", "timestep_sym.hip",
-           "force_sym.hip", "backward_sym.hip", "noalloc.hip"]
+           "force_sym.hip", "backward_sym.hip", "noalloc.hip", "split.hip"]
 
 ARCH = os.environ.get("TSBTS_OFFLOAD_ARCH", "gfx950")
 

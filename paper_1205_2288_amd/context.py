@@ -64,16 +64,21 @@ class Context:
         L.tsbts_bind_state(self.ctx, n, self.r, self.v, self.a, self.m, self.t_last, self.dt)
         return self
 
-    def tune(self, blocks=None, ipl=None, chunk=None, symmetric=None, check_indices=None):
+    def tune(self, blocks=None, ipl=None, chunk=None, symmetric=None, check_indices=None,
+             split=None):
         """Launch-shape tuning (see tsbts_tune): workgroups per split launch, kernel form
         (0 = scalar-load kernels, 1/2/4 = LDS kernels with that many targets per lane), j
         per split unit of the scalar-load kernels (0 = automatic, 64, 256), symmetric
-        all-targets kernels (0 = never, 1 = always, 2 = automatic); check_indices = 1:
-        every call checks its device active set against [0, n) first (debugging aid)."""
+        all-targets kernels (0 = never, 1 = always, 2 = automatic), split calls of large
+        partial active sets (0 = never, 1 = from 8192 targets, 2 = automatic);
+        check_indices = 1: every call checks its device active set against [0, n) first
+        (debugging aid)."""
         if check_indices is not None:
             L.tsbts_tune(self.ctx, L.TSBTS_TUNE_CHECK_INDICES, int(check_indices))
         if symmetric is not None:
             L.tsbts_tune(self.ctx, L.TSBTS_TUNE_SYMMETRIC, symmetric)
+        if split is not None:
+            L.tsbts_tune(self.ctx, L.TSBTS_TUNE_SPLIT, split)
         if blocks is not None:
             L.tsbts_tune(self.ctx, L.TSBTS_TUNE_BLOCKS, blocks)
         if ipl is not None:

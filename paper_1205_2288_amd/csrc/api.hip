@@ -110,8 +110,11 @@ int check_bound(tsbts_ctx *c) {
   return TSBTS_OK;
 }
 
-// Work list and partials of the symmetric all-targets force, when it serves the call.
+// Work list and partials of the symmetric all-targets force, when it serves the call,
+// and the buffers of a split call.
 int prepare_force_sym(tsbts_ctx *c, int32_t n_act) {
+  if (int s = split_prepare(c, n_act))
+    return fail(c, s, "split call: buffers not allocated");
   if (!force_sym_applies(c, n_act)) return TSBTS_OK;
   if (int s = sym_prepare(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4))
     return fail(c, s, "symmetric force: work list or partials not allocated");
@@ -284,6 +287,7 @@ int tsbts_destroy(tsbts_ctx *c) {
   dev_free(c->gord);
   if (c->sym_items) (void)hipFree(c->sym_items);
   if (c->sym_part) (void)hipFree(c->sym_part);
+  if (c->split_buf) (void)hipFree(c->split_buf);
   if (c->idx_flag_h) (void)hipHostFree(c->idx_flag_h);
   dev_free(c->idx_seen);
   dev_free(c->done);
@@ -321,6 +325,10 @@ int tsbts_tune(tsbts_ctx *c, int param, int value) {
     case TSBTS_TUNE_SYMMETRIC:
       if (value < 0 || value > 2) return fail(c, TSBTS_EINVAL, "symmetric must be 0, 1 or 2");
       c->tune_sym = value;
+      return TSBTS_OK;
+    case TSBTS_TUNE_SPLIT:
+      if (value < 0 || value > 2) return fail(c, TSBTS_EINVAL, "split must be 0, 1 or 2");
+      c->tune_split = value;
       return TSBTS_OK;
     case TSBTS_TUNE_CHECK_INDICES:
       if (value != 0 && value != 1) return fail(c, TSBTS_EINVAL, "check must be 0 or 1");
@@ -526,6 +534,7 @@ int tsbts_timestep(tsbts_ctx *c, const int32_t *idx, int32_t n_act, double eta, 
     if (int s = sym_prepare(c, 2, vb, vb))
       return fail(c, s, "symmetric criterion: work list or partials not allocated");
   }
+  if (int s = split_prepare(c, n_act)) return fail(c, s, "split call: buffers not allocated");
   hipError_t e = launch_timestep(c, idx, n_act, eta, dtc, stream);
   if (e != hipSuccess) return hip_fail(c, e, "tsbts_timestep launch");
   return TSBTS_OK;

@@ -256,12 +256,18 @@ hipError_t launch_history_begin(tsbts_ctx *c, hipStream_t st) {
   return hipGetLastError();
 }
 
+static_assert(kScanTile == kScanCounts, "tile sums of launch_exclusive_scan");
+
+hipError_t launch_exclusive_scan(const int32_t *cnt, int64_t n, int32_t *tsum, int32_t *off,
+                                 int32_t *cur, hipStream_t st) {
+  const int ntiles = static_cast<int>((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_sums, dim3(ntiles), dim3(kScanWG), 0, st, cnt, n, tsum);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanWG), 0, st, cnt, n, tsum, off, cur);
+  return hipGetLastError();
+}
+
 hipError_t launch_history_end(tsbts_ctx *c, hipStream_t st) {
-  const int ntiles = static_cast<int>((c->n + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_sums, dim3(ntiles), dim3(kScanWG), 0, st, c->h.cnt, c->n,
-                     c->h.tsum);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanWG), 0, st, c->h.cnt, c->n,
-                     c->h.tsum, c->h.off, c->h.cur);
+  (void)launch_exclusive_scan(c->h.cnt, c->n, c->h.tsum, c->h.off, c->h.cur, st);
   ScatterArgs p;
   p.count = c->h.count;
   p.cap = c->h.cap;

@@ -65,6 +65,15 @@ struct ForceArgs {
   uint32_t *done;   // finished-workgroup count of the small-set kernels
   int fuse_reduce;  // the small-set kernel's last workgroup reduces the partials
   CritArgs crit;    // ... and then takes the criterion (k_force_small_pred)
+  // Sources of k_force_scalar (null: the predicted arrays above): planes of stride snpad.
+  // self = 0 when they exclude the targets (no self pair to skip).
+  const float *s32 = nullptr;
+  const double *s64 = nullptr;
+  int64_t snpad = 0;
+  int self = 1;
+  // null, or [4][n_act]: acceleration (x, y, z) and potential from the other part of a
+  // split call, added to each target's sums where it is finished
+  const double *add = nullptr;
 };
 
 // Scale and store target q's sums; with the corrector, correct it (its inputs `ts` when
@@ -74,11 +83,17 @@ __device__ __forceinline__ void finish(const ForceArgs &A, int q, int64_t g, dou
                                        double sy, double sz, double sp,
                                        const TargetState *ts = nullptr) {
   const double k = Scale<V, NEWTON>::kAcc;
-  const double an[3] = {k * sx, k * sy, k * sz};
+  double an[3] = {k * sx, k * sy, k * sz};
+  double pn = -sp;
+  if (A.add) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) an[c] += A.add[c * A.n_act + q];
+    pn += A.add[3 * A.n_act + q];
+  }
   A.acc[q] = an[0];
   A.acc[A.n_act + q] = an[1];
   A.acc[2 * A.n_act + q] = an[2];
-  if (A.pot) A.pot[q] = -sp;
+  if (A.pot) A.pot[q] = pn;
   if (A.correct) correct_target(A.corr, q, g, an, ts ? *ts : load_target(A.corr, g));
 }
 
@@ -175,7 +190,7 @@ __device__ __forceinline__ void scalar_tile(const ForceArgs &A, const typename V
 #pragma unroll 8
   for (int jj = 0; jj < CH; ++jj) {
     const typename V::J J =
-        V::load_j(A.p32, A.p64, A.npad, jbase + jj, Scale<V, NEWTON>::kMass);
+        V::load_j(A.s32, A.s64, A.snpad, jbase + jj, Scale<V, NEWTON>::kMass);
     pair_acc<V, NEWTON, MASK, POT>(I, J, eps2, MASK && (jbase + jj == g), fx, fy, fz, fp);
   }
 }
@@ -193,14 +208,15 @@ __global__ __launch_bounds__(kWG) void k_force_scalar(ForceArgs A) {
   const int q = itile * kWG + static_cast<int>(threadIdx.x);
   const int g = A.idx[min(q, A.n_act - 1)];
   const typename V::I I = V::load_i(A.p32, A.p64, A.npad, g);
+  const int gs = A.self ? g : -1;  // the target's index among the sources
   double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
   for (int jt = jt0; jt < jt1; ++jt) {
     const int64_t jbase = static_cast<int64_t>(jt) * CH;
     F fx = F(0), fy = F(0), fz = F(0), fp = F(0);
-    if (__ballot(g >= jbase && g < jbase + CH) != 0)
-      scalar_tile<V, NEWTON, 1, POT, CH>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+    if (__ballot(gs >= jbase && gs < jbase + CH) != 0)
+      scalar_tile<V, NEWTON, 1, POT, CH>(A, I, gs, jbase, eps2, fx, fy, fz, fp);
     else
-      scalar_tile<V, NEWTON, 0, POT, CH>(A, I, g, jbase, eps2, fx, fy, fz, fp);
+      scalar_tile<V, NEWTON, 0, POT, CH>(A, I, gs, jbase, eps2, fx, fy, fz, fp);
     sx += static_cast<double>(fx);
     sy += static_cast<double>(fy);
     sz += static_cast<double>(fz);
@@ -583,7 +599,13 @@ hipError_t launch_reduce(ForceArgs &A, hipStream_t st) {
 
 template <class V, int NEWTON>
 hipError_t run_scalar(ForceArgs &A, hipStream_t st) {
-  A.n_jtiles = static_cast<int>(A.npad / A.chunk);
+  if (!A.s64) {
+    A.s32 = A.p32;
+    A.s64 = A.p64;
+    A.snpad = A.npad;
+    A.self = 1;
+  }
+  A.n_jtiles = static_cast<int>(A.snpad / A.chunk);
   A.plan = plan_split(A.n_act, 1, A.n_jtiles, A.blocks);
   const dim3 grid(A.plan.nblk), block(kWG);
   if (A.chunk == kChunkSmall) {
@@ -682,7 +704,7 @@ int64_t partial_elems_needed(const tsbts_ctx *c, int n_act) {
 
 hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                                double *pot, double *part, int blocks, hipStream_t st,
-                               const CorrectArgs *corr) {
+                               const CorrectArgs *corr, const GatherSrc *src) {
   ForceArgs A;
   A.crit.on = 0;
   A.correct = corr ? 1 : 0;
@@ -704,6 +726,18 @@ hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, doub
   A.chunk = scalar_chunk(c, n_act, 1);
   A.done = c->done;
   A.fuse_reduce = 0;
+  if (src) {
+    // the scalar-load kernel over the given sources (more targets than the small-set
+    // kernels take: split calls only)
+    if (n_act <= small_act_limit(c)) return hipErrorInvalidValue;
+    A.s32 = src->p32;
+    A.s64 = src->p64;
+    A.snpad = src->npad;
+    A.self = 0;
+    A.add = src->add;
+    A.scalar_j = 1;
+    A.chunk = scalar_chunk(c, n_act, 1);
+  }
   if (c->precision == TSBTS_FP64) return pick_ipl<Fp64, 0>(A, st);
   const bool sep64 = (c->flags & TSBTS_FLAG_HILO_SEPARATION) == 0;
   const bool newton = (c->flags & TSBTS_FLAG_NEWTON) != 0;
@@ -713,6 +747,10 @@ hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, doub
 
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr) {
+  if (split_applies(c, n_act)) {
+    const hipError_t e = launch_force_split(c, idx, n_act, acc, pot, st, corr);
+    if (e != hipErrorNotReady) return e;
+  }
   if (force_sym_applies(c, n_act)) {
     SymPlan plan;
     if (sym_plan(c, 4, 8, c->precision == TSBTS_FP64 ? 8 : 4, &plan))

@@ -255,12 +255,12 @@ bool force_sym_applies(const tsbts_ctx *c, int64_t n_act) {
 
 hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
                             double *acc, double *pot, hipStream_t st,
-                            const CorrectArgs *corr) {
+                            const CorrectArgs *corr, const SymSet *set) {
   ForceSymArgs A;
-  A.n = c->n;
-  A.npad = c->npad;
-  A.p32 = c->p32;
-  A.p64 = c->p64;
+  A.n = set ? set->n : c->n;
+  A.npad = set ? set->npad : c->npad;
+  A.p32 = set ? set->p32 : c->p32;
+  A.p64 = set ? set->p64 : c->p64;
   A.eps2 = static_cast<float>(c->eps * c->eps);
   A.eps2_64 = c->eps * c->eps;
   A.plan = plan;

@@ -87,6 +87,12 @@ struct tsbts_ctx {
   int sym_chunk = 0;
   void *sym_part = nullptr;
   int64_t sym_part_bytes = 0;
+  // split calls of large partial active sets (split.hip): one allocation for the compact
+  // copies of the targets and of the other particles (split_cap particles each), the
+  // marks and scan of the other particles, the symmetric part's results and work items
+  void *split_buf = nullptr;
+  int64_t split_cap = 0;
+  int tune_split = 2;  // 0 off, 1 from kSplitMinAct targets, 2 automatic
   char err[512] = {0};
 };
 
@@ -358,11 +364,26 @@ int predict_pending(tsbts_ctx *c, double t_block, int use_history, const Pending
 // With corr, every target's corrector (correct_one) runs where its force is final.
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr = nullptr);
+// Sources of a gather launch other than the context's predicted arrays (the second part
+// of a split call): n particles that exclude every target (no self pair), padded to npad,
+// planes laid out as the predicted arrays with stride npad; and the first part's results
+// for each target, combined with the gather's where the target is finished: for the force
+// [4][n_act] acceleration (x, y, z) and potential to add, for the criterion [2][n_act] the
+// maximum of q and the minimum of s*w.
+struct GatherSrc {
+  const float *p32;   // [12][npad] or null (float64 mode)
+  const double *p64;  // [5][npad]
+  const double *v64;  // [3][npad]
+  int64_t n, npad;
+  const double *add;
+};
 // The gather force kernels (never the symmetric ones) with split-j partials in `part`
-// and a split aiming for `blocks` workgroups.
+// and a split aiming for `blocks` workgroups; with `src`, its sources (always the
+// scalar-load kernel).
 hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                                double *pot, double *part, int blocks, hipStream_t st,
-                               const CorrectArgs *corr = nullptr);
+                               const CorrectArgs *corr = nullptr,
+                               const GatherSrc *src = nullptr);
 // float64 partials of that launch (0 when the j-range is not split).
 int64_t force_partial_elems(const tsbts_ctx *c, int n_act, int blocks);
 // Fixed partial-sum array of tsbts_force_noalloc: find its address on `device` (once per
@@ -372,6 +393,26 @@ hipError_t noalloc_setup(int device);
 double *noalloc_partials(int device);
 hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
                            double *dtc, hipStream_t st);
+// The gather criterion kernels with the sources `src` (the scalar-load kernel).
+hipError_t launch_timestep_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                                  double *dtc, hipStream_t st, const GatherSrc *src);
+// Split calls (split.hip): a large partial active set whose pairs among the targets are
+// evaluated once for both (symmetric kernels on a compact copy of the targets) and whose
+// pairs with the other particles by the gather kernels (a compact copy of those as
+// sources).  split_applies: whether it serves a call of n_act targets; split_prepare
+// allocates its buffers (host set-up; returns a status); the launches return
+// hipErrorNotReady, with nothing launched, when the buffers are not there.
+bool split_applies(const tsbts_ctx *c, int64_t n_act);
+int split_prepare(tsbts_ctx *c, int64_t n_act);
+hipError_t launch_force_split(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
+                              double *pot, hipStream_t st, const CorrectArgs *corr);
+hipError_t launch_timestep_split(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                                 double *dtc, hipStream_t st);
+// Exclusive scan of cnt[0 .. n) into off[0 .. n] (off[n]: the total) with tile sums in
+// tsum (one per 8192 counts); cur receives a copy of off[0 .. n) (may equal off).
+hipError_t launch_exclusive_scan(const int32_t *cnt, int64_t n, int32_t *tsum, int32_t *off,
+                                 int32_t *cur, hipStream_t st);
+constexpr int64_t kScanCounts = 8192;  // counts per tile sum of launch_exclusive_scan
 hipError_t launch_backward(tsbts_ctx *c, const int32_t *idx, int n_act, const double *ga,
                            const double *gp, double *gr, double *gm, hipStream_t st);
 hipError_t launch_energy(tsbts_ctx *c, const double *r, const double *v, const double *m,
@@ -407,15 +448,20 @@ hipError_t launch_force_predicted(tsbts_ctx *c, const int32_t *idx, int n_act, d
 // most kCritFuseTiles).
 constexpr int kCritFuseTiles = 8;
 bool small_criterion_fused(const tsbts_ctx *c, int n_act);
-// Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.
+// Symmetric all-targets criterion (timestep_sym.hip); plan from sym_plan.  With `set`, the
+// kernels run on that particle set instead of the context's predicted arrays; with `raw`,
+// each target's maximum and minimum go there unfinished ([2][n_act]) instead of to dtc.
 struct SymPlan;
+struct SymSet;
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,
-                               int n_act, double eta, double *dtc, hipStream_t st);
-// Symmetric all-targets force (force_sym.hip): whether it serves the call, and its launch.
+                               int n_act, double eta, double *dtc, hipStream_t st,
+                               const SymSet *set = nullptr, double *raw = nullptr);
+// Symmetric all-targets force (force_sym.hip): whether it serves the call, and its launch
+// (on `set` instead of the context's predicted arrays when given).
 bool force_sym_applies(const tsbts_ctx *c, int64_t n_act);
 hipError_t launch_force_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx, int n_act,
                             double *acc, double *pot, hipStream_t st,
-                            const CorrectArgs *corr);
+                            const CorrectArgs *corr, const SymSet *set = nullptr);
 // Symmetric all-targets force adjoint (backward_sym.hip), after the seeds are ordered.
 bool bwd_sym_applies(const tsbts_ctx *c, int64_t n_act);
 hipError_t launch_bwd_sym(tsbts_ctx *c, const SymPlan &plan, double *gr, double *gm,

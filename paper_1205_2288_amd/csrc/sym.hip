@@ -112,32 +112,39 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
     c->sym_items_npad = npad;
     c->sym_chunk = sh.chunk;
   }
-  const int64_t bytes = sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes);
-  if (bytes > c->sym_part_bytes) {
-    (void)hipDeviceSynchronize();
-    if (c->sym_part) (void)hipFree(c->sym_part);
+  return sym_reserve(c, sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes));
+}
+
+int sym_reserve(tsbts_ctx *c, int64_t bytes) {
+  if (bytes <= c->sym_part_bytes) return TSBTS_OK;
+  // earlier launches may still use the old buffer
+  (void)hipDeviceSynchronize();
+  if (c->sym_part) (void)hipFree(c->sym_part);
+  c->sym_part = nullptr;
+  c->sym_part_bytes = 0;
+  if (hipMalloc(&c->sym_part, bytes) != hipSuccess) {
+    (void)hipGetLastError();
     c->sym_part = nullptr;
-    c->sym_part_bytes = 0;
-    if (hipMalloc(&c->sym_part, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      c->sym_part = nullptr;
-      return TSBTS_ENOMEM;
-    }
-    c->sym_part_bytes = bytes;
+    return TSBTS_ENOMEM;
   }
+  c->sym_part_bytes = bytes;
   return TSBTS_OK;
 }
 
-bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *p) {
-  const int64_t npad = c->npad;
-  if (!c->sym_items || c->sym_items_npad != npad) return false;
+int64_t sym_set_bytes(int64_t npad, int nv, int row_bytes, int col_bytes) {
+  return sym_buffer_bytes(sym_shape(npad), npad, nv, row_bytes, col_bytes);
+}
+
+namespace {
+
+// The plan's shape and buffers for npad particles (items set by the caller).
+bool plan_layout(const tsbts_ctx *c, int64_t npad, int nv, int row_bytes, int col_bytes,
+                 SymPlan *p) {
   const SymShape sh = sym_shape(npad);
-  if (sh.chunk != c->sym_chunk) return false;
   const int64_t npad_rows = static_cast<int64_t>(sh.n_groups) * kSymGroupRows;
   const int64_t rows = static_cast<int64_t>(sh.max_slots) * npad_rows * nv * row_bytes;
-  if (sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes) > c->sym_part_bytes) return false;
-  p->items = static_cast<const int4 *>(c->sym_items);
-  p->n_items = c->sym_items_n;
+  if (!c->sym_part || sym_buffer_bytes(sh, npad, nv, row_bytes, col_bytes) > c->sym_part_bytes)
+    return false;
   p->n_groups = sh.n_groups;
   p->band_groups = sh.band_groups;
   p->n_bands = sh.n_bands;
@@ -151,6 +158,56 @@ bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan 
   p->inv = reinterpret_cast<int32_t *>(end - npad * static_cast<int64_t>(sizeof(int32_t)));
   p->aux = reinterpret_cast<float *>(end - npad * static_cast<int64_t>(sizeof(int32_t) +
                                                                       4 * sizeof(float)));
+  return true;
+}
+
+// Work item t of npad particles: the same list, in the same order, as sym_prepare builds
+// on the host (bands in order, each band's column chunks in order).
+__global__ __launch_bounds__(kWG) void k_sym_items(int4 *items, int n_items, int64_t npad,
+                                                   int band_groups, int chunk) {
+  const int t = blockIdx.x * kWG + threadIdx.x;
+  if (t >= n_items) return;
+  int b = 0, base = 0;
+  int64_t first = 0;
+  for (;;) {
+    first = static_cast<int64_t>(b) * band_groups * kSymGroupRows;
+    const int s = sym_slots(npad, first, chunk);
+    if (t < base + s) break;
+    base += s;
+    ++b;
+  }
+  const int slot = t - base;
+  const int64_t j0 = first + static_cast<int64_t>(slot) * chunk;
+  items[t] = make_int4(b, static_cast<int>(j0), static_cast<int>(std::min<int64_t>(j0 + chunk,
+                                                                                  npad)),
+                       slot);
+}
+
+}  // namespace
+
+bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *p) {
+  const int64_t npad = c->npad;
+  if (!c->sym_items || c->sym_items_npad != npad) return false;
+  if (sym_shape(npad).chunk != c->sym_chunk) return false;
+  if (!plan_layout(c, npad, nv, row_bytes, col_bytes, p)) return false;
+  p->items = static_cast<const int4 *>(c->sym_items);
+  p->n_items = c->sym_items_n;
+  return true;
+}
+
+bool sym_plan_set(const tsbts_ctx *c, int64_t npad, int nv, int row_bytes, int col_bytes,
+                  int4 *items, hipStream_t st, SymPlan *p) {
+  if (!plan_layout(c, npad, nv, row_bytes, col_bytes, p)) return false;
+  const SymShape sh = sym_shape(npad);
+  int n_items = 0;
+  for (int b = 0; b < sh.n_bands; ++b)
+    n_items += sym_slots(npad, static_cast<int64_t>(b) * sh.band_groups * kSymGroupRows,
+                         sh.chunk);
+  if (n_items > kSymMaxItems) return false;
+  hipLaunchKernelGGL(k_sym_items, dim3((n_items + kWG - 1) / kWG), dim3(kWG), 0, st, items,
+                     n_items, npad, sh.band_groups, sh.chunk);
+  p->items = items;
+  p->n_items = n_items;
   return true;
 }
 

@@ -187,4 +187,26 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes);
 // The plan if sym_prepare has provided for these sizes; false otherwise (no allocation).
 bool sym_plan(const tsbts_ctx *c, int nv, int row_bytes, int col_bytes, SymPlan *plan);
 
+// A particle set other than the context's predicted arrays (the compact copy of the
+// active particles of a split call): n particles padded to npad (a multiple of 512),
+// planes laid out as the predicted arrays with stride npad.
+struct SymSet {
+  int64_t n, npad;
+  const float *p32;   // [12][npad] or null (float64 mode)
+  const double *p64;  // [5][npad]
+  const double *v64;  // [3][npad]
+};
+// Work items of a set of npad particles, at most this many.
+constexpr int kSymMaxItems = kSymMaxBands * kSymMaxSlots;
+// Partial-buffer bytes the symmetric kernels need for a set of npad particles.
+int64_t sym_set_bytes(int64_t npad, int nv, int row_bytes, int col_bytes);
+// Grow the context's partial buffer to at least `bytes` (host set-up, synchronous);
+// returns a status.
+int sym_reserve(tsbts_ctx *c, int64_t bytes);
+// The plan for a set of npad particles: its work items written by a kernel on `st` into
+// `items` (kSymMaxItems entries), its partials in the context's buffer; false when that
+// buffer is too small (no allocation, nothing launched).
+bool sym_plan_set(const tsbts_ctx *c, int64_t npad, int nv, int row_bytes, int col_bytes,
+                  int4 *items, hipStream_t st, SymPlan *plan);
+
 }  // namespace tsbts

@@ -35,7 +35,32 @@ struct StepArgs {
   int chunk;     // j-particles per split unit of k_timestep_scalar
   uint32_t *done;   // finished-workgroup count of k_timestep_small
   int fuse_reduce;  // its last workgroup reduces the partials
+  // Sources of k_timestep_scalar (null s64: the predicted arrays above): sn particles,
+  // planes of stride snpad; self = 0 when they exclude the targets.
+  const float *s32 = nullptr;
+  const double *s64 = nullptr, *sv64 = nullptr;
+  int64_t snpad = 0, sn = 0;
+  int self = 1;
+  // null, or [2][n_act]: the other part of a split call's maximum of q and minimum of s*w
+  // for each target, combined where it is finished
+  const double *add = nullptr;
 };
+
+// The source planes of k_timestep_scalar (load_jv reads these fields).
+struct SrcPlanes {
+  const float *p32;
+  const double *p64, *v64;
+  int64_t npad;
+};
+
+// Finish target q from its maximum of q and minimum of s*w.
+__device__ __forceinline__ void finish_target(const StepArgs &A, int q, double qm, double sm) {
+  if (A.add) {
+    qm = fmax(qm, A.add[q]);
+    sm = fmin(sm, A.add[A.n_act + q]);
+  }
+  A.dtc[q] = finish_dt(A.eta, qm, sm);
+}
 
 template <class V, int MASK, int IPL, class J, class I, class F>
 __device__ __forceinline__ void step_tile(const J *sj, const I *Ir, const int *g, int64_t jbase,
@@ -105,14 +130,15 @@ __global__ __launch_bounds__(kWG) void k_timestep(StepArgs A) {
 // from the predicted planes into SGPRs, no LDS staging and no barriers.  Same tiles, vote
 // and partials as k_timestep.
 template <class V, int MASK, int IPL, int CH, class I, class F>
-__device__ __forceinline__ void scalar_step_tile(const StepArgs &A, const I *Ir, const int *g,
-                                                 int64_t jbase, F eps2, F *qmax, F *swmin) {
+__device__ __forceinline__ void scalar_step_tile(const SrcPlanes &S, int64_t sn, const I *Ir,
+                                                 const int *g, int64_t jbase, F eps2, F *qmax,
+                                                 F *swmin) {
 #pragma unroll 4
   for (int jj = 0; jj < CH; ++jj) {
-    const typename StepRec<V>::J Jr = load_jv<V>(A, jbase + jj);
+    const typename StepRec<V>::J Jr = load_jv<V>(S, jbase + jj);
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
-      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k] || jbase + jj >= A.n), qmax[k],
+      pair_step(Ir[k], Jr, eps2, MASK && (jbase + jj == g[k] || jbase + jj >= sn), qmax[k],
                 swmin[k]);
   }
 }
@@ -134,26 +160,28 @@ __global__ __launch_bounds__(kWG) void k_timestep_scalar(StepArgs A) {
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     q[k] = (itile * IPL + k) * kWG + tid;
-    g[k] = A.idx[min(q[k], A.n_act - 1)];
-    I[k] = load_iv<V>(A, g[k]);
+    const int t = A.idx[min(q[k], A.n_act - 1)];
+    I[k] = load_iv<V>(A, t);
+    g[k] = A.self ? t : -1;  // the target's index among the sources
     qmax[k] = F(0);
     swmin[k] = sizeof(F) == 4 ? static_cast<F>(__builtin_inff()) : static_cast<F>(__builtin_inf());
   }
+  const SrcPlanes S{A.s32, A.s64, A.sv64, A.snpad};
   for (int jt = jt0; jt < jt1; ++jt) {
     const int64_t jbase = static_cast<int64_t>(jt) * CH;
     bool mine = false;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) mine |= (g[k] >= jbase && g[k] < jbase + CH);
-    if (__ballot(mine) != 0 || jbase + CH > A.n)
-      scalar_step_tile<V, 1, IPL, CH>(A, I, g, jbase, eps2, qmax, swmin);
+    if (__ballot(mine) != 0 || jbase + CH > A.sn)
+      scalar_step_tile<V, 1, IPL, CH>(S, A.sn, I, g, jbase, eps2, qmax, swmin);
     else
-      scalar_step_tile<V, 0, IPL, CH>(A, I, g, jbase, eps2, qmax, swmin);
+      scalar_step_tile<V, 0, IPL, CH>(S, A.sn, I, g, jbase, eps2, qmax, swmin);
   }
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     if (q[k] >= A.n_act) continue;
     if (A.plan.n_slices == 1) {
-      A.dtc[q[k]] = finish_dt(A.eta, qmax[k], swmin[k]);
+      finish_target(A, q[k], qmax[k], swmin[k]);
     } else {
       double *out = A.part + static_cast<int64_t>(slice) * 2 * A.n_act;
       out[q[k]] = qmax[k];
@@ -257,7 +285,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce(StepArgs A) {
     qm = fmax(qm, in[q]);
     sm = fmin(sm, in[A.n_act + q]);
   }
-  A.dtc[q] = finish_dt(A.eta, qm, sm);
+  finish_target(A, q, qm, sm);
 }
 
 __global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
@@ -272,7 +300,7 @@ __global__ __launch_bounds__(kWG) void k_timestep_reduce_wave(StepArgs A) {
   }
   qm = wave_max(qm);
   sm = wave_min(sm);
-  if (lane == 0) A.dtc[q] = finish_dt(A.eta, qm, sm);
+  if (lane == 0) finish_target(A, q, qm, sm);
 }
 
 // Same, a workgroup per 64 consecutive targets whose kRowsWaves waves each combine a
@@ -301,7 +329,7 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_timestep_reduce_rows(StepAr
       qm = fmax(qm, sums[ww][0][lane]);
       sm = fmin(sm, sums[ww][1][lane]);
     }
-    A.dtc[q] = finish_dt(A.eta, qm, sm);
+    finish_target(A, q, qm, sm);
   }
 }
 
@@ -316,7 +344,15 @@ hipError_t run(StepArgs &A, hipStream_t st) {
     hipLaunchKernelGGL((k_timestep_small<V>), dim3(A.n_jtiles), dim3(kWG), 0, st, A);
     if (A.fuse_reduce) return hipGetLastError();
   } else if (A.scalar_j) {
-    A.n_jtiles = static_cast<int>(A.npad / A.chunk);
+    if (!A.s64) {
+      A.s32 = A.p32;
+      A.s64 = A.p64;
+      A.sv64 = A.v64;
+      A.snpad = A.npad;
+      A.sn = A.n;
+      A.self = 1;
+    }
+    A.n_jtiles = static_cast<int>(A.snpad / A.chunk);
     A.plan = plan_split(A.n_act, A.ipl, A.n_jtiles, A.blocks);
     const dim3 grid(A.plan.nblk), block(kWG);
     if (A.ipl == 2 && A.chunk == kTJ)
@@ -351,14 +387,10 @@ hipError_t run(StepArgs &A, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
-                           double *dtc, hipStream_t st) {
-  if (criterion_sym_applies(c, n_act)) {
-    SymPlan plan;
-    const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
-    if (sym_plan(c, 2, vb, vb, &plan))
-      return launch_timestep_sym(c, plan, idx, n_act, eta, dtc, st);
-  }
+namespace {
+
+// The gather kernels' arguments for the context's predicted arrays.
+StepArgs gather_args(tsbts_ctx *c, const int32_t *idx, int n_act, double eta, double *dtc) {
   StepArgs A;
   A.n = c->n;
   A.p32 = c->p32;
@@ -378,9 +410,48 @@ hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double e
   A.chunk = scalar_chunk(c, n_act, A.ipl);
   A.done = c->done + 1;
   A.fuse_reduce = 0;
+  return A;
+}
+
+hipError_t run_precision(const tsbts_ctx *c, StepArgs &A, hipStream_t st) {
   if (c->precision == TSBTS_FP64) return run<Fp64>(A, st);
   if (c->flags & TSBTS_FLAG_HILO_SEPARATION) return run<MixHiLo>(A, st);
   return run<MixSep64>(A, st);
+}
+
+}  // namespace
+
+hipError_t launch_timestep(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                           double *dtc, hipStream_t st) {
+  if (split_applies(c, n_act)) {
+    const hipError_t e = launch_timestep_split(c, idx, n_act, eta, dtc, st);
+    if (e != hipErrorNotReady) return e;
+  }
+  if (criterion_sym_applies(c, n_act)) {
+    SymPlan plan;
+    const int vb = c->precision == TSBTS_FP64 ? 8 : 4;
+    if (sym_plan(c, 2, vb, vb, &plan))
+      return launch_timestep_sym(c, plan, idx, n_act, eta, dtc, st);
+  }
+  StepArgs A = gather_args(c, idx, n_act, eta, dtc);
+  return run_precision(c, A, st);
+}
+
+hipError_t launch_timestep_gather(tsbts_ctx *c, const int32_t *idx, int n_act, double eta,
+                                  double *dtc, hipStream_t st, const GatherSrc *src) {
+  // the scalar-load kernel in the shape gather_args gives it from 8192 targets (two
+  // targets per lane), whose partials partial_elems_needed provides for
+  if (n_act < 8192 || !criterion_scalar_j(c, n_act)) return hipErrorInvalidValue;
+  StepArgs A = gather_args(c, idx, n_act, eta, dtc);
+  A.s32 = src->p32;
+  A.s64 = src->p64;
+  A.sv64 = src->v64;
+  A.snpad = src->npad;
+  A.sn = src->n;
+  A.self = 0;
+  A.add = src->add;
+  A.scalar_j = 1;
+  return run_precision(c, A, st);
 }
 
 }  // namespace tsbts

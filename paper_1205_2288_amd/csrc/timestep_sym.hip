@@ -22,6 +22,7 @@ struct StepSymArgs {
   int n_act;
   double eta;
   double *dtc;
+  double *raw;  // null, or [2][n_act]: max q and min s*w unfinished instead of dtc
 };
 
 // A row particle's weights in the column role (see pair_step_sym).
@@ -210,7 +211,12 @@ __global__ __launch_bounds__(kWG) void k_timestep_sym_reduce(StepSymArgs A) {
     qm = fmax(qm, static_cast<double>(c[0]));
     sm = fmin(sm, -static_cast<double>(c[A.npad]));
   }
-  A.dtc[q] = finish_dt(A.eta, qm, sm);
+  if (A.raw) {
+    A.raw[q] = qm;
+    A.raw[A.n_act + q] = sm;
+  } else {
+    A.dtc[q] = finish_dt(A.eta, qm, sm);
+  }
 }
 
 template <class V>
@@ -230,13 +236,15 @@ hipError_t run(StepSymArgs &A, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_timestep_sym(tsbts_ctx *c, const SymPlan &plan, const int32_t *idx,
-                               int n_act, double eta, double *dtc, hipStream_t st) {
+                               int n_act, double eta, double *dtc, hipStream_t st,
+                               const SymSet *set, double *raw) {
   StepSymArgs A;
-  A.n = c->n;
-  A.npad = c->npad;
-  A.p32 = c->p32;
-  A.p64 = c->p64;
-  A.v64 = c->v64;
+  A.n = set ? set->n : c->n;
+  A.npad = set ? set->npad : c->npad;
+  A.p32 = set ? set->p32 : c->p32;
+  A.p64 = set ? set->p64 : c->p64;
+  A.v64 = set ? set->v64 : c->v64;
+  A.raw = raw;
   A.eps2 = c->eps * c->eps;
   A.plan = plan;
   A.idx = idx;

@@ -60,10 +60,11 @@ def test_noalloc_force_equals_force_two_calls(precision):
 
 
 def test_noalloc_shrunk_split_and_full_set():
-    """N = 131072 with 130816 targets: tsbts_force's split needs more partials than the
-    fixed array holds, so the variant aims for fewer workgroups (another fixed order of
-    float64 tile sums); the full set is served by the symmetric kernels in tsbts_force and
-    by the gather kernels here."""
+    """N = 131072 with 130816 targets: tsbts_force's split-j launch needs more partials than
+    the fixed array holds, so the variant aims for fewer workgroups (another fixed order of
+    float64 tile sums); tsbts_force's split call of a large partial set (symmetric kernels
+    on the pairs among the targets) and the full set (symmetric kernels) sum other float32
+    partials than the gather kernels here."""
     n, eps, tb = 131072, 1.0 / 4096, 2.0 ** -8
     r, v, m, a, t_last, dt = _state(n, 12052293)
     with make_ctx(n, eps, "mixed") as ctx:
@@ -72,12 +73,21 @@ def test_noalloc_shrunk_split_and_full_set():
         k = 130816
         print(f"noalloc mixed n={n} n_active={k}", flush=True)
         idx = ctx.idx(active_subset(n, k, 99 + k))
+        # tsbts_force on the gather kernels too (split calls of large partial sets off)
+        ctx.tune(split=0)
         a1, p1, a2, p2 = _both(ctx, idx, tb)
         e = rel_err_vec(a2, a1)
         # float64 sums of the same float32 tile sums, grouped into fewer slices
         assert np.median(e) < 1e-14 and e.max() < 1e-11, (np.median(e), e.max())
         ep = np.abs(p2 - p1) / np.abs(p1)
         assert ep.max() < 1e-12, ep.max()
+        # a split call in tsbts_force: other float32 partial sums, the mixed bar
+        ctx.tune(split=1)
+        a1, p1, a2, p2 = _both(ctx, idx, tb)
+        e = rel_err_vec(a2, a1)
+        assert np.median(e) < 1e-6 and e.max() < 1e-5, (np.median(e), e.max())
+        ep = np.abs(p2 - p1) / np.abs(p1)
+        assert np.median(ep) < 1e-6 and ep.max() < 1e-5, (np.median(ep), ep.max())
         print(f"noalloc mixed n={n} n_active={n}", flush=True)
         idx = ctx.idx(np.arange(n, dtype=np.int32))
         a1, p1, a2, p2 = _both(ctx, idx, tb)
