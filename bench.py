@@ -14,7 +14,10 @@ h/2, h = 2^-10), and one benchmark step is one era [0, h] of the method with two
 
 So each step issues 3 N^2 force interactions (mixed precision) and N^2 adjoint
 interactions; `value` is (force + adjoint interactions) per second over the timed steps
-(inputs resident in HBM).  The same step is timed with the float64 force as the
+(inputs resident in HBM).  The library chooses its kernels as for any caller: the
+symmetric all-targets kernels for the calls with every particle active, split calls
+(symmetric kernels on the pairs among the active half, gather kernels on its pairs with
+the other half) for the half-active ones.  The same step is timed with the float64 force as the
 comparison, plus a sweep of single force calls at active fractions 2^-k.
 
 Prints one JSON line.  `--gpus` above 1 is not supported (one-GPU build).
@@ -69,26 +72,19 @@ FLOPS_ADJOINT_GATHER = 73.0  # fused all-active gather kernel: source 38 + targe
 # 16 hex digits) when the counters were taken; if they differ now, traffic is null.
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_KIB = {
-    "k_timestep_scalar": (29642.1, 131072.0,
-        ("timestep.hip", "criterion.hpp", "pair.hpp", "internal.hpp", "sym.hpp"),
-        "a6f59f3b43b730cd"),
-    "k_force_scalar": (20580.2, 65536.0,
-        ("force.hip", "force_pair.hpp", "pair.hpp", "internal.hpp", "correct.hpp", "sym.hpp",
-         "predict.hpp", "hermite.hpp", "criterion.hpp"),
-        "ee1f2680ecdd54a2"),
-    "k_timestep_sym": (200621.8, 132102.8,
+    "k_timestep_sym": (200805.3, 132102.7,
         ("timestep_sym.hip", "sym.hpp", "criterion.hpp", "pair.hpp", "internal.hpp"),
-        "ea7c2657d0d6eaf2"),
-    "k_force_sym": (134505.2, 363367.3,
+        "0ea120b43c4f421b"),
+    "k_force_sym": (134479.5, 363360.7,
         ("force_sym.hip", "sym.hpp", "force_pair.hpp", "pair.hpp", "internal.hpp",
          "correct.hpp"),
-        "33f531ef07b75214"),
-    "k_bwd_sym": (237087.2, 396406.2,
+        "9cb14d1bc07128f4"),
+    "k_bwd_sym": (237130.6, 396422.7,
         ("backward_sym.hip", "sym.hpp", "pair.hpp", "internal.hpp"),
-        "57d503efacb6528e"),
-    "k_energy_pairs": (18770.3, 256.0,
+        "b631e093cddd99c9"),
+    "k_energy_pairs": (18756.6, 256.0,
         ("energy.hip", "internal.hpp"),
-        "9c10355a20f99983"),
+        "999bec6dbfe71a46"),
 }
 
 
@@ -682,7 +678,11 @@ def main():
                    "n": n, "eps": cfg.eps, "seed": cfg.seed, "precision": "mixed",
                    "interactions_per_step": b.interactions,
                    "potential": "not computed in the timed block steps (the integrator "
-                                "does not use it); the sweeps time force + potential"},
+                                "does not use it); the sweeps time force + potential",
+                   "kernels": "library defaults: symmetric all-targets kernels when every "
+                              "particle is active, split calls for the half-active block "
+                              "steps; gather_kernels_only times the same step without "
+                              "either"},
         "roofline": roof,
         "rooflines": roofs,
         "force_interactions_per_s": n * n / (np.mean(ms["force_full"]) * 1e-3),

@@ -747,7 +747,9 @@ hipError_t launch_force_gather(tsbts_ctx *c, const int32_t *idx, int n_act, doub
 
 hipError_t launch_force(tsbts_ctx *c, const int32_t *idx, int n_act, double *acc,
                         double *pot, hipStream_t st, const CorrectArgs *corr) {
-  if (split_applies(c, n_act)) {
+  // automatic split calls only without the potential: the symmetric kernel's potential
+  // form (half the columns per transposition) costs what the split saves
+  if (split_applies(c, n_act) && (!pot || c->tune_split == 1)) {
     const hipError_t e = launch_force_split(c, idx, n_act, acc, pot, st, corr);
     if (e != hipErrorNotReady) return e;
   }
