@@ -16,10 +16,11 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_traffic_is_null_once_the_sources_change(monkeypatch):
     import bench
-    fetch, write, files, digest = bench.TRAFFIC_KIB["k_force_scalar"]
-    monkeypatch.setitem(bench.TRAFFIC_KIB, "k_force_scalar", (fetch, write, files, "0" * 16))
-    assert bench.traffic_bytes("k_force_scalar") is None
+    fetch, write, files, digest = bench.TRAFFIC_KIB["k_force_sym"]
+    monkeypatch.setitem(bench.TRAFFIC_KIB, "k_force_sym", (fetch, write, files, "0" * 16))
+    assert bench.traffic_bytes("k_force_sym") is None
     assert bench.traffic_bytes("k_no_such_kernel") is None
-    monkeypatch.setitem(bench.TRAFFIC_KIB, "k_force_scalar", (1.0, 2.0, files, digest))
-    got = bench.traffic_bytes("k_force_scalar")
+    assert bench.traffic_bytes("split_force") is None  # several kernels: no counter bytes
+    monkeypatch.setitem(bench.TRAFFIC_KIB, "k_force_sym", (1.0, 2.0, files, digest))
+    got = bench.traffic_bytes("k_force_sym")
     assert got is None or got == (1.0 * 2.0 + 2.0 * 1.0) * 1024.0
