@@ -73,6 +73,14 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
     path = None if state_dir is None else _state_path(state_dir, n, seed, eps, eta, passes,
                                                       era, dt_max, every, precision)
     series, wall_before, t_mark = [], 0.0, 0.0
+    eras_before = {}  # eras of each size in earlier sessions of this run
+
+    def era_sizes():
+        out = dict(eras_before)
+        for k, c in sim.era_sizes.items():
+            out[k] = out.get(k, 0) + c
+        return out
+
     if path is not None and os.path.exists(path):
         with np.load(path) as z:  # arrays only (no pickles)
             ck = {k: z[k] for k in z.files}
@@ -80,6 +88,8 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
         series = list(zip(ck["series_t"].tolist(), ck["series_e"].tolist()))
         wall_before = float(ck["wall_s"])
         t_mark = series[-1][0]
+        if "era_keys" in ck:
+            eras_before = dict(zip(ck["era_keys"].tolist(), ck["era_counts"].tolist()))
     t0 = time.perf_counter()
     complete = True
     while t_mark < t_end:
@@ -96,6 +106,9 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
             ck["series_t"] = np.array([p[0] for p in series])
             ck["series_e"] = np.array([p[1] for p in series])
             ck["wall_s"] = np.array(wall)
+            sizes = era_sizes()
+            ck["era_keys"] = np.array(list(sizes.keys()), dtype=str)
+            ck["era_counts"] = np.array(list(sizes.values()), dtype=np.int64)
             tmp = path + ".tmp.npz"
             np.savez(tmp, **ck)
             os.replace(tmp, path)
@@ -104,6 +117,7 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
             break
     wall = wall_before + time.perf_counter() - t0
     st = sim.stats
+    sizes = era_sizes()
     sim.close()
     e0 = series[0][1]
     t = np.array([p[0] for p in series])
@@ -117,7 +131,8 @@ def energy_error_run(n: int, seed: int, eps: float, eta: float, passes: int,
             "eta": eta, "eps": eps, "dt_max": dt_max, "t_end": t_end,
             "complete": complete, "t_reached": float(t[-1]),
             "max_err": float(err.max()), "final_err": float(err[-1]), "growth": growth,
-            "block_steps": st["block_steps"], "eras": st["eras"], "wall_s": wall,
+            "block_steps": st["block_steps"], "eras": st["eras"], "era_sizes": sizes,
+            "wall_s": wall,
             "series_t": t.tolist(), "series_err": err.tolist()}
 
 
@@ -218,6 +233,8 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=100.0)
     ap.add_argument("--eta", type=float, default=0.1)
     ap.add_argument("--eps", type=float, default=0.01)
+    ap.add_argument("--dt-max", type=float, default=1.0 / 64,
+                    help="largest step, and the fixed era of the dynamic study's fixed runs")
     ap.add_argument("--passes", type=int, nargs="+", default=None)
     ap.add_argument("--eras", type=float, nargs="+", default=None,
                     help="fixed era sizes of the era study (default 1/64 ... 1/4)")
@@ -245,13 +262,13 @@ def main(argv=None):
         if args.seed0 is not None:
             kw["seed0"] = args.seed0
         era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta, eps=args.eps,
-                  passes=tuple(args.passes or (3, 5)), every=args.every,
+                  dt_max=args.dt_max, passes=tuple(args.passes or (3, 5)), every=args.every,
                   workers=args.workers, **kw, **resume)
     else:
         kw = {} if args.seed0 is None else {"seed0": args.seed0}
         dynamic_era_study(n=args.n, seeds=args.seeds, t_end=args.t_end, eta=args.eta,
-                          eps=args.eps, passes=(args.passes or [3])[0], every=args.every,
-                          workers=args.workers, **kw, **resume)
+                          eps=args.eps, dt_max=args.dt_max, passes=(args.passes or [3])[0],
+                          every=args.every, workers=args.workers, **kw, **resume)
 
 
 if __name__ == "__main__":

@@ -269,6 +269,7 @@ def test_experiment_run_resumes_across_sessions(tmp_path):
     assert rest["series_err"] == full["series_err"]
     assert rest["block_steps"] == full["block_steps"]
     assert rest["growth"] == full["growth"]
+    assert rest["era_sizes"] == full["era_sizes"] and sum(full["era_sizes"].values()) == 32
 
 
 @pytest.mark.parametrize("prec,era", [("fp64", 1.0 / 8), ("mixed", None)])
