@@ -142,6 +142,14 @@ struct CritHistory {
     const double w = static_cast<double>(tt - gt[k]) / static_cast<double>(gt[k + 1] - gt[k]);
     return (1.0 - w) * gc[k] + w * gc[k + 1];
   }
+  // fetch the records value_at(i, ...) starts from into the cache
+  void prefetch(int32_t i) const {
+    if (static_cast<size_t>(i) >= cur.size()) return;
+    const size_t k = static_cast<size_t>(cur[i]);
+    if (k >= gt.size()) return;
+    __builtin_prefetch(&gt[k]);
+    __builtin_prefetch(&gc[k]);
+  }
 };
 
 }  // namespace
@@ -198,6 +206,19 @@ struct Scheduler {
       lvl[i] = l;
       pos[i] = static_cast<int32_t>(mem[l].size());
       mem[l].push_back(static_cast<int32_t>(i));
+    }
+  }
+  // fetch particle i's host state (scattered over n: the active lists come in level-list
+  // order) into the cache, with the start of its criterion history
+  void prefetch(int32_t i) const {
+    __builtin_prefetch(&t[i]);
+    __builtin_prefetch(&dt[i]);
+    __builtin_prefetch(&dtp[i]);
+    __builtin_prefetch(&dtc[i]);
+    __builtin_prefetch(&lvl[i]);
+    if (static_cast<size_t>(i) < prev.cur.size()) {
+      __builtin_prefetch(&prev.off[i]);
+      __builtin_prefetch(&prev.cur[i]);
     }
   }
   void move(int32_t i, int l) {
@@ -360,7 +381,12 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     const auto t_issued = clk::now();
     SCHED_CALL(wait_criterion(c, S, k, st));
     const auto t_done = clk::now();
+    // the state of the particles a few places ahead is fetched while this one is handled
+    // (random accesses over n otherwise take most of the loop's time at large n)
+    constexpr int32_t kAhead = 16;
     for (int32_t q = 0; q < k; ++q) {
+      if (q + kAhead < k) S.prefetch(S.idx_h[q + kAhead]);
+      if (q + kAhead / 2 < k) S.prev.prefetch(S.idx_h[q + kAhead / 2]);
       const int32_t i = S.idx_h[q];
       const double b = S.dtc_h[q];
       S.dtc[i] = b;
