@@ -64,15 +64,27 @@ int64_t era_end_rule(int64_t t0, int64_t first, int64_t last, int64_t largest,
 
 // step_rule with the previous pass's values at the ends of the two candidate steps given
 // on demand by end_dt() and end_2dt(): each is needed on some branches only.
+// Whether tb is a multiple of 2 dt, and whether tb / dt (rounded down) is even, for
+// tb >= 0: bit tests when dt is a power of two (every step of the scheduler), the
+// divisions otherwise.
+inline bool multiple_of_2dt(int64_t tb, int64_t dt) {
+  if (dt > 0 && (dt & (dt - 1)) == 0 && tb >= 0) return (tb & (2 * dt - 1)) == 0;
+  return tb % (2 * dt) == 0;
+}
+inline bool even_multiple(int64_t tb, int64_t dt) {
+  if (dt > 0 && (dt & (dt - 1)) == 0 && tb >= 0) return (tb & dt) == 0;
+  return (tb / dt) % 2 == 0;
+}
+
 template <class E1, class E2>
 int64_t step_rule_lazy(int first_pass, int64_t dt, int64_t tb, double begin, E1 end_dt,
                        E2 end_2dt, int64_t dt_min, int64_t dt_max) {
   if (first_pass) {
     const int64_t lvl = admissible_ticks(begin, begin, dt_min, dt_max);
-    if (lvl >= 2 * dt && tb % (2 * dt) == 0) return 2 * dt;
+    if (lvl >= 2 * dt && multiple_of_2dt(tb, dt)) return 2 * dt;
     return std::min(dt, lvl);
   }
-  const bool even = (tb / dt) % 2 == 0;
+  const bool even = even_multiple(tb, dt);
   if (even && 2 * dt <= dt_max && 2 * dt <= admissible_ticks(begin, end_2dt(), dt_min, dt_max))
     return 2 * dt;
   if (dt <= admissible_ticks(begin, end_dt(), dt_min, dt_max)) return dt;
@@ -88,10 +100,10 @@ int64_t step_rule(int first_pass, int64_t dt, int64_t tb, double begin, double e
 
 namespace {
 
+// Smallest l with 2^l >= dt (0 for dt <= 1).
 int level_of(int64_t dt) {
-  int l = 0;
-  while ((int64_t(1) << l) < dt) ++l;
-  return l;
+  if (dt <= 1) return 0;
+  return 64 - __builtin_clzll(static_cast<uint64_t>(dt - 1));
 }
 
 // Criterion values of one pass grouped by particle (time order kept).
@@ -166,6 +178,7 @@ struct Scheduler {
   // level member lists
   std::vector<int32_t> mem[kMaxLevel + 1];
   std::vector<int32_t> lvl, pos;
+  std::vector<uint64_t> list_bits;  // one bit per particle, zero between block steps
   // criterion histories
   CritHistory prev, cur;
   bool have_prev = false;
@@ -208,8 +221,26 @@ struct Scheduler {
       mem[l].push_back(static_cast<int32_t>(i));
     }
   }
-  // fetch particle i's host state (scattered over n: the active lists come in level-list
-  // order) into the cache, with the start of its criterion history
+  // Put the active list idx_h[0 .. k) in particle order (through a bitmap: k bit sets and
+  // a scan of n/64 words), so that the step rule reads the particles' host state in
+  // address order.
+  void sort_list(int32_t k) {
+    uint64_t *w = list_bits.data();
+    for (int32_t q = 0; q < k; ++q)
+      w[idx_h[q] >> 6] |= uint64_t(1) << (idx_h[q] & 63);
+    int32_t q = 0;
+    for (size_t b = 0; b < list_bits.size(); ++b) {
+      uint64_t x = w[b];
+      if (!x) continue;
+      w[b] = 0;
+      while (x) {
+        idx_h[q++] = static_cast<int32_t>(b * 64 + __builtin_ctzll(x));
+        x &= x - 1;
+      }
+    }
+  }
+  // fetch particle i's host state (scattered over n when the active list comes in
+  // level-list order) into the cache, with the start of its criterion history
   void prefetch(int32_t i) const {
     __builtin_prefetch(&t[i]);
     __builtin_prefetch(&dt[i]);
@@ -324,6 +355,9 @@ int flush_steps(tsbts_ctx *c, Scheduler &S, hipStream_t st) {
 }
 
 // One pass of an era: block steps until the next block time passes T1.
+// Active lists longer than this are put in particle order (Scheduler::sort_list).
+constexpr int32_t kSortList = 1024;
+
 int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
   const int64_t n = S.n;
   S.cur.clear();
@@ -342,6 +376,7 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
       std::copy(S.mem[l].begin(), S.mem[l].end(), S.idx_h + k);
       k += static_cast<int32_t>(S.mem[l].size());
     }
+    if (k > kSortList) S.sort_list(k);
     const double tbs = static_cast<double>(tb) * tsbts::kTick;
     const int64_t step = ++S.step_id;
     std::fill(reinterpret_cast<uint64_t *>(S.dtc_h), reinterpret_cast<uint64_t *>(S.dtc_h) + k,
@@ -545,6 +580,7 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   S->dtc.assign(n, 0.0);
   S->lvl.assign(n, 0);
   S->pos.assign(n, 0);
+  S->list_bits.assign((n + 63) / 64, 0);
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->idx_h), sizeof(int32_t) * n));
   // coherent: the kernels' criterion values reach host memory as they are written
   SCHED_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->dtc_h), sizeof(double) * n,
