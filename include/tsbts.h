@@ -407,6 +407,7 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
 /* options of tsbts_sched_option */
 #define TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR 1
 #define TSBTS_SCHED_PREDICT_ON_LOAD 2
+#define TSBTS_SCHED_RULE_THREADS 3
 
 /* Scheduler option (host only; applies from the next block step):
  *   TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR: 0 = the paper's order, criterion after the
@@ -420,6 +421,11 @@ int tsbts_sched_init(tsbts_ctx *ctx, double eta, int passes, double dt_min, doub
  *     block step instead of three or four, the same results bit for bit (default);
  *     0 = separate predictor and criterion launches.  Not combined with the option
  *     above.
+ *   TSBTS_SCHED_RULE_THREADS: host threads (1 .. 16; default 4) that share the step rule
+ *     (Algorithm 1 with the block condition) of block steps with at least 8192 active
+ *     particles; each particle's rule reads and writes its own state only, so the
+ *     results are the same for every value (1: the calling thread alone).  The threads
+ *     are started at the first such block step and kept until the scheduler is freed.
  * Returns TSBTS_ESTATE before tsbts_sched_init, TSBTS_EINVAL for an unknown option or
  * value. */
 int tsbts_sched_option(tsbts_ctx *ctx, int option, int value);

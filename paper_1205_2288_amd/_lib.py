@@ -172,6 +172,7 @@ TSBTS_TUNE_CHECK_INDICES = 5
 TSBTS_TUNE_SPLIT = 6
 TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR = 1
 TSBTS_SCHED_PREDICT_ON_LOAD = 2
+TSBTS_SCHED_RULE_THREADS = 3
 
 
 def tsbts_tune(ctx, param: int, value: int):

@@ -27,8 +27,13 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -126,6 +131,19 @@ struct CritHistory {
     t.push_back(tt);
     c.push_back(cc);
   }
+  // make room for k more records (filled with set); returns the first one's index
+  size_t extend(size_t k) {
+    const size_t base = pid.size();
+    pid.resize(base + k);
+    t.resize(base + k);
+    c.resize(base + k);
+    return base;
+  }
+  void set(size_t r, int32_t p, int64_t tt, double cc) {
+    pid[r] = p;
+    t[r] = tt;
+    c[r] = cc;
+  }
   void close(int64_t n) {
     off.assign(n + 1, 0);
     for (int32_t p : pid) ++off[p + 1];
@@ -164,6 +182,63 @@ struct CritHistory {
   }
 };
 
+// Host threads for the step rule of long active lists: run(f) calls f(part, parts) for
+// every part, the calling thread taking part 0, and returns when all have returned.
+class RulePool {
+ public:
+  explicit RulePool(int threads) : parts_(threads) {
+    for (int w = 1; w < threads; ++w) workers_.emplace_back([this, w] { loop(w); });
+  }
+  ~RulePool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    start_.notify_all();
+    for (auto &th : workers_) th.join();
+  }
+  int parts() const { return parts_; }
+  void run(const std::function<void(int, int)> &f) {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      job_ = &f;
+      remaining_ = parts_ - 1;
+      ++generation_;
+    }
+    start_.notify_all();
+    f(0, parts_);
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [this] { return remaining_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop(int w) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int, int)> *job;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        start_.wait(lk, [&] { return stop_ || generation_ != seen; });
+        if (stop_) return;
+        seen = generation_;
+        job = job_;
+      }
+      (*job)(w, parts_);
+      std::lock_guard<std::mutex> lk(m_);
+      if (--remaining_ == 0) done_.notify_one();
+    }
+  }
+  int parts_;
+  std::vector<std::thread> workers_;
+  std::mutex m_;
+  std::condition_variable start_, done_;
+  const std::function<void(int, int)> *job_ = nullptr;
+  uint64_t generation_ = 0;
+  int remaining_ = 0;
+  bool stop_ = false;
+};
+
 }  // namespace
 
 struct Scheduler {
@@ -179,6 +254,11 @@ struct Scheduler {
   std::vector<int32_t> mem[kMaxLevel + 1];
   std::vector<int32_t> lvl, pos;
   std::vector<uint64_t> list_bits;  // one bit per particle, zero between block steps
+  // the step rule of long lists on several host threads (rule_threads; 1: this one only)
+  int rule_threads = 4;
+  std::unique_ptr<RulePool> pool;
+  // per part of the list: the positions whose particle changes level, in list order
+  std::vector<int32_t> moved[16];
   // criterion histories
   CritHistory prev, cur;
   bool have_prev = false;
@@ -357,6 +437,8 @@ int flush_steps(tsbts_ctx *c, Scheduler &S, hipStream_t st) {
 // One pass of an era: block steps until the next block time passes T1.
 // Active lists longer than this are put in particle order (Scheduler::sort_list).
 constexpr int32_t kSortList = 1024;
+// Active lists of at least this many particles share the step rule among host threads.
+constexpr int32_t kParallelRule = 8192;
 
 int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
   const int64_t n = S.n;
@@ -416,30 +498,65 @@ int run_pass(tsbts_ctx *c, Scheduler &S, int p, int64_t T1, hipStream_t st) {
     const auto t_issued = clk::now();
     SCHED_CALL(wait_criterion(c, S, k, st));
     const auto t_done = clk::now();
-    // the state of the particles a few places ahead is fetched while this one is handled
-    // (random accesses over n otherwise take most of the loop's time at large n)
-    constexpr int32_t kAhead = 16;
-    for (int32_t q = 0; q < k; ++q) {
-      if (q + kAhead < k) S.prefetch(S.idx_h[q + kAhead]);
-      if (q + kAhead / 2 < k) S.prev.prefetch(S.idx_h[q + kAhead / 2]);
-      const int32_t i = S.idx_h[q];
-      const double b = S.dtc_h[q];
-      S.dtc[i] = b;
-      S.dtp[i] = tb - S.t[i];
-      S.t[i] = tb;
-      S.cur.add(i, tb, b);
-      const int64_t d = S.dt[i];
-      const int64_t nd = tsbts::step_rule_lazy(
-          p == 0, d, tb, b, [&] { return S.prev.value_at(i, tb + d, b); },
-          [&] { return S.prev.value_at(i, tb + 2 * d, b); }, S.dt_min, S.dt_max);
-      S.dtn_h[q] = static_cast<double>(nd) * tsbts::kTick;
-      const int l = tsbts::level_of(nd);  // nd = 2^l ticks (powers of two throughout)
-      if (q < tsbts::kInlinePend) S.pend_exp[q] = static_cast<int8_t>(l - tsbts::kTickBits);
-      if (nd != d) {
-        S.dt[i] = nd;
-        S.move(i, l);
+    // Step rule of every listed particle: its own state only (its cursor into the previous
+    // pass's criterion history included), so that parts of a long list can go to other
+    // host threads; the level lists change afterwards, in list order.  The state of the
+    // particles a few places ahead is fetched while one is handled (random accesses over
+    // n otherwise take most of the loop's time at large n).
+    const size_t rec0 = S.cur.extend(static_cast<size_t>(k));
+    auto rule = [&](int32_t q0, int32_t q1, std::vector<int32_t> &moved) {
+      constexpr int32_t kAhead = 16;
+      moved.clear();
+      for (int32_t q = q0; q < q1; ++q) {
+        if (q + kAhead < q1) S.prefetch(S.idx_h[q + kAhead]);
+        if (q + kAhead / 2 < q1) S.prev.prefetch(S.idx_h[q + kAhead / 2]);
+        const int32_t i = S.idx_h[q];
+        const double b = S.dtc_h[q];
+        S.dtc[i] = b;
+        S.dtp[i] = tb - S.t[i];
+        S.t[i] = tb;
+        S.cur.set(rec0 + q, i, tb, b);
+        const int64_t d = S.dt[i];
+        const int64_t nd = tsbts::step_rule_lazy(
+            p == 0, d, tb, b, [&] { return S.prev.value_at(i, tb + d, b); },
+            [&] { return S.prev.value_at(i, tb + 2 * d, b); }, S.dt_min, S.dt_max);
+        S.dtn_h[q] = static_cast<double>(nd) * tsbts::kTick;
+        if (q < tsbts::kInlinePend)
+          S.pend_exp[q] = static_cast<int8_t>(tsbts::level_of(nd) - tsbts::kTickBits);
+        if (nd != d) {
+          S.dt[i] = nd;
+          moved.push_back(q);
+        }
+      }
+    };
+    if (k >= kParallelRule && S.rule_threads > 1) {
+      if (!S.pool || S.pool->parts() != S.rule_threads) {
+        S.pool.reset();
+        try {
+          S.pool.reset(new tsbts::RulePool(S.rule_threads));
+        } catch (...) {  // no threads: this one does it all
+          S.pool.reset();
+          S.rule_threads = 1;
+        }
       }
     }
+    int parts = 1;
+    if (k >= kParallelRule && S.pool) {
+      parts = S.pool->parts();
+      const std::function<void(int, int)> part = [&](int w, int np) {
+        rule(static_cast<int32_t>(int64_t(k) * w / np),
+             static_cast<int32_t>(int64_t(k) * (w + 1) / np), S.moved[w]);
+      };
+      S.pool->run(part);
+    } else {
+      rule(0, k, S.moved[0]);
+    }
+    // level changes in list order (the parts are consecutive ranges of the list)
+    for (int w = 0; w < parts; ++w)
+      for (const int32_t q : S.moved[w]) {
+        const int32_t i = S.idx_h[q];
+        S.move(i, tsbts::level_of(S.dt[i]));  // steps are 2^l ticks throughout
+      }
     // the next block step's first kernel stores these steps; dtn_h is rewritten only
     // after the next synchronisation, when that kernel has run
     S.pending = true;
@@ -660,6 +777,11 @@ int tsbts_sched_option(tsbts_ctx *c, int option, int value) {
   if (!c) return TSBTS_EINVAL;
   Scheduler *S = static_cast<Scheduler *>(c->sched);
   if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_option: call tsbts_sched_init first");
+  if (option == TSBTS_SCHED_RULE_THREADS) {
+    if (value < 1 || value > 16) return sfail(c, TSBTS_EINVAL, "rule threads must be 1 .. 16");
+    S->rule_threads = value;
+    return TSBTS_OK;
+  }
   if (option != TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR &&
       option != TSBTS_SCHED_PREDICT_ON_LOAD)
     return sfail(c, TSBTS_EINVAL, "tsbts_sched_option: unknown option");

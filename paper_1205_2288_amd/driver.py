@@ -356,13 +356,15 @@ class NativeTSBTS:
 
     def __init__(self, r, v, m, eps, eta=0.1, passes=3, dt_max=1.0 / 64, dt_min=2.0 ** -20,
                  era=None, precision="mixed", separation="f64", newton=False,
-                 criterion="after", tune=None, predict_on_load=True):
+                 criterion="after", tune=None, predict_on_load=True, rule_threads=None):
         """criterion: "after" the corrector (the paper's order) or "before" it, with the
         predicted velocities, in the same pass over the pairs as the force.  tune: keyword
         arguments of Context.tune, applied before the first force evaluation.
         predict_on_load: small active sets predict their sources inside the force kernel,
         and on few particles take the criterion in it too (fewer launches per block step,
-        same results)."""
+        same results).  rule_threads: host threads sharing the step rule of block steps
+        with at least 8192 active particles (default 4; the same results for any
+        number)."""
         from . import _lib as L
         if criterion not in ("after", "before"):
             raise ValueError("criterion must be 'after' or 'before'")
@@ -379,6 +381,8 @@ class NativeTSBTS:
             L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_CRITERION_BEFORE_CORRECTOR, 1)
         L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_PREDICT_ON_LOAD,
                              1 if predict_on_load and criterion == "after" else 0)
+        if rule_threads is not None:
+            L.tsbts_sched_option(self.ctx.ctx, L.TSBTS_SCHED_RULE_THREADS, int(rule_threads))
         self._ek = torch.empty(2, dtype=torch.float64, device=self.ctx.device)
         self._host()
         self.wall_s = 0.0

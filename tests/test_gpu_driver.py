@@ -338,3 +338,24 @@ def test_native_step_timing_accounts_for_every_block_step():
     t = sim.step_timing()
     assert sum(x["block_steps"] for x in t.values()) == st["block_steps"]
     sim.close()
+
+
+def test_threaded_step_rule_equals_serial():
+    # block steps with at least 8192 active particles (here every era's all-particle
+    # steps and the larger partial ones) share the step rule among host threads; each
+    # particle's rule reads and writes its own state only, so the run is the same bit for
+    # bit with the calling thread alone
+    from paper_1205_2288_amd.driver import NativeTSBTS
+    n, eps = 16384, 1 / 256
+    r, v, m = plummer(n, 4600)
+    out = []
+    for threads in (1, 4):
+        sim = NativeTSBTS(r, v, m, eps, passes=3, era=1 / 16, dt_max=1 / 16,
+                          rule_threads=threads)
+        series = sim.run(1 / 8)
+        out.append((series, sim.state(), sim.stats["block_steps"]))
+        sim.close()
+    assert out[0][0] == out[1][0]
+    for key in ("t", "dt", "dtc", "r", "v", "a"):
+        assert np.array_equal(out[0][1][key], out[1][1][key]), key
+    assert out[0][2] == out[1][2]
