@@ -102,6 +102,26 @@ def test_split_not_used_below_its_sizes():
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["newton", "chunk"])
+def test_split_not_used_for_newton_or_tuned_chunk(case):
+    # the Newton-step form (no symmetric kernel) and a tuned j-unit keep the gather
+    # kernels: a forced split changes nothing
+    n, k, eps, eta = 20000, 12000, 1 / 256, 0.1
+    r, v, m = plummer(n, 4310, masses="loguniform")
+    ctx = make_ctx(n, eps, "mixed", "f64", newton=(case == "newton"))
+    if case == "chunk":
+        ctx.tune(chunk=256)
+    ctx.bind(r, v, m)
+    ctx.predict(0.0)
+    idx = _subset(n, k, 8)
+    out = []
+    for split in (0, 1):
+        ctx.tune(split=split)
+        out.append((ctx.force(idx, 0.0)[0].cpu().numpy(), ctx.timestep(idx, eta).cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_split_after_corrector(prec):
     # the corrector from split forces, then the criterion (the targets' velocities are
