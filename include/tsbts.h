@@ -102,8 +102,8 @@ int tsbts_destroy(tsbts_ctx *ctx);
  *                      pairs with the other particles by the gather kernels (a compact
  *                      copy of those as the sources); the criterion is then bit-identical,
  *                      force sums are combined in another fixed order (0 = never, 1 = from
- *                      8192 targets, 2 = automatic: from max(16384, n/8) targets, force
- *                      calls only without the potential; default 2).  The
+ *                      8192 targets, 2 = automatic: from 16384 targets, force calls only
+ *                      without the potential; default 2).  The
  *                      first such call on a context allocates the copies (about 270 bytes
  *                      per particle) and the symmetric partial buffers for its size.
  *   TSBTS_TUNE_CHECK_INDICES: 1 = every call that takes active_idx first checks on the

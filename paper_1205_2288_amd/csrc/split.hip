@@ -22,10 +22,7 @@ namespace tsbts {
 namespace {
 
 constexpr int64_t kSplitMinAct = 8192;    // targets, at least
-// Automatic use from max(kSplitAutoAct, n / kSplitAutoFrac) targets: the pairs saved grow
-// as k^2, the marks, scan and copies as n (they balance near k = 16384 at n = 131072).
-constexpr int64_t kSplitAutoAct = 16384;
-constexpr int64_t kSplitAutoFrac = 8;
+constexpr int64_t kSplitAutoAct = 16384;  // automatic use from this many targets
 
 // The split buffer for `cap` particles per copy.
 struct SplitBufs {
@@ -182,8 +179,7 @@ int value_bytes(const tsbts_ctx *c) { return c->precision == TSBTS_FP64 ? 8 : 4;
 
 bool split_applies(const tsbts_ctx *c, int64_t n_act) {
   if (c->tune_split == 0 || n_act >= c->n || n_act < kSplitMinAct) return false;
-  if (c->tune_split == 2 && (n_act < kSplitAutoAct || n_act < c->n / kSplitAutoFrac))
-    return false;
+  if (c->tune_split == 2 && n_act < kSplitAutoAct) return false;
   // the symmetric force has no Newton-step form; the gather part is the scalar-load
   // kernel in its default shapes
   if ((c->flags & TSBTS_FLAG_NEWTON) || !force_scalar_j(c) || c->tune_chunk != 0) return false;
