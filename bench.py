@@ -568,20 +568,24 @@ def force_calls(sizes, precision, reps=5):
     return {"workload": "plummer131k", "precision": precision, "calls": out}
 
 
-def native_run(name, t_end, precision, predict_on_load=None):
+def native_run(name, t_end, precision, predict_on_load=None, split=None):
     """One whole integration of a workload with the native scheduler (its own era, step
-    bounds and eta): wall time, block steps and the mean wall time per block step."""
+    bounds and eta): wall time, block steps and the mean wall time per block step.
+    ``split`` sets the split calls of large partial active sets (0 off, 1 from 8192
+    targets, 2 the library's automatic choice; None leaves the default)."""
     from paper_1205_2288_amd.driver import NativeTSBTS
     cfg = config(name)
     r, v, m = cfg.ic()
     kw = {} if predict_on_load is None else {"predict_on_load": bool(predict_on_load)}
+    if split is not None:
+        kw["tune"] = {"split": int(split)}
     sim = NativeTSBTS(r, v, m, cfg.eps, eta=cfg.eta, passes=3, era=cfg.era,
                       dt_max=cfg.dt_max, dt_min=cfg.dt_min, precision=precision, **kw)
     series = sim.run(t_end)
     st = sim.stats
     e0 = series[0][1]
     out = {"workload": name, "precision": precision, "t_end": t_end,
-           "predict_on_load": predict_on_load,
+           "predict_on_load": predict_on_load, "split": split,
            "wall_s": st["wall_s"], "block_steps": st["block_steps"],
            "us_per_block_step": st["wall_s"] / st["block_steps"] * 1e6,
            "interactions": st["interactions"], "eras": st["eras"],
@@ -602,7 +606,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-pass-cost", action="store_true")
     ap.add_argument("--native-run", default=None, metavar="WORKLOAD",
-                    help="only integrate WORKLOAD (plummer256, plummer4096) with the native "
+                    help="only integrate WORKLOAD (plummer256, plummer4096, plummer131k) with the native "
                          "scheduler to --t-end and print its block-step statistics (for "
                          "kernel traces of whole runs)")
     ap.add_argument("--t-end", type=float, default=1.0)
@@ -614,6 +618,9 @@ def main():
     ap.add_argument("--predict-on-load", type=int, default=None, choices=(0, 1),
                     help="native run: small active sets predicted inside the force kernel "
                          "(default: the scheduler's choice)")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1, 2),
+                    help="native run: split calls of large partial active sets (0 off, "
+                         "1 from 8192 targets, 2 automatic; default: the library's)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -635,7 +642,7 @@ def main():
         del src, dst
     if args.native_run:
         print(json.dumps(native_run(args.native_run, args.t_end, args.precision,
-                                    args.predict_on_load)))
+                                    args.predict_on_load, args.split)))
         return
     if args.force_calls:
         sizes = [int(x) for x in args.force_calls.split(",")]
