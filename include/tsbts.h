@@ -33,7 +33,7 @@ extern "C" {
 /* status codes */
 #define TSBTS_OK 0
 #define TSBTS_EINVAL (-1) /* invalid argument (null pointer, size or index out of range) */
-#define TSBTS_ENOMEM (-2) /* device allocation failed */
+#define TSBTS_ENOMEM (-2) /* device allocation failed (or the scheduler's host memory) */
 #define TSBTS_EHIP (-3)   /* a HIP runtime call failed; tsbts_last_error() has its text */
 #define TSBTS_ESTATE (-4) /* call out of order (e.g. force at a time that was not predicted) */
 

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <exception>
 #include <functional>
 #include <memory>
 #include <mutex>
@@ -38,6 +39,7 @@
 
 #include "internal.hpp"
 #include "predict.hpp"
+#include "rule_pool.hpp"
 
 namespace tsbts {
 
@@ -180,63 +182,6 @@ struct CritHistory {
     __builtin_prefetch(&gt[k]);
     __builtin_prefetch(&gc[k]);
   }
-};
-
-// Host threads for the step rule of long active lists: run(f) calls f(part, parts) for
-// every part, the calling thread taking part 0, and returns when all have returned.
-class RulePool {
- public:
-  explicit RulePool(int threads) : parts_(threads) {
-    for (int w = 1; w < threads; ++w) workers_.emplace_back([this, w] { loop(w); });
-  }
-  ~RulePool() {
-    {
-      std::lock_guard<std::mutex> lk(m_);
-      stop_ = true;
-    }
-    start_.notify_all();
-    for (auto &th : workers_) th.join();
-  }
-  int parts() const { return parts_; }
-  void run(const std::function<void(int, int)> &f) {
-    {
-      std::lock_guard<std::mutex> lk(m_);
-      job_ = &f;
-      remaining_ = parts_ - 1;
-      ++generation_;
-    }
-    start_.notify_all();
-    f(0, parts_);
-    std::unique_lock<std::mutex> lk(m_);
-    done_.wait(lk, [this] { return remaining_ == 0; });
-    job_ = nullptr;
-  }
-
- private:
-  void loop(int w) {
-    uint64_t seen = 0;
-    for (;;) {
-      const std::function<void(int, int)> *job;
-      {
-        std::unique_lock<std::mutex> lk(m_);
-        start_.wait(lk, [&] { return stop_ || generation_ != seen; });
-        if (stop_) return;
-        seen = generation_;
-        job = job_;
-      }
-      (*job)(w, parts_);
-      std::lock_guard<std::mutex> lk(m_);
-      if (--remaining_ == 0) done_.notify_one();
-    }
-  }
-  int parts_;
-  std::vector<std::thread> workers_;
-  std::mutex m_;
-  std::condition_variable start_, done_;
-  const std::function<void(int, int)> *job_ = nullptr;
-  uint64_t generation_ = 0;
-  int remaining_ = 0;
-  bool stop_ = false;
 };
 
 }  // namespace
@@ -627,6 +572,28 @@ void destroy_scheduler(tsbts_ctx *c) {
   free_sched(static_cast<Scheduler *>(c->sched));
   c->sched = nullptr;
 }
+
+namespace {
+
+// No C++ exception crosses the C interface: a host allocation that fails (the scheduler's
+// vectors) or a host thread that cannot be started becomes a status and a message.
+template <class F>
+int guarded(tsbts_ctx *c, const char *what, F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    snprintf(c->err, sizeof(c->err), "%s: host memory allocation failed", what);
+    return TSBTS_ENOMEM;
+  } catch (const std::exception &e) {
+    snprintf(c->err, sizeof(c->err), "%s: %s", what, e.what());
+    return TSBTS_ESTATE;
+  } catch (...) {
+    snprintf(c->err, sizeof(c->err), "%s: unexpected host failure", what);
+    return TSBTS_ESTATE;
+  }
+}
+
+}  // namespace
 }  // namespace tsbts
 
 extern "C" {
@@ -665,8 +632,8 @@ int tsbts_sched_era_end(int64_t t0, const int64_t *t_ticks, const int64_t *dt_ti
   return TSBTS_OK;
 }
 
-int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double dt_max,
-                     double era, hipStream_t st) {
+static int sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double dt_max,
+                      double era, hipStream_t st) {
   if (!c) return TSBTS_EINVAL;
   if (!c->r || !c->v || !c->a || !c->m || !c->t_last || !c->dt)
     return sfail(c, TSBTS_ESTATE, "tsbts_sched_init: no particle state bound");
@@ -732,7 +699,7 @@ int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double
   return TSBTS_OK;
 }
 
-int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
+static int sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
   if (!c) return TSBTS_EINVAL;
   Scheduler *S = static_cast<Scheduler *>(c->sched);
   if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_era: call tsbts_sched_init first");
@@ -808,9 +775,9 @@ int tsbts_sched_prev_steps(const tsbts_ctx *c, int64_t *dtp_ticks) {
   return TSBTS_OK;
 }
 
-int tsbts_sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_ticks,
-                        const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
-                        double time, hipStream_t st) {
+static int sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_ticks,
+                         const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
+                         double time, hipStream_t st) {
   if (!c) return TSBTS_EINVAL;
   Scheduler *S = static_cast<Scheduler *>(c->sched);
   if (!S) return sfail(c, TSBTS_ESTATE, "tsbts_sched_restore: call tsbts_sched_init first");
@@ -867,6 +834,27 @@ int tsbts_sched_state(const tsbts_ctx *c, int64_t *t_ticks, int64_t *dt_ticks, d
   if (stats) std::copy(S->stats, S->stats + 4, stats);
   if (time) *time = static_cast<double>(S->time) * tsbts::kTick;
   return TSBTS_OK;
+}
+
+int tsbts_sched_init(tsbts_ctx *c, double eta, int passes, double dt_min, double dt_max,
+                     double era, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  return tsbts::guarded(c, "tsbts_sched_init",
+                        [&] { return sched_init(c, eta, passes, dt_min, dt_max, era, st); });
+}
+
+int tsbts_sched_era(tsbts_ctx *c, double *era_end, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  return tsbts::guarded(c, "tsbts_sched_era", [&] { return sched_era(c, era_end, st); });
+}
+
+int tsbts_sched_restore(tsbts_ctx *c, const int64_t *t_ticks, const int64_t *dt_ticks,
+                        const int64_t *dtp_ticks, const double *dtc, const int64_t *stats,
+                        double time, hipStream_t st) {
+  if (!c) return TSBTS_EINVAL;
+  return tsbts::guarded(c, "tsbts_sched_restore", [&] {
+    return sched_restore(c, t_ticks, dt_ticks, dtp_ticks, dtc, stats, time, st);
+  });
 }
 
 }  // extern "C"

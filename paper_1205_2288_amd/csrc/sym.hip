@@ -1,5 +1,6 @@
 // Host side of the symmetric all-targets kernels: work items and partial buffers.
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "sym.hpp"
@@ -88,13 +89,19 @@ int sym_prepare(tsbts_ctx *c, int nv, int row_bytes, int col_bytes) {
   const SymShape sh = sym_shape(npad);
   if (c->sym_items_npad != npad || c->sym_chunk != sh.chunk) {
     std::vector<int4> items;
-    for (int b = 0; b < sh.n_bands; ++b) {
-      const int64_t first = static_cast<int64_t>(b) * sh.band_groups * kSymGroupRows;
-      int s = 0;
-      for (int64_t j0 = first; j0 < npad; j0 += sh.chunk, ++s)
-        items.push_back(make_int4(b, static_cast<int>(j0),
-                                  static_cast<int>(std::min<int64_t>(j0 + sh.chunk, npad)), s));
+    try {
+      for (int b = 0; b < sh.n_bands; ++b) {
+        const int64_t first = static_cast<int64_t>(b) * sh.band_groups * kSymGroupRows;
+        int s = 0;
+        for (int64_t j0 = first; j0 < npad; j0 += sh.chunk, ++s)
+          items.push_back(make_int4(b, static_cast<int>(j0),
+                                    static_cast<int>(std::min<int64_t>(j0 + sh.chunk, npad)),
+                                    s));
+      }
+    } catch (const std::bad_alloc &) {  // no exception leaves the library
+      return TSBTS_ENOMEM;
     }
+    (void)hipDeviceSynchronize();  // earlier launches may still read the old list
     if (c->sym_items) (void)hipFree(c->sym_items);
     c->sym_items = nullptr;
     c->sym_items_n = 0;

@@ -1,7 +1,8 @@
 """Host memory-safety checks (CPU tier): the oracle's C loops and the library's host-only
 code (the native scheduler's decision functions and the entry points' argument checks)
 built with AddressSanitizer and UBSan and run on random and extreme inputs
-(tests/asan/*.c*).  Device code is not instrumented."""
+(tests/asan/*.c*), and the step rule's thread pool also under ThreadSanitizer.  Device
+code is not instrumented."""
 import os
 import shutil
 import subprocess
@@ -54,3 +55,17 @@ def test_host_code_under_address_sanitizer(tmp_path):
     _run([HIPCC, "--offload-arch=gfx950", "-fsanitize=address,undefined", "-fno-gpu-sanitize", main, *objs, *rest, "-o", exe], tmp_path)
     res = _run([exe], tmp_path)
     assert "host rule and argument check ok" in res.stdout
+
+
+@pytest.mark.parametrize("sanitizer", ["address,undefined", "thread"])
+def test_rule_pool_under_sanitizers(tmp_path, sanitizer):
+    # the host threads of the step rule: every part once per call, a throwing part
+    # rethrown only after the others have ended, the pool usable afterwards
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "rule_pool_check")
+    _run(["g++", "-O1", "-g", "-std=c++17", "-pthread", f"-fsanitize={sanitizer}",
+          "-I" + os.path.join(PKG, "csrc"), os.path.join(ASAN, "rule_pool_check.cpp"),
+          "-o", exe], tmp_path)
+    res = _run([exe], tmp_path)
+    assert "rule pool check ok" in res.stdout
